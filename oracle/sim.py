@@ -1,0 +1,289 @@
+"""The frame and iteration loop of Algorithm 4, in float64.
+
+Paper: Algorithm 4 (unified GPU-friendly pipeline), with
+* Sec. 3.1: predicted state q~ = q_t + h v_t + h^2 M^-1 f_ext (gravity);
+* Eq. PD local / PD global: local projections and b = M q~ + h^2 sum w G^T p;
+* Sec. 5.2 (non-smooth constrained local-global integration): g, h vectors,
+  the Schur system (J A^-1 J^T + E) dlambda = (1/h^2)(h - J A^-1 g) (the sign of
+  Algorithms 3 and 4; the saddle-point equation prints the opposite sign, and
+  substituting q = A^-1 (g + h^2 J^T dlambda) into the second block row gives
+  the algorithms' sign), the update lambda += dlambda and the correction
+  q = A^-1 (b + h^2 J^T lambda);
+* Sec. 5.3: J = Omega H with the indicators of App. B, Schur term Omega W Omega
+  with the Delassus operator W = H A^-1 H^T formed once per frame;
+* Sec. 5.4: preconditioner r_n = h^2 W_jj (normal), r_f = h W_jj (friction);
+* App. A: delta_n = H_n q - d_n, h delta_dot_f = H_f (q - q_t) - h d_f.
+
+The global step is the plain definition u = A^-1 rhs, by a sparse LU
+factorisation of the constant node-level matrix A_n (A = A_n (x) I3).
+
+Readings: lambda^0 is the previous frame's impulse for the same (node,
+obstacle) key, re-expressed in the new contact frame (else 0); q^0 = q~;
+r_f uses (W_f1f1 + W_f2f2)/2; no clamping or projection of lambda.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import scipy.sparse.linalg as spla
+
+from . import contact as ct
+from . import fem
+from . import material as mat
+from .cr import conjugate_residual
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+@dataclasses.dataclass
+class FrameContacts:
+    node: np.ndarray
+    obst: np.ndarray
+    C: np.ndarray          # (c,3,3) rows n, f1, f2
+    d_n: np.ndarray
+    d_f: np.ndarray        # (c,2) f . u^
+    mu: np.ndarray
+    K: np.ndarray          # (c,c) [A_n^-1]_{v_j v_k}
+    W: np.ndarray          # (3c,3c)
+    r_n: np.ndarray
+    r_f: np.ndarray
+    gap: np.ndarray
+
+    @property
+    def c(self):
+        return len(self.node)
+
+
+class OracleSim:
+    def __init__(self, scene, cr_iters=None, pin_weight_scale=None, margin=None):
+        self.scene = scene
+        self.h = float(scene.h)
+        self.g = np.asarray(scene.gravity, np.float64)
+        self.rest = np.asarray(scene.rest, np.float64)
+        self.tets = np.asarray(scene.tets, np.int64)
+        n, m = len(self.rest), len(self.tets)
+        if m == 0 or n == 0:
+            raise OracleError("empty mesh")
+        if self.tets.min() < 0 or self.tets.max() >= n:
+            raise OracleError("tet index out of range")
+        if len(np.unique(self.tets.reshape(-1))) != n:
+            raise OracleError("unused node")
+        self.V, self.D = fem.rest_shape(self.rest, self.tets)
+        if not np.all(self.V > 0):
+            raise OracleError("non-positive tet volume")
+        self.model, self.mu, self.lam, self.k = fem.material_arrays(scene, m)
+        self.w = self.k * self.V
+        self.mass = fem.lumped_mass(n, self.tets, self.V, scene.rho)
+        self.pin_nodes = np.asarray(scene.pin_nodes, np.int64)
+        self.pin_group = np.asarray(scene.pin_group, np.int64)
+        scale = scene.pin_weight_scale if pin_weight_scale is None else pin_weight_scale
+        if len(self.pin_nodes) and not scale > 0:
+            raise OracleError("pin weight must be positive")
+        A0 = fem.system_matrix(n, self.tets, self.D, self.w, self.mass, self.h,
+                               np.zeros(0, np.int64), np.zeros(0))
+        self.pin_h2w = 1e3 * scale * A0.diagonal()[self.pin_nodes]
+        self.A = fem.system_matrix(n, self.tets, self.D, self.w, self.mass, self.h,
+                                   self.pin_nodes, self.pin_h2w)
+        self.lu = spla.splu(self.A.tocsc())
+        self.cr_iters = scene.cr_iters if cr_iters is None else cr_iters
+        self.margin = scene.margin if margin is None else margin
+        self.obstacles = list(scene.obstacles)
+        self.q = scene.q0().astype(np.float64)
+        self.v = scene.v0().astype(np.float64)
+        self.pin_x0 = self.q[self.pin_nodes].copy()
+        self.t = 0.0
+        self.prev = {}            # (node, obst) -> world-space impulse
+        self.n, self.m = n, m
+
+    # ---------------------------------------------------------------- basics
+    def solve(self, rhs):
+        """u = A^-1 rhs for an (n,3) right-hand side."""
+        return self.lu.solve(np.ascontiguousarray(rhs))
+
+    def predict(self, q_t=None, v_t=None):
+        q_t = self.q if q_t is None else q_t
+        v_t = self.v if v_t is None else v_t
+        return q_t + self.h * v_t + self.h * self.h * self.g[None, :]
+
+    def pin_target(self, t):
+        sc = self.scene
+        return fem.pin_targets(self.pin_x0, self.pin_group, sc.pin_lin_vel, sc.pin_ang_vel,
+                               sc.pin_pivot, t)
+
+    def local_step(self, q):
+        F = fem.deformation_gradient(q, self.tets, self.D)
+        return mat.local_step(self.model, F, self.mu, self.lam, self.k)
+
+    def rhs(self, q, q_pred, t_next):
+        """b = M q~ + h^2 sum w G^T p (+ pin terms) at positions q."""
+        P = self.local_step(q)
+        b = self.mass[:, None] * q_pred + self.h * self.h * fem.elastic_rhs(self.n, self.tets, self.D, self.w, P)
+        if len(self.pin_nodes):
+            np.add.at(b, self.pin_nodes, self.pin_h2w[:, None] * self.pin_target(t_next))
+        return b
+
+    # ---------------------------------------------------------------- contacts
+    def contacts_from_keys(self, node, obst, q_t):
+        """Frames, d_n, d_f, K, W and r for a given contact list (frames taken at q_t)."""
+        node = np.asarray(node, np.int64)
+        obst = np.asarray(obst, np.int64)
+        c = len(node)
+        C = np.zeros((c, 3, 3))
+        d_n = np.zeros(c)
+        d_f = np.zeros((c, 2))
+        mu = np.zeros(c)
+        gap = np.zeros(c)
+        for j in range(c):
+            ob = self.obstacles[obst[j]]
+            d, nrm = ct.sdf_normal(ob.type, ob.geom, q_t[node[j]])
+            f1, f2 = ct.tangent_basis(nrm)
+            C[j] = [nrm, f1, f2]
+            ph = q_t[node[j]] - d * np.asarray(nrm)
+            d_n[j] = float(np.dot(nrm, ph))
+            d_f[j] = [np.dot(f1, ob.vel), np.dot(f2, ob.vel)]
+            mu[j] = ob.mu
+            gap[j] = d
+        K, W = self.delassus(node, C)
+        Wd = np.diagonal(W)
+        r_n = self.h * self.h * Wd[0::3] if c else np.zeros(0)
+        r_f = self.h * 0.5 * (Wd[1::3] + Wd[2::3]) if c else np.zeros(0)
+        return FrameContacts(node, obst, C, d_n, d_f, mu, K, W, r_n, r_f, gap)
+
+    def delassus(self, node, C):
+        """K = B^T A_n^-1 B by multi-RHS solves; W_(j,k) = K_jk C_j C_k^T (A = A_n (x) I3)."""
+        c = len(node)
+        if c == 0:
+            return np.zeros((0, 0)), np.zeros((0, 0))
+        B = np.zeros((self.n, c))
+        B[node, np.arange(c)] = 1.0
+        Z = self.lu.solve(B)
+        K = Z[node, :]
+        K = 0.5 * (K + K.T)
+        W = np.einsum("jk,jab,kcb->jakc", K, C, C).reshape(3 * c, 3 * c)
+        return K, W
+
+    def detect(self, q_t, q_pred):
+        d = ct.detect(q_t, q_pred, self.obstacles, self.margin)
+        return d["node"], d["obst"]
+
+    def warm_start(self, fc):
+        lam = np.zeros((fc.c, 3))
+        for j in range(fc.c):
+            key = (int(fc.node[j]), int(fc.obst[j]))
+            if key in self.prev:
+                lam[j] = fc.C[j] @ self.prev[key]
+        return lam
+
+    # ---------------------------------------------------------------- one L-G iteration
+    def contact_eval(self, fc, q, q_t, lam):
+        """Omega, E, phi and the h vector at (q, lambda) (App. A, App. B, Sec. 5.2)."""
+        h = self.h
+        x = q[fc.node]
+        xt = q_t[fc.node]
+        n = fc.C[:, 0, :]
+        f = fc.C[:, 1:, :]
+        delta_n = np.einsum("ji,ji->j", n, x) - fc.d_n
+        hvf = np.einsum("jai,ji->ja", f, x - xt) - h * fc.d_f
+        vdot_f = hvf / h
+        phi_n, om_n, E_n = ct.normal_terms(delta_n, lam[:, 0], fc.r_n)
+        om_f, E_f, phi_f = ct.friction_terms(vdot_f, lam[:, 0], lam[:, 1:], fc.r_f, fc.mu)
+        Hq = np.einsum("jai,ji->ja", fc.C, x)                       # (c,3)
+        hv = np.empty((fc.c, 3))
+        hv[:, 0] = -phi_n + om_n * Hq[:, 0]
+        hv[:, 1:] = -h * phi_f + om_f[:, None] * Hq[:, 1:]
+        Om = np.stack([om_n, om_f, om_f], axis=1)
+        Ediag = np.stack([E_n / (h * h), E_f / h, E_f / h], axis=1)
+        return dict(delta_n=delta_n, vdot_f=vdot_f, Omega=Om, Ediag=Ediag, hvec=hv)
+
+    def H_T(self, fc, lam_c):
+        """H^T applied to per-contact (c,3) components -> nodal (n,3)."""
+        out = np.zeros((self.n, 3))
+        np.add.at(out, fc.node, np.einsum("jai,ja->ji", fc.C, lam_c))
+        return out
+
+    def H(self, fc, q):
+        return np.einsum("jai,ji->ja", fc.C, q[fc.node])
+
+    def iterate(self, fc, q, lam, q_t, q_pred, t_next, cr="fixed", cr_iters=None):
+        """One iteration of Algorithm 4; returns (q^{k+1}, lambda^{k+1}, info)."""
+        h = self.h
+        b = self.rhs(q, q_pred, t_next)
+        info = {}
+        if fc.c == 0:
+            qn = self.solve(b)
+            return qn, lam.copy(), info
+        ev = self.contact_eval(fc, q, q_t, lam)
+        Om = ev["Omega"]
+        g = b + h * h * self.H_T(fc, Om * lam)
+        ug = self.solve(g)
+        rhs = (ev["hvec"] - Om * self.H(fc, ug)) / (h * h)
+        om = Om.reshape(-1)
+        Mmat = om[:, None] * fc.W * om[None, :] + np.diag(ev["Ediag"].reshape(-1))
+        if cr == "exact":
+            dl = np.linalg.solve(Mmat, rhs.reshape(-1))
+        else:
+            its = self.cr_iters if cr_iters is None else cr_iters
+            dl = conjugate_residual(lambda x: Mmat @ x, rhs.reshape(-1), its)
+        lam_new = lam + dl.reshape(-1, 3)
+        qn = self.solve(b + h * h * self.H_T(fc, Om * lam_new))
+        info.update(ev)
+        info["dlam"] = dl.reshape(-1, 3)
+        info["cr_matrix"] = Mmat
+        info["cr_rhs"] = rhs.reshape(-1)
+        return qn, lam_new, info
+
+    def residual(self, fc, q, q_t, lam):
+        """NCP residual (metres) at (q, lambda)."""
+        if fc.c == 0:
+            return 0.0
+        x = q[fc.node]
+        n = fc.C[:, 0, :]
+        f = fc.C[:, 1:, :]
+        delta_n = np.einsum("ji,ji->j", n, x) - fc.d_n
+        vdot_f = (np.einsum("jai,ji->ja", f, x - q_t[fc.node]) - self.h * fc.d_f) / self.h
+        return ct.ncp_residual(delta_n, vdot_f, lam, fc.r_n, fc.r_f, fc.mu, self.h)
+
+    # ---------------------------------------------------------------- frames
+    def begin_frame(self):
+        q_t = self.q
+        q_pred = self.predict()
+        node, obst = self.detect(q_t, q_pred)
+        fc = self.contacts_from_keys(node, obst, q_t)
+        lam = self.warm_start(fc)
+        return q_t, q_pred, fc, lam
+
+    def end_frame(self, q_t, q, fc, lam):
+        self.v = (q - q_t) / self.h
+        self.q = q
+        self.t += self.h
+        self.prev = {(int(fc.node[j]), int(fc.obst[j])): fc.C[j].T @ lam[j] for j in range(fc.c)}
+
+    def step(self, frames=1, iters=None, tol=None, max_iters=200, cr="fixed"):
+        """Advance ``frames`` frames.  iters > 0: fixed count; iters == 0: until the NCP
+        residual is <= tol or max_iters.  Returns per-frame stats."""
+        iters = self.scene.iters if iters is None else iters
+        stats = []
+        for _ in range(frames):
+            q_t, q_pred, fc, lam = self.begin_frame()
+            q = q_pred.copy()
+            t_next = self.t + self.h
+            k = 0
+            res = None
+            while True:
+                q, lam, _ = self.iterate(fc, q, lam, q_t, q_pred, t_next, cr=cr)
+                k += 1
+                if iters > 0:
+                    if k >= iters:
+                        break
+                else:
+                    res = self.residual(fc, q, q_t, lam)
+                    if res <= tol or k >= max_iters:
+                        break
+            if res is None:
+                res = self.residual(fc, q, q_t, lam)
+            self.end_frame(q_t, q, fc, lam)
+            stats.append(dict(iters=k, contacts=fc.c, ncp=res))
+        return stats
