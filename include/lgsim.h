@@ -1,0 +1,233 @@
+/*
+ * lgsim.h -- C-ABI of the MI355X (gfx950) local-global hyperelastic solver with
+ * frictional contact (liblgsim_hip.so).
+ *
+ * The solver implements Algorithm 4 of "Fast But Accurate: A Real-Time
+ * Hyperelastic Simulator with Robust Frictional Contact" (arXiv 2503.15078):
+ * per frame, collision detection, the Delassus operator W = H S^T S H^T and the
+ * predicted state; per local-global iteration, the per-tet local projections
+ * (Eq. PD local), the right-hand side b (Eq. PD global), the non-smooth
+ * Fischer-Burmeister contact terms (Sec. 5.2, App. B), a Conjugate Residual
+ * solve of the Schur system (Sec. 5.2-5.3, Sec. 6) and the constrained global
+ * step q = S^T S (b + h^2 J^T lambda) (Sec. 4.2, Eq. rhs correction).
+ *
+ * Conventions for every call:
+ *  - Arrays passed in are host memory owned by the caller; they are read during
+ *    the call and copied (never retained).  Arrays passed out are host memory
+ *    owned by the caller and sized as documented.  The handle owns all device
+ *    memory it allocates.
+ *  - Node and tet arrays are in the caller's order; the library renumbers nodes
+ *    internally and converts back on every read.
+ *  - Every call returns SIM_OK (0) or a negative SIM_E_* code; on error the
+ *    message is available from sim_last_error() (thread-local) and the handle's
+ *    simulation state is unchanged unless stated otherwise.  No C++ exception
+ *    crosses the ABI.
+ *  - One handle must not be used by two threads at once.  Work is enqueued on the
+ *    handle's HIP stream; calls that return host data synchronise that stream.
+ */
+#ifndef LGSIM_H
+#define LGSIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SIM_OK = 0,
+  SIM_E_ARG = -1,       /* invalid argument                                        */
+  SIM_E_MESH = -2,      /* empty mesh, index out of range, unused node, volume <= 0 */
+  SIM_E_NOT_SPD = -3,   /* system matrix not positive definite                     */
+  SIM_E_NOMEM = -4,     /* host or device allocation failed                        */
+  SIM_E_DEVICE = -5,    /* HIP runtime error                                       */
+  SIM_E_STATE = -6,     /* call out of order                                       */
+  SIM_E_DIVERGED = -7,  /* non-finite state produced; state rolled back to frame start */
+  SIM_E_CAPACITY = -8   /* more contacts than sim_options.max_contacts             */
+};
+
+enum { SIM_ARAP = 0, SIM_COROT = 1, SIM_STABLE_NH = 2, SIM_MOONEY_RIVLIN = 3 };
+enum { SIM_OBST_HALFSPACE = 0, SIM_OBST_BOX = 1, SIM_OBST_CYLINDER = 2 };
+enum { SIM_WARM_ZERO = 0, SIM_WARM_PREV = 1, SIM_WARM_MLP = 2 };
+
+typedef struct lgsim* sim_t; /* opaque, library-owned */
+
+/* Tetrahedral mesh (Sec. 3.1: positions q, velocities v; Sec. 3.3: one local
+ * constraint per tet).  rest_xyz [n][3] and tets [m][4] are required; tets must be
+ * positively oriented.  init_xyz/init_vel [n][3] default to the rest shape and 0.
+ * Pinned nodes (positional constraints, Sec. 3.3 local step) carry a group index;
+ * the target of group g moves rigidly (sim_set_pin_motion). */
+typedef struct {
+  int32_t n_nodes, n_tets;
+  const double* rest_xyz;
+  const int32_t* tets;
+  const double* init_xyz;
+  const double* init_vel;
+  int32_t n_pins;
+  const int32_t* pin_nodes;
+  const int32_t* pin_group;
+} sim_mesh;
+
+/* Material (Sec. 3.3 local energies; models per Sec. 7.4): model is one of SIM_ARAP,
+ * SIM_COROT, SIM_STABLE_NH, SIM_MOONEY_RIVLIN.  Per-tet arrays [m] override the
+ * defaults when non-null. */
+typedef struct {
+  int32_t model;
+  double E, nu, rho;
+  const int32_t* tet_model;
+  const double* tet_E;
+  const double* tet_nu;
+} sim_material;
+
+/* Options.  cr_iters: Conjugate Residual iterations per L-G iteration (Sec. 7.1: 10).
+ * warm: initial impulse of a frame (SIM_WARM_*).  ncp_tol/max_iters: stopping rule of
+ * sim_step with iters == 0.  max_contacts: contact capacity (device buffers).
+ * hip_stream: a hipStream_t to enqueue on (null: the library creates its own). */
+typedef struct {
+  double gravity[3];
+  double pin_weight_scale; /* h^2 w_pin = 1e3 * scale * [A_n]_vv                */
+  double contact_margin;   /* metres; contact iff min(sdf(q_t), sdf(q~)) < margin */
+  int32_t cr_iters;
+  int32_t warm;
+  double ncp_tol;          /* metres */
+  int32_t max_iters;
+  int32_t max_contacts;
+  void* hip_stream;
+} sim_options;
+
+/* Obstacles (App. A: analytic contact partners).  geom by type:
+ *   HALFSPACE [px,py,pz, nx,ny,nz]        solid where n.(x-p) < 0
+ *   BOX       [cx,cy,cz, hx,hy,hz]        axis-aligned box, half extents
+ *   CYLINDER  [ax,ay,az, bx,by,bz, r]     capped cylinder
+ * mu is the Coulomb coefficient; vel is the obstacle velocity u^ entering d_f. */
+typedef struct {
+  int32_t type;
+  double geom[10];
+  double mu;
+  double vel[3];
+} sim_obstacle;
+
+/* Per-frame statistics.  ms_phase: 0 frame setup (predict, collision, Delassus,
+ * warm start), 1 local step + RHS, 2 S pass, 3 contact evaluation, 4 CR solve,
+ * 5 correction + S^T pass, 6 integrate, 7 residual. */
+typedef struct {
+  int32_t iters_done, n_contacts;
+  double ncp_res;
+  float ms_frame;
+  float ms_phase[8];
+} sim_stats;
+
+/* A contact: caller node id, obstacle index, frame rows (n, f1, f2), impulse
+ * (lambda_n, lambda_f1, lambda_f2) in that frame, signed distance at q_t. */
+typedef struct {
+  int32_t node, obstacle;
+  double frame[9];
+  double lambda[3];
+  double gap;
+} sim_contact;
+
+/* Fill *opt with defaults: gravity (0,0,-9.81), pin scale 1, margin 0, 10 CR
+ * iterations, previous-frame warm start, ncp_tol 1e-6, max_iters 200,
+ * max_contacts 2048, null stream. */
+int sim_options_default(sim_options* opt);
+
+/* Build a solver (Algorithm 4, first two lines): validates the mesh, assembles the
+ * constant system matrix A = M + h^2 sum w G^T G (Eq. PD global), factors it in
+ * float64 and forms S = L^-1 (Theorem 1, Algorithm 2), then uploads everything.
+ * h > 0 is the time step.  opt may be null (defaults).  On success *out owns the
+ * device state.  Errors: SIM_E_ARG, SIM_E_MESH, SIM_E_NOT_SPD, SIM_E_NOMEM,
+ * SIM_E_DEVICE. */
+int sim_create(const sim_mesh* mesh, const sim_material* mat, double h, const sim_options* opt,
+               sim_t* out);
+
+/* Replace the obstacle set (n >= 0; at most 64). */
+int sim_set_obstacles(sim_t s, int32_t n, const sim_obstacle* obs);
+
+/* Rigid motion of each pin group: target(t) = pivot + lin_vel t + R(ang_vel t)(x0 - pivot),
+ * x0 the pinned node's initial position.  Arrays [n_groups][3]; n_groups must cover
+ * every group index used by the mesh. */
+int sim_set_pin_motion(sim_t s, int32_t n_groups, const double* lin_vel, const double* ang_vel,
+                       const double* pivot);
+
+/* Advance `frames` frames (Algorithm 4 outer loop).  iters > 0: that many L-G
+ * iterations per frame; iters == 0: iterate until the NCP residual (max-norm, metres)
+ * is <= opt.ncp_tol or opt.max_iters is reached.  stats: null or [frames].
+ * Errors: SIM_E_CAPACITY (contacts beyond max_contacts; frame not advanced),
+ * SIM_E_DIVERGED (non-finite state; rolled back), SIM_E_DEVICE. */
+int sim_step(sim_t s, int32_t frames, int32_t iters, sim_stats* stats);
+
+/* Copy the state to the host: xyz/vel [n][3] in caller order (each may be null), and
+ * the last frame's contacts in canonical (node, obstacle) order into contacts[cap]
+ * (may be null); *n_contacts (may be null) receives the total count. */
+int sim_read_state(sim_t s, double* xyz, double* vel, sim_contact* contacts, int32_t cap,
+                   int32_t* n_contacts);
+
+/* Enqueue a device-to-device copy of the positions, float32 structure-of-arrays
+ * [3][n] in caller order, into d_xyz_soa (device memory owned by the caller, e.g. a
+ * torch tensor) on hip_stream (null: the handle's stream). */
+int sim_read_state_device(sim_t s, float* d_xyz_soa, void* hip_stream);
+
+/* Release everything owned by the handle (null is accepted). */
+int sim_destroy(sim_t s);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* sim_last_error(void);
+
+/* ---- batching (many independent scenes in one set of launches) -------------------
+ * Build a batch solver from several scene descriptions.  Scenes are concatenated:
+ * the block-diagonal system has one elimination forest, so every kernel of
+ * Algorithm 4 runs once per stage for all scenes, and the Conjugate Residual solves
+ * run per scene inside one cooperative launch.  All scenes share h and options.
+ * obstacles[i] / n_obstacles[i] describe scene i. */
+int sim_create_batch(int32_t count, const sim_mesh* meshes, const sim_material* mats,
+                     const int32_t* n_obstacles, const sim_obstacle* const* obstacles, double h,
+                     const sim_options* opt, sim_t* out);
+/* Scene count and per-scene node offsets ([count+1]) of a handle. */
+int sim_batch_info(sim_t s, int32_t* count, int32_t* node_offsets);
+
+/* ---- parity hooks (tests) --------------------------------------------------------
+ * Set a complete iterate state: frame start q_t, v_t [n][3], current iterate q_k
+ * [n][3] (caller order), simulation time t (frame start), and a contact list of c
+ * entries (node, obstacle, lambda in the frame of that contact; frame rows and gap
+ * are recomputed from q_t).  Recomputes the predicted state, frames, d_n, the
+ * Delassus operator and the preconditioner exactly as a frame start does, but keeps
+ * the given contact list and impulses. */
+int sim_set_iterate_state(sim_t s, const double* q_t, const double* v_t, const double* q_k,
+                          double t, int32_t c, const sim_contact* contacts);
+/* Run k L-G iterations from the current iterate state without ending the frame. */
+int sim_run_iterations(sim_t s, int32_t k);
+/* Read the current iterate q_k [n][3] (caller order) and the impulses [c][3] of the
+ * contact list, in canonical (node, obstacle) order. */
+int sim_read_iterate(sim_t s, double* q_k, double* lambda);
+/* u = S^T S b on the device (the global step, Algorithm 2): b, u [n][3] caller order. */
+int sim_global_solve(sim_t s, const double* b, double* u);
+/* Delta-form right-hand side of the current iterate: b - A q~ [n][3] (caller order),
+ * i.e. h^2 sum_t w_t G_t^T (p_t - G_t q~) + pin terms (Eq. PD local / PD global). */
+int sim_debug_rhs(sim_t s, double* rhs);
+/* Delassus block K = B^T A_n^-1 B of the current contact list ([c][c], canonical
+ * order), from which W_(j,k) = K_jk C_j C_k^T (Sec. 5.3). */
+int sim_debug_delassus(sim_t s, double* K);
+
+/* ---- host-only precompute inspection (no device needed) -------------------------
+ * Run only the host precomputation of sim_create and keep its products. */
+typedef struct lg_host* lg_host_t;
+int lg_host_create(const sim_mesh* mesh, const sim_material* mat, double h, double pin_weight_scale,
+                   int32_t want_dense_S, lg_host_t* out);
+/* info[0..7] = n, m, nnz(S), nnz(L), stored row floats, max depth, chains, 0. */
+int lg_host_info(lg_host_t hs, int64_t* info);
+/* perm[orig] = internal index; parent [n] etree in internal order (-1 for roots). */
+int lg_host_ordering(lg_host_t hs, int32_t* perm, int32_t* parent);
+/* Node-level A_n [n][n] dense, internal order (small meshes). */
+int lg_host_dense_A(lg_host_t hs, double* A);
+/* S = L^-1 [n][n] dense, internal order: float64 values if requested at creation. */
+int lg_host_dense_S(lg_host_t hs, double* S);
+/* S^T S b for b [n][3] internal order, using the float32 row and column storages on
+ * the host (checks both layouts). */
+int lg_host_apply_StS(lg_host_t hs, const double* b, double* u);
+int lg_host_destroy(lg_host_t hs);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LGSIM_H */

@@ -1,0 +1,1058 @@
+// C-ABI of the gfx950 solver: handle creation (precompute + upload), the frame and
+// iteration drivers of Algorithm 4, state readback and the parity hooks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+#include "precompute.hpp"
+#include "status.hpp"
+
+namespace lg {
+MeshIn mesh_in(const sim_mesh* m);
+MaterialIn material_in(const sim_material* m);
+}  // namespace lg
+
+namespace {
+
+constexpr int kSegFloats = 2048;  // S-pass segment length (floats) per wavefront
+
+#define HIPCHK(x)                                                                        \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess) {                                                              \
+      lg::set_error(std::string("HIP error: ") + hipGetErrorString(e_) + " at " #x);     \
+      return SIM_E_DEVICE;                                                               \
+    }                                                                                    \
+  } while (0)
+
+struct SceneMeta {
+  int n = 0, m = 0;
+  int node0 = 0;          // first internal node of the scene
+  int caller0 = 0;        // first caller-order node of the scene (batch concatenation)
+  int groups0 = 0;        // first global pin group
+  int n_groups = 0;
+  std::vector<int32_t> perm;  // local caller -> local internal
+  double margin = 0.0;
+};
+
+}  // namespace
+
+struct lgsim {
+  sim_options opt{};
+  lg::Dev d{};
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  std::vector<void*> allocs;
+  std::vector<SceneMeta> scenes;
+  std::vector<int32_t> iperm_caller;  // internal node -> caller node (global)
+  std::vector<int32_t> perm_caller;   // caller node -> internal node (global)
+  std::vector<lg::ObstacleDev> obst;  // host copy
+  std::vector<int> scene_obst0;
+  int cr_blocks = 1;
+  int* h_pinned = nullptr;            // [4]: n_contacts, overflow, bad, spare
+  float* h_res = nullptr;             // [NS]
+  int iter_c = 0;                     // contact count of the current iterate state
+  std::vector<int32_t> iter_canon;    // internal contact index -> canonical position
+  hipEvent_t ev[8] = {};
+  bool frame_open = false;
+
+  template <class T>
+  int alloc(T*& p, size_t count) {
+    void* q = nullptr;
+    size_t bytes = std::max<size_t>(1, count) * sizeof(T);
+    if (hipMalloc(&q, bytes) != hipSuccess) {
+      lg::set_error("hipMalloc failed (" + std::to_string(bytes) + " bytes)");
+      return SIM_E_NOMEM;
+    }
+    if (hipMemset(q, 0, bytes) != hipSuccess) {
+      lg::set_error("hipMemset failed");
+      return SIM_E_DEVICE;
+    }
+    allocs.push_back(q);
+    p = static_cast<T*>(q);
+    return SIM_OK;
+  }
+  ~lgsim() {
+    if (st) hipStreamSynchronize(st);
+    for (void* p : allocs) hipFree(p);
+    for (auto& e : ev)
+      if (e) hipEventDestroy(e);
+    if (h_pinned) hipHostFree(h_pinned);
+    if (h_res) hipHostFree(h_res);
+    if (own_stream && st) hipStreamDestroy(st);
+  }
+};
+
+namespace {
+
+template <class T>
+int upload(lgsim* s, T* dst, const T* src, size_t count) {
+  if (count == 0) return SIM_OK;
+  HIPCHK(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  return SIM_OK;
+}
+
+#define TRY(x)                 \
+  do {                         \
+    int rc_ = (x);             \
+    if (rc_ != SIM_OK) return rc_; \
+  } while (0)
+
+int check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    lg::set_error(std::string("kernel launch failed (") + what + "): " + hipGetErrorString(e));
+    return SIM_E_DEVICE;
+  }
+  return SIM_OK;
+}
+
+// Upload obstacles of all scenes.
+int push_obstacles(lgsim* s) {
+  auto& d = s->d;
+  if (!s->obst.empty()) TRY(upload(s, d.obst, s->obst.data(), s->obst.size()));
+  TRY(upload(s, d.scene_obst0, s->scene_obst0.data(), s->scene_obst0.size()));
+  return SIM_OK;
+}
+
+// Build one handle from host precomputations of several scenes (concatenated).
+int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vector<sim_obstacle>>& obs) {
+  auto& d = s->d;
+  const int NS = (int)hs.size();
+  int N = 0, M = 0, P = 0, G = 0;
+  s->scenes.resize(NS);
+  for (int k = 0; k < NS; ++k) {
+    auto& sm = s->scenes[k];
+    sm.n = hs[k].n;
+    sm.m = hs[k].m;
+    sm.node0 = N;
+    sm.caller0 = N;
+    sm.perm = hs[k].perm;
+    sm.margin = s->opt.contact_margin;
+    sm.groups0 = G;
+    int ng = 0;
+    for (int g : hs[k].pin_group) ng = std::max(ng, g + 1);
+    sm.n_groups = ng;
+    N += hs[k].n;
+    M += hs[k].m;
+    P += (int)hs[k].pin_nodes.size();
+    G += ng;
+  }
+  d.N = N;
+  d.N4 = ((N + 3) & ~3) + 4;
+  d.M = M;
+  d.P = P;
+  d.G = std::max(G, 1);
+  d.NS = NS;
+  d.CMAX = std::max(1, s->opt.max_contacts);
+  d.KCAP = std::min<int64_t>((int64_t)d.CMAX * d.CMAX, (int64_t)64 << 20);
+  d.h = hs[0].h;
+  for (int c = 0; c < 3; ++c) d.g[c] = s->opt.gravity[c];
+  d.cr_iters = s->opt.cr_iters;
+  d.warm = s->opt.warm;
+  s->perm_caller.resize(N);
+  s->iperm_caller.resize(N);
+  for (int k = 0; k < NS; ++k)
+    for (int o = 0; o < hs[k].n; ++o) {
+      int gi = s->scenes[k].node0 + hs[k].perm[o];
+      s->perm_caller[s->scenes[k].caller0 + o] = gi;
+      s->iperm_caller[gi] = s->scenes[k].caller0 + o;
+    }
+
+  // ---- node arrays
+  const int N4 = d.N4;
+  std::vector<float> qt(3 * (size_t)N4, 0.0f), vt(3 * (size_t)N4, 0.0f), pinw(N, 0.0f);
+  std::vector<int> node_scene(N, 0);
+  for (int k = 0; k < NS; ++k)
+    for (int o = 0; o < hs[k].n; ++o) {
+      int gi = s->scenes[k].node0 + hs[k].perm[o];
+      node_scene[gi] = k;
+      for (int c = 0; c < 3; ++c) {
+        qt[c * (size_t)N4 + gi] = (float)hs[k].init[3 * (size_t)o + c];
+        vt[c * (size_t)N4 + gi] = (float)hs[k].vel[3 * (size_t)o + c];
+      }
+    }
+  // pins
+  std::vector<int> pin_node(P), pin_group(P);
+  std::vector<double> pin_x0(3 * (size_t)std::max(P, 1));
+  {
+    int p = 0;
+    for (int k = 0; k < NS; ++k)
+      for (size_t q = 0; q < hs[k].pin_nodes.size(); ++q, ++p) {
+        int o = hs[k].pin_nodes[q];
+        int gi = s->scenes[k].node0 + hs[k].perm[o];
+        pin_node[p] = gi;
+        pin_group[p] = s->scenes[k].groups0 + hs[k].pin_group[q];
+        pinw[gi] = (float)hs[k].pin_h2w[q];
+        for (int c = 0; c < 3; ++c) pin_x0[c * (size_t)P + p] = (double)(float)hs[k].init[3 * (size_t)o + c];
+      }
+  }
+  // tets: internal node indices, sorted per scene by smallest node for locality
+  std::vector<int> tidx(4 * (size_t)M);
+  std::vector<float> dinv(9 * (size_t)M), hw(M), tmu(M), tlam(M), tk(M);
+  std::vector<unsigned char> tmodel(M);
+  {
+    int t0 = 0;
+    for (int k = 0; k < NS; ++k) {
+      auto& H = hs[k];
+      std::vector<int> order(H.m);
+      std::iota(order.begin(), order.end(), 0);
+      auto key = [&](int t) {
+        int mn = 1 << 30;
+        for (int a = 0; a < 4; ++a) mn = std::min(mn, H.perm[H.tets[4 * (size_t)t + a]]);
+        return mn;
+      };
+      std::vector<int> keys(H.m);
+      for (int t = 0; t < H.m; ++t) keys[t] = key(t);
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return keys[a] < keys[b]; });
+      for (int q = 0; q < H.m; ++q) {
+        int t = order[q], gt = t0 + q;
+        for (int a = 0; a < 4; ++a) tidx[a * (size_t)M + gt] = s->scenes[k].node0 + H.perm[H.tets[4 * (size_t)t + a]];
+        for (int e = 0; e < 9; ++e) dinv[e * (size_t)M + gt] = (float)H.Dm_inv[9 * (size_t)t + e];
+        hw[gt] = (float)(H.h * H.h * H.kstiff[t] * H.vol[t]);
+        tmu[gt] = (float)H.mu[t];
+        tlam[gt] = (float)H.lam[t];
+        tk[gt] = (float)H.kstiff[t];
+        tmodel[gt] = (unsigned char)H.model[t];
+      }
+      t0 += H.m;
+    }
+  }
+  // node -> (corner, tet) gather lists in increasing (tet, corner) order
+  std::vector<int> g_ptr(N + 1, 0), g_slot(4 * (size_t)M);
+  for (int t = 0; t < M; ++t)
+    for (int a = 0; a < 4; ++a) g_ptr[tidx[a * (size_t)M + t] + 1]++;
+  for (int v = 0; v < N; ++v) g_ptr[v + 1] += g_ptr[v];
+  {
+    std::vector<int> fill(g_ptr.begin(), g_ptr.end() - 1);
+    for (int t = 0; t < M; ++t)
+      for (int a = 0; a < 4; ++a) g_slot[fill[tidx[a * (size_t)M + t]]++] = a * M + t;
+  }
+  // S: row storage re-padded on global 4-aligned columns, column storage concatenated
+  std::vector<int64_t> row_ptr(N + 1, 0), col_ptr(N + 1, 0);
+  std::vector<int> row_lo4(N), parent(N), lo(N), depth(N), chain_end(N);
+  for (int k = 0; k < NS; ++k) {
+    int n0 = s->scenes[k].node0;
+    for (int i = 0; i < hs[k].n; ++i) {
+      int gi = n0 + i;
+      int lo4 = (n0 + hs[k].lo[i]) & ~3;
+      int hi4 = (gi & ~3) + 4;
+      row_lo4[gi] = lo4;
+      row_ptr[gi + 1] = hi4 - lo4;
+      col_ptr[gi + 1] = hs[k].col_ptr[i + 1] - hs[k].col_ptr[i];
+      parent[gi] = hs[k].parent[i] < 0 ? -1 : n0 + hs[k].parent[i];
+      lo[gi] = n0 + hs[k].lo[i];
+      depth[gi] = hs[k].depth[i];
+      chain_end[gi] = n0 + hs[k].chain_end[i];
+    }
+  }
+  for (int v = 0; v < N; ++v) {
+    row_ptr[v + 1] += row_ptr[v];
+    col_ptr[v + 1] += col_ptr[v];
+  }
+  // segments of the S pass
+  std::vector<int> seg_row, seg_col0, seg_len, long_row, long_seg0, long_nseg;
+  std::vector<int64_t> seg_off;
+  for (int i = 0; i < N; ++i) {
+    int64_t len = row_ptr[i + 1] - row_ptr[i];
+    int nseg = (int)((len + kSegFloats - 1) / kSegFloats);
+    if (nseg > 1) {
+      long_row.push_back(i);
+      long_seg0.push_back((int)seg_row.size());
+      long_nseg.push_back(nseg);
+    }
+    for (int q = 0; q < nseg; ++q) {
+      int64_t st = (int64_t)q * kSegFloats;
+      seg_row.push_back(nseg > 1 ? -(i + 1) : i);
+      seg_off.push_back(row_ptr[i] + st);
+      seg_col0.push_back(row_lo4[i] + (int)st);
+      seg_len.push_back((int)std::min<int64_t>(kSegFloats, len - st));
+    }
+  }
+  d.nseg = (int)seg_row.size();
+  d.nlong = (int)long_row.size();
+
+  // ---- allocate
+  const size_t NV = 3 * (size_t)N4;
+  const int CM = d.CMAX;
+  TRY(s->alloc(d.qt, NV));
+  TRY(s->alloc(d.vt, NV));
+  TRY(s->alloc(d.qp, NV));
+  TRY(s->alloc(d.q, NV));
+  TRY(s->alloc(d.b, NV));
+  TRY(s->alloc(d.y, NV));
+  TRY(s->alloc(d.tgt, NV));
+  TRY(s->alloc(d.tmp, NV));
+  TRY(s->alloc(d.iperm_caller, N));
+  TRY(s->alloc(d.pin_w, N));
+  TRY(s->alloc(d.node_scene, N));
+  TRY(s->alloc(d.g_ptr, N + 1));
+  TRY(s->alloc(d.g_slot, 4 * (size_t)M));
+  TRY(s->alloc(d.pin_node, P));
+  TRY(s->alloc(d.pin_group, P));
+  TRY(s->alloc(d.pin_x0, 3 * (size_t)std::max(P, 1)));
+  TRY(s->alloc(d.grp, 9 * (size_t)d.G));
+  TRY(s->alloc(d.tidx, 4 * (size_t)M));
+  TRY(s->alloc(d.dinv, 9 * (size_t)M));
+  TRY(s->alloc(d.hw, M));
+  TRY(s->alloc(d.tmu, M));
+  TRY(s->alloc(d.tlam, M));
+  TRY(s->alloc(d.tk, M));
+  TRY(s->alloc(d.tmodel, M));
+  TRY(s->alloc(d.fc, 12 * (size_t)M));
+  TRY(s->alloc(d.row_ptr, N + 1));
+  TRY(s->alloc(d.row_lo4, N));
+  TRY(s->alloc(d.row_val, (size_t)row_ptr[N]));
+  TRY(s->alloc(d.seg_row, d.nseg));
+  TRY(s->alloc(d.seg_col0, d.nseg));
+  TRY(s->alloc(d.seg_len, d.nseg));
+  TRY(s->alloc(d.seg_off, d.nseg));
+  TRY(s->alloc(d.long_row, d.nlong));
+  TRY(s->alloc(d.long_seg0, d.nlong));
+  TRY(s->alloc(d.long_nseg, d.nlong));
+  TRY(s->alloc(d.partial, 3 * (size_t)d.nseg));
+  TRY(s->alloc(d.col_ptr, N + 1));
+  TRY(s->alloc(d.col_val, (size_t)col_ptr[N]));
+  TRY(s->alloc(d.parent, N));
+  TRY(s->alloc(d.lo, N));
+  TRY(s->alloc(d.depth, N));
+  TRY(s->alloc(d.chain_end, N));
+  TRY(s->alloc(d.scene_node0, NS + 1));
+  TRY(s->alloc(d.scene_obst0, NS + 1));
+  TRY(s->alloc(d.scene_margin, NS));
+  TRY(s->alloc(d.obst, (size_t)lg::kMaxObstacles * NS));
+  TRY(s->alloc(d.n_contacts, 4));
+  TRY(s->alloc(d.overflow, 4));
+  TRY(s->alloc(d.cnt, N));
+  TRY(s->alloc(d.blk, (N + lg::kBlock - 1) / lg::kBlock + 1));
+  TRY(s->alloc(d.c_node, CM));
+  TRY(s->alloc(d.c_obst, CM));
+  TRY(s->alloc(d.c_scene, CM));
+  TRY(s->alloc(d.cC, 9 * (size_t)CM));
+  TRY(s->alloc(d.c_dn, CM));
+  TRY(s->alloc(d.c_df, 2 * (size_t)CM));
+  TRY(s->alloc(d.c_mu, CM));
+  TRY(s->alloc(d.c_rn, CM));
+  TRY(s->alloc(d.c_rf, CM));
+  TRY(s->alloc(d.c_gap, CM));
+  TRY(s->alloc(d.lam, 3 * (size_t)CM));
+  TRY(s->alloc(d.cs_off, NS + 1));
+  TRY(s->alloc(d.k_off, NS + 1));
+  TRY(s->alloc(d.tile_off, NS + 1));
+  TRY(s->alloc(d.K, (size_t)d.KCAP));
+  TRY(s->alloc(d.ad, CM));
+  TRY(s->alloc(d.pc_count, 4));
+  TRY(s->alloc(d.pc_node, CM));
+  TRY(s->alloc(d.pc_obst, CM));
+  TRY(s->alloc(d.pc_world, 3 * (size_t)CM));
+  for (float** p : {&d.Hu, &d.Om, &d.Et, &d.hv, &d.X, &d.F, &d.cr_x, &d.cr_r, &d.cr_p, &d.cr_Ar, &d.cr_Ap, &d.cr_Z})
+    TRY(s->alloc(*p, 3 * (size_t)CM));
+  TRY(s->alloc(d.cr_prod, 2 * (size_t)CM));
+  TRY(s->alloc(d.t, 1));
+  TRY(s->alloc(d.res, NS));
+  TRY(s->alloc(d.bad, 4));
+
+  // ---- upload constants
+  std::vector<float> row_val((size_t)row_ptr[N], 0.0f), col_val((size_t)col_ptr[N]);
+  for (int k = 0; k < NS; ++k) {
+    int n0 = s->scenes[k].node0;
+    auto& H = hs[k];
+    for (int i = 0; i < H.n; ++i) {
+      int gi = n0 + i;
+      // true entries are columns [lo_i, i] (local)
+      for (int j = H.lo[i]; j <= i; ++j)
+        row_val[row_ptr[gi] + (n0 + j - row_lo4[gi])] = H.row_val[H.row_ptr[i] + (j - H.row_lo4[i])];
+    }
+    std::copy(H.col_val.begin(), H.col_val.end(), col_val.begin() + col_ptr[n0]);
+    // release host S copies of this scene
+    std::vector<float>().swap(H.row_val);
+    std::vector<float>().swap(H.col_val);
+  }
+  std::vector<int> scene_node0(NS + 1);
+  std::vector<double> margins(NS);
+  for (int k = 0; k < NS; ++k) {
+    scene_node0[k] = s->scenes[k].node0;
+    margins[k] = s->scenes[k].margin;
+  }
+  scene_node0[NS] = N;
+  TRY(upload(s, d.qt, qt.data(), qt.size()));
+  TRY(upload(s, d.vt, vt.data(), vt.size()));
+  TRY(upload(s, d.pin_w, pinw.data(), pinw.size()));
+  TRY(upload(s, d.node_scene, node_scene.data(), node_scene.size()));
+  TRY(upload(s, d.iperm_caller, s->iperm_caller.data(), s->iperm_caller.size()));
+  TRY(upload(s, d.g_ptr, g_ptr.data(), g_ptr.size()));
+  TRY(upload(s, d.g_slot, g_slot.data(), g_slot.size()));
+  TRY(upload(s, d.pin_node, pin_node.data(), pin_node.size()));
+  TRY(upload(s, d.pin_group, pin_group.data(), pin_group.size()));
+  TRY(upload(s, d.pin_x0, pin_x0.data(), pin_x0.size()));
+  TRY(upload(s, d.tidx, tidx.data(), tidx.size()));
+  TRY(upload(s, d.dinv, dinv.data(), dinv.size()));
+  TRY(upload(s, d.hw, hw.data(), hw.size()));
+  TRY(upload(s, d.tmu, tmu.data(), tmu.size()));
+  TRY(upload(s, d.tlam, tlam.data(), tlam.size()));
+  TRY(upload(s, d.tk, tk.data(), tk.size()));
+  TRY(upload(s, d.tmodel, tmodel.data(), tmodel.size()));
+  TRY(upload(s, d.row_ptr, row_ptr.data(), row_ptr.size()));
+  TRY(upload(s, d.row_lo4, row_lo4.data(), row_lo4.size()));
+  TRY(upload(s, d.row_val, row_val.data(), row_val.size()));
+  TRY(upload(s, d.seg_row, seg_row.data(), seg_row.size()));
+  TRY(upload(s, d.seg_col0, seg_col0.data(), seg_col0.size()));
+  TRY(upload(s, d.seg_len, seg_len.data(), seg_len.size()));
+  TRY(upload(s, d.seg_off, seg_off.data(), seg_off.size()));
+  TRY(upload(s, d.long_row, long_row.data(), long_row.size()));
+  TRY(upload(s, d.long_seg0, long_seg0.data(), long_seg0.size()));
+  TRY(upload(s, d.long_nseg, long_nseg.data(), long_nseg.size()));
+  TRY(upload(s, d.col_ptr, col_ptr.data(), col_ptr.size()));
+  TRY(upload(s, d.col_val, col_val.data(), col_val.size()));
+  TRY(upload(s, d.parent, parent.data(), parent.size()));
+  TRY(upload(s, d.lo, lo.data(), lo.size()));
+  TRY(upload(s, d.depth, depth.data(), depth.size()));
+  TRY(upload(s, d.chain_end, chain_end.data(), chain_end.size()));
+  TRY(upload(s, d.scene_node0, scene_node0.data(), scene_node0.size()));
+  TRY(upload(s, d.scene_margin, margins.data(), margins.size()));
+  // obstacles
+  s->scene_obst0.assign(NS + 1, 0);
+  s->obst.clear();
+  for (int k = 0; k < NS; ++k) {
+    s->scene_obst0[k] = (int)s->obst.size();
+    if (k < (int)obs.size())
+      for (auto& o : obs[k]) {
+        lg::ObstacleDev od{};
+        od.type = o.type;
+        od.scene = k;
+        std::memcpy(od.geom, o.geom, sizeof(od.geom));
+        od.mu = o.mu;
+        std::memcpy(od.vel, o.vel, sizeof(od.vel));
+        s->obst.push_back(od);
+      }
+  }
+  s->scene_obst0[NS] = (int)s->obst.size();
+  TRY(push_obstacles(s));
+  // default pin motion: all groups static
+  std::vector<double> grp(9 * (size_t)d.G, 0.0);
+  TRY(upload(s, d.grp, grp.data(), grp.size()));
+  s->cr_blocks = std::max(1, std::min(lg::cr_max_blocks(), 256));
+  int per = (d.CMAX + s->cr_blocks - 1) / s->cr_blocks;
+  if (per > 256) {
+    lg::set_error("max_contacts too large for the CR launch");
+    return SIM_E_ARG;
+  }
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&s->h_pinned), 4 * sizeof(int), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&s->h_res), std::max(1, NS) * sizeof(float), hipHostMallocDefault));
+  for (auto& e : s->ev) HIPCHK(hipEventCreate(&e));
+  return SIM_OK;
+}
+
+int validate_obstacles(int32_t n, const sim_obstacle* obs) {
+  if (n < 0 || n > lg::kMaxObstacles || (n > 0 && !obs)) {
+    lg::set_error("bad obstacle count");
+    return SIM_E_ARG;
+  }
+  for (int i = 0; i < n; ++i) {
+    const auto& o = obs[i];
+    if (o.type < 0 || o.type > 2 || !(o.mu >= 0.0)) {
+      lg::set_error("bad obstacle " + std::to_string(i));
+      return SIM_E_ARG;
+    }
+    for (double g : o.geom)
+      if (!std::isfinite(g)) {
+        lg::set_error("non-finite obstacle geometry");
+        return SIM_E_ARG;
+      }
+    if (o.type == 0 && o.geom[3] * o.geom[3] + o.geom[4] * o.geom[4] + o.geom[5] * o.geom[5] == 0.0) {
+      lg::set_error("half-space with zero normal");
+      return SIM_E_ARG;
+    }
+    if (o.type == 2 && (!(o.geom[6] > 0.0) || (o.geom[0] == o.geom[3] && o.geom[1] == o.geom[4] && o.geom[2] == o.geom[5]))) {
+      lg::set_error("degenerate cylinder");
+      return SIM_E_ARG;
+    }
+  }
+  return SIM_OK;
+}
+
+// ---------------------------------------------------------------- drivers
+int frame_setup(lgsim* s) {
+  auto& d = s->d;
+  lg::launch_predict(d, s->st);
+  lg::launch_pins(d, s->st);
+  lg::launch_collide(d, s->st);
+  TRY(check_launch("collision"));
+  HIPCHK(hipMemcpyAsync(s->h_pinned, d.n_contacts, sizeof(int), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipMemcpyAsync(s->h_pinned + 1, d.overflow, sizeof(int), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  if (s->h_pinned[1]) {
+    lg::set_error("contact capacity exceeded: " + std::to_string(s->h_pinned[0]) + " contacts > max_contacts " +
+                  std::to_string(d.CMAX) + " (or Delassus storage full)");
+    int zero = 0;
+    HIPCHK(hipMemcpyAsync(d.overflow, &zero, sizeof(int), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return SIM_E_CAPACITY;
+  }
+  s->iter_c = s->h_pinned[0];
+  if (s->iter_c > 0) {
+    lg::launch_delassus(d, s->st);
+    lg::launch_warm_start(d, s->st, 0);
+  }
+  return check_launch("frame setup");
+}
+
+int iteration(lgsim* s, bool timed, float* ms) {
+  auto& d = s->d;
+  hipError_t cr_err = hipSuccess;
+  auto rec = [&](int i) {
+    if (timed) hipEventRecord(s->ev[i], s->st);
+  };
+  rec(1);
+  lg::launch_element(d, s->st);
+  lg::launch_gather(d, s->st);
+  rec(2);
+  lg::launch_spmv_S(d, s->st, d.b, d.y);
+  rec(3);
+  if (s->iter_c > 0) {
+    lg::launch_contact_prep(d, s->st);
+    rec(4);
+    cr_err = lg::launch_cr(d, s->st, s->cr_blocks);
+    rec(5);
+    lg::launch_apply_forces(d, s->st);
+  } else {
+    rec(4);
+    rec(5);
+  }
+  lg::launch_spmv_St(d, s->st, d.y, d.qp, d.q);
+  rec(6);
+  if (timed) {
+    hipEventSynchronize(s->ev[6]);
+    float t;
+    hipEventElapsedTime(&t, s->ev[1], s->ev[2]);
+    ms[1] += t;
+    hipEventElapsedTime(&t, s->ev[2], s->ev[3]);
+    ms[2] += t;
+    hipEventElapsedTime(&t, s->ev[3], s->ev[4]);
+    ms[3] += t;
+    hipEventElapsedTime(&t, s->ev[4], s->ev[5]);
+    ms[4] += t;
+    hipEventElapsedTime(&t, s->ev[5], s->ev[6]);
+    ms[5] += t;
+  }
+  if (cr_err != hipSuccess) {
+    lg::set_error(std::string("cooperative CR launch failed: ") + hipGetErrorString(cr_err));
+    return SIM_E_DEVICE;
+  }
+  return check_launch("iteration");
+}
+
+int read_residual(lgsim* s, double* worst) {
+  auto& d = s->d;
+  lg::launch_residual(d, s->st);
+  HIPCHK(hipMemcpyAsync(s->h_res, d.res, sizeof(float) * d.NS, hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  double w = 0.0;
+  for (int k = 0; k < d.NS; ++k) w = std::max(w, (double)s->h_res[k]);
+  *worst = w;
+  return SIM_OK;
+}
+
+int finish_frame(lgsim* s) {
+  auto& d = s->d;
+  lg::launch_check_finite(d, s->st);
+  lg::launch_integrate(d, s->st);
+  TRY(check_launch("integrate"));
+  HIPCHK(hipMemcpyAsync(s->h_pinned + 2, d.bad, sizeof(int), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  if (s->h_pinned[2]) {
+    int zero = 0;
+    HIPCHK(hipMemcpyAsync(d.bad, &zero, sizeof(int), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    lg::set_error("non-finite state; frame rolled back");
+    return SIM_E_DIVERGED;
+  }
+  return SIM_OK;
+}
+
+int sort_contacts_canonical(lgsim* s, int c, std::vector<int>& node, std::vector<int>& obst,
+                            std::vector<int32_t>& order) {
+  // order[k] = internal index of the k-th canonical contact
+  node.resize(c);
+  obst.resize(c);
+  HIPCHK(hipMemcpyAsync(node.data(), s->d.c_node, sizeof(int) * c, hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipMemcpyAsync(obst.data(), s->d.c_obst, sizeof(int) * c, hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  order.resize(c);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    int ca = s->iperm_caller[node[a]], cb = s->iperm_caller[node[b]];
+    if (ca != cb) return ca < cb;
+    return obst[a] < obst[b];
+  });
+  return SIM_OK;
+}
+
+int download_nodes(lgsim* s, const float* dsrc, double* out) {
+  auto& d = s->d;
+  std::vector<float> buf(3 * (size_t)d.N4);
+  HIPCHK(hipMemcpyAsync(buf.data(), dsrc, sizeof(float) * buf.size(), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  for (int gi = 0; gi < d.N; ++gi) {
+    int ci = s->iperm_caller[gi];
+    for (int c = 0; c < 3; ++c) out[3 * (size_t)ci + c] = buf[c * (size_t)d.N4 + gi];
+  }
+  return SIM_OK;
+}
+
+int upload_nodes(lgsim* s, const double* src, float* ddst) {
+  auto& d = s->d;
+  std::vector<float> buf(3 * (size_t)d.N4, 0.0f);
+  for (int ci = 0; ci < d.N; ++ci) {
+    int gi = s->perm_caller[ci];
+    for (int c = 0; c < 3; ++c) {
+      double v = src[3 * (size_t)ci + c];
+      if (!std::isfinite(v)) {
+        lg::set_error("non-finite input");
+        return SIM_E_ARG;
+      }
+      buf[c * (size_t)d.N4 + gi] = (float)v;
+    }
+  }
+  return upload(s, ddst, buf.data(), buf.size());
+}
+
+int create_common(int32_t count, const sim_mesh* meshes, const sim_material* mats, double h,
+                  const sim_options* opt, const std::vector<std::vector<sim_obstacle>>& obs, sim_t* out) {
+  if (!meshes || !mats || !out || count <= 0) {
+    lg::set_error("null argument");
+    return SIM_E_ARG;
+  }
+  *out = nullptr;
+  lgsim* s = nullptr;
+  try {
+    s = new lgsim();
+  } catch (...) {
+    lg::set_error("host allocation failed");
+    return SIM_E_NOMEM;
+  }
+  if (opt) s->opt = *opt;
+  else sim_options_default(&s->opt);
+  auto fail = [&](int rc) {
+    delete s;
+    return rc;
+  };
+  if (s->opt.cr_iters < 0 || s->opt.max_contacts <= 0 || s->opt.max_iters <= 0 || !(s->opt.ncp_tol > 0.0) ||
+      s->opt.warm < 0 || s->opt.warm > 2 || !(s->opt.contact_margin >= 0.0)) {
+    lg::set_error("bad options");
+    return fail(SIM_E_ARG);
+  }
+  if (s->opt.warm == SIM_WARM_MLP) s->opt.warm = SIM_WARM_PREV;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    lg::set_error("no HIP device");
+    return fail(SIM_E_DEVICE);
+  }
+  if (s->opt.hip_stream) {
+    s->st = static_cast<hipStream_t>(s->opt.hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) != hipSuccess) {
+      lg::set_error("stream creation failed");
+      return fail(SIM_E_DEVICE);
+    }
+    s->own_stream = true;
+  }
+  std::vector<lg::HostScene> hs(count);
+  try {
+    for (int k = 0; k < count; ++k) {
+      if (meshes[k].n_pins > 0 && (!meshes[k].pin_nodes || !meshes[k].pin_group)) {
+        lg::set_error("pins without arrays");
+        return fail(SIM_E_ARG);
+      }
+      std::string err;
+      int rc = lg::precompute(lg::mesh_in(&meshes[k]), lg::material_in(&mats[k]), h, s->opt.pin_weight_scale,
+                              false, hs[k], err);
+      if (rc != SIM_OK) {
+        lg::set_error(count > 1 ? "scene " + std::to_string(k) + ": " + err : err);
+        return fail(rc);
+      }
+    }
+    for (auto& o : obs) {
+      int rc = validate_obstacles((int)o.size(), o.data());
+      if (rc != SIM_OK) return fail(rc);
+    }
+    int rc = build(s, hs, obs);
+    if (rc != SIM_OK) return fail(rc);
+  } catch (const std::bad_alloc&) {
+    lg::set_error("host allocation failed");
+    return fail(SIM_E_NOMEM);
+  }
+  *out = s;
+  return SIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_options_default(sim_options* o) {
+  if (!o) return SIM_E_ARG;
+  std::memset(o, 0, sizeof(*o));
+  o->gravity[2] = -9.81;
+  o->pin_weight_scale = 1.0;
+  o->contact_margin = 0.0;
+  o->cr_iters = 10;
+  o->warm = SIM_WARM_PREV;
+  o->ncp_tol = 1e-6;
+  o->max_iters = 200;
+  o->max_contacts = 2048;
+  o->hip_stream = nullptr;
+  return SIM_OK;
+}
+
+int sim_create(const sim_mesh* mesh, const sim_material* mat, double h, const sim_options* opt, sim_t* out) {
+  std::vector<std::vector<sim_obstacle>> obs(1);
+  return create_common(1, mesh, mat, h, opt, obs, out);
+}
+
+int sim_create_batch(int32_t count, const sim_mesh* meshes, const sim_material* mats, const int32_t* n_obstacles,
+                     const sim_obstacle* const* obstacles, double h, const sim_options* opt, sim_t* out) {
+  if (count <= 0 || !n_obstacles || !obstacles) {
+    lg::set_error("bad batch arguments");
+    return SIM_E_ARG;
+  }
+  std::vector<std::vector<sim_obstacle>> obs(count);
+  for (int k = 0; k < count; ++k) {
+    if (n_obstacles[k] < 0 || (n_obstacles[k] > 0 && !obstacles[k])) {
+      lg::set_error("bad obstacle list");
+      return SIM_E_ARG;
+    }
+    obs[k].assign(obstacles[k], obstacles[k] + n_obstacles[k]);
+  }
+  return create_common(count, meshes, mats, h, opt, obs, out);
+}
+
+int sim_batch_info(sim_t s, int32_t* count, int32_t* node_offsets) {
+  if (!s) return SIM_E_ARG;
+  if (count) *count = (int32_t)s->scenes.size();
+  if (node_offsets) {
+    for (size_t k = 0; k < s->scenes.size(); ++k) node_offsets[k] = s->scenes[k].caller0;
+    node_offsets[s->scenes.size()] = s->d.N;
+  }
+  return SIM_OK;
+}
+
+int sim_set_obstacles(sim_t s, int32_t n, const sim_obstacle* obs) {
+  if (!s) {
+    lg::set_error("null handle");
+    return SIM_E_ARG;
+  }
+  if (s->scenes.size() != 1) {
+    lg::set_error("sim_set_obstacles applies to single-scene handles");
+    return SIM_E_STATE;
+  }
+  TRY(validate_obstacles(n, obs));
+  s->obst.clear();
+  for (int i = 0; i < n; ++i) {
+    lg::ObstacleDev od{};
+    od.type = obs[i].type;
+    od.scene = 0;
+    std::memcpy(od.geom, obs[i].geom, sizeof(od.geom));
+    od.mu = obs[i].mu;
+    std::memcpy(od.vel, obs[i].vel, sizeof(od.vel));
+    s->obst.push_back(od);
+  }
+  s->scene_obst0 = {0, n};
+  return push_obstacles(s);
+}
+
+int sim_set_pin_motion(sim_t s, int32_t n_groups, const double* lin, const double* ang, const double* pivot) {
+  if (!s || n_groups < 0 || (n_groups > 0 && (!lin || !ang || !pivot))) {
+    lg::set_error("bad pin motion arguments");
+    return SIM_E_ARG;
+  }
+  if (s->scenes.size() != 1) {
+    lg::set_error("sim_set_pin_motion applies to single-scene handles");
+    return SIM_E_STATE;
+  }
+  if (n_groups < s->scenes[0].n_groups) {
+    lg::set_error("pin motion must cover every pin group");
+    return SIM_E_ARG;
+  }
+  std::vector<double> grp(9 * (size_t)s->d.G, 0.0);
+  for (int g = 0; g < std::min(n_groups, s->d.G); ++g)
+    for (int c = 0; c < 3; ++c) {
+      grp[9 * g + c] = lin[3 * g + c];
+      grp[9 * g + 3 + c] = ang[3 * g + c];
+      grp[9 * g + 6 + c] = pivot[3 * g + c];
+    }
+  for (double v : grp)
+    if (!std::isfinite(v)) {
+      lg::set_error("non-finite pin motion");
+      return SIM_E_ARG;
+    }
+  return upload(s, s->d.grp, grp.data(), grp.size());
+}
+
+int sim_step(sim_t s, int32_t frames, int32_t iters, sim_stats* stats) {
+  if (!s || frames < 0 || iters < 0) {
+    lg::set_error("bad arguments");
+    return SIM_E_ARG;
+  }
+  for (int f = 0; f < frames; ++f) {
+    bool timed = stats != nullptr;
+    float ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    auto t0 = std::chrono::steady_clock::now();
+    if (timed) hipEventRecord(s->ev[0], s->st);
+    TRY(frame_setup(s));
+    if (timed) {
+      hipEventRecord(s->ev[7], s->st);
+      hipEventSynchronize(s->ev[7]);
+      hipEventElapsedTime(&ms[0], s->ev[0], s->ev[7]);
+    }
+    int k = 0;
+    double res = 0.0;
+    bool have_res = false;
+    while (true) {
+      TRY(iteration(s, timed, ms));
+      ++k;
+      if (iters > 0) {
+        if (k >= iters) break;
+      } else {
+        TRY(read_residual(s, &res));
+        have_res = true;
+        if (res <= s->opt.ncp_tol || k >= s->opt.max_iters) break;
+      }
+    }
+    TRY(check_launch("iterations"));
+    if (timed && !have_res) {
+      TRY(read_residual(s, &res));
+      have_res = true;
+    }
+    int rc = finish_frame(s);
+    if (rc != SIM_OK) return rc;
+    if (timed) {
+      HIPCHK(hipStreamSynchronize(s->st));
+      auto t1 = std::chrono::steady_clock::now();
+      auto& st = stats[f];
+      st.iters_done = k;
+      st.n_contacts = s->iter_c;
+      st.ncp_res = res;
+      st.ms_frame = std::chrono::duration<float, std::milli>(t1 - t0).count();
+      for (int q = 0; q < 8; ++q) st.ms_phase[q] = ms[q];
+    }
+  }
+  HIPCHK(hipStreamSynchronize(s->st));
+  return SIM_OK;
+}
+
+int sim_read_state(sim_t s, double* xyz, double* vel, sim_contact* contacts, int32_t cap, int32_t* n_contacts) {
+  if (!s || cap < 0) {
+    lg::set_error("bad arguments");
+    return SIM_E_ARG;
+  }
+  if (xyz) TRY(download_nodes(s, s->d.qt, xyz));
+  if (vel) TRY(download_nodes(s, s->d.vt, vel));
+  int c = 0;
+  HIPCHK(hipMemcpyAsync(&c, s->d.pc_count, sizeof(int), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  if (n_contacts) *n_contacts = c;
+  if (contacts && cap > 0 && c > 0) {
+    auto& d = s->d;
+    const int CM = d.CMAX;
+    std::vector<int> node(c), obst(c);
+    std::vector<float> C(9 * (size_t)CM), lam(3 * (size_t)CM);
+    std::vector<double> gap(c);
+    HIPCHK(hipMemcpyAsync(node.data(), d.pc_node, sizeof(int) * c, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipMemcpyAsync(obst.data(), d.pc_obst, sizeof(int) * c, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipMemcpyAsync(C.data(), d.cC, sizeof(float) * C.size(), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipMemcpyAsync(lam.data(), d.lam, sizeof(float) * lam.size(), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipMemcpyAsync(gap.data(), d.c_gap, sizeof(double) * c, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    std::vector<int> order(c);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      int ca = s->iperm_caller[node[a]], cb = s->iperm_caller[node[b]];
+      if (ca != cb) return ca < cb;
+      return obst[a] < obst[b];
+    });
+    for (int k = 0; k < std::min(c, cap); ++k) {
+      int j = order[k];
+      auto& o = contacts[k];
+      o.node = s->iperm_caller[node[j]];
+      int sc = s->obst[obst[j]].scene;
+      o.obstacle = obst[j] - s->scene_obst0[sc];
+      for (int q = 0; q < 9; ++q) o.frame[q] = C[(size_t)q * CM + j];
+      for (int q = 0; q < 3; ++q) o.lambda[q] = lam[(size_t)q * CM + j];
+      o.gap = gap[j];
+    }
+  }
+  return SIM_OK;
+}
+
+int sim_read_state_device(sim_t s, float* d_xyz, void* stream) {
+  if (!s || !d_xyz) {
+    lg::set_error("bad arguments");
+    return SIM_E_ARG;
+  }
+  // device-side scatter through the permutation, ordered after the handle's work
+  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : s->st;
+  if (st != s->st) {
+    HIPCHK(hipEventRecord(s->ev[7], s->st));
+    HIPCHK(hipStreamWaitEvent(st, s->ev[7], 0));
+  }
+  lg::launch_export_positions(s->d, st, d_xyz);
+  return check_launch("export positions");
+}
+
+int sim_destroy(sim_t s) {
+  delete s;
+  return SIM_OK;
+}
+
+// ---------------------------------------------------------------- parity hooks
+int sim_set_iterate_state(sim_t s, const double* q_t, const double* v_t, const double* q_k, double t, int32_t c,
+                          const sim_contact* contacts) {
+  if (!s || !q_t || !v_t || !q_k || c < 0 || (c > 0 && !contacts) || !std::isfinite(t)) {
+    lg::set_error("bad arguments");
+    return SIM_E_ARG;
+  }
+  auto& d = s->d;
+  if (c > d.CMAX) {
+    lg::set_error("too many contacts");
+    return SIM_E_CAPACITY;
+  }
+  if (s->scenes.size() != 1) {
+    lg::set_error("iterate state applies to single-scene handles");
+    return SIM_E_STATE;
+  }
+  TRY(upload_nodes(s, q_t, d.qt));
+  TRY(upload_nodes(s, v_t, d.vt));
+  TRY(upload(s, d.t, &t, 1));
+  lg::launch_predict(d, s->st);
+  lg::launch_pins(d, s->st);
+  TRY(check_launch("predict"));
+  TRY(upload_nodes(s, q_k, d.q));
+  // contact list into internal order (internal node, obstacle)
+  std::vector<int> order(c);
+  std::iota(order.begin(), order.end(), 0);
+  for (int k = 0; k < c; ++k) {
+    if (contacts[k].node < 0 || contacts[k].node >= d.N || contacts[k].obstacle < 0 ||
+        contacts[k].obstacle >= (int)s->obst.size()) {
+      lg::set_error("bad contact entry");
+      return SIM_E_ARG;
+    }
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    int na = s->perm_caller[contacts[a].node], nb = s->perm_caller[contacts[b].node];
+    if (na != nb) return na < nb;
+    return contacts[a].obstacle < contacts[b].obstacle;
+  });
+  std::vector<int> node(c), obst(c), scene(c, 0);
+  std::vector<float> lam(3 * (size_t)d.CMAX, 0.0f);
+  s->iter_canon.assign(c, 0);
+  for (int j = 0; j < c; ++j) {
+    const auto& e = contacts[order[j]];
+    node[j] = s->perm_caller[e.node];
+    obst[j] = e.obstacle;
+    for (int q = 0; q < 3; ++q) lam[q * (size_t)d.CMAX + j] = (float)e.lambda[q];
+    s->iter_canon[j] = order[j];
+  }
+  int cc[2] = {c, 0};
+  TRY(upload(s, d.n_contacts, cc, 1));
+  TRY(upload(s, d.c_node, node.data(), c));
+  TRY(upload(s, d.c_obst, obst.data(), c));
+  TRY(upload(s, d.c_scene, scene.data(), c));
+  TRY(upload(s, d.lam, lam.data(), lam.size()));
+  s->iter_c = c;
+  lg::launch_frames_for_list(d, s->st);
+  if (c > 0) {
+    lg::launch_delassus(d, s->st);
+    lg::launch_warm_start(d, s->st, 1);
+  }
+  TRY(check_launch("iterate state"));
+  HIPCHK(hipMemcpyAsync(s->h_pinned + 1, d.overflow, sizeof(int), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  if (s->h_pinned[1]) {
+    int zero = 0;
+    HIPCHK(hipMemcpyAsync(d.overflow, &zero, sizeof(int), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    lg::set_error("Delassus storage capacity exceeded");
+    return SIM_E_CAPACITY;
+  }
+  return SIM_OK;
+}
+
+int sim_run_iterations(sim_t s, int32_t k) {
+  if (!s || k < 0) {
+    lg::set_error("bad arguments");
+    return SIM_E_ARG;
+  }
+  float ms[8] = {};
+  for (int i = 0; i < k; ++i) TRY(iteration(s, false, ms));
+  TRY(check_launch("iterations"));
+  HIPCHK(hipStreamSynchronize(s->st));
+  return SIM_OK;
+}
+
+int sim_read_iterate(sim_t s, double* q_k, double* lambda) {
+  if (!s) return SIM_E_ARG;
+  if (q_k) TRY(download_nodes(s, s->d.q, q_k));
+  if (lambda && s->iter_c > 0) {
+    auto& d = s->d;
+    std::vector<float> lam(3 * (size_t)d.CMAX);
+    HIPCHK(hipMemcpyAsync(lam.data(), d.lam, sizeof(float) * lam.size(), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    std::vector<int> node, obst;
+    std::vector<int32_t> order;
+    TRY(sort_contacts_canonical(s, s->iter_c, node, obst, order));
+    for (int k = 0; k < s->iter_c; ++k)
+      for (int q = 0; q < 3; ++q) lambda[3 * (size_t)k + q] = lam[(size_t)q * d.CMAX + order[k]];
+  }
+  return SIM_OK;
+}
+
+int sim_global_solve(sim_t s, const double* b, double* u) {
+  if (!s || !b || !u) {
+    lg::set_error("bad arguments");
+    return SIM_E_ARG;
+  }
+  auto& d = s->d;
+  // uses the b / y iteration buffers as scratch
+  TRY(upload_nodes(s, b, d.b));
+  lg::launch_spmv_S(d, s->st, d.b, d.y);
+  lg::launch_spmv_St(d, s->st, d.y, nullptr, d.tmp);
+  TRY(check_launch("global solve"));
+  return download_nodes(s, d.tmp, u);
+}
+
+int sim_debug_rhs(sim_t s, double* rhs) {
+  if (!s || !rhs) return SIM_E_ARG;
+  auto& d = s->d;
+  lg::launch_element(d, s->st);
+  lg::launch_gather(d, s->st);
+  TRY(check_launch("rhs"));
+  return download_nodes(s, d.b, rhs);
+}
+
+int sim_debug_delassus(sim_t s, double* K) {
+  if (!s || !K) return SIM_E_ARG;
+  int c = s->iter_c;
+  if (c == 0) return SIM_OK;
+  auto& d = s->d;
+  std::vector<float> Kd((size_t)c * c);
+  HIPCHK(hipMemcpyAsync(Kd.data(), d.K, sizeof(float) * Kd.size(), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  std::vector<int> node, obst;
+  std::vector<int32_t> order;
+  TRY(sort_contacts_canonical(s, c, node, obst, order));
+  for (int a = 0; a < c; ++a)
+    for (int b2 = 0; b2 < c; ++b2) K[(size_t)a * c + b2] = Kd[(size_t)order[a] * c + order[b2]];
+  return SIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// Device data layout and kernel entry points of the gfx950 solver.
+//
+// All node arrays are structure-of-arrays float32 in the internal (nested-dissection
+// postorder) numbering, padded to N4 = round_up(N, 4) + 4 entries per coordinate so
+// that the S pass can read b in aligned float4 groups.  A batch of scenes is the
+// concatenation of its scenes' node ranges: the block-diagonal system has one
+// elimination forest, so the element, S and S^T kernels do not know about scenes.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lg {
+
+constexpr int kBlock = 256;
+constexpr int kWave = 64;
+constexpr int kMaxObstacles = 64;
+constexpr int kDelTile = 32;      // Delassus tile (contacts x contacts)
+constexpr int kDelChunk = 64;     // Delassus depth chunk staged in LDS
+
+struct ObstacleDev {
+  int type;
+  int scene;
+  double geom[10];
+  double mu;
+  double vel[3];
+};
+
+// Pointers to device memory, passed by value to kernels.
+struct Dev {
+  // sizes
+  int N, N4, M, P, G, NS;          // nodes, padded nodes, tets, pins, pin groups, scenes
+  int CMAX;                        // contact capacity (all scenes)
+  int64_t KCAP;                    // Delassus storage capacity (floats)
+  int nseg, nlong;                 // S-pass segments, multi-segment rows
+  double h;
+  double g[3];
+  int cr_iters;
+  int warm;
+  // nodes
+  float *qt, *vt, *qp, *q, *b, *y, *tgt, *pin_w, *tmp;
+  int *node_scene;
+  int *iperm_caller;               // internal node -> caller node
+  int *g_ptr, *g_slot;             // node -> (corner*M + tet) gather lists
+  // pins
+  int *pin_node, *pin_group;
+  double *pin_x0;                  // [3][P]
+  double *grp;                     // [G][9]: lin(3), ang(3), pivot(3)
+  // tets
+  int *tidx;                       // [4][M]
+  float *dinv;                     // [9][M] rows d1,d2,d3
+  float *hw, *tmu, *tlam, *tk;     // h^2 w, mu, lambda, k
+  unsigned char *tmodel;
+  float *fc;                       // [12][M] corner forces
+  // S storage
+  int64_t *row_ptr;
+  int *row_lo4;
+  float *row_val;
+  int *seg_row, *seg_col0, *seg_len;
+  int64_t *seg_off;
+  int *long_row, *long_seg0, *long_nseg;
+  float *partial;                  // [3][nseg]
+  int64_t *col_ptr;
+  float *col_val;
+  int *parent, *lo, *depth, *chain_end;
+  // scenes
+  int *scene_node0;                // [NS+1]
+  int *scene_obst0;                // [NS+1]
+  double *scene_margin;            // [NS]
+  ObstacleDev *obst;               // [kMaxObstacles * NS] (flat, scene ranges)
+  // contacts (internal order: by internal node, then obstacle)
+  int *n_contacts;                 // [1]
+  int *overflow;                   // [1]
+  int *cnt, *blk;                  // collision scan scratch [N], [N/256+1]
+  int *c_node, *c_obst, *c_scene;
+  float *cC;                       // [9][CMAX]
+  float *c_dn, *c_df, *c_mu, *c_rn, *c_rf;  // df: [2][CMAX]
+  double *c_gap;
+  float *lam;                      // [3][CMAX]
+  int *cs_off;                     // [NS+1] contact range per scene
+  int64_t *k_off;                  // [NS+1] Delassus block offsets
+  int *tile_off;                   // [NS+1] Delassus tile offsets
+  float *K;
+  int *ad;                         // adjacent LCA depth [CMAX]
+  // previous frame
+  int *pc_count;
+  int *pc_node, *pc_obst;
+  float *pc_world;                 // [3][CMAX]
+  // iteration scratch [3][CMAX] each
+  float *Hu, *Om, *Et, *hv, *X, *F;
+  float *cr_x, *cr_r, *cr_p, *cr_Ar, *cr_Ap, *cr_Z, *cr_prod;  // prod: [2][CMAX]
+  // frame state
+  double *t;                       // [1] simulation time at frame start
+  float *res;                      // [NS] NCP residual per scene
+  int *bad;                        // [1] non-finite flag
+};
+
+// kernels (launch helpers live in the .hip files)
+void launch_predict(const Dev& d, hipStream_t st);
+void launch_pins(const Dev& d, hipStream_t st);
+void launch_collide(const Dev& d, hipStream_t st);
+void launch_frames_for_list(const Dev& d, hipStream_t st);
+void launch_delassus(const Dev& d, hipStream_t st);
+void launch_warm_start(const Dev& d, hipStream_t st, int keep_lambda);
+void launch_element(const Dev& d, hipStream_t st);
+void launch_gather(const Dev& d, hipStream_t st);
+void launch_spmv_S(const Dev& d, hipStream_t st, const float* b, float* y);
+void launch_spmv_St(const Dev& d, hipStream_t st, const float* y, const float* base, float* u);
+void launch_contact_prep(const Dev& d, hipStream_t st);
+hipError_t launch_cr(const Dev& d, hipStream_t st, int cr_blocks);
+void launch_apply_forces(const Dev& d, hipStream_t st);
+void launch_residual(const Dev& d, hipStream_t st);
+void launch_integrate(const Dev& d, hipStream_t st);
+void launch_check_finite(const Dev& d, hipStream_t st);
+void launch_export_positions(const Dev& d, hipStream_t st, float* out);
+int cr_max_blocks();
+
+}  // namespace lg

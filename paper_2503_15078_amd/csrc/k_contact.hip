@@ -1,0 +1,851 @@
+// Contact kernels: collision detection with order-preserving compaction, contact
+// frames (App. A), the Delassus block K = B^T S^T S B (Sec. 5.3, W = H S^T S H^T),
+// the complementarity preconditioner (Sec. 5.4), the warm start, the per-iteration
+// Fischer-Burmeister evaluation (Sec. 5.2, App. B), the Conjugate Residual solve of
+// the Schur system (Sec. 5.2, Sec. 6) and the NCP residual.
+#include <hip/hip_cooperative_groups.h>
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+
+namespace cg = cooperative_groups;
+
+namespace lg {
+
+// ---------------------------------------------------------------- float64 geometry
+// Signed distance and outward normal of an obstacle, in float64, with the operation
+// order fixed and no contraction, so that contact decisions are reproducible bit for
+// bit by any IEEE implementation following the same order.
+__device__ void tangents64(const double n[3], double f1[3], double f2[3]) {
+#pragma clang fp contract(off)
+  double a0 = fabs(n[0]), a1 = fabs(n[1]), a2 = fabs(n[2]);
+  int k = 0;
+  if (a1 < (k == 0 ? a0 : a1)) k = 1;
+  if (a2 < (k == 0 ? a0 : a1)) k = 2;
+  double ek[3] = {0.0, 0.0, 0.0};
+  ek[k] = 1.0;
+  double dot = n[0] * ek[0] + n[1] * ek[1] + n[2] * ek[2];
+  double t0 = ek[0] - dot * n[0], t1 = ek[1] - dot * n[1], t2 = ek[2] - dot * n[2];
+  double tn = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+  f1[0] = t0 / tn;
+  f1[1] = t1 / tn;
+  f1[2] = t2 / tn;
+  f2[0] = n[1] * f1[2] - n[2] * f1[1];
+  f2[1] = n[2] * f1[0] - n[0] * f1[2];
+  f2[2] = n[0] * f1[1] - n[1] * f1[0];
+}
+
+__device__ double sdf64(const ObstacleDev& ob, const double x[3], double nrm[3]) {
+#pragma clang fp contract(off)
+  const double* g = ob.geom;
+  if (ob.type == 0) {
+    double nn = sqrt(g[3] * g[3] + g[4] * g[4] + g[5] * g[5]);
+    nrm[0] = g[3] / nn;
+    nrm[1] = g[4] / nn;
+    nrm[2] = g[5] / nn;
+    return nrm[0] * (x[0] - g[0]) + nrm[1] * (x[1] - g[1]) + nrm[2] * (x[2] - g[2]);
+  }
+  if (ob.type == 1) {
+    double r[3] = {x[0] - g[0], x[1] - g[1], x[2] - g[2]};
+    double q[3] = {fabs(r[0]) - g[3], fabs(r[1]) - g[4], fabs(r[2]) - g[5]};
+    double sg[3] = {r[0] >= 0.0 ? 1.0 : -1.0, r[1] >= 0.0 ? 1.0 : -1.0, r[2] >= 0.0 ? 1.0 : -1.0};
+    double o[3] = {q[0] > 0.0 ? q[0] : 0.0, q[1] > 0.0 ? q[1] : 0.0, q[2] > 0.0 ? q[2] : 0.0};
+    double out = sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
+    if (out > 0.0) {
+      for (int c = 0; c < 3; ++c) nrm[c] = o[c] * sg[c] / out;
+      return out;
+    }
+    int ax = 0;
+    if (q[1] > q[ax]) ax = 1;
+    if (q[2] > q[ax]) ax = 2;
+    nrm[0] = nrm[1] = nrm[2] = 0.0;
+    nrm[ax] = sg[ax];
+    return q[ax];
+  }
+  // capped cylinder
+  double e0 = g[3] - g[0], e1 = g[4] - g[1], e2 = g[5] - g[2];
+  double L = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+  double u[3] = {e0 / L, e1 / L, e2 / L};
+  double r0 = x[0] - g[0], r1 = x[1] - g[1], r2 = x[2] - g[2];
+  double t = r0 * u[0] + r1 * u[1] + r2 * u[2];
+  double w0 = r0 - t * u[0], w1 = r1 - t * u[1], w2 = r2 - t * u[2];
+  double rho = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
+  double dr = rho - g[6];
+  double da, s[3];
+  if (t < 0.0) {
+    da = -t;
+    s[0] = -u[0];
+    s[1] = -u[1];
+    s[2] = -u[2];
+  } else {
+    da = t - L;
+    s[0] = u[0];
+    s[1] = u[1];
+    s[2] = u[2];
+  }
+  double wh[3];
+  if (rho > 0.0) {
+    wh[0] = w0 / rho;
+    wh[1] = w1 / rho;
+    wh[2] = w2 / rho;
+  } else {
+    double f2[3];
+    tangents64(u, wh, f2);
+  }
+  if (dr > 0.0 && da > 0.0) {
+    double out = sqrt(dr * dr + da * da);
+    for (int c = 0; c < 3; ++c) nrm[c] = (dr * wh[c] + da * s[c]) / out;
+    return out;
+  }
+  if (dr > 0.0) {
+    for (int c = 0; c < 3; ++c) nrm[c] = wh[c];
+    return dr;
+  }
+  if (da > 0.0) {
+    for (int c = 0; c < 3; ++c) nrm[c] = s[c];
+    return da;
+  }
+  if (dr > da) {
+    for (int c = 0; c < 3; ++c) nrm[c] = wh[c];
+    return dr;
+  }
+  for (int c = 0; c < 3; ++c) nrm[c] = s[c];
+  return da;
+}
+
+// contact predicate: min(sdf(q_t), sdf(q~)) < margin with q~ = (q_t + h v_t) + (h h) g in float64
+__device__ bool in_contact(const Dev& d, const ObstacleDev& ob, int v, double margin) {
+#pragma clang fp contract(off)
+  double xt[3], xp[3], nrm[3];
+  double hh = d.h * d.h;
+  for (int c = 0; c < 3; ++c) {
+    xt[c] = (double)d.qt[c * d.N4 + v];
+    xp[c] = (xt[c] + d.h * (double)d.vt[c * d.N4 + v]) + hh * d.g[c];
+  }
+  double dt = sdf64(ob, xt, nrm);
+  double dp = sdf64(ob, xp, nrm);
+  return (dt < dp ? dt : dp) < margin;
+}
+
+// frame rows (n, f1, f2) at q_t, d_n = n . (x_t - sdf n), d_f = f . u^, gap = sdf(x_t)
+__device__ void write_contact_frame(const Dev& d, int j, int v, const ObstacleDev& ob) {
+#pragma clang fp contract(off)
+  double xt[3], n[3], f1[3], f2[3];
+  for (int c = 0; c < 3; ++c) xt[c] = (double)d.qt[c * d.N4 + v];
+  double dist = sdf64(ob, xt, n);
+  tangents64(n, f1, f2);
+  double ph[3] = {xt[0] - dist * n[0], xt[1] - dist * n[1], xt[2] - dist * n[2]};
+  const double* rows[3] = {n, f1, f2};
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) d.cC[(r * 3 + c) * d.CMAX + j] = (float)rows[r][c];
+  d.c_dn[j] = (float)(n[0] * ph[0] + n[1] * ph[1] + n[2] * ph[2]);
+  d.c_df[j] = (float)(f1[0] * ob.vel[0] + f1[1] * ob.vel[1] + f1[2] * ob.vel[2]);
+  d.c_df[d.CMAX + j] = (float)(f2[0] * ob.vel[0] + f2[1] * ob.vel[1] + f2[2] * ob.vel[2]);
+  d.c_mu[j] = (float)ob.mu;
+  d.c_gap[j] = dist;
+}
+
+// ---------------------------------------------------------------- detection + compaction
+__global__ void k_collide_count(Dev d) {
+  __shared__ int red[kBlock];
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  int cnt = 0;
+  if (v < d.N) {
+    int s = d.node_scene[v];
+    double margin = d.scene_margin[s];
+    for (int o = d.scene_obst0[s]; o < d.scene_obst0[s + 1]; ++o) cnt += in_contact(d, d.obst[o], v, margin);
+    d.cnt[v] = cnt;
+  }
+  red[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) d.blk[blockIdx.x] = red[0];
+}
+
+// single block: exclusive scan of the per-block counts; total -> n_contacts
+__global__ void k_collide_scan(Dev d, int nblk) {
+  __shared__ int part[1024];
+  int per = (nblk + 1023) / 1024;
+  int b0 = threadIdx.x * per, b1 = min(nblk, b0 + per);
+  int s = 0;
+  for (int b = b0; b < b1; ++b) s += d.blk[b];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int t = 0; t < 1024; ++t) {
+      int x = part[t];
+      part[t] = acc;
+      acc += x;
+    }
+    d.n_contacts[0] = acc;
+    if (acc > d.CMAX) d.overflow[0] = 1;
+  }
+  __syncthreads();
+  int acc = part[threadIdx.x];
+  for (int b = b0; b < b1; ++b) {
+    int x = d.blk[b];
+    d.blk[b] = acc;
+    acc += x;
+  }
+}
+
+__global__ void k_collide_write(Dev d) {
+  __shared__ int sc[kBlock];
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  int cnt = v < d.N ? d.cnt[v] : 0;
+  sc[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int o = 1; o < kBlock; o <<= 1) {
+    int x = threadIdx.x >= o ? sc[threadIdx.x - o] : 0;
+    __syncthreads();
+    sc[threadIdx.x] += x;
+    __syncthreads();
+  }
+  if (v >= d.N || cnt == 0) return;
+  int j = d.blk[blockIdx.x] + sc[threadIdx.x] - cnt;
+  int s = d.node_scene[v];
+  double margin = d.scene_margin[s];
+  for (int o = d.scene_obst0[s]; o < d.scene_obst0[s + 1]; ++o) {
+    const ObstacleDev& ob = d.obst[o];
+    if (!in_contact(d, ob, v, margin)) continue;
+    if (j < d.CMAX) {
+      d.c_node[j] = v;
+      d.c_obst[j] = o;
+      d.c_scene[j] = s;
+      write_contact_frame(d, j, v, ob);
+    }
+    ++j;
+  }
+}
+
+// per-scene contact ranges, Delassus block offsets and tile offsets
+__global__ void k_scene_offsets(Dev d) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int c = min(d.n_contacts[0], d.CMAX);
+  int j = 0;
+  int64_t koff = 0;
+  int toff = 0;
+  for (int s = 0; s < d.NS; ++s) {
+    d.cs_off[s] = j;
+    d.k_off[s] = koff;
+    d.tile_off[s] = toff;
+    int j1 = j;
+    while (j1 < c && d.c_scene[j1] == s) ++j1;
+    int cs = j1 - j;
+    koff += (int64_t)cs * cs;
+    int T = (cs + kDelTile - 1) / kDelTile;
+    toff += T * (T + 1) / 2;
+    j = j1;
+  }
+  d.cs_off[d.NS] = j;
+  d.k_off[d.NS] = koff;
+  d.tile_off[d.NS] = toff;
+  if (koff > d.KCAP) d.overflow[0] = 1;
+}
+
+void launch_collide(const Dev& d, hipStream_t st) {
+  int nblk = (d.N + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_collide_count, dim3(nblk), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_collide_scan, dim3(1), dim3(1024), 0, st, d, nblk);
+  hipLaunchKernelGGL(k_collide_write, dim3(nblk), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_scene_offsets, dim3(1), dim3(64), 0, st, d);
+}
+
+// frames for a contact list set from the host (parity hook)
+__global__ void k_frames_for_list(Dev d) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int c = min(d.n_contacts[0], d.CMAX);
+  if (j >= c) return;
+  write_contact_frame(d, j, d.c_node[j], d.obst[d.c_obst[j]]);
+}
+
+void launch_frames_for_list(const Dev& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_frames_for_list, dim3((d.CMAX + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_scene_offsets, dim3(1), dim3(64), 0, st, d);
+}
+
+// ---------------------------------------------------------------- Delassus block
+// K_jk = [A_n^-1]_{v_j v_k} = sum over the common ancestors i of v_j and v_k of
+// S_{i v_j} S_{i v_k} (Theorem 1: column v of S lives on the ancestor path of v).
+// Contacts are sorted by node (a DFS order of the elimination forest), so the
+// depth of LCA(v_j, v_k), j < k, is the minimum over adjacent pairs in [j, k).
+__global__ void k_adjacent_lca(Dev d) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int c = min(d.n_contacts[0], d.CMAX);
+  if (i >= c - 1) return;
+  if (d.c_scene[i] != d.c_scene[i + 1]) {
+    d.ad[i] = -1;
+    return;
+  }
+  int u = d.c_node[i], w = d.c_node[i + 1];
+  int a = u, lca = -1;
+  while (a != -1) {
+    int e = d.chain_end[a];
+    if (e >= w) {
+      lca = a > w ? a : w;
+      break;
+    }
+    a = d.parent[e];
+  }
+  d.ad[i] = lca < 0 ? -1 : d.depth[lca];
+}
+
+// Persistent tiles of kDelTile x kDelTile contact pairs (upper triangle per scene).
+// The column paths of both contacts are staged root-aligned in LDS in chunks; a pair
+// accumulates only over its common prefix (its common ancestors).
+__global__ void __launch_bounds__(kBlock) k_delassus_tiles(Dev d) {
+  __shared__ float PJ[kDelTile][kDelChunk + 1];
+  __shared__ float PK[kDelTile][kDelChunk + 1];
+  __shared__ int LJK[kDelTile][kDelTile];
+  __shared__ int sufJ[kDelTile], preK[kDelTile];
+  __shared__ int dJ[kDelTile], dK[kDelTile];
+  __shared__ int64_t cJ[kDelTile], cK[kDelTile];
+  __shared__ int red[kBlock];
+  __shared__ int maxL;
+  if (d.k_off[d.NS] > d.KCAP) return;  // Delassus storage full (reported as overflow)
+  const int total = d.tile_off[d.NS];
+  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    // locate scene and (tj, tk) with tj <= tk
+    int s = 0;
+    while (d.tile_off[s + 1] <= tile) ++s;
+    int cs = d.cs_off[s], cnt = d.cs_off[s + 1] - cs;
+    int T = (cnt + kDelTile - 1) / kDelTile;
+    int rem = tile - d.tile_off[s], tj = 0;
+    while (rem >= T - tj) {
+      rem -= T - tj;
+      ++tj;
+    }
+    int tk = tj + rem;
+    int J0 = cs + tj * kDelTile, K0 = cs + tk * kDelTile;
+    int nJ = min(kDelTile, cs + cnt - J0), nK = min(kDelTile, cs + cnt - K0);
+    int tid = threadIdx.x;
+    if (tid < kDelTile) {
+      int j = J0 + tid, k = K0 + tid;
+      if (tid < nJ) {
+        dJ[tid] = d.depth[d.c_node[j]];
+        cJ[tid] = d.col_ptr[d.c_node[j]];
+        int m = 1 << 30;
+        for (int q = j; q < J0 + nJ - 1 && tj != tk; ++q) m = min(m, d.ad[q] < 0 ? -1 : d.ad[q]);
+        sufJ[tid] = m;  // min ad[j .. J0+nJ-2] (off-diagonal tiles only)
+      }
+      if (tid < nK) {
+        dK[tid] = d.depth[d.c_node[k]];
+        cK[tid] = d.col_ptr[d.c_node[k]];
+        int m = 1 << 30;
+        for (int q = K0; q < k; ++q) m = min(m, d.ad[q] < 0 ? -1 : d.ad[q]);
+        preK[tid] = m;  // min ad[K0 .. k-1]
+      }
+    }
+    // min over the gap ad[J0+nJ-1 .. K0-1] (includes the boundary pair)
+    int gm = 1 << 30;
+    if (tj != tk)
+      for (int q = J0 + nJ - 1 + tid; q < K0; q += kBlock) gm = min(gm, d.ad[q] < 0 ? -1 : d.ad[q]);
+    red[tid] = gm;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+      if (tid < o) red[tid] = min(red[tid], red[tid + o]);
+      __syncthreads();
+    }
+    int gap_min = red[0];
+    int lmax = 0;
+    for (int p = tid; p < kDelTile * kDelTile; p += kBlock) {
+      int a = p / kDelTile, b = p % kDelTile;
+      int L = 0;
+      if (a < nJ && b < nK) {
+        int j = J0 + a, k = K0 + b;
+        if (tj == tk) {
+          if (k == j) {
+            L = dJ[a] + 1;
+          } else if (k > j) {
+            int m = 1 << 30;
+            for (int q = j; q < k; ++q) m = min(m, d.ad[q] < 0 ? -1 : d.ad[q]);
+            L = m + 1;
+          }
+        } else {
+          int m = min(min(sufJ[a], gap_min), preK[b]);
+          L = m + 1;
+        }
+        if (L < 0) L = 0;
+      }
+      LJK[a][b] = L;
+      lmax = max(lmax, L);
+    }
+    __syncthreads();
+    red[tid] = lmax;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+      if (tid < o) red[tid] = max(red[tid], red[tid + o]);
+      __syncthreads();
+    }
+    if (tid == 0) maxL = red[0];
+    __syncthreads();
+    // each thread: 4 pairs (a, b) = (tid / 8, (tid % 8) * 4 + r)
+    const int a = tid / 8, b0 = (tid % 8) * 4;
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int base = 0; base < maxL; base += kDelChunk) {
+      for (int p = tid; p < kDelTile * kDelChunk; p += kBlock) {
+        int r = p / kDelChunk, q = p % kDelChunk;
+        int depthidx = base + q;  // 0 = root
+        float vj = 0.0f, vk = 0.0f;
+        if (r < nJ && depthidx <= dJ[r]) vj = d.col_val[cJ[r] + (dJ[r] - depthidx)];
+        if (r < nK && depthidx <= dK[r]) vk = d.col_val[cK[r] + (dK[r] - depthidx)];
+        PJ[r][q] = vj;
+        PK[r][q] = vk;
+      }
+      __syncthreads();
+      for (int r = 0; r < 4; ++r) {
+        int L = LJK[a][b0 + r] - base;
+        int lim = min(L, kDelChunk);
+        float sacc = 0.0f;
+        for (int q = 0; q < lim; ++q) sacc += PJ[a][q] * PK[b0 + r][q];
+        acc[r] += sacc;
+      }
+      __syncthreads();
+    }
+    const int64_t ko = d.k_off[s];
+    for (int r = 0; r < 4; ++r) {
+      int b = b0 + r;
+      if (a < nJ && b < nK) {
+        int j = J0 + a - cs, k = K0 + b - cs;
+        if (tj != tk || k >= j) {
+          d.K[ko + (int64_t)j * cnt + k] = acc[r];
+          d.K[ko + (int64_t)k * cnt + j] = acc[r];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+void launch_delassus(const Dev& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_adjacent_lca, dim3((d.CMAX + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_delassus_tiles, dim3(1024), dim3(kBlock), 0, st, d);
+}
+
+// ---------------------------------------------------------------- warm start + r
+// r_n = h^2 K_jj, r_f = h K_jj (W_jj of the normal and tangent rows, Sec. 5.4);
+// lambda^0: previous frame's world impulse of the same (node, obstacle) re-expressed
+// in the new frame, else 0 (keep_lambda: impulses were set by the host).
+__global__ void k_warm_start(Dev d, int keep_lambda) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int c = min(d.n_contacts[0], d.CMAX);
+  if (j >= c) return;
+  int s = d.c_scene[j];
+  int cs = d.cs_off[s], cnt = d.cs_off[s + 1] - cs;
+  if (d.k_off[d.NS] > d.KCAP) return;
+  float kjj = d.K[d.k_off[s] + (int64_t)(j - cs) * cnt + (j - cs)];
+  d.c_rn[j] = (float)(d.h * d.h) * kjj;
+  d.c_rf[j] = (float)d.h * kjj;
+  if (keep_lambda) return;
+  float l[3] = {0.0f, 0.0f, 0.0f};
+  if (d.warm == 1) {
+    int pc = d.pc_count[0];
+    int key_n = d.c_node[j], key_o = d.c_obst[j];
+    int lo = 0, hi = pc;
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      int mn = d.pc_node[mid], mo = d.pc_obst[mid];
+      if (mn < key_n || (mn == key_n && mo < key_o)) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo < pc && d.pc_node[lo] == key_n && d.pc_obst[lo] == key_o) {
+      float w[3] = {d.pc_world[lo], d.pc_world[d.CMAX + lo], d.pc_world[2 * d.CMAX + lo]};
+      for (int r = 0; r < 3; ++r)
+        l[r] = d.cC[(r * 3 + 0) * d.CMAX + j] * w[0] + d.cC[(r * 3 + 1) * d.CMAX + j] * w[1] +
+               d.cC[(r * 3 + 2) * d.CMAX + j] * w[2];
+    }
+  }
+  for (int r = 0; r < 3; ++r) d.lam[r * d.CMAX + j] = l[r];
+}
+
+void launch_warm_start(const Dev& d, hipStream_t st, int keep_lambda) {
+  hipLaunchKernelGGL(k_warm_start, dim3((d.CMAX + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d, keep_lambda);
+}
+
+// ---------------------------------------------------------------- per-iteration contact terms
+__device__ inline float wave_sum_c(float v) {
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+struct FBTerms {
+  float om_n, E_n, phi_n, om_f, E_f, phi_f[2];
+};
+
+// App. B, Fischer-Burmeister rows.  Readings: rho_n = 0 takes omega_n = 1 - 1/sqrt2,
+// E_n = (1 - 1/sqrt2) r_n; friction rows are inactive (omega_f = 0, E_f = 1) when
+// lambda_n <= 0, mu = 0, or the compliance is infinite; 0/0 gives E_f = 0.
+__device__ FBTerms fb_terms(float dn, const float vf[2], const float l[3], float rn, float rf, float mu) {
+  FBTerms t;
+  float rho = sqrtf(dn * dn + rn * rn * l[0] * l[0]);
+  t.phi_n = dn + rn * l[0] - rho;
+  if (rho > 0.0f) {
+    t.om_n = 1.0f - dn / rho;
+    t.E_n = (1.0f - rn * l[0] / rho) * rn;
+  } else {
+    t.om_n = 1.0f - 0.70710678118654752f;
+    t.E_n = (1.0f - 0.70710678118654752f) * rn;
+  }
+  float s = sqrtf(vf[0] * vf[0] + vf[1] * vf[1]);
+  float lf = sqrtf(l[1] * l[1] + l[2] * l[2]);
+  float gam = mu * l[0] - lf;
+  float rhof = sqrtf(s * s + rf * rf * gam * gam);
+  float den = s + mu * rf * l[0] - rhof;
+  float num = rhof - rf * gam;
+  bool active = (l[0] > 0.0f) && (mu > 0.0f) && !(den == 0.0f && num != 0.0f);
+  if (active) {
+    t.om_f = 1.0f;
+    t.E_f = den != 0.0f ? num / den * rf : 0.0f;
+  } else {
+    t.om_f = 0.0f;
+    t.E_f = 1.0f;
+  }
+  t.phi_f[0] = t.om_f * vf[0] + t.E_f * l[1];
+  t.phi_f[1] = t.om_f * vf[1] + t.E_f * l[2];
+  return t;
+}
+
+// One wavefront per contact: u_v = q~_v + (S^T y)_v along the ancestor path of v
+// (the unconstrained solve A^-1 b at the contact node), then Omega, E~, the h vector
+// (Sec. 5.2) and X = C^T (Omega lambda) for the W Omega lambda term of J A^-1 g.
+__global__ void __launch_bounds__(kBlock) k_contact_prep(Dev d) {
+  const int j = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int c = min(d.n_contacts[0], d.CMAX);
+  if (j >= c) return;
+  const int v = d.c_node[j];
+  const float* col = d.col_val + d.col_ptr[v];
+  float ax = 0.0f, ay = 0.0f, az = 0.0f;
+  int t = 0, a = v;
+  while (a != -1) {
+    int e = __builtin_amdgcn_readfirstlane(d.chain_end[a]);
+    int len = e - a + 1;
+    for (int k = lane; k < len; k += kWave) {
+      float s = col[t + k];
+      ax += s * d.y[a + k];
+      ay += s * d.y[d.N4 + a + k];
+      az += s * d.y[2 * d.N4 + a + k];
+    }
+    t += len;
+    a = __builtin_amdgcn_readfirstlane(d.parent[e]);
+  }
+  ax = wave_sum_c(ax);
+  ay = wave_sum_c(ay);
+  az = wave_sum_c(az);
+  if (lane != 0) return;
+  const int CM = d.CMAX;
+  const float h = (float)d.h;
+  float u[3] = {d.qp[v] + ax, d.qp[d.N4 + v] + ay, d.qp[2 * d.N4 + v] + az};
+  float x[3], xt[3];
+  for (int q = 0; q < 3; ++q) {
+    x[q] = d.q[q * d.N4 + v];
+    xt[q] = d.qt[q * d.N4 + v];
+  }
+  float C[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int q = 0; q < 3; ++q) C[r][q] = d.cC[(r * 3 + q) * CM + j];
+  float l[3] = {d.lam[j], d.lam[CM + j], d.lam[2 * CM + j]};
+  float Hq[3], Hu[3], hvf[2];
+  for (int r = 0; r < 3; ++r) {
+    Hq[r] = C[r][0] * x[0] + C[r][1] * x[1] + C[r][2] * x[2];
+    Hu[r] = C[r][0] * u[0] + C[r][1] * u[1] + C[r][2] * u[2];
+  }
+  float dn = Hq[0] - d.c_dn[j];
+  for (int r = 0; r < 2; ++r)
+    hvf[r] = C[r + 1][0] * (x[0] - xt[0]) + C[r + 1][1] * (x[1] - xt[1]) + C[r + 1][2] * (x[2] - xt[2]) -
+             h * d.c_df[r * CM + j];
+  float vf[2] = {hvf[0] / h, hvf[1] / h};
+  FBTerms f = fb_terms(dn, vf, l, d.c_rn[j], d.c_rf[j], d.c_mu[j]);
+  float om[3] = {f.om_n, f.om_f, f.om_f};
+  d.Om[j] = om[0];
+  d.Om[CM + j] = om[1];
+  d.Om[2 * CM + j] = om[2];
+  d.Et[j] = f.E_n / (h * h);
+  d.Et[CM + j] = f.E_f / h;
+  d.Et[2 * CM + j] = f.E_f / h;
+  d.hv[j] = -f.phi_n + f.om_n * Hq[0];
+  d.hv[CM + j] = -h * f.phi_f[0] + f.om_f * Hq[1];
+  d.hv[2 * CM + j] = -h * f.phi_f[1] + f.om_f * Hq[2];
+  for (int r = 0; r < 3; ++r) d.Hu[r * CM + j] = Hu[r];
+  float ol[3] = {om[0] * l[0], om[1] * l[1], om[2] * l[2]};
+  for (int q = 0; q < 3; ++q) d.X[q * CM + j] = C[0][q] * ol[0] + C[1][q] * ol[1] + C[2][q] * ol[2];
+}
+
+void launch_contact_prep(const Dev& d, hipStream_t st) {
+  int waves_per_block = kBlock / kWave;
+  hipLaunchKernelGGL(k_contact_prep, dim3((d.CMAX + waves_per_block - 1) / waves_per_block), dim3(kBlock), 0,
+                     st, d);
+}
+
+// ---------------------------------------------------------------- Conjugate Residual
+// Solves (Omega W Omega + E~) dlambda = (h_vec - Omega (H u + h^2 W Omega lambda)) / h^2
+// per scene with W_(j,k) = K_jk C_j C_k^T, from dlambda = 0, for d.cr_iters iterations
+// (stopping only on exact breakdown), then lambda += dlambda and
+// F = h^2 C^T (Omega lambda).  One cooperative launch; each block owns a contiguous
+// range of contacts; scene-wise dot products are summed in a fixed order.
+__device__ float block_sum(float v, float* red) {
+  v = wave_sum_c(v);
+  int w = threadIdx.x / kWave;
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) red[w] = v;
+  __syncthreads();
+  float s = 0.0f;
+  for (int q = 0; q < kBlock / kWave; ++q) s += red[q];
+  return s;
+}
+
+// Y = sum_k K_jk Z_k over the scene of contact j (block cooperative)
+__device__ void k_row_matvec(const Dev& d, int j, const float* Z, float Y[3], float* red) {
+  int s = d.c_scene[j];
+  int cs = d.cs_off[s], cnt = d.cs_off[s + 1] - cs;
+  const float* Krow = d.K + d.k_off[s] + (int64_t)(j - cs) * cnt;
+  float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+  for (int k = threadIdx.x; k < cnt; k += kBlock) {
+    float kv = Krow[k];
+    a0 += kv * Z[cs + k];
+    a1 += kv * Z[d.CMAX + cs + k];
+    a2 += kv * Z[2 * d.CMAX + cs + k];
+  }
+  Y[0] = block_sum(a0, red);
+  Y[1] = block_sum(a1, red);
+  Y[2] = block_sum(a2, red);
+}
+
+__device__ float scene_sum(const Dev& d, int j, const float* prod, float* red) {
+  int s = d.c_scene[j];
+  int cs = d.cs_off[s], ce = d.cs_off[s + 1];
+  float a = 0.0f;
+  for (int k = cs + (int)threadIdx.x; k < ce; k += kBlock) a += prod[k];
+  return block_sum(a, red);
+}
+
+constexpr int kCrMaxPerBlock = 256;
+
+__global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
+  __shared__ float red[kBlock / kWave];
+  __shared__ float s_rAr[kCrMaxPerBlock], s_ApAp[kCrMaxPerBlock];
+  cg::grid_group grid = cg::this_grid();
+  // with the Delassus storage full every block skips all work (uniform, no grid sync)
+  const int c = d.k_off[d.NS] > d.KCAP ? 0 : min(d.n_contacts[0], d.CMAX);
+  const int G = gridDim.x;
+  const int per = (c + G - 1) / G;
+  const int j0 = blockIdx.x * per, j1 = min(c, j0 + per);
+  const int CM = d.CMAX;
+  const float h = (float)d.h, h2 = (float)(d.h * d.h);
+  float* x = d.cr_x;
+  float* r = d.cr_r;
+  float* p = d.cr_p;
+  float* Ar = d.cr_Ar;
+  float* Ap = d.cr_Ap;
+  float* Z = d.cr_Z;
+  float* prodA = d.cr_prod;
+  float* prodB = d.cr_prod + CM;
+  auto cval = [&](int j, int rr, int q) { return d.cC[(rr * 3 + q) * CM + j]; };
+  // Z_j = C_j^T (Omega_j v_j)
+  auto setZ = [&](int j, const float* vec) {
+    float ov[3];
+    for (int q = 0; q < 3; ++q) ov[q] = d.Om[q * CM + j] * vec[q * CM + j];
+    for (int q = 0; q < 3; ++q) Z[q * CM + j] = cval(j, 0, q) * ov[0] + cval(j, 1, q) * ov[1] + cval(j, 2, q) * ov[2];
+  };
+  // M v at row j, from Y = K Z
+  auto applyM = [&](int j, const float Y[3], const float* vec, float out[3]) {
+    for (int rr = 0; rr < 3; ++rr) {
+      float cy = cval(j, rr, 0) * Y[0] + cval(j, rr, 1) * Y[1] + cval(j, rr, 2) * Y[2];
+      out[rr] = d.Om[rr * CM + j] * cy + d.Et[rr * CM + j] * vec[rr * CM + j];
+    }
+  };
+  // [A] right-hand side, x = 0, r = rhs
+  for (int j = j0; j < j1; ++j) {
+    float Y[3];
+    k_row_matvec(d, j, d.X, Y, red);
+    if (threadIdx.x == 0) {
+      for (int rr = 0; rr < 3; ++rr) {
+        float cy = cval(j, rr, 0) * Y[0] + cval(j, rr, 1) * Y[1] + cval(j, rr, 2) * Y[2];
+        float rhs = (d.hv[rr * CM + j] - d.Om[rr * CM + j] * (d.Hu[rr * CM + j] + h2 * cy)) / h2;
+        x[rr * CM + j] = 0.0f;
+        r[rr * CM + j] = rhs;
+      }
+      setZ(j, r);
+    }
+  }
+  grid.sync();
+  // [B] Ar = M r, p = r, Ap = Ar
+  for (int j = j0; j < j1; ++j) {
+    float Y[3];
+    k_row_matvec(d, j, Z, Y, red);
+    if (threadIdx.x == 0) {
+      float out[3];
+      applyM(j, Y, r, out);
+      float pa = 0.0f, pb = 0.0f;
+      for (int rr = 0; rr < 3; ++rr) {
+        Ar[rr * CM + j] = out[rr];
+        p[rr * CM + j] = r[rr * CM + j];
+        Ap[rr * CM + j] = out[rr];
+        pa += r[rr * CM + j] * out[rr];
+        pb += out[rr] * out[rr];
+      }
+      prodA[j] = pa;
+      prodB[j] = pb;
+    }
+  }
+  grid.sync();
+  for (int j = j0; j < j1; ++j) {
+    float a = scene_sum(d, j, prodA, red);
+    float b = scene_sum(d, j, prodB, red);
+    if (threadIdx.x == 0) {
+      s_rAr[j - j0] = a;
+      s_ApAp[j - j0] = b;
+    }
+  }
+  __syncthreads();
+  for (int it = 0; it < d.cr_iters; ++it) {
+    // [D] x += alpha p, r -= alpha Ap
+    for (int j = j0; j < j1; ++j) {
+      if (threadIdx.x == 0) {
+        float rAr = s_rAr[j - j0], ApAp = s_ApAp[j - j0];
+        if (ApAp != 0.0f && rAr != 0.0f) {
+          float alpha = rAr / ApAp;
+          for (int rr = 0; rr < 3; ++rr) {
+            x[rr * CM + j] += alpha * p[rr * CM + j];
+            r[rr * CM + j] -= alpha * Ap[rr * CM + j];
+          }
+        }
+        setZ(j, r);
+      }
+    }
+    grid.sync();
+    // [E] Ar = M r, prodA = r . Ar
+    for (int j = j0; j < j1; ++j) {
+      float Y[3];
+      k_row_matvec(d, j, Z, Y, red);
+      if (threadIdx.x == 0) {
+        float out[3];
+        applyM(j, Y, r, out);
+        float pa = 0.0f;
+        for (int rr = 0; rr < 3; ++rr) {
+          Ar[rr * CM + j] = out[rr];
+          pa += r[rr * CM + j] * out[rr];
+        }
+        prodA[j] = pa;
+      }
+    }
+    grid.sync();
+    // [F] beta, p = r + beta p, Ap = Ar + beta Ap, prodB = Ap . Ap
+    for (int j = j0; j < j1; ++j) {
+      float rAr_new = scene_sum(d, j, prodA, red);
+      if (threadIdx.x == 0) {
+        float rAr = s_rAr[j - j0], ApAp = s_ApAp[j - j0];
+        float pb = 0.0f;
+        if (ApAp != 0.0f && rAr != 0.0f) {
+          float beta = rAr_new / rAr;
+          s_rAr[j - j0] = rAr_new;
+          for (int rr = 0; rr < 3; ++rr) {
+            p[rr * CM + j] = r[rr * CM + j] + beta * p[rr * CM + j];
+            Ap[rr * CM + j] = Ar[rr * CM + j] + beta * Ap[rr * CM + j];
+          }
+        }
+        for (int rr = 0; rr < 3; ++rr) pb += Ap[rr * CM + j] * Ap[rr * CM + j];
+        prodB[j] = pb;
+      }
+    }
+    grid.sync();
+    // [G] (Ap, Ap)
+    for (int j = j0; j < j1; ++j) {
+      float b = scene_sum(d, j, prodB, red);
+      if (threadIdx.x == 0) {
+        // a scene that broke down keeps its state: leave its sums untouched
+        if (s_ApAp[j - j0] != 0.0f && s_rAr[j - j0] != 0.0f) s_ApAp[j - j0] = b;
+      }
+    }
+    __syncthreads();
+  }
+  // [H] lambda += dlambda, F = h^2 C^T (Omega lambda)
+  for (int j = j0; j < j1; ++j) {
+    if (threadIdx.x == 0) {
+      float ol[3];
+      for (int rr = 0; rr < 3; ++rr) {
+        float l = d.lam[rr * CM + j] + x[rr * CM + j];
+        d.lam[rr * CM + j] = l;
+        ol[rr] = d.Om[rr * CM + j] * l;
+      }
+      for (int q = 0; q < 3; ++q)
+        d.F[q * CM + j] = h2 * (cval(j, 0, q) * ol[0] + cval(j, 1, q) * ol[1] + cval(j, 2, q) * ol[2]);
+    }
+  }
+  (void)h;
+}
+
+int cr_max_blocks() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(k_cr), kBlock, 0) !=
+      hipSuccess)
+    return 1;
+  return max(1, min(cus * max(per, 1), 1024));
+}
+
+hipError_t launch_cr(const Dev& d, hipStream_t st, int cr_blocks) {
+  Dev dd = d;
+  void* args[] = {&dd};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_cr), dim3(cr_blocks), dim3(kBlock), args, 0,
+                                    st);
+}
+
+// ---------------------------------------------------------------- NCP residual (metres)
+// max over contacts of |FB(delta_n, r_n lambda_n)|, and for lambda_n > 0
+// h |FB(s, r_f gamma)| and h |vdot_f + s lambda_f/|lambda_f||, else h r_f |lambda_f|.
+__global__ void k_residual(Dev d) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int c = min(d.n_contacts[0], d.CMAX);
+  if (j >= c) return;
+  const int CM = d.CMAX;
+  const float h = (float)d.h;
+  int v = d.c_node[j];
+  float x[3], xt[3];
+  for (int q = 0; q < 3; ++q) {
+    x[q] = d.q[q * d.N4 + v];
+    xt[q] = d.qt[q * d.N4 + v];
+  }
+  float C[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int q = 0; q < 3; ++q) C[r][q] = d.cC[(r * 3 + q) * CM + j];
+  float dn = C[0][0] * x[0] + C[0][1] * x[1] + C[0][2] * x[2] - d.c_dn[j];
+  float vf[2];
+  for (int r = 0; r < 2; ++r)
+    vf[r] = (C[r + 1][0] * (x[0] - xt[0]) + C[r + 1][1] * (x[1] - xt[1]) + C[r + 1][2] * (x[2] - xt[2]) -
+             h * d.c_df[r * CM + j]) / h;
+  float l[3] = {d.lam[j], d.lam[CM + j], d.lam[2 * CM + j]};
+  float rn = d.c_rn[j], rf = d.c_rf[j], mu = d.c_mu[j];
+  float a = rn * l[0];
+  float res = fabsf(dn + a - sqrtf(dn * dn + a * a));
+  float s = sqrtf(vf[0] * vf[0] + vf[1] * vf[1]);
+  float lf = sqrtf(l[1] * l[1] + l[2] * l[2]);
+  if (l[0] > 0.0f) {
+    float b = rf * (mu * l[0] - lf);
+    res = fmaxf(res, h * fabsf(s + b - sqrtf(s * s + b * b)));
+    if (lf > 0.0f) {
+      float e0 = vf[0] + s * l[1] / lf, e1 = vf[1] + s * l[2] / lf;
+      res = fmaxf(res, h * sqrtf(e0 * e0 + e1 * e1));
+    }
+  } else {
+    res = fmaxf(res, h * rf * lf);
+  }
+  if (!(res == res)) res = 3.0e38f;  // NaN -> huge
+  atomicMax(reinterpret_cast<unsigned int*>(d.res) + d.c_scene[j], __float_as_uint(res));
+}
+
+__global__ void k_zero_res(Dev d) {
+  for (int s = threadIdx.x; s < d.NS; s += blockDim.x) d.res[s] = 0.0f;
+}
+
+void launch_residual(const Dev& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_res, dim3(1), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_residual, dim3((d.CMAX + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d);
+}
+
+}  // namespace lg

@@ -1,0 +1,329 @@
+"""Thin ctypes binding of liblgsim_hip.so (argument marshalling only).
+
+Every step of the solver runs in the library's HIP kernels; this module only
+converts numpy arrays / scene descriptions into the C structures declared in
+``include/lgsim.h`` and back.  PyTorch is used only to pass device memory and
+streams (``read_state_device``).  Loading fails loudly if the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_NAME = "liblgsim_hip.so"
+LIB_PATH = os.path.join(_HERE, LIB_NAME)
+
+SIM_OK = 0
+ERRORS = {-1: "SIM_E_ARG", -2: "SIM_E_MESH", -3: "SIM_E_NOT_SPD", -4: "SIM_E_NOMEM",
+          -5: "SIM_E_DEVICE", -6: "SIM_E_STATE", -7: "SIM_E_DIVERGED", -8: "SIM_E_CAPACITY"}
+
+
+class SimError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class sim_mesh(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_tets", C.c_int32),
+                ("rest_xyz", C.POINTER(C.c_double)), ("tets", C.POINTER(C.c_int32)),
+                ("init_xyz", C.POINTER(C.c_double)), ("init_vel", C.POINTER(C.c_double)),
+                ("n_pins", C.c_int32), ("pin_nodes", C.POINTER(C.c_int32)),
+                ("pin_group", C.POINTER(C.c_int32))]
+
+
+class sim_material(C.Structure):
+    _fields_ = [("model", C.c_int32), ("E", C.c_double), ("nu", C.c_double), ("rho", C.c_double),
+                ("tet_model", C.POINTER(C.c_int32)), ("tet_E", C.POINTER(C.c_double)),
+                ("tet_nu", C.POINTER(C.c_double))]
+
+
+class sim_options(C.Structure):
+    _fields_ = [("gravity", C.c_double * 3), ("pin_weight_scale", C.c_double),
+                ("contact_margin", C.c_double), ("cr_iters", C.c_int32), ("warm", C.c_int32),
+                ("ncp_tol", C.c_double), ("max_iters", C.c_int32), ("max_contacts", C.c_int32),
+                ("hip_stream", C.c_void_p)]
+
+
+class sim_obstacle(C.Structure):
+    _fields_ = [("type", C.c_int32), ("geom", C.c_double * 10), ("mu", C.c_double),
+                ("vel", C.c_double * 3)]
+
+
+class sim_stats(C.Structure):
+    _fields_ = [("iters_done", C.c_int32), ("n_contacts", C.c_int32), ("ncp_res", C.c_double),
+                ("ms_frame", C.c_float), ("ms_phase", C.c_float * 8)]
+
+
+class sim_contact(C.Structure):
+    _fields_ = [("node", C.c_int32), ("obstacle", C.c_int32), ("frame", C.c_double * 9),
+                ("lambda_", C.c_double * 3), ("gap", C.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load the built library (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    d, i32, i64 = C.c_double, C.c_int32, C.c_int64
+    sig = {
+        "sim_options_default": [P(sim_options)],
+        "sim_create": [P(sim_mesh), P(sim_material), d, P(sim_options), P(C.c_void_p)],
+        "sim_set_obstacles": [C.c_void_p, i32, P(sim_obstacle)],
+        "sim_set_pin_motion": [C.c_void_p, i32, P(d), P(d), P(d)],
+        "sim_step": [C.c_void_p, i32, i32, P(sim_stats)],
+        "sim_read_state": [C.c_void_p, P(d), P(d), P(sim_contact), i32, P(i32)],
+        "sim_read_state_device": [C.c_void_p, C.c_void_p, C.c_void_p],
+        "sim_destroy": [C.c_void_p],
+        "sim_create_batch": [i32, P(sim_mesh), P(sim_material), P(i32), P(P(sim_obstacle)), d,
+                             P(sim_options), P(C.c_void_p)],
+        "sim_batch_info": [C.c_void_p, P(i32), P(i32)],
+        "sim_set_iterate_state": [C.c_void_p, P(d), P(d), P(d), d, i32, P(sim_contact)],
+        "sim_run_iterations": [C.c_void_p, i32],
+        "sim_read_iterate": [C.c_void_p, P(d), P(d)],
+        "sim_global_solve": [C.c_void_p, P(d), P(d)],
+        "sim_debug_rhs": [C.c_void_p, P(d)],
+        "sim_debug_delassus": [C.c_void_p, P(d)],
+        "lg_host_create": [P(sim_mesh), P(sim_material), d, d, i32, P(C.c_void_p)],
+        "lg_host_info": [C.c_void_p, P(i64)],
+        "lg_host_ordering": [C.c_void_p, P(i32), P(i32)],
+        "lg_host_dense_A": [C.c_void_p, P(d)],
+        "lg_host_dense_S": [C.c_void_p, P(d)],
+        "lg_host_apply_StS": [C.c_void_p, P(d), P(d)],
+        "lg_host_destroy": [C.c_void_p],
+    }
+    for name, args in sig.items():
+        if not hasattr(lib, name):
+            continue
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.sim_last_error.argtypes = []
+    lib.sim_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != SIM_OK:
+        raise SimError(rc, _lib.sim_last_error().decode())
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32)) if a is not None else None
+
+
+class _Marshal:
+    """Keeps the numpy buffers of one scene alive while the C structs point at them."""
+
+    def __init__(self, scene):
+        self.rest = np.ascontiguousarray(scene.rest, np.float64)
+        self.tets = np.ascontiguousarray(scene.tets, np.int32)
+        self.init = None if scene.init_pos is None else np.ascontiguousarray(scene.init_pos, np.float64)
+        self.vel = None if scene.init_vel is None else np.ascontiguousarray(scene.init_vel, np.float64)
+        self.pins = np.ascontiguousarray(scene.pin_nodes, np.int32)
+        self.groups = np.ascontiguousarray(scene.pin_group, np.int32)
+        self.mesh = sim_mesh(len(self.rest), len(self.tets), _dp(self.rest), _ip(self.tets),
+                             _dp(self.init), _dp(self.vel), len(self.pins),
+                             _ip(self.pins) if len(self.pins) else None,
+                             _ip(self.groups) if len(self.pins) else None)
+        self.tm = None if scene.tet_model is None else np.ascontiguousarray(scene.tet_model, np.int32)
+        self.tE = None if scene.tet_E is None else np.ascontiguousarray(scene.tet_E, np.float64)
+        self.tnu = None if scene.tet_nu is None else np.ascontiguousarray(scene.tet_nu, np.float64)
+        self.mat = sim_material(scene.model, scene.E, scene.nu, scene.rho, _ip(self.tm), _dp(self.tE),
+                                _dp(self.tnu))
+        obs = (sim_obstacle * max(1, len(scene.obstacles)))()
+        for k, ob in enumerate(scene.obstacles):
+            obs[k].type = ob.type
+            for q in range(10):
+                obs[k].geom[q] = float(ob.geom[q])
+            obs[k].mu = ob.mu
+            for q in range(3):
+                obs[k].vel[q] = float(ob.vel[q])
+        self.obs = obs
+        self.n_obs = len(scene.obstacles)
+
+
+def options_for(scene, **kw):
+    lib = load()
+    o = sim_options()
+    _check(lib.sim_options_default(C.byref(o)))
+    for q in range(3):
+        o.gravity[q] = float(scene.gravity[q])
+    o.pin_weight_scale = scene.pin_weight_scale
+    o.contact_margin = scene.margin
+    o.cr_iters = scene.cr_iters
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class HostPrecompute:
+    """Host-only products of sim_create (ordering, S) for inspection on the CPU."""
+
+    def __init__(self, scene, want_dense_S=False):
+        lib = load()
+        self._m = _Marshal(scene)
+        h = C.c_void_p()
+        _check(lib.lg_host_create(C.byref(self._m.mesh), C.byref(self._m.mat), scene.h,
+                                  scene.pin_weight_scale, int(want_dense_S), C.byref(h)))
+        self.h = h
+        info = np.zeros(8, np.int64)
+        _check(lib.lg_host_info(h, info.ctypes.data_as(C.POINTER(C.c_int64))))
+        self.n, self.m, self.nnz_S, self.nnz_L, self.row_floats, self.max_depth, self.chains = map(int, info[:7])
+
+    def ordering(self):
+        perm = np.zeros(self.n, np.int32)
+        parent = np.zeros(self.n, np.int32)
+        _check(_lib.lg_host_ordering(self.h, _ip(perm), _ip(parent)))
+        return perm, parent
+
+    def dense_A(self):
+        A = np.zeros((self.n, self.n))
+        _check(_lib.lg_host_dense_A(self.h, _dp(A)))
+        return A
+
+    def dense_S(self):
+        S = np.zeros((self.n, self.n))
+        _check(_lib.lg_host_dense_S(self.h, _dp(S)))
+        return S
+
+    def apply_StS(self, b):
+        b = np.ascontiguousarray(b, np.float64)
+        u = np.zeros_like(b)
+        _check(_lib.lg_host_apply_StS(self.h, _dp(b), _dp(u)))
+        return u
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.lg_host_destroy(self.h)
+            self.h = None
+
+
+class Sim:
+    """One solver handle (a single scene or a batch)."""
+
+    def __init__(self, scene=None, batch=None, stream=None, **opt):
+        lib = load()
+        self.scenes = [scene] if scene is not None else list(batch)
+        self._ms = [_Marshal(s) for s in self.scenes]
+        s0 = self.scenes[0]
+        self.opt = options_for(s0, **opt)
+        if stream is not None:
+            self.opt.hip_stream = C.c_void_p(stream)
+        h = C.c_void_p()
+        if scene is not None:
+            _check(lib.sim_create(C.byref(self._ms[0].mesh), C.byref(self._ms[0].mat), s0.h,
+                                  C.byref(self.opt), C.byref(h)))
+            self.h = h
+            if self._ms[0].n_obs:
+                _check(lib.sim_set_obstacles(h, self._ms[0].n_obs, self._ms[0].obs))
+        else:
+            k = len(self.scenes)
+            meshes = (sim_mesh * k)(*[m.mesh for m in self._ms])
+            mats = (sim_material * k)(*[m.mat for m in self._ms])
+            nobs = np.array([m.n_obs for m in self._ms], np.int32)
+            obsp = (C.POINTER(sim_obstacle) * k)(*[C.cast(m.obs, C.POINTER(sim_obstacle)) for m in self._ms])
+            _check(lib.sim_create_batch(k, meshes, mats, _ip(nobs), obsp, s0.h, C.byref(self.opt),
+                                        C.byref(h)))
+            self.h = h
+        self.n = sum(s.n for s in self.scenes)
+        groups = [s for s in self.scenes if len(s.pin_lin_vel)]
+        if scene is not None and len(s0.pin_lin_vel):
+            lin = np.ascontiguousarray(s0.pin_lin_vel, np.float64)
+            ang = np.ascontiguousarray(s0.pin_ang_vel, np.float64)
+            piv = np.ascontiguousarray(s0.pin_pivot, np.float64)
+            _check(lib.sim_set_pin_motion(h, len(lin), _dp(lin), _dp(ang), _dp(piv)))
+        del groups
+
+    def step(self, frames=1, iters=None, stats=True):
+        iters = self.scenes[0].iters if iters is None else iters
+        st = (sim_stats * frames)() if stats else None
+        _check(_lib.sim_step(self.h, frames, iters, st))
+        if not stats:
+            return None
+        return [dict(iters=s.iters_done, contacts=s.n_contacts, ncp=s.ncp_res, ms=s.ms_frame,
+                     phases=list(s.ms_phase)) for s in st]
+
+    def read_state(self, cap=0):
+        q = np.zeros((self.n, 3))
+        v = np.zeros((self.n, 3))
+        nc = C.c_int32(0)
+        _check(_lib.sim_read_state(self.h, _dp(q), _dp(v), None, 0, C.byref(nc)))
+        contacts = None
+        if nc.value > 0:
+            buf = (sim_contact * nc.value)()
+            _check(_lib.sim_read_state(self.h, None, None, buf, nc.value, C.byref(nc)))
+            contacts = dict(node=np.array([c.node for c in buf], np.int64),
+                            obst=np.array([c.obstacle for c in buf], np.int64),
+                            frame=np.array([list(c.frame) for c in buf]).reshape(-1, 3, 3),
+                            lam=np.array([list(c.lambda_) for c in buf]),
+                            gap=np.array([c.gap for c in buf]))
+        else:
+            contacts = dict(node=np.zeros(0, np.int64), obst=np.zeros(0, np.int64),
+                            frame=np.zeros((0, 3, 3)), lam=np.zeros((0, 3)), gap=np.zeros(0))
+        return q, v, contacts
+
+    def read_state_device(self, out_tensor, stream=None):
+        """Copy positions (float32 [3][n], caller order) into a device tensor."""
+        _check(_lib.sim_read_state_device(self.h, C.c_void_p(out_tensor.data_ptr()),
+                                          C.c_void_p(stream) if stream else None))
+
+    def set_iterate_state(self, q_t, v_t, q_k, t, node, obst, lam):
+        c = len(node)
+        buf = (sim_contact * max(1, c))()
+        for j in range(c):
+            buf[j].node = int(node[j])
+            buf[j].obstacle = int(obst[j])
+            for q in range(3):
+                buf[j].lambda_[q] = float(lam[j][q])
+        _check(_lib.sim_set_iterate_state(self.h, _dp(np.ascontiguousarray(q_t, np.float64)),
+                                          _dp(np.ascontiguousarray(v_t, np.float64)),
+                                          _dp(np.ascontiguousarray(q_k, np.float64)), float(t), c, buf))
+
+    def run_iterations(self, k=1):
+        _check(_lib.sim_run_iterations(self.h, k))
+
+    def read_iterate(self, c):
+        q = np.zeros((self.n, 3))
+        lam = np.zeros((max(c, 1), 3))
+        _check(_lib.sim_read_iterate(self.h, _dp(q), _dp(lam)))
+        return q, lam[:c]
+
+    def global_solve(self, b):
+        b = np.ascontiguousarray(b, np.float64)
+        u = np.zeros_like(b)
+        _check(_lib.sim_global_solve(self.h, _dp(b), _dp(u)))
+        return u
+
+    def debug_rhs(self):
+        r = np.zeros((self.n, 3))
+        _check(_lib.sim_debug_rhs(self.h, _dp(r)))
+        return r
+
+    def debug_delassus(self, c):
+        K = np.zeros((max(c, 1), max(c, 1)))
+        _check(_lib.sim_debug_delassus(self.h, _dp(K)))
+        return K[:c, :c]
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()

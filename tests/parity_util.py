@@ -1,0 +1,44 @@
+"""Shared helpers of the GPU parity tests: run the HIP solver and the FP64 oracle from
+the same input state (rounded to float32-representable values) and compare."""
+import numpy as np
+
+from oracle.sim import OracleSim
+
+
+def f32(a):
+    return np.asarray(a, np.float64).astype(np.float32).astype(np.float64)
+
+
+def rel_inf(a, b, scale=None):
+    s = np.abs(b).max() if scale is None else scale
+    return float(np.abs(a - b).max() / max(s, 1e-300))
+
+
+def oracle_state_after(scene, frames, iters=None):
+    """Oracle state (q_t, v_t, t, contacts, lambda) at the start of frame `frames`:
+    runs `frames` frames, then detects the next frame's contacts."""
+    o = OracleSim(scene)
+    if frames:
+        o.step(frames, iters=iters)
+    q_t, q_pred, fc, lam = o.begin_frame()
+    return o, q_t, o.v.copy(), o.t, fc, lam
+
+
+def iterate_pair(sim_factory, scene, q_t, v_t, q_k, t, node, obst, lam, k=1, cr="fixed", cr_iters=None):
+    """k iterations from the same state on the GPU and in the oracle.
+
+    Returns (q_gpu, lam_gpu, q_oracle, lam_oracle, oracle, fc)."""
+    q_t, v_t, q_k, lam = f32(q_t), f32(v_t), f32(q_k), f32(lam)
+    sim = sim_factory(scene)
+    sim.set_iterate_state(q_t, v_t, q_k, t, node, obst, lam)
+    sim.run_iterations(k)
+    qg, lg = sim.read_iterate(len(node))
+    o = OracleSim(scene, cr_iters=cr_iters)
+    o.t = t
+    q_pred = o.predict(q_t, v_t)
+    fc = o.contacts_from_keys(node, obst, q_t)
+    q, lo = q_k.copy(), lam.copy()
+    for _ in range(k):
+        q, lo, _ = o.iterate(fc, q, lo, q_t, q_pred, t + o.h, cr=cr)
+    sim.close()
+    return qg, lg, q, lo, o, fc

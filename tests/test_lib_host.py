@@ -1,0 +1,116 @@
+"""CPU tests of the HIP library: it loads, exports every symbol of include/lgsim.h, and
+its host precomputation (ordering, Cholesky, S = L^-1) agrees with the oracle and with
+Theorem 1 (no device calls)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import sparse_inverse as si
+from oracle.sim import OracleSim
+from paper_2503_15078_amd import lgsim, scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "lgsim.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char\s*\*)\s+(\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_header_symbols():
+    lib = lgsim.load()
+    names = header_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def _tiny(dims, model=1, E=1e5):
+    rest, tets = scenes.voxel_mesh(np.ones(tuple(d - 1 for d in dims), bool), 0.02)
+    return scenes.Scene("t", rest, tets, model, E, 0.3, 1000.0, 0.01, np.zeros(3), [], 0.005, 1, 10, 1)
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2), (3, 2, 2), (3, 3, 3), (4, 4, 3)])
+def test_host_sparse_inverse_against_oracle(dims):
+    sc = _tiny(dims)
+    hp = lgsim.HostPrecompute(sc, want_dense_S=True)
+    perm, parent = hp.ordering()
+    A = hp.dense_A()
+    S = hp.dense_S()
+    o = OracleSim(sc)
+    Ao = np.zeros((o.n, o.n))
+    Ao[np.ix_(perm, perm)] = o.A.toarray()
+    np.testing.assert_allclose(A, Ao, rtol=1e-13, atol=1e-14 * np.abs(Ao).max())
+    # Theorem 1: pattern of L^-1 = ancestors in the elimination tree (oracle's etree)
+    par = si.etree_from_pattern(si.symbolic_pattern(Ao))
+    assert np.array_equal(par, parent)
+    assert np.all((parent == -1) | (parent > np.arange(len(parent))))    # postordered
+    anc = si.ancestors_pattern(parent)
+    nz = np.abs(S) > 1e-13 * np.abs(S).max()
+    assert np.array_equal(nz, anc)
+    assert hp.nnz_S == (si.depth(parent) + 1).sum()
+    n = len(A)
+    np.testing.assert_allclose(S.T @ S @ Ao, np.eye(n), atol=1e-11)
+    np.testing.assert_allclose(S @ Ao @ S.T, np.eye(n), atol=1e-11)
+    # float32 row and column storages reproduce A^-1 b
+    b = np.random.default_rng(0).standard_normal((n, 3))
+    u = hp.apply_StS(b)
+    ref = np.linalg.solve(Ao, b)
+    assert np.abs(u - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+def test_host_postorder_subtrees_contiguous():
+    sc = scenes.twist_bar(0, nodes=(12, 5, 5))
+    hp = lgsim.HostPrecompute(sc)
+    _, parent = hp.ordering()
+    n = len(parent)
+    size = np.ones(n, np.int64)
+    for j in range(n):
+        if parent[j] >= 0:
+            size[parent[j]] += size[j]
+    # in a postorder the subtree of i is [i - size_i + 1, i]
+    lo = np.arange(n) - size + 1
+    for j in range(n):
+        if parent[j] >= 0:
+            assert lo[parent[j]] <= lo[j] and j < parent[j]
+    assert hp.nnz_S == size.sum()
+
+
+def test_host_rejects_bad_meshes():
+    sc = _tiny((3, 3, 3))
+    bad = scenes.Scene(**{**sc.__dict__})
+    t = sc.tets.copy()
+    t[0, [1, 2]] = t[0, [2, 1]]           # inverted tet
+    bad.tets = t
+    with pytest.raises(lgsim.SimError) as e:
+        lgsim.HostPrecompute(bad)
+    assert e.value.code == -2
+    bad.tets = sc.tets.copy()
+    bad.tets[0, 0] = sc.n + 5              # index out of range
+    with pytest.raises(lgsim.SimError) as e:
+        lgsim.HostPrecompute(bad)
+    assert e.value.code == -2
+    bad.tets = sc.tets.copy()
+    bad.rest = np.vstack([sc.rest, [[9.0, 9.0, 9.0]]])   # unused node
+    with pytest.raises(lgsim.SimError) as e:
+        lgsim.HostPrecompute(bad)
+    assert e.value.code == -2
+    bad.rest = sc.rest.copy()
+    bad.pin_nodes = np.array([0], np.int32)
+    bad.pin_group = np.array([0], np.int32)
+    bad.pin_weight_scale = 0.0
+    with pytest.raises(lgsim.SimError) as e:
+        lgsim.HostPrecompute(bad)
+    assert e.value.code == -1
+
+
+def test_host_pin_weights_match_oracle():
+    sc = scenes.twist_bar(0, nodes=(6, 4, 4))
+    hp = lgsim.HostPrecompute(sc)
+    perm, _ = hp.ordering()
+    o = OracleSim(sc)
+    A = hp.dense_A()
+    np.testing.assert_allclose(np.diag(A)[perm], o.A.diagonal(), rtol=1e-12)
