@@ -167,6 +167,14 @@ int sim_read_state(sim_t s, double* xyz, double* vel, sim_contact* contacts, int
  * torch tensor) on hip_stream (null: the handle's stream). */
 int sim_read_state_device(sim_t s, float* d_xyz_soa, void* hip_stream);
 
+/* Checkpoint / resume on the device: sim_save_state copies the frame state (positions,
+ * velocities, time, previous-frame contacts and impulses) into a device-side snapshot
+ * owned by the handle; sim_restore_state copies it back.  Both are stream-ordered
+ * device-to-device copies (no host synchronisation).  Restore before any save:
+ * SIM_E_STATE. */
+int sim_save_state(sim_t s);
+int sim_restore_state(sim_t s);
+
 /* Release everything owned by the handle (null is accepted). */
 int sim_destroy(sim_t s);
 

@@ -62,7 +62,12 @@ struct lgsim {
   int iter_c = 0;                     // contact count of the current iterate state
   std::vector<int32_t> iter_canon;    // internal contact index -> canonical position
   hipEvent_t ev[8] = {};
-  bool frame_open = false;
+  std::vector<hipEvent_t> fev;        // per-frame timing events
+  struct Snapshot {
+    float *qt = nullptr, *vt = nullptr, *pc_world = nullptr;
+    double* t = nullptr;
+    int *pc_count = nullptr, *pc_node = nullptr, *pc_obst = nullptr;
+  } snap;
 
   template <class T>
   int alloc(T*& p, size_t count) {
@@ -85,6 +90,7 @@ struct lgsim {
     for (void* p : allocs) hipFree(p);
     for (auto& e : ev)
       if (e) hipEventDestroy(e);
+    for (auto& e : fev) hipEventDestroy(e);
     if (h_pinned) hipHostFree(h_pinned);
     if (h_res) hipHostFree(h_res);
     if (own_stream && st) hipStreamDestroy(st);
@@ -338,6 +344,8 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   TRY(s->alloc(d.c_obst, CM));
   TRY(s->alloc(d.c_scene, CM));
   TRY(s->alloc(d.cC, 9 * (size_t)CM));
+  TRY(s->alloc(d.cC64, 9 * (size_t)CM));
+  TRY(s->alloc(d.c_dn64, CM));
   TRY(s->alloc(d.c_dn, CM));
   TRY(s->alloc(d.c_df, 2 * (size_t)CM));
   TRY(s->alloc(d.c_mu, CM));
@@ -354,9 +362,10 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   TRY(s->alloc(d.pc_node, CM));
   TRY(s->alloc(d.pc_obst, CM));
   TRY(s->alloc(d.pc_world, 3 * (size_t)CM));
-  for (float** p : {&d.Hu, &d.Om, &d.Et, &d.hv, &d.X, &d.F, &d.cr_x, &d.cr_r, &d.cr_p, &d.cr_Ar, &d.cr_Ap, &d.cr_Z})
+  for (float** p : {&d.Om, &d.Et, &d.hv, &d.X, &d.F, &d.cr_x, &d.cr_r, &d.cr_p, &d.cr_Ar, &d.cr_Ap, &d.cr_Z})
     TRY(s->alloc(*p, 3 * (size_t)CM));
-  TRY(s->alloc(d.cr_prod, 2 * (size_t)CM));
+  TRY(s->alloc(d.cr_prod, 3 * (size_t)CM));
+  TRY(s->alloc(d.cr_sync, 4));
   TRY(s->alloc(d.t, 1));
   TRY(s->alloc(d.res, NS));
   TRY(s->alloc(d.bad, 4));
@@ -440,7 +449,11 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   // default pin motion: all groups static
   std::vector<double> grp(9 * (size_t)d.G, 0.0);
   TRY(upload(s, d.grp, grp.data(), grp.size()));
-  s->cr_blocks = std::max(1, std::min(lg::cr_max_blocks(), 256));
+  {
+    int want = 128;
+    if (const char* e = std::getenv("LGSIM_CR_BLOCKS")) want = std::max(1, std::atoi(e));
+    s->cr_blocks = std::max(1, std::min(lg::cr_max_blocks(), want));
+  }
   int per = (d.CMAX + s->cr_blocks - 1) / s->cr_blocks;
   if (per > 256) {
     lg::set_error("max_contacts too large for the CR launch");
@@ -481,69 +494,59 @@ int validate_obstacles(int32_t n, const sim_obstacle* obs) {
 }
 
 // ---------------------------------------------------------------- drivers
+// Frame start (Algorithm 4): predicted state, pin targets, collision detection with
+// compaction, Delassus operator and warm start.  No host synchronisation: every kernel
+// reads the contact count from device memory and grids are sized by capacity.
 int frame_setup(lgsim* s) {
   auto& d = s->d;
   lg::launch_predict(d, s->st);
   lg::launch_pins(d, s->st);
   lg::launch_collide(d, s->st);
-  TRY(check_launch("collision"));
-  HIPCHK(hipMemcpyAsync(s->h_pinned, d.n_contacts, sizeof(int), hipMemcpyDeviceToHost, s->st));
-  HIPCHK(hipMemcpyAsync(s->h_pinned + 1, d.overflow, sizeof(int), hipMemcpyDeviceToHost, s->st));
-  HIPCHK(hipStreamSynchronize(s->st));
-  if (s->h_pinned[1]) {
-    lg::set_error("contact capacity exceeded: " + std::to_string(s->h_pinned[0]) + " contacts > max_contacts " +
-                  std::to_string(d.CMAX) + " (or Delassus storage full)");
-    int zero = 0;
-    HIPCHK(hipMemcpyAsync(d.overflow, &zero, sizeof(int), hipMemcpyHostToDevice, s->st));
-    HIPCHK(hipStreamSynchronize(s->st));
-    return SIM_E_CAPACITY;
-  }
-  s->iter_c = s->h_pinned[0];
-  if (s->iter_c > 0) {
-    lg::launch_delassus(d, s->st);
-    lg::launch_warm_start(d, s->st, 0);
-  }
+  lg::launch_delassus(d, s->st);
+  lg::launch_warm_start(d, s->st, 0);
+  s->iter_c = -1;  // known after the next synchronisation
   return check_launch("frame setup");
 }
 
-int iteration(lgsim* s, bool timed, float* ms) {
+// Timing events of one frame: [0] frame start, [1] setup done, then 6 per iteration,
+// then integrate start/end and residual end.
+hipEvent_t* frame_event(lgsim* s, int i) {
+  while ((int)s->fev.size() <= i) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    s->fev.push_back(e);
+  }
+  return &s->fev[i];
+}
+
+int iteration(lgsim* s, bool timed, int it) {
   auto& d = s->d;
   hipError_t cr_err = hipSuccess;
+  const int base = 2 + 6 * it;
   auto rec = [&](int i) {
-    if (timed) hipEventRecord(s->ev[i], s->st);
+    if (timed) {
+      hipEvent_t* e = frame_event(s, base + i);
+      if (e) hipEventRecord(*e, s->st);
+    }
   };
-  rec(1);
+  rec(0);
   lg::launch_element(d, s->st);
   lg::launch_gather(d, s->st);
-  rec(2);
+  rec(1);
   lg::launch_spmv_S(d, s->st, d.b, d.y);
-  rec(3);
-  if (s->iter_c > 0) {
+  rec(2);
+  if (s->iter_c != 0) {
     lg::launch_contact_prep(d, s->st);
-    rec(4);
+    rec(3);
     cr_err = lg::launch_cr(d, s->st, s->cr_blocks);
-    rec(5);
     lg::launch_apply_forces(d, s->st);
-  } else {
     rec(4);
-    rec(5);
+  } else {
+    rec(3);
+    rec(4);
   }
   lg::launch_spmv_St(d, s->st, d.y, d.qp, d.q);
-  rec(6);
-  if (timed) {
-    hipEventSynchronize(s->ev[6]);
-    float t;
-    hipEventElapsedTime(&t, s->ev[1], s->ev[2]);
-    ms[1] += t;
-    hipEventElapsedTime(&t, s->ev[2], s->ev[3]);
-    ms[2] += t;
-    hipEventElapsedTime(&t, s->ev[3], s->ev[4]);
-    ms[3] += t;
-    hipEventElapsedTime(&t, s->ev[4], s->ev[5]);
-    ms[4] += t;
-    hipEventElapsedTime(&t, s->ev[5], s->ev[6]);
-    ms[5] += t;
-  }
+  rec(5);
   if (cr_err != hipSuccess) {
     lg::set_error(std::string("cooperative CR launch failed: ") + hipGetErrorString(cr_err));
     return SIM_E_DEVICE;
@@ -551,28 +554,71 @@ int iteration(lgsim* s, bool timed, float* ms) {
   return check_launch("iteration");
 }
 
+// phases: 0 setup, 1 local + gather, 2 S pass, 3 contact evaluation, 4 CR + force
+// update, 5 S^T pass, 6 integrate, 7 residual
+void collect_times(lgsim* s, int iters, float* ms) {
+  auto el = [&](int a, int b) {
+    float t = 0.0f;
+    if (a < (int)s->fev.size() && b < (int)s->fev.size()) hipEventElapsedTime(&t, s->fev[a], s->fev[b]);
+    return t;
+  };
+  ms[0] += el(0, 1);
+  for (int it = 0; it < iters; ++it) {
+    int b = 2 + 6 * it;
+    for (int p = 0; p < 5; ++p) ms[1 + p] += el(b + p, b + p + 1);
+  }
+  int e = 2 + 6 * iters;
+  ms[6] += el(e, e + 1);
+  ms[7] += el(e + 1, e + 2);
+}
+
 int read_residual(lgsim* s, double* worst) {
   auto& d = s->d;
   lg::launch_residual(d, s->st);
   HIPCHK(hipMemcpyAsync(s->h_res, d.res, sizeof(float) * d.NS, hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipMemcpyAsync(s->h_pinned, d.n_contacts, sizeof(int), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipMemcpyAsync(s->h_pinned + 1, d.overflow, sizeof(int), hipMemcpyDeviceToHost, s->st));
   HIPCHK(hipStreamSynchronize(s->st));
   double w = 0.0;
   for (int k = 0; k < d.NS; ++k) w = std::max(w, (double)s->h_res[k]);
   *worst = w;
+  s->iter_c = s->h_pinned[0];
   return SIM_OK;
 }
 
+// Clears a device flag after it was reported.
+int clear_flag(lgsim* s, int* dflag) {
+  int zero = 0;
+  HIPCHK(hipMemcpyAsync(dflag, &zero, sizeof(int), hipMemcpyHostToDevice, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  return SIM_OK;
+}
+
+// Integration unless the frame overflowed or produced non-finite positions (then the
+// frame is dropped and the state stays at the frame start).
 int finish_frame(lgsim* s) {
   auto& d = s->d;
   lg::launch_check_finite(d, s->st);
   lg::launch_integrate(d, s->st);
   TRY(check_launch("integrate"));
+  return SIM_OK;
+}
+
+int frame_status(lgsim* s) {
+  auto& d = s->d;
+  HIPCHK(hipMemcpyAsync(s->h_pinned, d.n_contacts, sizeof(int), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipMemcpyAsync(s->h_pinned + 1, d.overflow, sizeof(int), hipMemcpyDeviceToHost, s->st));
   HIPCHK(hipMemcpyAsync(s->h_pinned + 2, d.bad, sizeof(int), hipMemcpyDeviceToHost, s->st));
   HIPCHK(hipStreamSynchronize(s->st));
+  s->iter_c = s->h_pinned[0];
+  if (s->h_pinned[1]) {
+    TRY(clear_flag(s, d.overflow));
+    lg::set_error("contact capacity exceeded: " + std::to_string(s->h_pinned[0]) + " contacts, max_contacts " +
+                  std::to_string(d.CMAX) + " (or Delassus storage full); frame not advanced");
+    return SIM_E_CAPACITY;
+  }
   if (s->h_pinned[2]) {
-    int zero = 0;
-    HIPCHK(hipMemcpyAsync(d.bad, &zero, sizeof(int), hipMemcpyHostToDevice, s->st));
-    HIPCHK(hipStreamSynchronize(s->st));
+    TRY(clear_flag(s, d.bad));
     lg::set_error("non-finite state; frame rolled back");
     return SIM_E_DIVERGED;
   }
@@ -804,41 +850,50 @@ int sim_step(sim_t s, int32_t frames, int32_t iters, sim_stats* stats) {
     return SIM_E_ARG;
   }
   for (int f = 0; f < frames; ++f) {
-    bool timed = stats != nullptr;
-    float ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const bool timed = stats != nullptr;
     auto t0 = std::chrono::steady_clock::now();
-    if (timed) hipEventRecord(s->ev[0], s->st);
+    auto rec = [&](int i) {
+      if (timed) {
+        hipEvent_t* e = frame_event(s, i);
+        if (e) hipEventRecord(*e, s->st);
+      }
+    };
+    rec(0);
     TRY(frame_setup(s));
-    if (timed) {
-      hipEventRecord(s->ev[7], s->st);
-      hipEventSynchronize(s->ev[7]);
-      hipEventElapsedTime(&ms[0], s->ev[0], s->ev[7]);
-    }
+    rec(1);
     int k = 0;
     double res = 0.0;
     bool have_res = false;
     while (true) {
-      TRY(iteration(s, timed, ms));
+      TRY(iteration(s, timed, k));
       ++k;
       if (iters > 0) {
         if (k >= iters) break;
       } else {
         TRY(read_residual(s, &res));
         have_res = true;
-        if (res <= s->opt.ncp_tol || k >= s->opt.max_iters) break;
+        if (s->h_pinned[1] || res <= s->opt.ncp_tol || k >= s->opt.max_iters) break;
       }
     }
-    TRY(check_launch("iterations"));
+    rec(2 + 6 * k);
+    TRY(finish_frame(s));
+    rec(3 + 6 * k);
     if (timed && !have_res) {
-      TRY(read_residual(s, &res));
-      have_res = true;
+      lg::launch_residual(s->d, s->st);
+      HIPCHK(hipMemcpyAsync(s->h_res, s->d.res, sizeof(float) * s->d.NS, hipMemcpyDeviceToHost, s->st));
     }
-    int rc = finish_frame(s);
+    rec(4 + 6 * k);
+    int rc = frame_status(s);
     if (rc != SIM_OK) return rc;
     if (timed) {
-      HIPCHK(hipStreamSynchronize(s->st));
+      if (!have_res) {
+        res = 0.0;
+        for (int q = 0; q < s->d.NS; ++q) res = std::max(res, (double)s->h_res[q]);
+      }
       auto t1 = std::chrono::steady_clock::now();
       auto& st = stats[f];
+      float ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      collect_times(s, k, ms);
       st.iters_done = k;
       st.n_contacts = s->iter_c;
       st.ncp_res = res;
@@ -911,6 +966,49 @@ int sim_read_state_device(sim_t s, float* d_xyz, void* stream) {
 
 int sim_destroy(sim_t s) {
   delete s;
+  return SIM_OK;
+}
+
+int sim_save_state(sim_t s) {
+  if (!s) return SIM_E_ARG;
+  auto& d = s->d;
+  auto& b = s->snap;
+  const size_t NV = 3 * (size_t)d.N4, CM = d.CMAX;
+  if (!b.qt) {
+    TRY(s->alloc(b.qt, NV));
+    TRY(s->alloc(b.vt, NV));
+    TRY(s->alloc(b.t, 1));
+    TRY(s->alloc(b.pc_count, 4));
+    TRY(s->alloc(b.pc_node, CM));
+    TRY(s->alloc(b.pc_obst, CM));
+    TRY(s->alloc(b.pc_world, 3 * CM));
+  }
+  HIPCHK(hipMemcpyAsync(b.qt, d.qt, NV * sizeof(float), hipMemcpyDeviceToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(b.vt, d.vt, NV * sizeof(float), hipMemcpyDeviceToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(b.t, d.t, sizeof(double), hipMemcpyDeviceToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(b.pc_count, d.pc_count, sizeof(int), hipMemcpyDeviceToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(b.pc_node, d.pc_node, CM * sizeof(int), hipMemcpyDeviceToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(b.pc_obst, d.pc_obst, CM * sizeof(int), hipMemcpyDeviceToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(b.pc_world, d.pc_world, 3 * CM * sizeof(float), hipMemcpyDeviceToDevice, s->st));
+  return SIM_OK;
+}
+
+int sim_restore_state(sim_t s) {
+  if (!s) return SIM_E_ARG;
+  auto& d = s->d;
+  auto& b = s->snap;
+  if (!b.qt) {
+    lg::set_error("no saved state");
+    return SIM_E_STATE;
+  }
+  const size_t NV = 3 * (size_t)d.N4, CM = d.CMAX;
+  HIPCHK(hipMemcpyAsync(d.qt, b.qt, NV * sizeof(float), hipMemcpyDeviceToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(d.vt, b.vt, NV * sizeof(float), hipMemcpyDeviceToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(d.t, b.t, sizeof(double), hipMemcpyDeviceToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(d.pc_count, b.pc_count, sizeof(int), hipMemcpyDeviceToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(d.pc_node, b.pc_node, CM * sizeof(int), hipMemcpyDeviceToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(d.pc_obst, b.pc_obst, CM * sizeof(int), hipMemcpyDeviceToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(d.pc_world, b.pc_world, 3 * CM * sizeof(float), hipMemcpyDeviceToDevice, s->st));
   return SIM_OK;
 }
 
@@ -992,8 +1090,7 @@ int sim_run_iterations(sim_t s, int32_t k) {
     lg::set_error("bad arguments");
     return SIM_E_ARG;
   }
-  float ms[8] = {};
-  for (int i = 0; i < k; ++i) TRY(iteration(s, false, ms));
+  for (int i = 0; i < k; ++i) TRY(iteration(s, false, i));
   TRY(check_launch("iterations"));
   HIPCHK(hipStreamSynchronize(s->st));
   return SIM_OK;

@@ -15,7 +15,7 @@ namespace lg {
 constexpr int kBlock = 256;
 constexpr int kWave = 64;
 constexpr int kMaxObstacles = 64;
-constexpr int kDelTile = 32;      // Delassus tile (contacts x contacts)
+constexpr int kDelTile = 16;      // Delassus tile (contacts x contacts)
 constexpr int kDelChunk = 64;     // Delassus depth chunk staged in LDS
 
 struct ObstacleDev {
@@ -73,7 +73,8 @@ struct Dev {
   int *overflow;                   // [1]
   int *cnt, *blk;                  // collision scan scratch [N], [N/256+1]
   int *c_node, *c_obst, *c_scene;
-  float *cC;                       // [9][CMAX]
+  float *cC;                       // [9][CMAX] frame rows n, f1, f2
+  double *cC64, *c_dn64;           // the same frame and d_n in float64 (normal gap)
   float *c_dn, *c_df, *c_mu, *c_rn, *c_rf;  // df: [2][CMAX]
   double *c_gap;
   float *lam;                      // [3][CMAX]
@@ -87,8 +88,9 @@ struct Dev {
   int *pc_node, *pc_obst;
   float *pc_world;                 // [3][CMAX]
   // iteration scratch [3][CMAX] each
-  float *Hu, *Om, *Et, *hv, *X, *F;
-  float *cr_x, *cr_r, *cr_p, *cr_Ar, *cr_Ap, *cr_Z, *cr_prod;  // prod: [2][CMAX]
+  float *Om, *Et, *hv, *X, *F;     // hv: h_vec - Omega H u (delta form)
+  float *cr_x, *cr_r, *cr_p, *cr_Ar, *cr_Ap, *cr_Z, *cr_prod;  // prod: [3][CMAX]
+  int *cr_sync;                    // device-wide barrier counter of the CR launch
   // frame state
   double *t;                       // [1] simulation time at frame start
   float *res;                      // [NS] NCP residual per scene

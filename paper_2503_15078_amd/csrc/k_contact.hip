@@ -3,12 +3,9 @@
 // the complementarity preconditioner (Sec. 5.4), the warm start, the per-iteration
 // Fischer-Burmeister evaluation (Sec. 5.2, App. B), the Conjugate Residual solve of
 // the Schur system (Sec. 5.2, Sec. 6) and the NCP residual.
-#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
-
-namespace cg = cooperative_groups;
 
 namespace lg {
 
@@ -137,8 +134,13 @@ __device__ void write_contact_frame(const Dev& d, int j, int v, const ObstacleDe
   double ph[3] = {xt[0] - dist * n[0], xt[1] - dist * n[1], xt[2] - dist * n[2]};
   const double* rows[3] = {n, f1, f2};
   for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) d.cC[(r * 3 + c) * d.CMAX + j] = (float)rows[r][c];
-  d.c_dn[j] = (float)(n[0] * ph[0] + n[1] * ph[1] + n[2] * ph[2]);
+    for (int c = 0; c < 3; ++c) {
+      d.cC[(r * 3 + c) * d.CMAX + j] = (float)rows[r][c];
+      d.cC64[(r * 3 + c) * d.CMAX + j] = rows[r][c];
+    }
+  double dn = n[0] * ph[0] + n[1] * ph[1] + n[2] * ph[2];
+  d.c_dn[j] = (float)dn;
+  d.c_dn64[j] = dn;
   d.c_df[j] = (float)(f1[0] * ob.vel[0] + f1[1] * ob.vel[1] + f1[2] * ob.vel[2]);
   d.c_df[d.CMAX + j] = (float)(f2[0] * ob.vel[0] + f2[1] * ob.vel[1] + f2[2] * ob.vel[2]);
   d.c_mu[j] = (float)ob.mu;
@@ -223,28 +225,35 @@ __global__ void k_collide_write(Dev d) {
 }
 
 // per-scene contact ranges, Delassus block offsets and tile offsets
+// one block: contacts are sorted by scene, so scene s starts at lower_bound(c_scene, s);
+// then prefix sums of the per-scene Delassus block sizes and tile counts
 __global__ void k_scene_offsets(Dev d) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int c = min(d.n_contacts[0], d.CMAX);
-  int j = 0;
-  int64_t koff = 0;
-  int toff = 0;
-  for (int s = 0; s < d.NS; ++s) {
-    d.cs_off[s] = j;
-    d.k_off[s] = koff;
-    d.tile_off[s] = toff;
-    int j1 = j;
-    while (j1 < c && d.c_scene[j1] == s) ++j1;
-    int cs = j1 - j;
-    koff += (int64_t)cs * cs;
-    int T = (cs + kDelTile - 1) / kDelTile;
-    toff += T * (T + 1) / 2;
-    j = j1;
+  const int c = min(d.n_contacts[0], d.CMAX);
+  for (int s = threadIdx.x; s <= d.NS; s += blockDim.x) {
+    int lo = 0, hi = c;
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (d.c_scene[mid] < s) lo = mid + 1;
+      else hi = mid;
+    }
+    d.cs_off[s] = (s == d.NS) ? c : lo;
   }
-  d.cs_off[d.NS] = j;
-  d.k_off[d.NS] = koff;
-  d.tile_off[d.NS] = toff;
-  if (koff > d.KCAP) d.overflow[0] = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t koff = 0;
+    int toff = 0;
+    for (int s = 0; s < d.NS; ++s) {
+      d.k_off[s] = koff;
+      d.tile_off[s] = toff;
+      int cs = d.cs_off[s + 1] - d.cs_off[s];
+      koff += (int64_t)cs * cs;
+      int T = (cs + kDelTile - 1) / kDelTile;
+      toff += T * (T + 1) / 2;
+    }
+    d.k_off[d.NS] = koff;
+    d.tile_off[d.NS] = toff;
+    if (koff > d.KCAP) d.overflow[0] = 1;
+  }
 }
 
 void launch_collide(const Dev& d, hipStream_t st) {
@@ -383,9 +392,12 @@ __global__ void __launch_bounds__(kBlock) k_delassus_tiles(Dev d) {
     }
     if (tid == 0) maxL = red[0];
     __syncthreads();
-    // each thread: 4 pairs (a, b) = (tid / 8, (tid % 8) * 4 + r)
-    const int a = tid / 8, b0 = (tid % 8) * 4;
-    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    // each thread: kPP pairs (a, b0 + r) of the tile
+    constexpr int kPP = kDelTile * kDelTile / kBlock;
+    constexpr int kCols = kDelTile / kPP;
+    const int a = tid / kCols, b0 = (tid % kCols) * kPP;
+    float acc[kPP];
+    for (int r = 0; r < kPP; ++r) acc[r] = 0.0f;
     for (int base = 0; base < maxL; base += kDelChunk) {
       for (int p = tid; p < kDelTile * kDelChunk; p += kBlock) {
         int r = p / kDelChunk, q = p % kDelChunk;
@@ -397,7 +409,7 @@ __global__ void __launch_bounds__(kBlock) k_delassus_tiles(Dev d) {
         PK[r][q] = vk;
       }
       __syncthreads();
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < kPP; ++r) {
         int L = LJK[a][b0 + r] - base;
         int lim = min(L, kDelChunk);
         float sacc = 0.0f;
@@ -407,7 +419,7 @@ __global__ void __launch_bounds__(kBlock) k_delassus_tiles(Dev d) {
       __syncthreads();
     }
     const int64_t ko = d.k_off[s];
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < kPP; ++r) {
       int b = b0 + r;
       if (a < nJ && b < nK) {
         int j = J0 + a - cs, k = K0 + b - cs;
@@ -516,6 +528,7 @@ __global__ void __launch_bounds__(kBlock) k_contact_prep(Dev d) {
   const int j = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
   const int lane = threadIdx.x & (kWave - 1);
   const int c = min(d.n_contacts[0], d.CMAX);
+  if (blockIdx.x == 0 && threadIdx.x == 0) d.cr_sync[0] = 0;  // barrier counter of the CR launch
   if (j >= c) return;
   const int v = d.c_node[j];
   const float* col = d.col_val + d.col_ptr[v];
@@ -539,22 +552,24 @@ __global__ void __launch_bounds__(kBlock) k_contact_prep(Dev d) {
   if (lane != 0) return;
   const int CM = d.CMAX;
   const float h = (float)d.h;
-  float u[3] = {d.qp[v] + ax, d.qp[d.N4 + v] + ay, d.qp[2 * d.N4 + v] + az};
-  float x[3], xt[3];
+  float x[3], xt[3], du[3];
   for (int q = 0; q < 3; ++q) {
     x[q] = d.q[q * d.N4 + v];
     xt[q] = d.qt[q * d.N4 + v];
   }
+  // u - x^k = (q~ - x^k) + (S^T y)_v: a difference of nearby values, kept small
+  du[0] = (d.qp[v] - x[0]) + ax;
+  du[1] = (d.qp[d.N4 + v] - x[1]) + ay;
+  du[2] = (d.qp[2 * d.N4 + v] - x[2]) + az;
   float C[3][3];
   for (int r = 0; r < 3; ++r)
     for (int q = 0; q < 3; ++q) C[r][q] = d.cC[(r * 3 + q) * CM + j];
   float l[3] = {d.lam[j], d.lam[CM + j], d.lam[2 * CM + j]};
-  float Hq[3], Hu[3], hvf[2];
-  for (int r = 0; r < 3; ++r) {
-    Hq[r] = C[r][0] * x[0] + C[r][1] * x[1] + C[r][2] * x[2];
-    Hu[r] = C[r][0] * u[0] + C[r][1] * u[1] + C[r][2] * u[2];
-  }
-  float dn = Hq[0] - d.c_dn[j];
+  // delta_n = n . x - d_n in float64 (absolute coordinates, small difference)
+  double dn64 = d.cC64[0 * CM + j] * (double)x[0] + d.cC64[1 * CM + j] * (double)x[1] +
+                d.cC64[2 * CM + j] * (double)x[2] - d.c_dn64[j];
+  float dn = (float)dn64;
+  float hvf[2];
   for (int r = 0; r < 2; ++r)
     hvf[r] = C[r + 1][0] * (x[0] - xt[0]) + C[r + 1][1] * (x[1] - xt[1]) + C[r + 1][2] * (x[2] - xt[2]) -
              h * d.c_df[r * CM + j];
@@ -567,10 +582,12 @@ __global__ void __launch_bounds__(kBlock) k_contact_prep(Dev d) {
   d.Et[j] = f.E_n / (h * h);
   d.Et[CM + j] = f.E_f / h;
   d.Et[2 * CM + j] = f.E_f / h;
-  d.hv[j] = -f.phi_n + f.om_n * Hq[0];
-  d.hv[CM + j] = -h * f.phi_f[0] + f.om_f * Hq[1];
-  d.hv[2 * CM + j] = -h * f.phi_f[1] + f.om_f * Hq[2];
-  for (int r = 0; r < 3; ++r) d.Hu[r * CM + j] = Hu[r];
+  // h_vec - Omega H u = -(phi_n, h phi_f) - Omega C (u - x^k)   (Sec. 5.2, with H q^k cancelled)
+  float Cdu[3];
+  for (int r = 0; r < 3; ++r) Cdu[r] = C[r][0] * du[0] + C[r][1] * du[1] + C[r][2] * du[2];
+  d.hv[j] = -f.phi_n - om[0] * Cdu[0];
+  d.hv[CM + j] = -h * f.phi_f[0] - om[1] * Cdu[1];
+  d.hv[2 * CM + j] = -h * f.phi_f[1] - om[2] * Cdu[2];
   float ol[3] = {om[0] * l[0], om[1] * l[1], om[2] * l[2]};
   for (int q = 0; q < 3; ++q) d.X[q * CM + j] = C[0][q] * ol[0] + C[1][q] * ol[1] + C[2][q] * ol[2];
 }
@@ -579,221 +596,6 @@ void launch_contact_prep(const Dev& d, hipStream_t st) {
   int waves_per_block = kBlock / kWave;
   hipLaunchKernelGGL(k_contact_prep, dim3((d.CMAX + waves_per_block - 1) / waves_per_block), dim3(kBlock), 0,
                      st, d);
-}
-
-// ---------------------------------------------------------------- Conjugate Residual
-// Solves (Omega W Omega + E~) dlambda = (h_vec - Omega (H u + h^2 W Omega lambda)) / h^2
-// per scene with W_(j,k) = K_jk C_j C_k^T, from dlambda = 0, for d.cr_iters iterations
-// (stopping only on exact breakdown), then lambda += dlambda and
-// F = h^2 C^T (Omega lambda).  One cooperative launch; each block owns a contiguous
-// range of contacts; scene-wise dot products are summed in a fixed order.
-__device__ float block_sum(float v, float* red) {
-  v = wave_sum_c(v);
-  int w = threadIdx.x / kWave;
-  __syncthreads();
-  if ((threadIdx.x & (kWave - 1)) == 0) red[w] = v;
-  __syncthreads();
-  float s = 0.0f;
-  for (int q = 0; q < kBlock / kWave; ++q) s += red[q];
-  return s;
-}
-
-// Y = sum_k K_jk Z_k over the scene of contact j (block cooperative)
-__device__ void k_row_matvec(const Dev& d, int j, const float* Z, float Y[3], float* red) {
-  int s = d.c_scene[j];
-  int cs = d.cs_off[s], cnt = d.cs_off[s + 1] - cs;
-  const float* Krow = d.K + d.k_off[s] + (int64_t)(j - cs) * cnt;
-  float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
-  for (int k = threadIdx.x; k < cnt; k += kBlock) {
-    float kv = Krow[k];
-    a0 += kv * Z[cs + k];
-    a1 += kv * Z[d.CMAX + cs + k];
-    a2 += kv * Z[2 * d.CMAX + cs + k];
-  }
-  Y[0] = block_sum(a0, red);
-  Y[1] = block_sum(a1, red);
-  Y[2] = block_sum(a2, red);
-}
-
-__device__ float scene_sum(const Dev& d, int j, const float* prod, float* red) {
-  int s = d.c_scene[j];
-  int cs = d.cs_off[s], ce = d.cs_off[s + 1];
-  float a = 0.0f;
-  for (int k = cs + (int)threadIdx.x; k < ce; k += kBlock) a += prod[k];
-  return block_sum(a, red);
-}
-
-constexpr int kCrMaxPerBlock = 256;
-
-__global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
-  __shared__ float red[kBlock / kWave];
-  __shared__ float s_rAr[kCrMaxPerBlock], s_ApAp[kCrMaxPerBlock];
-  cg::grid_group grid = cg::this_grid();
-  // with the Delassus storage full every block skips all work (uniform, no grid sync)
-  const int c = d.k_off[d.NS] > d.KCAP ? 0 : min(d.n_contacts[0], d.CMAX);
-  const int G = gridDim.x;
-  const int per = (c + G - 1) / G;
-  const int j0 = blockIdx.x * per, j1 = min(c, j0 + per);
-  const int CM = d.CMAX;
-  const float h = (float)d.h, h2 = (float)(d.h * d.h);
-  float* x = d.cr_x;
-  float* r = d.cr_r;
-  float* p = d.cr_p;
-  float* Ar = d.cr_Ar;
-  float* Ap = d.cr_Ap;
-  float* Z = d.cr_Z;
-  float* prodA = d.cr_prod;
-  float* prodB = d.cr_prod + CM;
-  auto cval = [&](int j, int rr, int q) { return d.cC[(rr * 3 + q) * CM + j]; };
-  // Z_j = C_j^T (Omega_j v_j)
-  auto setZ = [&](int j, const float* vec) {
-    float ov[3];
-    for (int q = 0; q < 3; ++q) ov[q] = d.Om[q * CM + j] * vec[q * CM + j];
-    for (int q = 0; q < 3; ++q) Z[q * CM + j] = cval(j, 0, q) * ov[0] + cval(j, 1, q) * ov[1] + cval(j, 2, q) * ov[2];
-  };
-  // M v at row j, from Y = K Z
-  auto applyM = [&](int j, const float Y[3], const float* vec, float out[3]) {
-    for (int rr = 0; rr < 3; ++rr) {
-      float cy = cval(j, rr, 0) * Y[0] + cval(j, rr, 1) * Y[1] + cval(j, rr, 2) * Y[2];
-      out[rr] = d.Om[rr * CM + j] * cy + d.Et[rr * CM + j] * vec[rr * CM + j];
-    }
-  };
-  // [A] right-hand side, x = 0, r = rhs
-  for (int j = j0; j < j1; ++j) {
-    float Y[3];
-    k_row_matvec(d, j, d.X, Y, red);
-    if (threadIdx.x == 0) {
-      for (int rr = 0; rr < 3; ++rr) {
-        float cy = cval(j, rr, 0) * Y[0] + cval(j, rr, 1) * Y[1] + cval(j, rr, 2) * Y[2];
-        float rhs = (d.hv[rr * CM + j] - d.Om[rr * CM + j] * (d.Hu[rr * CM + j] + h2 * cy)) / h2;
-        x[rr * CM + j] = 0.0f;
-        r[rr * CM + j] = rhs;
-      }
-      setZ(j, r);
-    }
-  }
-  grid.sync();
-  // [B] Ar = M r, p = r, Ap = Ar
-  for (int j = j0; j < j1; ++j) {
-    float Y[3];
-    k_row_matvec(d, j, Z, Y, red);
-    if (threadIdx.x == 0) {
-      float out[3];
-      applyM(j, Y, r, out);
-      float pa = 0.0f, pb = 0.0f;
-      for (int rr = 0; rr < 3; ++rr) {
-        Ar[rr * CM + j] = out[rr];
-        p[rr * CM + j] = r[rr * CM + j];
-        Ap[rr * CM + j] = out[rr];
-        pa += r[rr * CM + j] * out[rr];
-        pb += out[rr] * out[rr];
-      }
-      prodA[j] = pa;
-      prodB[j] = pb;
-    }
-  }
-  grid.sync();
-  for (int j = j0; j < j1; ++j) {
-    float a = scene_sum(d, j, prodA, red);
-    float b = scene_sum(d, j, prodB, red);
-    if (threadIdx.x == 0) {
-      s_rAr[j - j0] = a;
-      s_ApAp[j - j0] = b;
-    }
-  }
-  __syncthreads();
-  for (int it = 0; it < d.cr_iters; ++it) {
-    // [D] x += alpha p, r -= alpha Ap
-    for (int j = j0; j < j1; ++j) {
-      if (threadIdx.x == 0) {
-        float rAr = s_rAr[j - j0], ApAp = s_ApAp[j - j0];
-        if (ApAp != 0.0f && rAr != 0.0f) {
-          float alpha = rAr / ApAp;
-          for (int rr = 0; rr < 3; ++rr) {
-            x[rr * CM + j] += alpha * p[rr * CM + j];
-            r[rr * CM + j] -= alpha * Ap[rr * CM + j];
-          }
-        }
-        setZ(j, r);
-      }
-    }
-    grid.sync();
-    // [E] Ar = M r, prodA = r . Ar
-    for (int j = j0; j < j1; ++j) {
-      float Y[3];
-      k_row_matvec(d, j, Z, Y, red);
-      if (threadIdx.x == 0) {
-        float out[3];
-        applyM(j, Y, r, out);
-        float pa = 0.0f;
-        for (int rr = 0; rr < 3; ++rr) {
-          Ar[rr * CM + j] = out[rr];
-          pa += r[rr * CM + j] * out[rr];
-        }
-        prodA[j] = pa;
-      }
-    }
-    grid.sync();
-    // [F] beta, p = r + beta p, Ap = Ar + beta Ap, prodB = Ap . Ap
-    for (int j = j0; j < j1; ++j) {
-      float rAr_new = scene_sum(d, j, prodA, red);
-      if (threadIdx.x == 0) {
-        float rAr = s_rAr[j - j0], ApAp = s_ApAp[j - j0];
-        float pb = 0.0f;
-        if (ApAp != 0.0f && rAr != 0.0f) {
-          float beta = rAr_new / rAr;
-          s_rAr[j - j0] = rAr_new;
-          for (int rr = 0; rr < 3; ++rr) {
-            p[rr * CM + j] = r[rr * CM + j] + beta * p[rr * CM + j];
-            Ap[rr * CM + j] = Ar[rr * CM + j] + beta * Ap[rr * CM + j];
-          }
-        }
-        for (int rr = 0; rr < 3; ++rr) pb += Ap[rr * CM + j] * Ap[rr * CM + j];
-        prodB[j] = pb;
-      }
-    }
-    grid.sync();
-    // [G] (Ap, Ap)
-    for (int j = j0; j < j1; ++j) {
-      float b = scene_sum(d, j, prodB, red);
-      if (threadIdx.x == 0) {
-        // a scene that broke down keeps its state: leave its sums untouched
-        if (s_ApAp[j - j0] != 0.0f && s_rAr[j - j0] != 0.0f) s_ApAp[j - j0] = b;
-      }
-    }
-    __syncthreads();
-  }
-  // [H] lambda += dlambda, F = h^2 C^T (Omega lambda)
-  for (int j = j0; j < j1; ++j) {
-    if (threadIdx.x == 0) {
-      float ol[3];
-      for (int rr = 0; rr < 3; ++rr) {
-        float l = d.lam[rr * CM + j] + x[rr * CM + j];
-        d.lam[rr * CM + j] = l;
-        ol[rr] = d.Om[rr * CM + j] * l;
-      }
-      for (int q = 0; q < 3; ++q)
-        d.F[q * CM + j] = h2 * (cval(j, 0, q) * ol[0] + cval(j, 1, q) * ol[1] + cval(j, 2, q) * ol[2]);
-    }
-  }
-  (void)h;
-}
-
-int cr_max_blocks() {
-  int dev = 0, cus = 0, per = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 1;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(k_cr), kBlock, 0) !=
-      hipSuccess)
-    return 1;
-  return max(1, min(cus * max(per, 1), 1024));
-}
-
-hipError_t launch_cr(const Dev& d, hipStream_t st, int cr_blocks) {
-  Dev dd = d;
-  void* args[] = {&dd};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_cr), dim3(cr_blocks), dim3(kBlock), args, 0,
-                                    st);
 }
 
 // ---------------------------------------------------------------- NCP residual (metres)
@@ -814,7 +616,8 @@ __global__ void k_residual(Dev d) {
   float C[3][3];
   for (int r = 0; r < 3; ++r)
     for (int q = 0; q < 3; ++q) C[r][q] = d.cC[(r * 3 + q) * CM + j];
-  float dn = C[0][0] * x[0] + C[0][1] * x[1] + C[0][2] * x[2] - d.c_dn[j];
+  float dn = (float)(d.cC64[0 * CM + j] * (double)x[0] + d.cC64[1 * CM + j] * (double)x[1] +
+                     d.cC64[2 * CM + j] * (double)x[2] - d.c_dn64[j]);
   float vf[2];
   for (int r = 0; r < 2; ++r)
     vf[r] = (C[r + 1][0] * (x[0] - xt[0]) + C[r + 1][1] * (x[1] - xt[1]) + C[r + 1][2] * (x[2] - xt[2]) -

@@ -387,7 +387,7 @@ void launch_check_finite(const Dev& d, hipStream_t st) {
 // produced a non-finite state.  Also advances the simulation time.
 __global__ void k_integrate(Dev d) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (d.bad[0]) return;
+  if (d.bad[0] || d.overflow[0]) return;
   if (v < d.N) {
     const float ih = (float)(1.0 / d.h);
     for (int c = 0; c < 3; ++c) {
@@ -399,13 +399,13 @@ __global__ void k_integrate(Dev d) {
 }
 
 __global__ void k_advance_time(Dev d) {
-  if (threadIdx.x == 0 && blockIdx.x == 0 && !d.bad[0]) d.t[0] += d.h;
+  if (threadIdx.x == 0 && blockIdx.x == 0 && !d.bad[0] && !d.overflow[0]) d.t[0] += d.h;
 }
 
 // Save the frame's contacts (key and world-space impulse) for the next warm start.
 __global__ void k_save_contacts(Dev d) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (d.bad[0]) return;
+  if (d.bad[0] || d.overflow[0]) return;
   int c = min(d.n_contacts[0], d.CMAX);
   if (j == 0) d.pc_count[0] = c;
   if (j >= c) return;

@@ -73,6 +73,12 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    try:
+        # share torch's HIP runtime: torch links the runtime by file name, the library
+        # by soname; loading torch first makes both resolve to one runtime instance
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     P = C.POINTER
     d, i32, i64 = C.c_double, C.c_int32, C.c_int64
@@ -85,6 +91,8 @@ def load():
         "sim_read_state": [C.c_void_p, P(d), P(d), P(sim_contact), i32, P(i32)],
         "sim_read_state_device": [C.c_void_p, C.c_void_p, C.c_void_p],
         "sim_destroy": [C.c_void_p],
+        "sim_save_state": [C.c_void_p],
+        "sim_restore_state": [C.c_void_p],
         "sim_create_batch": [i32, P(sim_mesh), P(sim_material), P(i32), P(P(sim_obstacle)), d,
                              P(sim_options), P(C.c_void_p)],
         "sim_batch_info": [C.c_void_p, P(i32), P(i32)],
@@ -277,6 +285,12 @@ class Sim:
             contacts = dict(node=np.zeros(0, np.int64), obst=np.zeros(0, np.int64),
                             frame=np.zeros((0, 3, 3)), lam=np.zeros((0, 3)), gap=np.zeros(0))
         return q, v, contacts
+
+    def save_state(self):
+        _check(_lib.sim_save_state(self.h))
+
+    def restore_state(self):
+        _check(_lib.sim_restore_state(self.h))
 
     def read_state_device(self, out_tensor, stream=None):
         """Copy positions (float32 [3][n], caller order) into a device tensor."""

@@ -296,14 +296,15 @@ def star_profile_mesh(seed: int, target=(19300, 19700), layers: int = 15, voxel:
 def teaser_scene(seed: int = 0, contacts: int = 800, model: int = MODEL_SNH, E: float = 1e6,
                  nu: float = 0.45, mu: float = 0.3, iters: int = 5, cr_iters: int = 10,
                  frames: int = 300, h: float = 0.01, split: int = 5,
-                 target=(19300, 19700)) -> Scene:
+                 target=(19300, 19700), drop_speed: float = 0.1) -> Scene:
     """Teaser-scale scene (~19.5k nodes, 58.5k DoFs).
 
-    A seeded extruded star lies on a slightly tilted seeded ground plane; the tip of
-    the +x arm is a pinned handle pulled at 0.5 m/s towards a gap between two seeded
-    static capped cylinders.  The plane offset is placed so that the collision
-    predicate (min of the signed distance at q_t and at the predicted state, compared
-    with the margin) selects exactly ``contacts`` nodes at frame 0.
+    A seeded extruded star moving down at ``drop_speed`` reaches a slightly tilted
+    seeded ground plane; the tip of the +x arm is a pinned handle pulled at 0.5 m/s
+    towards a gap between two seeded static capped cylinders.  The plane offset is
+    placed so that the collision predicate (min of the signed distance at q_t and at
+    the predicted state, compared with the margin) selects exactly ``contacts`` nodes
+    at frame 0.
     """
     rng = np.random.default_rng(1000 + seed)
     voxel = 0.01
@@ -313,14 +314,16 @@ def teaser_scene(seed: int = 0, contacts: int = 800, model: int = MODEL_SNH, E: 
     tilt = rng.uniform(-0.02, 0.02, size=2)
     nrm = np.array([tilt[0], tilt[1], 1.0])
     nrm /= np.linalg.norm(nrm)
-    # predicted state at rest: x + h^2 g; choose offset between the c-th and (c+1)-th
-    pred = rest + h * h * g
+    # predicted state x + h v + h^2 g; choose offset between the c-th and (c+1)-th
+    vel = np.zeros_like(rest)
+    vel[:, 2] = -drop_speed
+    pred = rest + h * vel + h * h * g
     s = np.sort(pred @ nrm)
     off = 0.5 * (s[contacts - 1] + s[contacts]) - margin
     ground = Obstacle.make(OBST_HALFSPACE, list(nrm * off) + list(nrm), mu)
     # handle: tip of the +x arm
     xmax = rest[:, 0].max()
-    handle = np.nonzero(rest[:, 0] > xmax - 0.06)[0].astype(np.int32)
+    handle = np.nonzero(rest[:, 0] > xmax - 0.03)[0].astype(np.int32)
     # two cylinders forming a gap ahead of the handle (vertical axes)
     ywidth = rest[:, 1].max() - rest[:, 1].min()
     gap = ywidth * rng.uniform(0.35, 0.5)
@@ -330,7 +333,7 @@ def teaser_scene(seed: int = 0, contacts: int = 800, model: int = MODEL_SNH, E: 
     cyl1 = Obstacle.make(OBST_CYLINDER, [cx, 0.5 * gap + rad, zlo, cx, 0.5 * gap + rad, zhi, rad], mu)
     cyl2 = Obstacle.make(OBST_CYLINDER, [cx, -0.5 * gap - rad, zlo, cx, -0.5 * gap - rad, zhi, rad], mu)
     return Scene("teaser", rest, tets, model, E, nu, 1000.0, h, g, [ground, cyl1, cyl2], margin,
-                 iters, cr_iters, frames, init_pos=rest.copy(),
+                 iters, cr_iters, frames, init_pos=rest.copy(), init_vel=vel,
                  pin_nodes=handle, pin_group=np.zeros(len(handle), np.int32),
                  pin_lin_vel=np.array([[0.5, 0.0, 0.0]]), pin_ang_vel=np.zeros((1, 3)),
                  pin_pivot=np.zeros((1, 3)))
