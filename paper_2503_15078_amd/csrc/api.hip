@@ -364,7 +364,7 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   TRY(s->alloc(d.pc_world, 3 * (size_t)CM));
   for (float** p : {&d.Om, &d.Et, &d.hv, &d.X, &d.F, &d.cr_x, &d.cr_r, &d.cr_p, &d.cr_Ar, &d.cr_Ap, &d.cr_Z})
     TRY(s->alloc(*p, 3 * (size_t)CM));
-  TRY(s->alloc(d.cr_prod, 3 * (size_t)CM));
+  TRY(s->alloc(d.cr_prod, (size_t)lg::cr_partial_floats(1024)));
   TRY(s->alloc(d.cr_sync, 4));
   TRY(s->alloc(d.t, 1));
   TRY(s->alloc(d.res, NS));
@@ -450,8 +450,9 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   std::vector<double> grp(9 * (size_t)d.G, 0.0);
   TRY(upload(s, d.grp, grp.data(), grp.size()));
   {
-    int want = 128;
-    if (const char* e = std::getenv("LGSIM_CR_BLOCKS")) want = std::max(1, std::atoi(e));
+    // enough blocks that each owns at most 256 contacts of the capacity; 32 by default
+    int want = std::max(32, (d.CMAX + 255) / 256);
+    if (const char* e = std::getenv("LGSIM_CR_BLOCKS")) want = std::max(want, std::atoi(e));
     s->cr_blocks = std::max(1, std::min(lg::cr_max_blocks(), want));
   }
   int per = (d.CMAX + s->cr_blocks - 1) / s->cr_blocks;

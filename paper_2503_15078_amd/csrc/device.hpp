@@ -116,5 +116,6 @@ void launch_integrate(const Dev& d, hipStream_t st);
 void launch_check_finite(const Dev& d, hipStream_t st);
 void launch_export_positions(const Dev& d, hipStream_t st, float* out);
 int cr_max_blocks();
+int cr_partial_floats(int blocks);
 
 }  // namespace lg

@@ -9,41 +9,31 @@
 // breakdown), then lambda += dlambda and F = h^2 C^T (Omega lambda) for the force
 // update of the global step.
 //
-// One persistent launch (cooperative, so all blocks are co-resident).  Each block owns
-// a contiguous range of contacts and keeps their rows of K in LDS when they fit.  The
-// blocks meet at a device-wide barrier (an agent-scope counter) twice per iteration:
-// once after publishing Z = C^T (Omega r) for the matrix-vector product, once after
-// publishing the per-contact terms of (r, Ar), (Ar, Ar) and (Ar, Ap).  (Ap, Ap) for
-// the next step follows from those by expanding Ap + = Ar + beta Ap, which saves the
-// third reduction of the textbook recurrence.  Scene sums run in a fixed order, so
-// the result is deterministic.
+// One persistent launch (cooperative, so all blocks are co-resident).  Each block owns a
+// contiguous range of contacts; its rows of K, its slices of x, r, p, Ar, Ap and the
+// gathered Z = C^T (Omega r) of the scenes it touches live in LDS.  Blocks meet at a
+// device-wide barrier (an agent-scope counter) twice per iteration: after publishing
+// their slice of Z, and after publishing per-scene partial sums of (r, Ar), (Ar, Ar),
+// (Ar, Ap).  (Ap, Ap) of the next step follows by expanding Ap+ = Ar + beta Ap.  Partial
+// sums are combined in block order, so results are deterministic.
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
 
 namespace lg {
 
-constexpr int kCrLdsFloats = 16384;  // 64 KB of K rows per block
-constexpr int kCrMaxRows = 256;
+constexpr int kCrKFloats = 20480;   // 80 KB of K rows per block
+constexpr int kCrZFloats = 3 * 2048;  // gathered Z of the touched scenes
+constexpr int kCrRows = 256;        // max contacts per block
+constexpr int kCrSlots = 3;         // partial sums per (block, scene slot)
 
 __device__ inline float wave_sum_cr(float v) {
   for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
   return v;
 }
 
-__device__ inline float block_sum_cr(float v, float* red) {
-  v = wave_sum_cr(v);
-  const int w = threadIdx.x / kWave;
-  __syncthreads();
-  if ((threadIdx.x & (kWave - 1)) == 0) red[w] = v;
-  __syncthreads();
-  float s = 0.0f;
-  for (int q = 0; q < kBlock / kWave; ++q) s += red[q];
-  return s;
-}
-
 // Device-wide barrier: the counter is zeroed by the contact kernel that precedes this
-// launch; barrier number b waits until all G blocks have arrived b+1 times.
+// launch; barrier number b waits until all G blocks have arrived b times.
 __device__ inline void grid_barrier(unsigned* ctr, unsigned target) {
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -53,15 +43,14 @@ __device__ inline void grid_barrier(unsigned* ctr, unsigned target) {
   __syncthreads();
 }
 
-struct CrRow {
-  int j, s, cs, cnt;
-  const float* K;  // row of K (LDS or global)
-};
-
 __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
-  __shared__ float red[kBlock / kWave];
-  __shared__ float Ks[kCrLdsFloats];
-  __shared__ float s_rAr[kCrMaxRows], s_ApAp[kCrMaxRows], s_sum[3][kCrMaxRows];
+  __shared__ float Ks[kCrKFloats];
+  __shared__ float Zs[kCrZFloats];
+  __shared__ float vx[3][kCrRows], vr[3][kCrRows], vp[3][kCrRows], vAr[3][kCrRows], vAp[3][kCrRows];
+  __shared__ float Cl[9][kCrRows], Oml[3][kCrRows], Etl[3][kCrRows];
+  __shared__ float prod[kCrSlots][kCrRows];
+  __shared__ float s_rAr[kCrRows], s_ApAp[kCrRows], s_sum[kCrSlots][kCrRows];
+  __shared__ int koffs[kCrRows + 1];
   const int c = d.k_off[d.NS] > d.KCAP ? 0 : min(d.n_contacts[0], d.CMAX);
   if (c == 0) return;  // uniform across the grid: no block reaches a barrier
   unsigned* ctr = reinterpret_cast<unsigned*>(d.cr_sync);
@@ -69,202 +58,240 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
   unsigned nbar = 0;
   const int per = (c + (int)G - 1) / (int)G;
   const int j0 = min(c, (int)blockIdx.x * per), j1 = min(c, j0 + per);
+  const int R = j1 - j0;
   const int CM = d.CMAX;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const float h2 = (float)(d.h * d.h);
-  float *x = d.cr_x, *r = d.cr_r, *p = d.cr_p, *Ar = d.cr_Ar, *Ap = d.cr_Ap, *Z = d.cr_Z;
-  float* prod = d.cr_prod;  // [3][CMAX]: (r,Ar), (Ar,Ar), (Ar,Ap) per contact
+  float* Zg = d.cr_Z;
+  float* part = d.cr_prod;  // [G][kCrRows][kCrSlots] partial sums per (block, scene slot)
+  // scenes touched by this block: [sfirst, slast]
+  const int sfirst = R > 0 ? d.c_scene[j0] : 0;
+  const int slast = R > 0 ? d.c_scene[j1 - 1] : -1;
+  const int zlo = R > 0 ? d.cs_off[sfirst] : 0;
+  const int zhi = R > 0 ? d.cs_off[slast + 1] : 0;
+  const bool z_in_lds = 3 * (zhi - zlo) <= kCrZFloats;
 
-  // stage this block's K rows in LDS when they fit
-  int need = 0;
-  for (int j = j0; j < j1; ++j) {
-    int s = d.c_scene[j];
-    need += d.cs_off[s + 1] - d.cs_off[s];
-  }
-  const bool in_lds = need <= kCrLdsFloats;
-  {
+  // ---- stage per-contact data and K rows
+  if (tid == 0) {
     int o = 0;
-    for (int j = j0; j < j1; ++j) {
-      int s = d.c_scene[j], cs = d.cs_off[s], cnt = d.cs_off[s + 1] - cs;
+    for (int t = 0; t < R; ++t) {
+      int s = d.c_scene[j0 + t];
+      koffs[t] = o;
+      o += d.cs_off[s + 1] - d.cs_off[s];
+    }
+    koffs[R] = o;
+  }
+  for (int t = tid; t < R; t += kBlock) {
+    int j = j0 + t;
+    for (int q = 0; q < 9; ++q) Cl[q][t] = d.cC[q * CM + j];
+    for (int q = 0; q < 3; ++q) {
+      Oml[q][t] = d.Om[q * CM + j];
+      Etl[q][t] = d.Et[q * CM + j];
+    }
+  }
+  __syncthreads();
+  const bool k_in_lds = koffs[R] <= kCrKFloats;
+  if (k_in_lds)
+    for (int t = 0; t < R; ++t) {
+      int j = j0 + t, s = d.c_scene[j], cs = d.cs_off[s], cnt = d.cs_off[s + 1] - cs;
       const float* src = d.K + d.k_off[s] + (int64_t)(j - cs) * cnt;
-      if (in_lds)
-        for (int k = threadIdx.x; k < cnt; k += kBlock) Ks[o + k] = src[k];
-      o += cnt;
-    }
-    __syncthreads();
-  }
-  auto row = [&](int j, int& o) {
-    CrRow rw;
-    rw.j = j;
-    rw.s = d.c_scene[j];
-    rw.cs = d.cs_off[rw.s];
-    rw.cnt = d.cs_off[rw.s + 1] - rw.cs;
-    rw.K = in_lds ? Ks + o : d.K + d.k_off[rw.s] + (int64_t)(j - rw.cs) * rw.cnt;
-    o += rw.cnt;
-    return rw;
-  };
-  auto cval = [&](int j, int rr, int q) { return d.cC[(rr * 3 + q) * CM + j]; };
-  // Y = sum_k K_jk V_k over the scene (block cooperative)
-  auto matvec = [&](const CrRow& rw, const float* V, float Y[3]) {
-    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
-    for (int k = threadIdx.x; k < rw.cnt; k += kBlock) {
-      float kv = rw.K[k];
-      a0 += kv * V[rw.cs + k];
-      a1 += kv * V[CM + rw.cs + k];
-      a2 += kv * V[2 * CM + rw.cs + k];
-    }
-    Y[0] = block_sum_cr(a0, red);
-    Y[1] = block_sum_cr(a1, red);
-    Y[2] = block_sum_cr(a2, red);
-  };
-  // out = Omega (C_j Y) + E~ v_j
-  auto applyM = [&](int j, const float Y[3], const float* v, float out[3]) {
-    for (int rr = 0; rr < 3; ++rr) {
-      float cy = cval(j, rr, 0) * Y[0] + cval(j, rr, 1) * Y[1] + cval(j, rr, 2) * Y[2];
-      out[rr] = d.Om[rr * CM + j] * cy + d.Et[rr * CM + j] * v[rr * CM + j];
-    }
-  };
-  auto setZ = [&](int j, const float* v) {
-    float ov[3];
-    for (int q = 0; q < 3; ++q) ov[q] = d.Om[q * CM + j] * v[q * CM + j];
-    for (int q = 0; q < 3; ++q) Z[q * CM + j] = cval(j, 0, q) * ov[0] + cval(j, 1, q) * ov[1] + cval(j, 2, q) * ov[2];
-  };
-  // sums of prod[t] over the scene of each owned contact, t < nt (reused across equal scenes)
-  auto scene_sums = [&](int nt) {
-    int prev = -1;
-    for (int j = j0; j < j1; ++j) {
-      int s = d.c_scene[j];
-      if (s != prev) {
-        int cs = d.cs_off[s], ce = d.cs_off[s + 1];
-        for (int t = 0; t < nt; ++t) {
-          float a = 0.0f;
-          for (int k = cs + (int)threadIdx.x; k < ce; k += kBlock) a += prod[t * CM + k];
-          float v = block_sum_cr(a, red);
-          if (threadIdx.x == 0)
-            for (int q = j; q < j1 && d.c_scene[q] == s; ++q) s_sum[t][q - j0] = v;
-        }
-        prev = s;
-      }
-    }
-    __syncthreads();
-  };
-
-  // ---- setup: r = rhs, x = 0
-  {
-    int o = 0;
-    for (int j = j0; j < j1; ++j) {
-      CrRow rw = row(j, o);
-      float Y[3];
-      matvec(rw, d.X, Y);  // X = C^T (Omega lambda): W Omega lambda term
-      if (threadIdx.x == 0) {
-        for (int rr = 0; rr < 3; ++rr) {
-          float cy = cval(j, rr, 0) * Y[0] + cval(j, rr, 1) * Y[1] + cval(j, rr, 2) * Y[2];
-          x[rr * CM + j] = 0.0f;
-          r[rr * CM + j] = (d.hv[rr * CM + j] - d.Om[rr * CM + j] * h2 * cy) / h2;
-        }
-        setZ(j, r);
-      }
-    }
-  }
-  grid_barrier(ctr, G * ++nbar);
-  // Ar = M r, p = r, Ap = Ar; (r, Ar), (Ap, Ap)
-  {
-    int o = 0;
-    for (int j = j0; j < j1; ++j) {
-      CrRow rw = row(j, o);
-      float Y[3];
-      matvec(rw, Z, Y);
-      if (threadIdx.x == 0) {
-        float out[3], pa = 0.0f, pb = 0.0f;
-        applyM(j, Y, r, out);
-        for (int rr = 0; rr < 3; ++rr) {
-          float rv = r[rr * CM + j];
-          Ar[rr * CM + j] = out[rr];
-          p[rr * CM + j] = rv;
-          Ap[rr * CM + j] = out[rr];
-          pa += rv * out[rr];
-          pb += out[rr] * out[rr];
-        }
-        prod[j] = pa;
-        prod[CM + j] = pb;
-      }
-    }
-  }
-  grid_barrier(ctr, G * ++nbar);
-  scene_sums(2);
-  if (threadIdx.x == 0)
-    for (int j = j0; j < j1; ++j) {
-      s_rAr[j - j0] = s_sum[0][j - j0];
-      s_ApAp[j - j0] = s_sum[1][j - j0];
+      for (int k = tid; k < cnt; k += kBlock) Ks[koffs[t] + k] = src[k];
     }
   __syncthreads();
 
-  for (int it = 0; it < d.cr_iters; ++it) {
-    // x += alpha p, r -= alpha Ap; publish Z = C^T (Omega r)
-    if (threadIdx.x == 0)
-      for (int j = j0; j < j1; ++j) {
-        float rAr = s_rAr[j - j0], ApAp = s_ApAp[j - j0];
-        if (ApAp != 0.0f && rAr != 0.0f) {
-          float alpha = rAr / ApAp;
-          for (int rr = 0; rr < 3; ++rr) {
-            x[rr * CM + j] += alpha * p[rr * CM + j];
-            r[rr * CM + j] -= alpha * Ap[rr * CM + j];
-          }
-        }
-        setZ(j, r);
+  // Y_t = sum_k K_jk V_k for every owned row t (one wavefront per row); V is the
+  // gathered vector (LDS when it fits, else global), indexed by contact.
+  auto matvec_rows = [&](const float* V, int vstride, int vbase, float Y[][kCrRows]) {
+    for (int t = wave; t < R; t += kBlock / kWave) {
+      int j = j0 + t, s = d.c_scene[j], cs = d.cs_off[s], cnt = d.cs_off[s + 1] - cs;
+      const float* Krow = k_in_lds ? Ks + koffs[t] : d.K + d.k_off[s] + (int64_t)(j - cs) * cnt;
+      float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+      for (int k = lane; k < cnt; k += kWave) {
+        float kv = Krow[k];
+        int idx = cs + k - vbase;
+        a0 += kv * V[idx];
+        a1 += kv * V[vstride + idx];
+        a2 += kv * V[2 * vstride + idx];
       }
-    grid_barrier(ctr, G * ++nbar);
-    // Ar = M r; per-contact (r, Ar), (Ar, Ar), (Ar, Ap)
-    {
-      int o = 0;
-      for (int j = j0; j < j1; ++j) {
-        CrRow rw = row(j, o);
-        float Y[3];
-        matvec(rw, Z, Y);
-        if (threadIdx.x == 0) {
-          float out[3], a = 0.0f, b = 0.0f, e = 0.0f;
-          applyM(j, Y, r, out);
-          for (int rr = 0; rr < 3; ++rr) {
-            Ar[rr * CM + j] = out[rr];
-            a += r[rr * CM + j] * out[rr];
-            b += out[rr] * out[rr];
-            e += out[rr] * Ap[rr * CM + j];
-          }
-          prod[j] = a;
-          prod[CM + j] = b;
-          prod[2 * CM + j] = e;
+      a0 = wave_sum_cr(a0);
+      a1 = wave_sum_cr(a1);
+      a2 = wave_sum_cr(a2);
+      if (lane == 0) {
+        Y[0][t] = a0;
+        Y[1][t] = a1;
+        Y[2][t] = a2;
+      }
+    }
+    __syncthreads();
+  };
+  // gather Z of the touched scenes into LDS after a barrier
+  auto gather_Z = [&]() {
+    if (z_in_lds) {
+      int n = zhi - zlo;
+      for (int k = tid; k < n; k += kBlock) {
+        Zs[k] = Zg[zlo + k];
+        Zs[n + k] = Zg[CM + zlo + k];
+        Zs[2 * n + k] = Zg[2 * CM + zlo + k];
+      }
+    }
+    __syncthreads();
+  };
+  auto matvec_Z = [&](float Y[][kCrRows]) {
+    if (z_in_lds) matvec_rows(Zs, zhi - zlo, zlo, Y);
+    else matvec_rows(Zg, CM, 0, Y);
+  };
+  // publish Z_j = C_j^T (Omega_j v_j) for owned contacts
+  auto publish_Z = [&](float v[][kCrRows]) {
+    for (int t = tid; t < R; t += kBlock) {
+      float ov[3] = {Oml[0][t] * v[0][t], Oml[1][t] * v[1][t], Oml[2][t] * v[2][t]};
+      for (int q = 0; q < 3; ++q) Zg[q * CM + j0 + t] = Cl[q][t] * ov[0] + Cl[3 + q][t] * ov[1] + Cl[6 + q][t] * ov[2];
+    }
+  };
+  // out = Omega (C Y) + E~ v (row t), in place into Y
+  auto applyM = [&](float Y[][kCrRows], float v[][kCrRows]) {
+    for (int t = tid; t < R; t += kBlock) {
+      float y[3] = {Y[0][t], Y[1][t], Y[2][t]};
+      for (int rr = 0; rr < 3; ++rr) {
+        float cy = Cl[3 * rr][t] * y[0] + Cl[3 * rr + 1][t] * y[1] + Cl[3 * rr + 2][t] * y[2];
+        Y[rr][t] = Oml[rr][t] * cy + Etl[rr][t] * v[rr][t];
+      }
+    }
+    __syncthreads();
+  };
+  // per-scene partial sums of prod[0..nt) over owned contacts -> global partials
+  auto publish_partials = [&](int nt) {
+    for (int slot = wave; slot <= slast - sfirst; slot += kBlock / kWave) {
+      int s = sfirst + slot;
+      int t0 = max(d.cs_off[s], j0) - j0, t1 = min(d.cs_off[s + 1], j1) - j0;
+      for (int q = 0; q < nt; ++q) {
+        float a = 0.0f;
+        for (int t = t0 + lane; t < t1; t += kWave) a += prod[q][t];
+        a = wave_sum_cr(a);
+        if (lane == 0) part[((int64_t)blockIdx.x * kCrRows + slot) * kCrSlots + q] = a;
+      }
+    }
+  };
+  // scene sums: for each touched scene, sum the partials of all blocks holding it
+  auto gather_sums = [&](int nt) {
+    for (int slot = wave; slot <= slast - sfirst; slot += kBlock / kWave) {
+      int s = sfirst + slot;
+      int b0 = d.cs_off[s] / per, b1 = (d.cs_off[s + 1] - 1) / per;
+      for (int q = 0; q < nt; ++q) {
+        float a = 0.0f;
+        for (int b = b0 + lane; b <= b1; b += kWave) {
+          int sb = d.c_scene[b * per];  // first scene of block b
+          a += part[((int64_t)b * kCrRows + (s - sb)) * kCrSlots + q];
+        }
+        a = wave_sum_cr(a);
+        if (lane == 0) {
+          int t0 = max(d.cs_off[s], j0) - j0, t1 = min(d.cs_off[s + 1], j1) - j0;
+          for (int t = t0; t < t1; ++t) s_sum[q][t] = a;
         }
       }
     }
-    grid_barrier(ctr, G * ++nbar);
-    scene_sums(3);
-    if (threadIdx.x == 0)
-      for (int j = j0; j < j1; ++j) {
-        float rAr = s_rAr[j - j0], ApAp = s_ApAp[j - j0];
-        if (ApAp != 0.0f && rAr != 0.0f) {  // a scene that broke down keeps its state
-          float rAr_new = s_sum[0][j - j0], ArAr = s_sum[1][j - j0], ArAp = s_sum[2][j - j0];
-          float beta = rAr_new / rAr;
-          for (int rr = 0; rr < 3; ++rr) {
-            p[rr * CM + j] = r[rr * CM + j] + beta * p[rr * CM + j];
-            Ap[rr * CM + j] = Ar[rr * CM + j] + beta * Ap[rr * CM + j];
-          }
-          s_rAr[j - j0] = rAr_new;
-          s_ApAp[j - j0] = ArAr + 2.0f * beta * ArAp + beta * beta * ApAp;
+    __syncthreads();
+  };
+
+  // ---- setup: r = (g - Omega h^2 W Omega lambda) / h^2, x = 0
+  {
+    float(*Y)[kCrRows] = vAr;
+    matvec_rows(d.X, CM, 0, Y);  // X = C^T (Omega lambda) from the contact kernel
+    for (int t = tid; t < R; t += kBlock) {
+      int j = j0 + t;
+      float y[3] = {Y[0][t], Y[1][t], Y[2][t]};
+      for (int rr = 0; rr < 3; ++rr) {
+        float cy = Cl[3 * rr][t] * y[0] + Cl[3 * rr + 1][t] * y[1] + Cl[3 * rr + 2][t] * y[2];
+        vx[rr][t] = 0.0f;
+        vr[rr][t] = (d.hv[rr * CM + j] - Oml[rr][t] * h2 * cy) / h2;
+      }
+    }
+    __syncthreads();
+    publish_Z(vr);
+  }
+  grid_barrier(ctr, G * ++nbar);
+  gather_Z();
+  matvec_Z(vAr);
+  applyM(vAr, vr);
+  for (int t = tid; t < R; t += kBlock) {
+    float a = 0.0f, b = 0.0f;
+    for (int rr = 0; rr < 3; ++rr) {
+      vp[rr][t] = vr[rr][t];
+      vAp[rr][t] = vAr[rr][t];
+      a += vr[rr][t] * vAr[rr][t];
+      b += vAr[rr][t] * vAr[rr][t];
+    }
+    prod[0][t] = a;
+    prod[1][t] = b;
+  }
+  __syncthreads();
+  publish_partials(2);
+  grid_barrier(ctr, G * ++nbar);
+  gather_sums(2);
+  for (int t = tid; t < R; t += kBlock) {
+    s_rAr[t] = s_sum[0][t];
+    s_ApAp[t] = s_sum[1][t];
+  }
+  __syncthreads();
+
+  for (int it = 0; it < d.cr_iters; ++it) {
+    // x += alpha p, r -= alpha Ap; publish Z of r
+    for (int t = tid; t < R; t += kBlock) {
+      float rAr = s_rAr[t], ApAp = s_ApAp[t];
+      if (ApAp != 0.0f && rAr != 0.0f) {
+        float alpha = rAr / ApAp;
+        for (int rr = 0; rr < 3; ++rr) {
+          vx[rr][t] += alpha * vp[rr][t];
+          vr[rr][t] -= alpha * vAp[rr][t];
         }
       }
+    }
+    __syncthreads();
+    publish_Z(vr);
+    grid_barrier(ctr, G * ++nbar);
+    gather_Z();
+    matvec_Z(vAr);
+    applyM(vAr, vr);
+    for (int t = tid; t < R; t += kBlock) {
+      float a = 0.0f, b = 0.0f, e = 0.0f;
+      for (int rr = 0; rr < 3; ++rr) {
+        a += vr[rr][t] * vAr[rr][t];
+        b += vAr[rr][t] * vAr[rr][t];
+        e += vAr[rr][t] * vAp[rr][t];
+      }
+      prod[0][t] = a;
+      prod[1][t] = b;
+      prod[2][t] = e;
+    }
+    __syncthreads();
+    publish_partials(3);
+    grid_barrier(ctr, G * ++nbar);
+    gather_sums(3);
+    for (int t = tid; t < R; t += kBlock) {
+      float rAr = s_rAr[t], ApAp = s_ApAp[t];
+      if (ApAp != 0.0f && rAr != 0.0f) {  // a scene that broke down keeps its state
+        float rAr_new = s_sum[0][t], ArAr = s_sum[1][t], ArAp = s_sum[2][t];
+        float beta = rAr_new / rAr;
+        for (int rr = 0; rr < 3; ++rr) {
+          vp[rr][t] = vr[rr][t] + beta * vp[rr][t];
+          vAp[rr][t] = vAr[rr][t] + beta * vAp[rr][t];
+        }
+        s_rAr[t] = rAr_new;
+        s_ApAp[t] = ArAr + 2.0f * beta * ArAp + beta * beta * ApAp;
+      }
+    }
     __syncthreads();
   }
   // lambda += dlambda; F = h^2 C^T (Omega lambda)
-  if (threadIdx.x == 0)
-    for (int j = j0; j < j1; ++j) {
-      float ol[3];
-      for (int rr = 0; rr < 3; ++rr) {
-        float l = d.lam[rr * CM + j] + x[rr * CM + j];
-        d.lam[rr * CM + j] = l;
-        ol[rr] = d.Om[rr * CM + j] * l;
-      }
-      for (int q = 0; q < 3; ++q)
-        d.F[q * CM + j] = h2 * (cval(j, 0, q) * ol[0] + cval(j, 1, q) * ol[1] + cval(j, 2, q) * ol[2]);
+  for (int t = tid; t < R; t += kBlock) {
+    int j = j0 + t;
+    float ol[3];
+    for (int rr = 0; rr < 3; ++rr) {
+      float l = d.lam[rr * CM + j] + vx[rr][t];
+      d.lam[rr * CM + j] = l;
+      ol[rr] = Oml[rr][t] * l;
     }
+    for (int q = 0; q < 3; ++q) d.F[q * CM + j] = h2 * (Cl[q][t] * ol[0] + Cl[3 + q][t] * ol[1] + Cl[6 + q][t] * ol[2]);
+  }
 }
 
 int cr_max_blocks() {
@@ -276,6 +303,8 @@ int cr_max_blocks() {
     return 1;
   return max(1, min(cus * max(per, 1), 1024));
 }
+
+int cr_partial_floats(int blocks) { return blocks * kCrRows * kCrSlots; }
 
 hipError_t launch_cr(const Dev& d, hipStream_t st, int cr_blocks) {
   Dev dd = d;
