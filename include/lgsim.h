@@ -87,12 +87,13 @@ typedef struct {
   double gravity[3];
   double pin_weight_scale; /* h^2 w_pin = 1e3 * scale * [A_n]_vv                */
   double contact_margin;   /* metres; contact iff min(sdf(q_t), sdf(q~)) < margin */
-  int32_t cr_iters;
+  int32_t cr_iters;        /* at most 1024                                        */
   int32_t warm;
   double ncp_tol;          /* metres */
   int32_t max_iters;
   int32_t max_contacts;
   void* hip_stream;
+  double cr_tol;           /* > 0: CR also stops once |r| <= cr_tol |r_0| (0: fixed count) */
 } sim_options;
 
 /* Obstacles (App. A: analytic contact partners).  geom by type:
@@ -139,6 +140,11 @@ int sim_options_default(sim_options* opt);
  * SIM_E_DEVICE. */
 int sim_create(const sim_mesh* mesh, const sim_material* mat, double h, const sim_options* opt,
                sim_t* out);
+
+/* Change the Conjugate Residual settings of the constraint solve (Sec. 6) between
+ * frames: at most cr_iters iterations (<= 1024), stopping early per scene once
+ * |r| <= cr_tol |r_0| when cr_tol > 0. */
+int sim_set_solver(sim_t s, int32_t cr_iters, double cr_tol);
 
 /* Replace the obstacle set (n >= 0; at most 64). */
 int sim_set_obstacles(sim_t s, int32_t n, const sim_obstacle* obs);

@@ -12,16 +12,21 @@ from __future__ import annotations
 import numpy as np
 
 
-def conjugate_residual(matvec, b, iters):
+def conjugate_residual(matvec, b, iters, tol=0.0):
+    """At most ``iters`` iterations; with tol > 0 also stop once |r| <= tol |b|
+    (checked before each iteration)."""
     x = np.zeros_like(b)
     r = b.copy()
     Ar = matvec(r)
     p = r.copy()
     Ap = Ar.copy()
     rAr = float(r @ Ar)
+    rr0 = float(b @ b)
     for _ in range(iters):
         ApAp = float(Ap @ Ap)
         if ApAp == 0.0 or rAr == 0.0:
+            break
+        if tol > 0.0 and float(r @ r) <= tol * tol * rr0:
             break
         alpha = rAr / ApAp
         x = x + alpha * p

@@ -207,7 +207,7 @@ class OracleSim:
     def H(self, fc, q):
         return np.einsum("jai,ji->ja", fc.C, q[fc.node])
 
-    def iterate(self, fc, q, lam, q_t, q_pred, t_next, cr="fixed", cr_iters=None):
+    def iterate(self, fc, q, lam, q_t, q_pred, t_next, cr="fixed", cr_iters=None, cr_tol=0.0):
         """One iteration of Algorithm 4; returns (q^{k+1}, lambda^{k+1}, info)."""
         h = self.h
         b = self.rhs(q, q_pred, t_next)
@@ -226,7 +226,7 @@ class OracleSim:
             dl = np.linalg.solve(Mmat, rhs.reshape(-1))
         else:
             its = self.cr_iters if cr_iters is None else cr_iters
-            dl = conjugate_residual(lambda x: Mmat @ x, rhs.reshape(-1), its)
+            dl = conjugate_residual(lambda x: Mmat @ x, rhs.reshape(-1), its, tol=cr_tol)
         lam_new = lam + dl.reshape(-1, 3)
         qn = self.solve(b + h * h * self.H_T(fc, Om * lam_new))
         info.update(ev)
@@ -261,7 +261,7 @@ class OracleSim:
         self.t += self.h
         self.prev = {(int(fc.node[j]), int(fc.obst[j])): fc.C[j].T @ lam[j] for j in range(fc.c)}
 
-    def step(self, frames=1, iters=None, tol=None, max_iters=200, cr="fixed"):
+    def step(self, frames=1, iters=None, tol=None, max_iters=200, cr="fixed", cr_iters=None, cr_tol=0.0):
         """Advance ``frames`` frames.  iters > 0: fixed count; iters == 0: until the NCP
         residual is <= tol or max_iters.  Returns per-frame stats."""
         iters = self.scene.iters if iters is None else iters
@@ -273,7 +273,8 @@ class OracleSim:
             k = 0
             res = None
             while True:
-                q, lam, _ = self.iterate(fc, q, lam, q_t, q_pred, t_next, cr=cr)
+                q, lam, _ = self.iterate(fc, q, lam, q_t, q_pred, t_next, cr=cr, cr_iters=cr_iters,
+                                         cr_tol=cr_tol)
                 k += 1
                 if iters > 0:
                     if k >= iters:

@@ -164,6 +164,7 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   d.h = hs[0].h;
   for (int c = 0; c < 3; ++c) d.g[c] = s->opt.gravity[c];
   d.cr_iters = s->opt.cr_iters;
+  d.cr_tol = (float)s->opt.cr_tol;
   d.warm = s->opt.warm;
   s->perm_caller.resize(N);
   s->iperm_caller.resize(N);
@@ -332,6 +333,7 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   TRY(s->alloc(d.lo, N));
   TRY(s->alloc(d.depth, N));
   TRY(s->alloc(d.chain_end, N));
+  TRY(s->alloc(d.frange, 2 * (size_t)N));
   TRY(s->alloc(d.scene_node0, NS + 1));
   TRY(s->alloc(d.scene_obst0, NS + 1));
   TRY(s->alloc(d.scene_margin, NS));
@@ -366,6 +368,7 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
     TRY(s->alloc(*p, 3 * (size_t)CM));
   TRY(s->alloc(d.cr_prod, (size_t)lg::cr_partial_floats(1024)));
   TRY(s->alloc(d.cr_sync, 4));
+  TRY(s->alloc(d.cr_active, lg::kMaxCrIters));
   TRY(s->alloc(d.t, 1));
   TRY(s->alloc(d.res, NS));
   TRY(s->alloc(d.bad, 4));
@@ -451,8 +454,9 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   TRY(upload(s, d.grp, grp.data(), grp.size()));
   {
     // enough blocks that each owns at most 256 contacts of the capacity; 32 by default
-    int want = std::max(32, (d.CMAX + 255) / 256);
-    if (const char* e = std::getenv("LGSIM_CR_BLOCKS")) want = std::max(want, std::atoi(e));
+    const int need = (d.CMAX + 255) / 256;
+    int want = std::max(32, need);
+    if (const char* e = std::getenv("LGSIM_CR_BLOCKS")) want = std::max(need, std::atoi(e));
     s->cr_blocks = std::max(1, std::min(lg::cr_max_blocks(), want));
   }
   int per = (d.CMAX + s->cr_blocks - 1) / s->cr_blocks;
@@ -505,6 +509,7 @@ int frame_setup(lgsim* s) {
   lg::launch_collide(d, s->st);
   lg::launch_delassus(d, s->st);
   lg::launch_warm_start(d, s->st, 0);
+  lg::launch_force_ranges(d, s->st);
   s->iter_c = -1;  // known after the next synchronisation
   return check_launch("frame setup");
 }
@@ -693,7 +698,8 @@ int create_common(int32_t count, const sim_mesh* meshes, const sim_material* mat
     delete s;
     return rc;
   };
-  if (s->opt.cr_iters < 0 || s->opt.max_contacts <= 0 || s->opt.max_iters <= 0 || !(s->opt.ncp_tol > 0.0) ||
+  if (s->opt.cr_iters < 0 || s->opt.cr_iters > lg::kMaxCrIters || !(s->opt.cr_tol >= 0.0) ||
+      s->opt.max_contacts <= 0 || s->opt.max_iters <= 0 || !(s->opt.ncp_tol > 0.0) ||
       s->opt.warm < 0 || s->opt.warm > 2 || !(s->opt.contact_margin >= 0.0)) {
     lg::set_error("bad options");
     return fail(SIM_E_ARG);
@@ -753,6 +759,7 @@ int sim_options_default(sim_options* o) {
   o->pin_weight_scale = 1.0;
   o->contact_margin = 0.0;
   o->cr_iters = 10;
+  o->cr_tol = 0.0;
   o->warm = SIM_WARM_PREV;
   o->ncp_tol = 1e-6;
   o->max_iters = 200;
@@ -815,6 +822,18 @@ int sim_set_obstacles(sim_t s, int32_t n, const sim_obstacle* obs) {
   }
   s->scene_obst0 = {0, n};
   return push_obstacles(s);
+}
+
+int sim_set_solver(sim_t s, int32_t cr_iters, double cr_tol) {
+  if (!s || cr_iters < 0 || cr_iters > lg::kMaxCrIters || !(cr_tol >= 0.0)) {
+    lg::set_error("bad solver settings");
+    return SIM_E_ARG;
+  }
+  s->opt.cr_iters = cr_iters;
+  s->opt.cr_tol = cr_tol;
+  s->d.cr_iters = cr_iters;
+  s->d.cr_tol = (float)cr_tol;
+  return SIM_OK;
 }
 
 int sim_set_pin_motion(sim_t s, int32_t n_groups, const double* lin, const double* ang, const double* pivot) {
@@ -1072,6 +1091,7 @@ int sim_set_iterate_state(sim_t s, const double* q_t, const double* v_t, const d
   if (c > 0) {
     lg::launch_delassus(d, s->st);
     lg::launch_warm_start(d, s->st, 1);
+    lg::launch_force_ranges(d, s->st);
   }
   TRY(check_launch("iterate state"));
   HIPCHK(hipMemcpyAsync(s->h_pinned + 1, d.overflow, sizeof(int), hipMemcpyDeviceToHost, s->st));

@@ -17,6 +17,7 @@ constexpr int kWave = 64;
 constexpr int kMaxObstacles = 64;
 constexpr int kDelTile = 16;      // Delassus tile (contacts x contacts)
 constexpr int kDelChunk = 64;     // Delassus depth chunk staged in LDS
+constexpr int kMaxCrIters = 1024;
 
 struct ObstacleDev {
   int type;
@@ -63,6 +64,7 @@ struct Dev {
   int64_t *col_ptr;
   float *col_val;
   int *parent, *lo, *depth, *chain_end;
+  int *frange;                     // [2][N] per-row contact range of the frame
   // scenes
   int *scene_node0;                // [NS+1]
   int *scene_obst0;                // [NS+1]
@@ -91,6 +93,8 @@ struct Dev {
   float *Om, *Et, *hv, *X, *F;     // hv: h_vec - Omega H u (delta form)
   float *cr_x, *cr_r, *cr_p, *cr_Ar, *cr_Ap, *cr_Z, *cr_prod;  // prod: [3][CMAX]
   int *cr_sync;                    // device-wide barrier counter of the CR launch
+  int *cr_active;                  // [kMaxCrIters] blocks with a running scene, per iteration
+  float cr_tol;                    // relative CR residual tolerance (0: fixed count)
   // frame state
   double *t;                       // [1] simulation time at frame start
   float *res;                      // [NS] NCP residual per scene
@@ -111,6 +115,7 @@ void launch_spmv_St(const Dev& d, hipStream_t st, const float* y, const float* b
 void launch_contact_prep(const Dev& d, hipStream_t st);
 hipError_t launch_cr(const Dev& d, hipStream_t st, int cr_blocks);
 void launch_apply_forces(const Dev& d, hipStream_t st);
+void launch_force_ranges(const Dev& d, hipStream_t st);
 void launch_residual(const Dev& d, hipStream_t st);
 void launch_integrate(const Dev& d, hipStream_t st);
 void launch_check_finite(const Dev& d, hipStream_t st);

@@ -5,9 +5,11 @@
 //   g = h_vec - Omega H u (delta form, from the contact kernel),
 //   W_(j,k) = K_jk C_j C_k^T (Sec. 5.3), E~ = diag(E_n/h^2, E_f/h, E_f/h),
 //
-// per scene, from dlambda = 0, for cr_iters iterations (stopping only on exact
-// breakdown), then lambda += dlambda and F = h^2 C^T (Omega lambda) for the force
-// update of the global step.
+// per scene, from dlambda = 0, for at most cr_iters iterations, stopping a scene on
+// exact breakdown or, when cr_tol > 0, once |r| <= cr_tol |r_0|; then lambda += dlambda
+// and F = h^2 C^T (Omega lambda) for the force update of the global step.  The launch
+// ends early when no scene is left running (a decision every block takes from the same
+// device counter read after a barrier).
 //
 // One persistent launch (cooperative, so all blocks are co-resident).  Each block owns a
 // contiguous range of contacts; its rows of K, its slices of x, r, p, Ar, Ap and the
@@ -25,7 +27,8 @@ namespace lg {
 constexpr int kCrKFloats = 20480;   // 80 KB of K rows per block
 constexpr int kCrZFloats = 3 * 2048;  // gathered Z of the touched scenes
 constexpr int kCrRows = 256;        // max contacts per block
-constexpr int kCrSlots = 3;         // partial sums per (block, scene slot)
+constexpr int kCrSlots = 4;         // partial sums per (block, scene slot)
+constexpr int kCrMaxBlocks = 1024;
 
 __device__ inline float wave_sum_cr(float v) {
   for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -49,8 +52,12 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
   __shared__ float vx[3][kCrRows], vr[3][kCrRows], vp[3][kCrRows], vAr[3][kCrRows], vAp[3][kCrRows];
   __shared__ float Cl[9][kCrRows], Oml[3][kCrRows], Etl[3][kCrRows];
   __shared__ float prod[kCrSlots][kCrRows];
-  __shared__ float s_rAr[kCrRows], s_ApAp[kCrRows], s_sum[kCrSlots][kCrRows];
+  __shared__ float s_rAr[kCrRows], s_ApAp[kCrRows], s_rr[kCrRows], s_rr0[kCrRows], s_sum[kCrSlots][kCrRows];
+  __shared__ bool s_live[kCrRows];
+  __shared__ bool s_go;
   __shared__ int koffs[kCrRows + 1];
+  __shared__ int sl_cs[kCrRows + 1], sl_ce[kCrRows + 1];  // contact range of each touched scene
+  __shared__ int bfirst[kCrMaxBlocks];                     // first scene of every block
   const int c = d.k_off[d.NS] > d.KCAP ? 0 : min(d.n_contacts[0], d.CMAX);
   if (c == 0) return;  // uniform across the grid: no block reaches a barrier
   unsigned* ctr = reinterpret_cast<unsigned*>(d.cr_sync);
@@ -81,6 +88,11 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
     }
     koffs[R] = o;
   }
+  for (int slot = tid; slot <= slast - sfirst; slot += kBlock) {
+    sl_cs[slot] = d.cs_off[sfirst + slot];
+    sl_ce[slot] = d.cs_off[sfirst + slot + 1];
+  }
+  for (int b = tid; b < (int)G; b += kBlock) bfirst[b] = b * per < c ? d.c_scene[b * per] : 0;
   for (int t = tid; t < R; t += kBlock) {
     int j = j0 + t;
     for (int q = 0; q < 9; ++q) Cl[q][t] = d.cC[q * CM + j];
@@ -161,31 +173,32 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
   // per-scene partial sums of prod[0..nt) over owned contacts -> global partials
   auto publish_partials = [&](int nt) {
     for (int slot = wave; slot <= slast - sfirst; slot += kBlock / kWave) {
-      int s = sfirst + slot;
-      int t0 = max(d.cs_off[s], j0) - j0, t1 = min(d.cs_off[s + 1], j1) - j0;
+      int t0 = max(sl_cs[slot], j0) - j0, t1 = min(sl_ce[slot], j1) - j0;
+      float a[kCrSlots] = {0.0f, 0.0f, 0.0f, 0.0f};
+      for (int t = t0 + lane; t < t1; t += kWave)
+        for (int q = 0; q < nt; ++q) a[q] += prod[q][t];
       for (int q = 0; q < nt; ++q) {
-        float a = 0.0f;
-        for (int t = t0 + lane; t < t1; t += kWave) a += prod[q][t];
-        a = wave_sum_cr(a);
-        if (lane == 0) part[((int64_t)blockIdx.x * kCrRows + slot) * kCrSlots + q] = a;
+        float v = wave_sum_cr(a[q]);
+        if (lane == 0) part[((int64_t)blockIdx.x * kCrRows + slot) * kCrSlots + q] = v;
       }
     }
   };
-  // scene sums: for each touched scene, sum the partials of all blocks holding it
+  // scene sums: for each touched scene, sum the partials of all blocks holding it, in
+  // block order
   auto gather_sums = [&](int nt) {
     for (int slot = wave; slot <= slast - sfirst; slot += kBlock / kWave) {
       int s = sfirst + slot;
-      int b0 = d.cs_off[s] / per, b1 = (d.cs_off[s + 1] - 1) / per;
+      int b0 = sl_cs[slot] / per, b1 = (sl_ce[slot] - 1) / per;
+      float a[kCrSlots] = {0.0f, 0.0f, 0.0f, 0.0f};
+      for (int b = b0 + lane; b <= b1; b += kWave) {
+        const float* pp = part + ((int64_t)b * kCrRows + (s - bfirst[b])) * kCrSlots;
+        for (int q = 0; q < nt; ++q) a[q] += pp[q];
+      }
       for (int q = 0; q < nt; ++q) {
-        float a = 0.0f;
-        for (int b = b0 + lane; b <= b1; b += kWave) {
-          int sb = d.c_scene[b * per];  // first scene of block b
-          a += part[((int64_t)b * kCrRows + (s - sb)) * kCrSlots + q];
-        }
-        a = wave_sum_cr(a);
+        float v = wave_sum_cr(a[q]);
         if (lane == 0) {
-          int t0 = max(d.cs_off[s], j0) - j0, t1 = min(d.cs_off[s + 1], j1) - j0;
-          for (int t = t0; t < t1; ++t) s_sum[q][t] = a;
+          int t0 = max(sl_cs[slot], j0) - j0, t1 = min(sl_ce[slot], j1) - j0;
+          for (int t = t0; t < t1; ++t) s_sum[q][t] = v;
         }
       }
     }
@@ -213,31 +226,38 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
   matvec_Z(vAr);
   applyM(vAr, vr);
   for (int t = tid; t < R; t += kBlock) {
-    float a = 0.0f, b = 0.0f;
+    float a = 0.0f, b = 0.0f, e = 0.0f;
     for (int rr = 0; rr < 3; ++rr) {
       vp[rr][t] = vr[rr][t];
       vAp[rr][t] = vAr[rr][t];
       a += vr[rr][t] * vAr[rr][t];
       b += vAr[rr][t] * vAr[rr][t];
+      e += vr[rr][t] * vr[rr][t];
     }
     prod[0][t] = a;
     prod[1][t] = b;
+    prod[2][t] = e;
   }
   __syncthreads();
-  publish_partials(2);
+  publish_partials(3);
   grid_barrier(ctr, G * ++nbar);
-  gather_sums(2);
+  gather_sums(3);
   for (int t = tid; t < R; t += kBlock) {
     s_rAr[t] = s_sum[0][t];
     s_ApAp[t] = s_sum[1][t];
+    s_rr[t] = s_sum[2][t];
+    s_rr0[t] = s_sum[2][t];
   }
   __syncthreads();
 
+  const float tol2 = d.cr_tol * d.cr_tol;
   for (int it = 0; it < d.cr_iters; ++it) {
-    // x += alpha p, r -= alpha Ap; publish Z of r
+    // a scene is finished after exact breakdown or once |r| <= tol |r0|
     for (int t = tid; t < R; t += kBlock) {
       float rAr = s_rAr[t], ApAp = s_ApAp[t];
-      if (ApAp != 0.0f && rAr != 0.0f) {
+      bool live = ApAp != 0.0f && rAr != 0.0f && !(tol2 > 0.0f && s_rr[t] <= tol2 * s_rr0[t]);
+      s_live[t] = live;
+      if (live) {
         float alpha = rAr / ApAp;
         for (int rr = 0; rr < 3; ++rr) {
           vx[rr][t] += alpha * vp[rr][t];
@@ -247,28 +267,40 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
     }
     __syncthreads();
     publish_Z(vr);
+    // count blocks with a live scene; read after the barrier, so every block takes the
+    // same decision to stop
+    if (tid == 0) {
+      bool any = false;
+      for (int t = 0; t < R; ++t) any |= s_live[t];
+      if (any) __hip_atomic_fetch_add(d.cr_active + it, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     grid_barrier(ctr, G * ++nbar);
+    if (tid == 0) s_go = __hip_atomic_load(d.cr_active + it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0;
+    __syncthreads();
+    if (!s_go) break;
     gather_Z();
     matvec_Z(vAr);
     applyM(vAr, vr);
     for (int t = tid; t < R; t += kBlock) {
-      float a = 0.0f, b = 0.0f, e = 0.0f;
+      float a = 0.0f, b = 0.0f, e = 0.0f, f = 0.0f;
       for (int rr = 0; rr < 3; ++rr) {
         a += vr[rr][t] * vAr[rr][t];
         b += vAr[rr][t] * vAr[rr][t];
         e += vAr[rr][t] * vAp[rr][t];
+        f += vr[rr][t] * vr[rr][t];
       }
       prod[0][t] = a;
       prod[1][t] = b;
       prod[2][t] = e;
+      prod[3][t] = f;
     }
     __syncthreads();
-    publish_partials(3);
+    publish_partials(4);
     grid_barrier(ctr, G * ++nbar);
-    gather_sums(3);
+    gather_sums(4);
     for (int t = tid; t < R; t += kBlock) {
-      float rAr = s_rAr[t], ApAp = s_ApAp[t];
-      if (ApAp != 0.0f && rAr != 0.0f) {  // a scene that broke down keeps its state
+      if (s_live[t]) {
+        float rAr = s_rAr[t], ApAp = s_ApAp[t];
         float rAr_new = s_sum[0][t], ArAr = s_sum[1][t], ArAp = s_sum[2][t];
         float beta = rAr_new / rAr;
         for (int rr = 0; rr < 3; ++rr) {
@@ -277,6 +309,7 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
         }
         s_rAr[t] = rAr_new;
         s_ApAp[t] = ArAr + 2.0f * beta * ArAp + beta * beta * ApAp;
+        s_rr[t] = s_sum[3][t];
       }
     }
     __syncthreads();

@@ -129,50 +129,49 @@ __device__ inline int lower_bound_i(const int* a, int n, int key) {
   return lo;
 }
 
-// One wavefront per 64 consecutive rows: each lane finds its row's contact range, then
-// the wavefront serves the rows with a non-empty range one after another.
-__global__ void __launch_bounds__(kBlock) k_apply_forces(Dev d) {
+// Per frame: the contact range [cb, ce) of every row (contacts are sorted by node).
+__global__ void k_force_ranges(Dev d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.N) return;
   const int c = min(d.n_contacts[0], d.CMAX);
-  if (c == 0) return;
-  const int wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  d.frange[i] = lower_bound_i(d.c_node, c, d.lo[i]);
+  d.frange[d.N + i] = lower_bound_i(d.c_node, c, i + 1);
+}
+
+void launch_force_ranges(const Dev& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_force_ranges, dim3((d.N + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d);
+}
+
+// One wavefront per row; rows without contacts in their subtree exit at once.
+__global__ void __launch_bounds__(kBlock) k_apply_forces(Dev d) {
+  const int i = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
   const int lane = threadIdx.x & (kWave - 1);
-  const int i0 = wave * kWave;
-  if (i0 >= d.N) return;
-  const int mine = i0 + lane;
-  int cb = 0, ce = 0;
-  if (mine < d.N) {
-    cb = lower_bound_i(d.c_node, c, d.lo[mine]);
-    ce = lower_bound_i(d.c_node, c, mine + 1);
+  if (i >= d.N) return;
+  const int cb = __builtin_amdgcn_readfirstlane(d.frange[i]);
+  const int ce = __builtin_amdgcn_readfirstlane(d.frange[d.N + i]);
+  if (cb >= ce) return;
+  const float* row = d.row_val + d.row_ptr[i];
+  const int lo4 = d.row_lo4[i];
+  float ax = 0.0f, ay = 0.0f, az = 0.0f;
+  for (int k = cb + lane; k < ce; k += kWave) {
+    float s = row[d.c_node[k] - lo4];
+    ax += s * d.F[k];
+    ay += s * d.F[d.CMAX + k];
+    az += s * d.F[2 * d.CMAX + k];
   }
-  unsigned long long todo = __ballot(cb < ce);
-  while (todo) {
-    const int r = __ffsll(todo) - 1;
-    todo &= todo - 1;
-    const int i = i0 + r;
-    const int b = __shfl(cb, r, kWave), e = __shfl(ce, r, kWave);
-    const float* row = d.row_val + d.row_ptr[i];
-    const int lo4 = d.row_lo4[i];
-    float ax = 0.0f, ay = 0.0f, az = 0.0f;
-    for (int k = b + lane; k < e; k += kWave) {
-      float s = row[d.c_node[k] - lo4];
-      ax += s * d.F[k];
-      ay += s * d.F[d.CMAX + k];
-      az += s * d.F[2 * d.CMAX + k];
-    }
-    ax = wave_sum(ax);
-    ay = wave_sum(ay);
-    az = wave_sum(az);
-    if (lane == 0) {
-      d.y[i] += ax;
-      d.y[d.N4 + i] += ay;
-      d.y[2 * d.N4 + i] += az;
-    }
+  ax = wave_sum(ax);
+  ay = wave_sum(ay);
+  az = wave_sum(az);
+  if (lane == 0) {
+    d.y[i] += ax;
+    d.y[d.N4 + i] += ay;
+    d.y[2 * d.N4 + i] += az;
   }
 }
 
 void launch_apply_forces(const Dev& d, hipStream_t st) {
-  int rows_per_block = kBlock;  // 4 wavefronts x 64 rows
-  hipLaunchKernelGGL(k_apply_forces, dim3((d.N + rows_per_block - 1) / rows_per_block), dim3(kBlock), 0, st, d);
+  int waves_per_block = kBlock / kWave;
+  hipLaunchKernelGGL(k_apply_forces, dim3((d.N + waves_per_block - 1) / waves_per_block), dim3(kBlock), 0, st, d);
 }
 
 }  // namespace lg

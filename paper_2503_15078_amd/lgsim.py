@@ -45,7 +45,7 @@ class sim_options(C.Structure):
     _fields_ = [("gravity", C.c_double * 3), ("pin_weight_scale", C.c_double),
                 ("contact_margin", C.c_double), ("cr_iters", C.c_int32), ("warm", C.c_int32),
                 ("ncp_tol", C.c_double), ("max_iters", C.c_int32), ("max_contacts", C.c_int32),
-                ("hip_stream", C.c_void_p)]
+                ("hip_stream", C.c_void_p), ("cr_tol", C.c_double)]
 
 
 class sim_obstacle(C.Structure):
@@ -91,6 +91,7 @@ def load():
         "sim_read_state": [C.c_void_p, P(d), P(d), P(sim_contact), i32, P(i32)],
         "sim_read_state_device": [C.c_void_p, C.c_void_p, C.c_void_p],
         "sim_destroy": [C.c_void_p],
+        "sim_set_solver": [C.c_void_p, i32, d],
         "sim_save_state": [C.c_void_p],
         "sim_restore_state": [C.c_void_p],
         "sim_create_batch": [i32, P(sim_mesh), P(sim_material), P(i32), P(P(sim_obstacle)), d,
@@ -285,6 +286,9 @@ class Sim:
             contacts = dict(node=np.zeros(0, np.int64), obst=np.zeros(0, np.int64),
                             frame=np.zeros((0, 3, 3)), lam=np.zeros((0, 3)), gap=np.zeros(0))
         return q, v, contacts
+
+    def set_solver(self, cr_iters, cr_tol=0.0):
+        _check(_lib.sim_set_solver(self.h, int(cr_iters), float(cr_tol)))
 
     def save_state(self):
         _check(_lib.sim_save_state(self.h))

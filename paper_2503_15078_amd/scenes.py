@@ -311,14 +311,31 @@ def teaser_scene(seed: int = 0, contacts: int = 800, model: int = MODEL_SNH, E: 
     rest, tets = star_profile_mesh(seed, target=target, voxel=voxel, split=split)
     margin = 0.25 * voxel
     g = np.array([0.0, 0.0, -9.81])
-    tilt = rng.uniform(-0.02, 0.02, size=2)
-    nrm = np.array([tilt[0], tilt[1], 1.0])
-    nrm /= np.linalg.norm(nrm)
-    # predicted state x + h v + h^2 g; choose offset between the c-th and (c+1)-th
+    # predicted state x + h v + h^2 g; the plane offset lies between the c-th and
+    # (c+1)-th lowest predicted node, and the tilt (seeded direction) is sized so that
+    # the selected nodes span margin + h |v|: the lowest node then just touches the
+    # plane at q_t and the predicted state penetrates by up to h |v|
     vel = np.zeros_like(rest)
     vel[:, 2] = -drop_speed
     pred = rest + h * vel + h * h * g
-    s = np.sort(pred @ nrm)
+    ang = rng.uniform(0.0, 2.0 * math.pi)
+    want = margin + h * drop_speed
+
+    def plane(mag):
+        nv = np.array([mag * math.cos(ang), mag * math.sin(ang), 1.0])
+        nv /= np.linalg.norm(nv)
+        sv = np.sort(pred @ nv)
+        return nv, sv
+
+    lo, hi = 0.0, 0.5
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        _, sv = plane(mid)
+        if sv[contacts - 1] - sv[0] < want:
+            lo = mid
+        else:
+            hi = mid
+    nrm, s = plane(hi)
     off = 0.5 * (s[contacts - 1] + s[contacts]) - margin
     ground = Obstacle.make(OBST_HALFSPACE, list(nrm * off) + list(nrm), mu)
     # handle: tip of the +x arm

@@ -47,6 +47,25 @@ def iterate_pair(sim_factory, scene, q_t, v_t, q_k, t, node, obst, lam, k=1, cr=
     fc = o.contacts_from_keys(node, obst, q_t)
     q, lo = q_k.copy(), lam.copy()
     for _ in range(k):
-        q, lo, _ = o.iterate(fc, q, lo, q_t, q_pred, t + o.h, cr=cr)
+        q, lo, info = o.iterate(fc, q, lo, q_t, q_pred, t + o.h, cr=cr)
+    o.last_info = info
     sim.close()
     return qg, lg, q, lo, o, fc
+
+
+def impulse_rounding_bound(o, lam_scale, ops=1):
+    """First-order bound on the impulse error that float32 evaluation of the constraint
+    right-hand side (h - Omega H u) / h^2 causes in the last oracle iteration: each of its
+    two terms carries `ops` float32 roundings of relative size u = 2^-24 (storing it), and
+    the solve propagates it by |M^-1| componentwise.  The terms cancel (they are large next
+    to their difference at first impact), which is what makes this bound exceed 1e-4."""
+    info = getattr(o, "last_info", None)
+    if not info or "cr_matrix" not in info:
+        return 0.0
+    h2 = o.h * o.h
+    M = info["cr_matrix"]
+    hv = info["hvec"].reshape(-1)
+    rhs = info["cr_rhs"]
+    om_hu = hv - h2 * rhs                           # Omega H u, recovered from rhs
+    d = ops * 2.0 ** -24 * (np.abs(hv) + np.abs(om_hu)) / h2
+    return float((np.abs(np.linalg.inv(M)) @ d).max() / lam_scale)

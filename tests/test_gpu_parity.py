@@ -2,7 +2,9 @@
 
 Tolerances (per iteration, same float32-representable input state on both sides):
 positions ||dq||_inf / ||q_oracle||_inf <= 1e-5; impulses
-||dl||_inf / max(||l_oracle||_inf, 1e-3 m_total |g|) <= 1e-4.  Contact lists are
+||dl||_inf / max(||l_oracle||_inf, 1e-3 m_total |g|) <= max(1e-4, B), where B is the
+first-order float32 rounding bound of the constraint right-hand side propagated through
+the constraint system (tests.parity_util.impulse_rounding_bound).  Contact lists are
 compared bit for bit (the oracle evaluates the contact predicate in float64 on the
 GPU's own float32 state)."""
 import numpy as np
@@ -11,7 +13,7 @@ import pytest
 from oracle import fem
 from oracle.sim import OracleSim
 from paper_2503_15078_amd import lgsim, scenes
-from tests.parity_util import f32, iterate_pair, oracle_state_after, rel_inf
+from tests.parity_util import f32, impulse_rounding_bound, iterate_pair, oracle_state_after, rel_inf
 
 pytestmark = pytest.mark.gpu
 
@@ -120,7 +122,8 @@ def test_one_iteration_with_contacts(frames):
                                             cr="exact", gpu_cr_iters=100)
     assert rel_inf(qg, qo) <= 1e-5
     lam_scale = max(np.abs(lo).max(), 1e-3 * o2.mass.sum() * 9.81)
-    assert rel_inf(lg_, lo, lam_scale) <= 1e-4, rel_inf(lg_, lo, lam_scale)
+    bound = max(1e-4, impulse_rounding_bound(o2, lam_scale))
+    assert rel_inf(lg_, lo, lam_scale) <= bound, (rel_inf(lg_, lo, lam_scale), bound)
 
 
 def test_contact_list_bit_exact_over_frames():
@@ -184,9 +187,45 @@ def test_teaser_contacts_and_iteration():
     lam = np.zeros((len(node), 3))
     q_k = o.predict(q_t, v_t)
     qg, lg_, qo, lo, o2, fc2 = iterate_pair(make_sim, sc, q_t, v_t, q_k, 0.0, node, obst, lam, k=1)
+    lam_scale = max(np.abs(lo).max(), 1e-3 * o2.mass.sum() * 9.81)
+    print(f"paper-mode gaps: positions {rel_inf(qg, qo):.2e} impulses {rel_inf(lg_, lo, lam_scale):.2e}")
+    # converged constraint solve on both sides
+    qg, lg_, qo, lo, o2, fc2 = iterate_pair(make_sim, sc, q_t, v_t, q_k, 0.0, node, obst, lam, k=1,
+                                            cr="exact", gpu_cr_iters=1000)
     assert rel_inf(qg, qo) <= 1e-5
     lam_scale = max(np.abs(lo).max(), 1e-3 * o2.mass.sum() * 9.81)
-    print(f"paper-mode impulse gap {rel_inf(lg_, lo, lam_scale):.2e}")
+    bound = max(1e-4, impulse_rounding_bound(o2, lam_scale))
+    assert rel_inf(lg_, lo, lam_scale) <= bound, (rel_inf(lg_, lo, lam_scale), bound)
+
+
+def test_frames_to_tolerance_judged_by_oracle():
+    """Frames iterated until the GPU's NCP residual is <= 1e-6 m (CR to a relative
+    residual of 1e-4, at most 200 local-global iterations).  The oracle's float64
+    residual of the GPU's final state and impulses confirms every reported residual;
+    frames that end at the iteration cap are the impact frames, on which the oracle's own
+    iteration (with an exact constraint solve) does not reach 1e-6 in 200 iterations
+    either."""
+    sc = scenes.cube_drop(3)
+    sim = make_sim(sc, cr_iters=300, cr_tol=1e-4)
+    o = OracleSim(sc)
+    converged = capped = 0
+    for f in range(25):
+        q0, v0, _ = sim.read_state()
+        st = sim.step(1, iters=0)[0]
+        q1, v1, con = sim.read_state()
+        if st["contacts"] == 0:
+            continue
+        fc = o.contacts_from_keys(con["node"], con["obst"], q0)
+        res = o.residual(fc, q1, q0, con["lam"])
+        if st["ncp"] <= 1e-6:
+            assert res <= 2e-6, (f, res, st)
+            converged += 1
+        else:
+            assert st["iters"] == 200, (f, st)
+            assert abs(res - st["ncp"]) <= 1e-7 + 0.05 * res, (f, res, st)
+            capped += 1
+    assert converged >= 10 and capped <= 6, (converged, capped)
+    sim.close()
 
 
 def test_batch_equals_single_scenes():
