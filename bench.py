@@ -76,6 +76,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--tol-frames", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cr-variant", type=int, default=0, choices=[0, 1],
+                    help="form of the CR iteration: 0 textbook (two exchanges per step), 1 pipelined (one)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the benchmark, run a plain float32 copy of 256 MiB three times "
+                         "(reference kernel for scaling the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; a scene batch is the unit of work and "
@@ -95,7 +100,7 @@ def main():
     nnz_s = hp.nnz_S
     del hp
     log(f"n={sc.n} m={sc.m} nnz(S)={nnz_s}; creating solver")
-    sim = lgsim.Sim(sc)
+    sim = lgsim.Sim(sc, cr_variant=args.cr_variant)
     sim.save_state()
 
     def frame(stats=True, iters=ITERS):
@@ -135,7 +140,7 @@ def main():
     log("to-tolerance frames")
     # iterate until the NCP residual is <= 1e-6 m; the constraint solve runs CR to a
     # relative residual of TOL_CR (at most TOL_CR_ITERS iterations) instead of 10
-    sim.set_solver(TOL_CR_ITERS, TOL_CR)
+    sim.set_solver(TOL_CR_ITERS, TOL_CR, args.cr_variant)
     tol = []
     for _ in range(args.tol_frames):
         sim.restore_state()
@@ -163,15 +168,24 @@ def main():
                                 f"stable Neo-Hookean E=1e6 nu=0.45, h=0.01 s, {contacts} contacts, "
                                 f"{ITERS} L-G iterations/frame, 10 CR iterations; one step = one frame"),
                    "nodes": sc.n, "tets": sc.m, "contacts": contacts, "nnz_S": nnz_s,
-                   "iters_per_frame": ITERS},
+                   "iters_per_frame": ITERS, "cr_variant": ["textbook", "pipelined"][args.cr_variant]},
         "phases_ms_per_launch": phase_ms,
-        "ms_per_frame_to_ncp_1e-6": round(float(np.median([t[0] for t in tol])), 3),
+        "ms_per_frame_to_ncp_1e-6": round(float(np.median([t[0] for t in tol])), 3) if tol else None,
         "to_tolerance_solver": f"CR to relative residual {TOL_CR} (at most {TOL_CR_ITERS} iterations)",
         "iters_to_ncp_1e-6": [int(t[1]) for t in tol],
         "ncp_res_reached": [float(t[2]) for t in tol],
         "paper_context_ms_per_iter": PAPER_MS_PER_ITER,
         "roofline": roofline,
     }
+    if args.copy_probe:
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.neg(a, out=b)
+        torch.cuda.synchronize()
+        out["copy_probe"] = {"kernel": "torch neg (elementwise)", "read_bytes": 4 * a.numel(),
+                             "write_bytes": 4 * a.numel()}
+        del a, b
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(sc)

@@ -94,7 +94,17 @@ typedef struct {
   int32_t max_contacts;
   void* hip_stream;
   double cr_tol;           /* > 0: CR also stops once |r| <= cr_tol |r_0| (0: fixed count) */
+  int32_t cr_variant;      /* SIM_CR_TEXTBOOK (default) or SIM_CR_PIPELINED */
 } sim_options;
+
+/* Forms of the Conjugate Residual iteration; both give the same iterates in exact
+ * arithmetic.  TEXTBOOK exchanges data between the solver's blocks twice per step
+ * (the residual, then the inner products) and reaches float32 accuracy when run to
+ * convergence.  PIPELINED carries M r and M p by recurrence, with M r replaced by its
+ * true value after every exchange, and exchanges once per step: about half the
+ * synchronisation, with a relative accuracy floor near 1e-4 of the solution when run
+ * to convergence (fine for a fixed handful of steps or a loose tolerance). */
+enum { SIM_CR_TEXTBOOK = 0, SIM_CR_PIPELINED = 1 };
 
 /* Obstacles (App. A: analytic contact partners).  geom by type:
  *   HALFSPACE [px,py,pz, nx,ny,nz]        solid where n.(x-p) < 0
@@ -143,8 +153,8 @@ int sim_create(const sim_mesh* mesh, const sim_material* mat, double h, const si
 
 /* Change the Conjugate Residual settings of the constraint solve (Sec. 6) between
  * frames: at most cr_iters iterations (<= 1024), stopping early per scene once
- * |r| <= cr_tol |r_0| when cr_tol > 0. */
-int sim_set_solver(sim_t s, int32_t cr_iters, double cr_tol);
+ * |r| <= cr_tol |r_0| when cr_tol > 0, in the form cr_variant (SIM_CR_*). */
+int sim_set_solver(sim_t s, int32_t cr_iters, double cr_tol, int32_t cr_variant);
 
 /* Replace the obstacle set (n >= 0; at most 64). */
 int sim_set_obstacles(sim_t s, int32_t n, const sim_obstacle* obs);

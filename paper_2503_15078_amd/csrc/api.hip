@@ -364,11 +364,12 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   TRY(s->alloc(d.pc_node, CM));
   TRY(s->alloc(d.pc_obst, CM));
   TRY(s->alloc(d.pc_world, 3 * (size_t)CM));
-  for (float** p : {&d.Om, &d.Et, &d.hv, &d.X, &d.F, &d.cr_x, &d.cr_r, &d.cr_p, &d.cr_Ar, &d.cr_Ap, &d.cr_Z})
+  for (float** p : {&d.Om, &d.Et, &d.hv, &d.X, &d.F})
     TRY(s->alloc(*p, 3 * (size_t)CM));
-  TRY(s->alloc(d.cr_prod, (size_t)lg::cr_partial_floats(1024)));
-  TRY(s->alloc(d.cr_sync, 4));
-  TRY(s->alloc(d.cr_active, lg::kMaxCrIters));
+  // two exchange buffers alternating per barrier, each with up to two 3-vectors
+  TRY(s->alloc(d.cr_Z, 2 * 2 * 3 * (size_t)CM));
+  TRY(s->alloc(d.cr_prod, (size_t)lg::cr_partial_floats(lg::kCrMaxBlocks, std::max(1, NS))));
+  TRY(s->alloc(d.cr_sync, lg::kCrMaxBarriers + 1));
   TRY(s->alloc(d.t, 1));
   TRY(s->alloc(d.res, NS));
   TRY(s->alloc(d.bad, 4));
@@ -453,9 +454,11 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   std::vector<double> grp(9 * (size_t)d.G, 0.0);
   TRY(upload(s, d.grp, grp.data(), grp.size()));
   {
-    // enough blocks that each owns at most 256 contacts of the capacity; 32 by default
+    // enough blocks that each owns at most 256 contacts of the capacity; 64 by default
+    // (fastest of 8..128 on 800 contacts: fewer blocks lengthen the per-block matvec,
+    // more lengthen the device-wide barrier)
     const int need = (d.CMAX + 255) / 256;
-    int want = std::max(32, need);
+    int want = std::max(64, need);
     if (const char* e = std::getenv("LGSIM_CR_BLOCKS")) want = std::max(need, std::atoi(e));
     s->cr_blocks = std::max(1, std::min(lg::cr_max_blocks(), want));
   }
@@ -544,7 +547,7 @@ int iteration(lgsim* s, bool timed, int it) {
   if (s->iter_c != 0) {
     lg::launch_contact_prep(d, s->st);
     rec(3);
-    cr_err = lg::launch_cr(d, s->st, s->cr_blocks);
+    cr_err = lg::launch_cr(d, s->st, s->cr_blocks, s->opt.cr_variant);
     lg::launch_apply_forces(d, s->st);
     rec(4);
   } else {
@@ -614,9 +617,15 @@ int frame_status(lgsim* s) {
   auto& d = s->d;
   HIPCHK(hipMemcpyAsync(s->h_pinned, d.n_contacts, sizeof(int), hipMemcpyDeviceToHost, s->st));
   HIPCHK(hipMemcpyAsync(s->h_pinned + 1, d.overflow, sizeof(int), hipMemcpyDeviceToHost, s->st));
-  HIPCHK(hipMemcpyAsync(s->h_pinned + 2, d.bad, sizeof(int), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipMemcpyAsync(s->h_pinned + 2, d.bad, 2 * sizeof(int), hipMemcpyDeviceToHost, s->st));
   HIPCHK(hipStreamSynchronize(s->st));
   s->iter_c = s->h_pinned[0];
+  if (s->h_pinned[3]) {
+    TRY(clear_flag(s, d.bad));
+    TRY(clear_flag(s, d.bad + 1));
+    lg::set_error("constraint solver blocks were not all resident (device busy with other work); frame rolled back");
+    return SIM_E_DEVICE;
+  }
   if (s->h_pinned[1]) {
     TRY(clear_flag(s, d.overflow));
     lg::set_error("contact capacity exceeded: " + std::to_string(s->h_pinned[0]) + " contacts, max_contacts " +
@@ -699,6 +708,7 @@ int create_common(int32_t count, const sim_mesh* meshes, const sim_material* mat
     return rc;
   };
   if (s->opt.cr_iters < 0 || s->opt.cr_iters > lg::kMaxCrIters || !(s->opt.cr_tol >= 0.0) ||
+      (s->opt.cr_variant != SIM_CR_TEXTBOOK && s->opt.cr_variant != SIM_CR_PIPELINED) ||
       s->opt.max_contacts <= 0 || s->opt.max_iters <= 0 || !(s->opt.ncp_tol > 0.0) ||
       s->opt.warm < 0 || s->opt.warm > 2 || !(s->opt.contact_margin >= 0.0)) {
     lg::set_error("bad options");
@@ -760,6 +770,7 @@ int sim_options_default(sim_options* o) {
   o->contact_margin = 0.0;
   o->cr_iters = 10;
   o->cr_tol = 0.0;
+  o->cr_variant = SIM_CR_TEXTBOOK;
   o->warm = SIM_WARM_PREV;
   o->ncp_tol = 1e-6;
   o->max_iters = 200;
@@ -824,13 +835,15 @@ int sim_set_obstacles(sim_t s, int32_t n, const sim_obstacle* obs) {
   return push_obstacles(s);
 }
 
-int sim_set_solver(sim_t s, int32_t cr_iters, double cr_tol) {
-  if (!s || cr_iters < 0 || cr_iters > lg::kMaxCrIters || !(cr_tol >= 0.0)) {
+int sim_set_solver(sim_t s, int32_t cr_iters, double cr_tol, int32_t cr_variant) {
+  if (!s || cr_iters < 0 || cr_iters > lg::kMaxCrIters || !(cr_tol >= 0.0) ||
+      (cr_variant != SIM_CR_TEXTBOOK && cr_variant != SIM_CR_PIPELINED)) {
     lg::set_error("bad solver settings");
     return SIM_E_ARG;
   }
   s->opt.cr_iters = cr_iters;
   s->opt.cr_tol = cr_tol;
+  s->opt.cr_variant = cr_variant;
   s->d.cr_iters = cr_iters;
   s->d.cr_tol = (float)cr_tol;
   return SIM_OK;

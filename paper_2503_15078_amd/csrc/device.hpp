@@ -18,6 +18,8 @@ constexpr int kMaxObstacles = 64;
 constexpr int kDelTile = 16;      // Delassus tile (contacts x contacts)
 constexpr int kDelChunk = 64;     // Delassus depth chunk staged in LDS
 constexpr int kMaxCrIters = 1024;
+constexpr int kCrMaxBlocks = 1024;  // blocks of the CR launch (partial sums)
+constexpr int kCrMaxBarriers = 2 * kMaxCrIters + 2;  // device-wide barriers of one CR launch
 
 struct ObstacleDev {
   int type;
@@ -91,14 +93,14 @@ struct Dev {
   float *pc_world;                 // [3][CMAX]
   // iteration scratch [3][CMAX] each
   float *Om, *Et, *hv, *X, *F;     // hv: h_vec - Omega H u (delta form)
-  float *cr_x, *cr_r, *cr_p, *cr_Ar, *cr_Ap, *cr_Z, *cr_prod;  // prod: [3][CMAX]
-  int *cr_sync;                    // device-wide barrier counter of the CR launch
-  int *cr_active;                  // [kMaxCrIters] blocks with a running scene, per iteration
+  float *cr_Z;                     // [2][2][3][CMAX] exchanged C^T (Omega v) of the CR launch
+  float *cr_prod;                  // per-(block, scene slot) partial sums of the CR launch
+  unsigned *cr_sync;               // [kCrMaxBarriers + 1] arrival counters of the CR launch
   float cr_tol;                    // relative CR residual tolerance (0: fixed count)
   // frame state
   double *t;                       // [1] simulation time at frame start
   float *res;                      // [NS] NCP residual per scene
-  int *bad;                        // [1] non-finite flag
+  int *bad;                        // [0] frame invalid (non-finite state or [1]); [1] CR barrier abandoned
 };
 
 // kernels (launch helpers live in the .hip files)
@@ -113,7 +115,7 @@ void launch_gather(const Dev& d, hipStream_t st);
 void launch_spmv_S(const Dev& d, hipStream_t st, const float* b, float* y);
 void launch_spmv_St(const Dev& d, hipStream_t st, const float* y, const float* base, float* u);
 void launch_contact_prep(const Dev& d, hipStream_t st);
-hipError_t launch_cr(const Dev& d, hipStream_t st, int cr_blocks);
+hipError_t launch_cr(const Dev& d, hipStream_t st, int cr_blocks, int variant);  // variant: SIM_CR_*
 void launch_apply_forces(const Dev& d, hipStream_t st);
 void launch_force_ranges(const Dev& d, hipStream_t st);
 void launch_residual(const Dev& d, hipStream_t st);
@@ -121,6 +123,6 @@ void launch_integrate(const Dev& d, hipStream_t st);
 void launch_check_finite(const Dev& d, hipStream_t st);
 void launch_export_positions(const Dev& d, hipStream_t st, float* out);
 int cr_max_blocks();
-int cr_partial_floats(int blocks);
+int64_t cr_partial_floats(int blocks, int scenes);
 
 }  // namespace lg

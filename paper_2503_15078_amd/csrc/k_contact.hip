@@ -528,10 +528,8 @@ __global__ void __launch_bounds__(kBlock) k_contact_prep(Dev d) {
   const int j = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
   const int lane = threadIdx.x & (kWave - 1);
   const int c = min(d.n_contacts[0], d.CMAX);
-  if (blockIdx.x == 0) {  // counters of the CR launch that follows
-    if (threadIdx.x == 0) d.cr_sync[0] = 0;
-    for (int k = threadIdx.x; k < min(d.cr_iters, kMaxCrIters); k += blockDim.x) d.cr_active[k] = 0;
-  }
+  if (blockIdx.x == 0)  // barrier counters of the CR launch that follows
+    for (int k = threadIdx.x; k <= min(2 * d.cr_iters + 2, kCrMaxBarriers); k += blockDim.x) d.cr_sync[k] = 0u;
   if (j >= c) return;
   const int v = d.c_node[j];
   const float* col = d.col_val + d.col_ptr[v];

@@ -1,66 +1,118 @@
 // Conjugate Residual solve of the Schur system of the constrained global step
 // (Sec. 5.2, Eq. saddle point with the sign of Algorithms 3 and 4; solver per Sec. 6):
 //
-//   (Omega W Omega + E~) dlambda = (g - Omega h^2 W Omega lambda) / h^2,
+//   M dlambda = (g - Omega h^2 W Omega lambda) / h^2,   M = Omega W Omega + E~,
 //   g = h_vec - Omega H u (delta form, from the contact kernel),
 //   W_(j,k) = K_jk C_j C_k^T (Sec. 5.3), E~ = diag(E_n/h^2, E_f/h, E_f/h),
 //
 // per scene, from dlambda = 0, for at most cr_iters iterations, stopping a scene on
 // exact breakdown or, when cr_tol > 0, once |r| <= cr_tol |r_0|; then lambda += dlambda
-// and F = h^2 C^T (Omega lambda) for the force update of the global step.  The launch
-// ends early when no scene is left running (a decision every block takes from the same
-// device counter read after a barrier).
+// and F = h^2 C^T (Omega lambda) for the force update of the global step.
 //
-// One persistent launch (cooperative, so all blocks are co-resident).  Each block owns a
-// contiguous range of contacts; its rows of K, its slices of x, r, p, Ar, Ap and the
-// gathered Z = C^T (Omega r) of the scenes it touches live in LDS.  Blocks meet at a
-// device-wide barrier (an agent-scope counter) twice per iteration: after publishing
-// their slice of Z, and after publishing per-scene partial sums of (r, Ar), (Ar, Ar),
-// (Ar, Ap).  (Ap, Ap) of the next step follows by expanding Ap+ = Ar + beta Ap.  Partial
-// sums are combined in block order, so results are deterministic.
+// Two forms of CR, the same iterates in exact arithmetic (x, r, p, q = M p, w = M r):
+//  - textbook (variant 0): per step, exchange r, compute w = M r, exchange the inner
+//    products (r, w), (w, w), (w, q), (r, r); two exchanges between blocks per step.
+//  - pipelined (variant 1): also carry z = M q by recurrence and update w -= alpha z,
+//    so that the products of the next step, M w~ (for z = M w~ + beta z) and the inner
+//    products, need a single exchange.  r is exchanged with it and w is then replaced
+//    by the true M r, which keeps the recurrence error to one step (without that
+//    replacement float32 CR stalls far from convergence).
+// In both, (q, q) of the next step follows by expanding q+ = w + beta q.
+//
+// One persistent launch.  Its grid never exceeds the number of compute units and its
+// LDS allows one block per CU, so on a device that runs nothing else all blocks are
+// resident together (kernels on one stream run one after another).  The wait at a
+// barrier is bounded: a block that waits too long marks the frame failed (the frame is
+// then rolled back and the host reports a device error) and every block leaves.  Each
+// block owns a contiguous range of contacts; its rows of K, its slices of the vectors and
+// the gathered Z = C^T (Omega v) of the scenes it touches live in LDS, every row and
+// every scene's slice padded to a multiple of 4 floats so the products run on float4.  Blocks publish their slices
+// of Z and per-scene partial sums, then meet the others at a device-wide barrier (an
+// agent-scope arrival counter per barrier).  Exchange buffers alternate with the barrier's
+// parity, since a block may publish step k+1 while another still reads step k.  Partial
+// sums are combined in block order, so results are deterministic.  The launch ends early
+// when no block has a running scene, a decision every block reads from the same counter.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "device.hpp"
 
 namespace lg {
 
-constexpr int kCrKFloats = 20480;   // 80 KB of K rows per block
-constexpr int kCrZFloats = 3 * 2048;  // gathered Z of the touched scenes
-constexpr int kCrRows = 256;        // max contacts per block
-constexpr int kCrSlots = 4;         // partial sums per (block, scene slot)
-constexpr int kCrMaxBlocks = 1024;
+constexpr int kCrKFloats = 20480;     // 80 KB of (padded) K rows per block
+constexpr int kCrZFloats = 3 * 2048;  // gathered (padded) Z of the touched scenes
+constexpr int kCrRows = 256;          // max contacts per block
+constexpr int kCrSlots = 4;           // partial sums per (block, scene slot)
+constexpr unsigned kCrSpinLimit = 1u << 21;  // polls before a barrier wait is abandoned
 
 __device__ inline float wave_sum_cr(float v) {
   for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
   return v;
 }
-
-// Device-wide barrier: the counter is zeroed by the contact kernel that precedes this
-// launch; barrier number b waits until all G blocks have arrived b times.
-__device__ inline void grid_barrier(unsigned* ctr, unsigned target) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) __builtin_amdgcn_s_sleep(1);
+__device__ inline int pad4(int n) { return (n + 3) & ~3; }
+// largest i in [0, n) with a[i] <= e (a ascending, a[0] <= e)
+__device__ inline int slot_of(const int* a, int n, int e) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (a[mid] <= e) lo = mid;
+    else hi = mid - 1;
   }
-  __syncthreads();
+  return lo;
 }
 
+// Device-wide barrier number b (b = 1, 2, ...), one arrival counter per barrier number,
+// zeroed by the contact kernel that precedes the launch.  Thread 0 of a block adds 1,
+// plus 2^16 while the block still has a running scene, with an agent-scope release
+// (after the block barrier, so the block's global writes are published); it leaves once
+// the low 16 bits reach G and acquires.  The high bits then hold the same live count in
+// every block.  Returns 1 (some block live), 0 (none) or -1 (the wait was abandoned;
+// the failure flags are set).
+__device__ inline int grid_barrier(unsigned* ctrs, unsigned b, bool live, int* s_st, int* fail) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned* ctr = ctrs + b;
+    __hip_atomic_fetch_add(ctr, live ? 0x10001u : 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned v, polls = 0;
+    while (((v = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) & 0xFFFFu) < gridDim.x &&
+           ++polls < kCrSpinLimit)
+      __builtin_amdgcn_s_sleep(1);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if ((v & 0xFFFFu) < gridDim.x) {
+      __hip_atomic_store(fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);      // frame not valid
+      __hip_atomic_store(fail + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // cause: CR barrier
+      *s_st = -1;
+    } else {
+      *s_st = (v >> 16) != 0u ? 1 : 0;
+    }
+  }
+  __syncthreads();
+  return *s_st;
+}
+
+template <int V>
 __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
-  __shared__ float Ks[kCrKFloats];
-  __shared__ float Zs[kCrZFloats];
-  __shared__ float vx[3][kCrRows], vr[3][kCrRows], vp[3][kCrRows], vAr[3][kCrRows], vAp[3][kCrRows];
+  constexpr int NZ = V == 0 ? 1 : 2;  // vectors exchanged per step
+  __shared__ __align__(16) float Ks[kCrKFloats];
+  __shared__ __align__(16) float Zs[kCrZFloats];
+  __shared__ float vx[3][kCrRows], vr[3][kCrRows], vp[3][kCrRows], vw[3][kCrRows], vq[3][kCrRows],
+      vn[3][kCrRows];
+  __shared__ float vz[V == 0 ? 1 : 3][V == 0 ? 1 : kCrRows], vm[V == 0 ? 1 : 3][V == 0 ? 1 : kCrRows];
   __shared__ float Cl[9][kCrRows], Oml[3][kCrRows], Etl[3][kCrRows];
-  __shared__ float prod[kCrSlots][kCrRows];
-  __shared__ float s_rAr[kCrRows], s_ApAp[kCrRows], s_rr[kCrRows], s_rr0[kCrRows], s_sum[kCrSlots][kCrRows];
+  __shared__ float prod[kCrSlots][kCrRows];  // per-row products; after a barrier, scene sums
+  __shared__ float s_g[kCrRows], s_qq[kCrRows], s_rr[kCrRows], s_rr0[kCrRows];
   __shared__ bool s_live[kCrRows];
-  __shared__ bool s_go;
-  __shared__ int koffs[kCrRows + 1];
-  __shared__ int sl_cs[kCrRows + 1], sl_ce[kCrRows + 1];  // contact range of each touched scene
-  __shared__ int bfirst[kCrMaxBlocks];                     // first scene of every block
+  __shared__ int s_st;
+  // per touched scene slot: contact range, K offset in global memory, first padded row
+  // in Ks, first padded contact in Zs (both prefix sums, with the totals at index nsl)
+  __shared__ int sl_cs[kCrRows + 1], sl_ce[kCrRows + 1], sl_koff[kCrRows + 1], sl_kb[kCrRows + 1],
+      sl_zb[kCrRows + 1];
+  __shared__ int row_slot[kCrRows];
   const int c = d.k_off[d.NS] > d.KCAP ? 0 : min(d.n_contacts[0], d.CMAX);
   if (c == 0) return;  // uniform across the grid: no block reaches a barrier
-  unsigned* ctr = reinterpret_cast<unsigned*>(d.cr_sync);
+  unsigned* ctrs = d.cr_sync;
+  int* fail = d.bad;  // [0]: frame invalid, [1]: the CR barrier was abandoned
   const unsigned G = gridDim.x;
   unsigned nbar = 0;
   const int per = (c + (int)G - 1) / (int)G;
@@ -69,32 +121,21 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
   const int CM = d.CMAX;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const float h2 = (float)(d.h * d.h);
-  float* Zg = d.cr_Z;
-  float* part = d.cr_prod;  // [G][kCrRows][kCrSlots] partial sums per (block, scene slot)
-  // scenes touched by this block: [sfirst, slast]
+  const int64_t part_half = (int64_t)d.NS * G * kCrSlots;  // partials [2][scene][block][slot]
+  // scenes touched by this block: [sfirst, sfirst + nsl)
   const int sfirst = R > 0 ? d.c_scene[j0] : 0;
-  const int slast = R > 0 ? d.c_scene[j1 - 1] : -1;
-  const int zlo = R > 0 ? d.cs_off[sfirst] : 0;
-  const int zhi = R > 0 ? d.cs_off[slast + 1] : 0;
-  const bool z_in_lds = 3 * (zhi - zlo) <= kCrZFloats;
+  const int nsl = R > 0 ? d.c_scene[j1 - 1] - sfirst + 1 : 0;
 
-  // ---- stage per-contact data and K rows
-  if (tid == 0) {
-    int o = 0;
-    for (int t = 0; t < R; ++t) {
-      int s = d.c_scene[j0 + t];
-      koffs[t] = o;
-      o += d.cs_off[s + 1] - d.cs_off[s];
-    }
-    koffs[R] = o;
+  // ---- stage per-contact data, slot tables and K rows
+  for (int sl = tid; sl < nsl; sl += kBlock) {
+    const int s = sfirst + sl;
+    sl_cs[sl] = d.cs_off[s];
+    sl_ce[sl] = d.cs_off[s + 1];
+    sl_koff[sl] = d.k_off[s];
   }
-  for (int slot = tid; slot <= slast - sfirst; slot += kBlock) {
-    sl_cs[slot] = d.cs_off[sfirst + slot];
-    sl_ce[slot] = d.cs_off[sfirst + slot + 1];
-  }
-  for (int b = tid; b < (int)G; b += kBlock) bfirst[b] = b * per < c ? d.c_scene[b * per] : 0;
   for (int t = tid; t < R; t += kBlock) {
     int j = j0 + t;
+    row_slot[t] = d.c_scene[j] - sfirst;
     for (int q = 0; q < 9; ++q) Cl[q][t] = d.cC[q * CM + j];
     for (int q = 0; q < 3; ++q) {
       Oml[q][t] = d.Om[q * CM + j];
@@ -102,65 +143,194 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
     }
   }
   __syncthreads();
-  const bool k_in_lds = koffs[R] <= kCrKFloats;
-  if (k_in_lds)
-    for (int t = 0; t < R; ++t) {
-      int j = j0 + t, s = d.c_scene[j], cs = d.cs_off[s], cnt = d.cs_off[s + 1] - cs;
-      const float* src = d.K + d.k_off[s] + (int64_t)(j - cs) * cnt;
-      for (int k = tid; k < cnt; k += kBlock) Ks[koffs[t] + k] = src[k];
+  if (wave == 0) {  // exclusive prefix sums of the padded K rows and Z slices per slot
+    int ck = 0, cz = 0;
+    for (int base = 0; base < nsl; base += kWave) {
+      const int sl = base + lane;
+      int nk = 0, nz = 0;
+      if (sl < nsl) {
+        const int cnt = sl_ce[sl] - sl_cs[sl];
+        const int rows = min(sl_ce[sl], j1) - max(sl_cs[sl], j0);
+        nk = rows * pad4(cnt);
+        nz = pad4(cnt);
+      }
+      int vk = nk, vz2 = nz;
+      for (int o = 1; o < kWave; o <<= 1) {
+        int uk = __shfl_up(vk, o, kWave), uz = __shfl_up(vz2, o, kWave);
+        if (lane >= o) {
+          vk += uk;
+          vz2 += uz;
+        }
+      }
+      if (sl < nsl) {
+        sl_kb[sl] = ck + vk - nk;
+        sl_zb[sl] = cz + vz2 - nz;
+      }
+      ck += __shfl(vk, kWave - 1, kWave);
+      cz += __shfl(vz2, kWave - 1, kWave);
     }
+    if (lane == 0) {
+      sl_kb[nsl] = ck;
+      sl_zb[nsl] = cz;
+    }
+  }
   __syncthreads();
+  const bool k_in_lds = sl_kb[nsl] <= kCrKFloats;
+  const int zpad = sl_zb[nsl];
+  const bool z_in_lds = 3 * NZ * zpad <= kCrZFloats;
+  if (k_in_lds && nsl == 1) {
+    // one scene: the block's rows are contiguous in K; eight loads in flight per thread
+    const int cs = sl_cs[0], cnt = sl_ce[0] - cs, pc = pad4(cnt), total = R * cnt;
+    const float* src = d.K + sl_koff[0] + (int64_t)(j0 - cs) * cnt;
+    const float inv = 1.0f / (float)cnt;
+    for (int base = 0; base < total; base += 8 * kBlock) {
+      float v[8];
+      int di[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = base + tid + u * kBlock;
+        int r = (int)((float)e * inv), k = e - r * cnt;
+        if (k >= cnt) {
+          ++r;
+          k -= cnt;
+        } else if (k < 0) {
+          --r;
+          k += cnt;
+        }
+        di[u] = r * pc + k;
+        v[u] = e < total ? src[e] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (base + tid + u * kBlock < total) Ks[di[u]] = v[u];
+    }
+    for (int e = tid; e < R * (pc - cnt); e += kBlock) Ks[(e / (pc - cnt)) * pc + cnt + e % (pc - cnt)] = 0.0f;
+  } else if (k_in_lds) {
+    // padded element e of Ks: slot, row within the slot, column; pads are zero
+    const int total = sl_kb[nsl];
+    for (int e = tid; e < total; e += kBlock) {
+      const int sl = slot_of(sl_kb, nsl, e);
+      const int cnt = sl_ce[sl] - sl_cs[sl], pc = pad4(cnt);
+      const int off = e - sl_kb[sl], r = off / pc, k = off - r * pc;
+      const int j = max(sl_cs[sl], j0) + r;
+      Ks[e] = k < cnt ? d.K[sl_koff[sl] + (int64_t)(j - sl_cs[sl]) * cnt + k] : 0.0f;
+    }
+  }
 
-  // Y_t = sum_k K_jk V_k for every owned row t (one wavefront per row); V is the
-  // gathered vector (LDS when it fits, else global), indexed by contact.
-  auto matvec_rows = [&](const float* V, int vstride, int vbase, float Y[][kCrRows]) {
+  // copy components [0, 3 nv) of the touched scenes' contacts (component q of contact k
+  // at Vg[q CM + k]) into Zs, slot by slot at the padded offsets; pads are zero.  No
+  // block barrier.
+  auto stage = [&](const float* Vg, int nv) {
+    if (nsl == 1) {  // one scene: all loads of a round issued before the stores
+      const int cs = sl_cs[0], cnt = sl_ce[0] - cs;
+      for (int base = 0; base < zpad; base += 4 * kBlock) {
+        float v[4][6];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = base + tid + u * kBlock;
+#pragma unroll
+          for (int q = 0; q < 6; ++q)
+            if (q < 3 * nv) v[u][q] = e < cnt ? Vg[q * CM + cs + e] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = base + tid + u * kBlock;
+          if (e < zpad)
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+              if (q < 3 * nv) Zs[q * zpad + e] = v[u][q];
+        }
+      }
+      return;
+    }
+    for (int e = tid; e < zpad; e += kBlock) {
+      const int sl = slot_of(sl_zb, nsl, e);
+      const int k = e - sl_zb[sl] + sl_cs[sl];
+      const bool ok = k < sl_ce[sl];
+      float v[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q)
+        if (q < 3 * nv) v[q] = ok ? Vg[q * CM + k] : 0.0f;
+#pragma unroll
+      for (int q = 0; q < 6; ++q)
+        if (q < 3 * nv) Zs[q * zpad + e] = v[q];
+    }
+  };
+  // Y_v,t = sum_k K_jk V_v,k for every owned row t and nv vectors.  staged: K and V in
+  // LDS, 16 lanes per row over float4 columns (16 rows per pass); else one wavefront per
+  // row with V_v,k component q at Vg[(3 v + q) CM + k] in global memory.
+  auto matvec_rows = [&](auto nv, bool staged, const float* Vg, float (*Y0)[kCrRows], float (*Y1)[kCrRows]) {
+    constexpr int NV = decltype(nv)::value;
+    if (k_in_lds && staged) {
+      const int grp = tid >> 4, gl = tid & 15;
+      for (int t = grp; t < R; t += kBlock / 16) {
+        const int sl = row_slot[t], cs = sl_cs[sl], pc = pad4(sl_ce[sl] - cs);
+        const int rrow = j0 + t - max(cs, j0);
+        const float4* K4 = reinterpret_cast<const float4*>(Ks + sl_kb[sl] + rrow * pc);
+        const float* zb = Zs + sl_zb[sl];
+        float a[3 * NV];
+#pragma unroll
+        for (int q = 0; q < 3 * NV; ++q) a[q] = 0.0f;
+#pragma unroll 2
+        for (int k4 = gl; k4 < pc / 4; k4 += 16) {
+          const float4 kv = K4[k4];
+#pragma unroll
+          for (int q = 0; q < 3 * NV; ++q) {
+            const float4 z = reinterpret_cast<const float4*>(zb + q * zpad)[k4];
+            a[q] += kv.x * z.x + kv.y * z.y + kv.z * z.z + kv.w * z.w;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 3 * NV; ++q)
+          for (int o = 8; o > 0; o >>= 1) a[q] += __shfl_xor(a[q], o, 16);
+        if (gl == 0) {
+          for (int q = 0; q < 3; ++q) Y0[q][t] = a[q];
+          if constexpr (NV == 2)
+            for (int q = 0; q < 3; ++q) Y1[q][t] = a[3 + q];
+        }
+      }
+      __syncthreads();
+      return;
+    }
     for (int t = wave; t < R; t += kBlock / kWave) {
-      int j = j0 + t, s = d.c_scene[j], cs = d.cs_off[s], cnt = d.cs_off[s + 1] - cs;
-      const float* Krow = k_in_lds ? Ks + koffs[t] : d.K + d.k_off[s] + (int64_t)(j - cs) * cnt;
-      float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+      const int sl = row_slot[t], cs = sl_cs[sl], cnt = sl_ce[sl] - cs, pc = pad4(cnt);
+      const int rrow = j0 + t - max(cs, j0);
+      const float* Krow = k_in_lds ? Ks + sl_kb[sl] + rrow * pc : d.K + sl_koff[sl] + (int64_t)(j0 + t - cs) * cnt;
+      float a[3 * NV];
+      for (int q = 0; q < 3 * NV; ++q) a[q] = 0.0f;
       for (int k = lane; k < cnt; k += kWave) {
-        float kv = Krow[k];
-        int idx = cs + k - vbase;
-        a0 += kv * V[idx];
-        a1 += kv * V[vstride + idx];
-        a2 += kv * V[2 * vstride + idx];
+        const float kv = Krow[k];
+#pragma unroll
+        for (int q = 0; q < 3 * NV; ++q) a[q] += kv * (staged ? Zs[q * zpad + sl_zb[sl] + k] : Vg[q * CM + cs + k]);
       }
-      a0 = wave_sum_cr(a0);
-      a1 = wave_sum_cr(a1);
-      a2 = wave_sum_cr(a2);
+      for (int q = 0; q < 3 * NV; ++q) a[q] = wave_sum_cr(a[q]);
       if (lane == 0) {
-        Y[0][t] = a0;
-        Y[1][t] = a1;
-        Y[2][t] = a2;
+        for (int q = 0; q < 3; ++q) Y0[q][t] = a[q];
+        if constexpr (NV == 2)
+          for (int q = 0; q < 3; ++q) Y1[q][t] = a[3 + q];
       }
     }
     __syncthreads();
   };
-  // gather Z of the touched scenes into LDS after a barrier
-  auto gather_Z = [&]() {
+  // K times the first nv vectors of exchange buffer `buf`, staged into Zs when they fit
+  auto exch = [&](int buf) { return d.cr_Z + (int64_t)buf * 3 * NZ * CM; };
+  auto matvec_Z = [&](auto nv, int buf, float (*Y0)[kCrRows], float (*Y1)[kCrRows]) {
     if (z_in_lds) {
-      int n = zhi - zlo;
-      for (int k = tid; k < n; k += kBlock) {
-        Zs[k] = Zg[zlo + k];
-        Zs[n + k] = Zg[CM + zlo + k];
-        Zs[2 * n + k] = Zg[2 * CM + zlo + k];
-      }
+      stage(exch(buf), decltype(nv)::value);
+      __syncthreads();
     }
-    __syncthreads();
+    matvec_rows(nv, z_in_lds, exch(buf), Y0, Y1);
   };
-  auto matvec_Z = [&](float Y[][kCrRows]) {
-    if (z_in_lds) matvec_rows(Zs, zhi - zlo, zlo, Y);
-    else matvec_rows(Zg, CM, 0, Y);
-  };
-  // publish Z_j = C_j^T (Omega_j v_j) for owned contacts
-  auto publish_Z = [&](float v[][kCrRows]) {
+  // publish Z_j = C_j^T (Omega_j v_j) for owned contacts as vector `slot` of buffer `buf`
+  auto publish_Z = [&](int buf, int slot, float (*v)[kCrRows]) {
+    float* Zg = exch(buf) + 3 * slot * CM;
     for (int t = tid; t < R; t += kBlock) {
       float ov[3] = {Oml[0][t] * v[0][t], Oml[1][t] * v[1][t], Oml[2][t] * v[2][t]};
       for (int q = 0; q < 3; ++q) Zg[q * CM + j0 + t] = Cl[q][t] * ov[0] + Cl[3 + q][t] * ov[1] + Cl[6 + q][t] * ov[2];
     }
   };
   // out = Omega (C Y) + E~ v (row t), in place into Y
-  auto applyM = [&](float Y[][kCrRows], float v[][kCrRows]) {
+  auto applyM = [&](float (*Y)[kCrRows], float (*v)[kCrRows]) {
     for (int t = tid; t < R; t += kBlock) {
       float y[3] = {Y[0][t], Y[1][t], Y[2][t]};
       for (int rr = 0; rr < 3; ++rr) {
@@ -170,123 +340,56 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
     }
     __syncthreads();
   };
-  // per-scene partial sums of prod[0..nt) over owned contacts -> global partials
-  auto publish_partials = [&](int nt) {
-    for (int slot = wave; slot <= slast - sfirst; slot += kBlock / kWave) {
-      int t0 = max(sl_cs[slot], j0) - j0, t1 = min(sl_ce[slot], j1) - j0;
+  // per-scene partial sums of prod[0..nt) over owned contacts -> buffer `buf`
+  auto publish_partials = [&](int buf, int nt) {
+    float* part = d.cr_prod + buf * part_half;
+    for (int sl = wave; sl < nsl; sl += kBlock / kWave) {
+      int t0 = max(sl_cs[sl], j0) - j0, t1 = min(sl_ce[sl], j1) - j0;
       float a[kCrSlots] = {0.0f, 0.0f, 0.0f, 0.0f};
       for (int t = t0 + lane; t < t1; t += kWave)
         for (int q = 0; q < nt; ++q) a[q] += prod[q][t];
       for (int q = 0; q < nt; ++q) {
         float v = wave_sum_cr(a[q]);
-        if (lane == 0) part[((int64_t)blockIdx.x * kCrRows + slot) * kCrSlots + q] = v;
+        if (lane == 0) part[((int64_t)(sfirst + sl) * G + blockIdx.x) * kCrSlots + q] = v;
       }
     }
   };
-  // scene sums: for each touched scene, sum the partials of all blocks holding it, in
-  // block order
-  auto gather_sums = [&](int nt) {
-    for (int slot = wave; slot <= slast - sfirst; slot += kBlock / kWave) {
-      int s = sfirst + slot;
-      int b0 = sl_cs[slot] / per, b1 = (sl_ce[slot] - 1) / per;
+  // scene sums into prod[q][t] for every owned row: for each touched scene, the partials
+  // of all blocks holding it, added in block order.  With stage_nv > 0, also stage that
+  // many vectors of exchange buffer `buf` into Zs, its loads issued together with the
+  // first round of partial-sum loads.
+  auto gather_sums = [&](int buf, int nt, int stage_nv) {
+    const float* part = d.cr_prod + buf * part_half;
+    for (int sl = wave, round = 0; sl < nsl || round == 0; sl += kBlock / kWave, ++round) {
+      const bool mine = sl < nsl;
+      int b0 = 0, b1 = -1;
+      if (mine) {
+        b0 = sl_cs[sl] / per;
+        b1 = (sl_ce[sl] - 1) / per;
+      }
       float a[kCrSlots] = {0.0f, 0.0f, 0.0f, 0.0f};
       for (int b = b0 + lane; b <= b1; b += kWave) {
-        const float* pp = part + ((int64_t)b * kCrRows + (s - bfirst[b])) * kCrSlots;
+        const float* pp = part + ((int64_t)(sfirst + sl) * G + b) * kCrSlots;
         for (int q = 0; q < nt; ++q) a[q] += pp[q];
       }
+      if (round == 0 && stage_nv > 0 && z_in_lds) stage(exch(buf), stage_nv);
+      if (!mine) continue;
+      const int t0 = max(sl_cs[sl], j0) - j0, t1 = min(sl_ce[sl], j1) - j0;
       for (int q = 0; q < nt; ++q) {
-        float v = wave_sum_cr(a[q]);
-        if (lane == 0) {
-          int t0 = max(sl_cs[slot], j0) - j0, t1 = min(sl_ce[slot], j1) - j0;
-          for (int t = t0; t < t1; ++t) s_sum[q][t] = v;
-        }
+        const float v = wave_sum_cr(a[q]);
+        for (int t = t0 + lane; t < t1; t += kWave) prod[q][t] = v;
       }
     }
     __syncthreads();
   };
-
-  // ---- setup: r = (g - Omega h^2 W Omega lambda) / h^2, x = 0
-  {
-    float(*Y)[kCrRows] = vAr;
-    matvec_rows(d.X, CM, 0, Y);  // X = C^T (Omega lambda) from the contact kernel
-    for (int t = tid; t < R; t += kBlock) {
-      int j = j0 + t;
-      float y[3] = {Y[0][t], Y[1][t], Y[2][t]};
-      for (int rr = 0; rr < 3; ++rr) {
-        float cy = Cl[3 * rr][t] * y[0] + Cl[3 * rr + 1][t] * y[1] + Cl[3 * rr + 2][t] * y[2];
-        vx[rr][t] = 0.0f;
-        vr[rr][t] = (d.hv[rr * CM + j] - Oml[rr][t] * h2 * cy) / h2;
-      }
-    }
-    __syncthreads();
-    publish_Z(vr);
-  }
-  grid_barrier(ctr, G * ++nbar);
-  gather_Z();
-  matvec_Z(vAr);
-  applyM(vAr, vr);
-  for (int t = tid; t < R; t += kBlock) {
-    float a = 0.0f, b = 0.0f, e = 0.0f;
-    for (int rr = 0; rr < 3; ++rr) {
-      vp[rr][t] = vr[rr][t];
-      vAp[rr][t] = vAr[rr][t];
-      a += vr[rr][t] * vAr[rr][t];
-      b += vAr[rr][t] * vAr[rr][t];
-      e += vr[rr][t] * vr[rr][t];
-    }
-    prod[0][t] = a;
-    prod[1][t] = b;
-    prod[2][t] = e;
-  }
-  __syncthreads();
-  publish_partials(3);
-  grid_barrier(ctr, G * ++nbar);
-  gather_sums(3);
-  for (int t = tid; t < R; t += kBlock) {
-    s_rAr[t] = s_sum[0][t];
-    s_ApAp[t] = s_sum[1][t];
-    s_rr[t] = s_sum[2][t];
-    s_rr0[t] = s_sum[2][t];
-  }
-  __syncthreads();
-
-  const float tol2 = d.cr_tol * d.cr_tol;
-  for (int it = 0; it < d.cr_iters; ++it) {
-    // a scene is finished after exact breakdown or once |r| <= tol |r0|
-    for (int t = tid; t < R; t += kBlock) {
-      float rAr = s_rAr[t], ApAp = s_ApAp[t];
-      bool live = ApAp != 0.0f && rAr != 0.0f && !(tol2 > 0.0f && s_rr[t] <= tol2 * s_rr0[t]);
-      s_live[t] = live;
-      if (live) {
-        float alpha = rAr / ApAp;
-        for (int rr = 0; rr < 3; ++rr) {
-          vx[rr][t] += alpha * vp[rr][t];
-          vr[rr][t] -= alpha * vAp[rr][t];
-        }
-      }
-    }
-    __syncthreads();
-    publish_Z(vr);
-    // count blocks with a live scene; read after the barrier, so every block takes the
-    // same decision to stop
-    if (tid == 0) {
-      bool any = false;
-      for (int t = 0; t < R; ++t) any |= s_live[t];
-      if (any) __hip_atomic_fetch_add(d.cr_active + it, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    grid_barrier(ctr, G * ++nbar);
-    if (tid == 0) s_go = __hip_atomic_load(d.cr_active + it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0;
-    __syncthreads();
-    if (!s_go) break;
-    gather_Z();
-    matvec_Z(vAr);
-    applyM(vAr, vr);
+  // inner products of one step into prod: (r, w), (w, w), (w, q), (r, r)
+  auto products = [&]() {
     for (int t = tid; t < R; t += kBlock) {
       float a = 0.0f, b = 0.0f, e = 0.0f, f = 0.0f;
       for (int rr = 0; rr < 3; ++rr) {
-        a += vr[rr][t] * vAr[rr][t];
-        b += vAr[rr][t] * vAr[rr][t];
-        e += vAr[rr][t] * vAp[rr][t];
+        a += vr[rr][t] * vw[rr][t];
+        b += vw[rr][t] * vw[rr][t];
+        e += vw[rr][t] * vq[rr][t];
         f += vr[rr][t] * vr[rr][t];
       }
       prod[0][t] = a;
@@ -295,21 +398,110 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
       prod[3][t] = f;
     }
     __syncthreads();
-    publish_partials(4);
-    grid_barrier(ctr, G * ++nbar);
-    gather_sums(4);
+  };
+  const std::integral_constant<int, 1> one{};
+  const std::integral_constant<int, 2> two{};
+
+  // ---- setup: r = (g - Omega h^2 W Omega lambda) / h^2, x = 0, w = M r, p = r, q = w
+  // (X = C^T (Omega lambda) from the contact kernel)
+  if (z_in_lds) stage(d.X, 1);
+  __syncthreads();
+  matvec_rows(one, z_in_lds, d.X, vn, vn);
+  for (int t = tid; t < R; t += kBlock) {
+    int j = j0 + t;
+    float y[3] = {vn[0][t], vn[1][t], vn[2][t]};
+    for (int rr = 0; rr < 3; ++rr) {
+      float cy = Cl[3 * rr][t] * y[0] + Cl[3 * rr + 1][t] * y[1] + Cl[3 * rr + 2][t] * y[2];
+      vx[rr][t] = 0.0f;
+      vr[rr][t] = (d.hv[rr * CM + j] - Oml[rr][t] * h2 * cy) / h2;
+    }
+  }
+  __syncthreads();
+  publish_Z((nbar + 1) & 1, 0, vr);
+  if (grid_barrier(ctrs, ++nbar, true, &s_st, fail) < 0) return;
+  matvec_Z(one, nbar & 1, vw, vw);
+  applyM(vw, vr);
+  for (int t = tid; t < R; t += kBlock)
+    for (int rr = 0; rr < 3; ++rr) vq[rr][t] = vw[rr][t];  // (w, q) is not used here
+  products();
+  if constexpr (V == 1) publish_Z((nbar + 1) & 1, 0, vw);
+  publish_partials((nbar + 1) & 1, 4);
+  if (grid_barrier(ctrs, ++nbar, true, &s_st, fail) < 0) return;
+  gather_sums(nbar & 1, 4, V == 1 ? 1 : 0);
+  for (int t = tid; t < R; t += kBlock) {
+    s_g[t] = prod[0][t];
+    s_qq[t] = prod[1][t];
+    s_rr[t] = prod[3][t];
+    s_rr0[t] = prod[3][t];
+    for (int rr = 0; rr < 3; ++rr) vp[rr][t] = vr[rr][t];
+  }
+  if constexpr (V == 1) {
+    matvec_rows(one, z_in_lds, exch(nbar & 1), vz, vz);  // z = M q = M w
+    applyM(vz, vw);
+  } else {
+    __syncthreads();
+  }
+
+  const float tol2 = d.cr_tol * d.cr_tol;
+  for (int it = 0; it < d.cr_iters; ++it) {
+    // a scene is finished after exact breakdown or once |r| <= tol |r_0|
+    int mine = 0;
+    for (int t = tid; t < R; t += kBlock) {
+      float g = s_g[t], qq = s_qq[t];
+      bool live = qq != 0.0f && g != 0.0f && !(tol2 > 0.0f && s_rr[t] <= tol2 * s_rr0[t]);
+      s_live[t] = live;
+      mine |= live ? 1 : 0;
+      if (live) {
+        float alpha = g / qq;
+        for (int rr = 0; rr < 3; ++rr) {
+          vx[rr][t] += alpha * vp[rr][t];
+          vr[rr][t] -= alpha * vq[rr][t];
+          if constexpr (V == 1) vw[rr][t] -= alpha * vz[rr][t];
+        }
+      }
+    }
+    const bool block_live = __syncthreads_or(mine) != 0;
+    if (it + 1 == d.cr_iters) break;
+    if constexpr (V == 0) {
+      publish_Z((nbar + 1) & 1, 0, vr);
+      const int st = grid_barrier(ctrs, ++nbar, block_live, &s_st, fail);
+      if (st < 0) return;
+      if (st == 0) break;
+      matvec_Z(one, nbar & 1, vw, vw);
+      applyM(vw, vr);  // w = M r
+      products();
+      publish_partials((nbar + 1) & 1, 4);
+      if (grid_barrier(ctrs, ++nbar, true, &s_st, fail) < 0) return;
+      gather_sums(nbar & 1, 4, 0);
+    } else {
+      products();  // with the recurrence w~
+      publish_Z((nbar + 1) & 1, 0, vw);
+      publish_Z((nbar + 1) & 1, 1, vr);
+      publish_partials((nbar + 1) & 1, 4);
+      const int st = grid_barrier(ctrs, ++nbar, block_live, &s_st, fail);
+      if (st < 0) return;
+      if (st == 0) break;
+      gather_sums(nbar & 1, 4, 2);
+      matvec_rows(two, z_in_lds, exch(nbar & 1), vn, vm);
+      applyM(vn, vw);  // n = M w~
+      applyM(vm, vr);  // true M r
+    }
     for (int t = tid; t < R; t += kBlock) {
       if (s_live[t]) {
-        float rAr = s_rAr[t], ApAp = s_ApAp[t];
-        float rAr_new = s_sum[0][t], ArAr = s_sum[1][t], ArAp = s_sum[2][t];
-        float beta = rAr_new / rAr;
+        float g = s_g[t], qq = s_qq[t];
+        float g_new = prod[0][t], ww = prod[1][t], wq = prod[2][t];
+        float beta = g_new / g;
         for (int rr = 0; rr < 3; ++rr) {
           vp[rr][t] = vr[rr][t] + beta * vp[rr][t];
-          vAp[rr][t] = vAr[rr][t] + beta * vAp[rr][t];
+          vq[rr][t] = vw[rr][t] + beta * vq[rr][t];
+          if constexpr (V == 1) {
+            vz[rr][t] = vn[rr][t] + beta * vz[rr][t];
+            vw[rr][t] = vm[rr][t];
+          }
         }
-        s_rAr[t] = rAr_new;
-        s_ApAp[t] = ArAr + 2.0f * beta * ArAp + beta * beta * ApAp;
-        s_rr[t] = s_sum[3][t];
+        s_g[t] = g_new;
+        s_qq[t] = ww + 2.0f * beta * wq + beta * beta * qq;
+        s_rr[t] = prod[3][t];
       }
     }
     __syncthreads();
@@ -328,22 +520,24 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
 }
 
 int cr_max_blocks() {
-  int dev = 0, cus = 0, per = 0;
+  int dev = 0, cus = 0, per = 0, per1 = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 1;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(k_cr), kBlock, 0) !=
-      hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(k_cr<0>), kBlock, 0) !=
+          hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per1, reinterpret_cast<const void*>(k_cr<1>), kBlock, 0) !=
+          hipSuccess)
     return 1;
-  return max(1, min(cus * max(per, 1), 1024));
+  // at most one block per CU is resident (LDS), so the grid must not exceed the CU count
+  return max(1, min(cus * max(min(per, per1), 1), min(cus, kCrMaxBlocks)));
 }
 
-int cr_partial_floats(int blocks) { return blocks * kCrRows * kCrSlots; }
+int64_t cr_partial_floats(int blocks, int scenes) { return 2 * (int64_t)scenes * blocks * kCrSlots; }
 
-hipError_t launch_cr(const Dev& d, hipStream_t st, int cr_blocks) {
-  Dev dd = d;
-  void* args[] = {&dd};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_cr), dim3(cr_blocks), dim3(kBlock), args, 0,
-                                    st);
+hipError_t launch_cr(const Dev& d, hipStream_t st, int cr_blocks, int variant) {
+  if (variant == 1) hipLaunchKernelGGL(k_cr<1>, dim3(cr_blocks), dim3(kBlock), 0, st, d);
+  else hipLaunchKernelGGL(k_cr<0>, dim3(cr_blocks), dim3(kBlock), 0, st, d);
+  return hipGetLastError();
 }
 
 }  // namespace lg

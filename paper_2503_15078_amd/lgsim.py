@@ -45,7 +45,7 @@ class sim_options(C.Structure):
     _fields_ = [("gravity", C.c_double * 3), ("pin_weight_scale", C.c_double),
                 ("contact_margin", C.c_double), ("cr_iters", C.c_int32), ("warm", C.c_int32),
                 ("ncp_tol", C.c_double), ("max_iters", C.c_int32), ("max_contacts", C.c_int32),
-                ("hip_stream", C.c_void_p), ("cr_tol", C.c_double)]
+                ("hip_stream", C.c_void_p), ("cr_tol", C.c_double), ("cr_variant", C.c_int32)]
 
 
 class sim_obstacle(C.Structure):
@@ -287,8 +287,8 @@ class Sim:
                             frame=np.zeros((0, 3, 3)), lam=np.zeros((0, 3)), gap=np.zeros(0))
         return q, v, contacts
 
-    def set_solver(self, cr_iters, cr_tol=0.0):
-        _check(_lib.sim_set_solver(self.h, int(cr_iters), float(cr_tol)))
+    def set_solver(self, cr_iters, cr_tol=0.0, cr_variant=0):
+        _check(_lib.sim_set_solver(self.h, int(cr_iters), float(cr_tol), int(cr_variant)))
 
     def save_state(self):
         _check(_lib.sim_save_state(self.h))
