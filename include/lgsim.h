@@ -232,6 +232,67 @@ int sim_debug_rhs(sim_t s, double* rhs);
  * order), from which W_(j,k) = K_jk C_j C_k^T (Sec. 5.3). */
 int sim_debug_delassus(sim_t s, double* K);
 
+/* ---- learned warm start (not part of the paper: the paper leaves the initial impulse
+ * of a frame open; the plain start re-uses the previous frame's impulse per contact
+ * key).  A network 12 -> 128 -> 128 -> 3 (GELU; inputs padded to 16) predicts the
+ * frame's converged impulse from per-contact features, all computed on the device at
+ * the frame start, with l the mean rest edge length of the scene:
+ *   f0 (n . x~ - d_n) / l     normal gap at the predicted position (App. A frame)
+ *   f1..3 n                   contact normal, world frame
+ *   f4..6 h C (v_t - u) / l   velocity relative to the obstacle, contact frame
+ *   f7..9 h^2 K_jj lambda_prev / l   previous-frame impulse, contact frame
+ *   f10 log K_jj              Delassus diagonal (r_n = h^2 K_jj, Sec. 5.4)
+ *   f11 mu, f12..15 0
+ * and its output y gives lambda = y l / (h^2 K_jj), projected onto the friction cone;
+ * a contact whose prediction is not finite keeps the previous-frame impulse.
+ * Parameters: float32, SIM_MLP_N_PARAMS values in the order W1 [128][16], b1 [128],
+ * W2 [128][128], b2 [128], W3 [16][128] (rows 3..15 unused), b3 [16]; the device uses
+ * bf16 copies of the weights and bf16 activations with float32 accumulation. */
+#define SIM_MLP_N_PARAMS 20752
+#define SIM_MLP_N_FEATURES 16
+#define SIM_MLP_MAX_BATCH 16384
+
+/* Upload the network used by SIM_WARM_MLP frames (copied; n_params must equal
+ * SIM_MLP_N_PARAMS, else SIM_E_ARG).  Stepping in SIM_WARM_MLP mode without a model is
+ * SIM_E_STATE. */
+int sim_set_warm_model(sim_t s, const float* params, int32_t n_params);
+/* Switch the warm start between frames (SIM_WARM_*). */
+int sim_set_warm_mode(sim_t s, int32_t warm);
+/* on != 0: compute the contact features at every frame start (needed by
+ * sim_read_training_pairs in modes other than SIM_WARM_MLP). */
+int sim_record_training_pairs(sim_t s, int32_t on);
+/* Features [c][16] of the last frame's contacts, taken at that frame's start, and their
+ * scaled impulses at its end, h^2 K_jj lambda / l [c][3] (contact frame), into host
+ * buffers of cap rows, in the canonical contact order of sim_read_state (node and
+ * obstacle keys as there; both nullable); *n = c.  SIM_E_CAPACITY when c > cap
+ * (nothing copied), SIM_E_STATE when features are not recorded. */
+int sim_read_training_pairs(sim_t s, int32_t* node, int32_t* obstacle, float* feat, float* target, int32_t cap,
+                            int32_t* n);
+
+/* ---- trainer of the warm-start network ------------------------------------------
+ * Device-resident float32 parameters with Adam moments (beta1 0.9, beta2 0.999, eps
+ * 1e-8, bias-corrected; Kingma and Ba 2015).  Batches are device pointers: d_x [n][16]
+ * float32 features, d_t [n][3] float32 targets, loss = mean over n x 3 of (y - t)^2;
+ * a training or gradient batch holds at most SIM_MLP_MAX_BATCH samples.
+ * Work is enqueued on hip_stream (null: the default stream).  The gradient is a sum of
+ * per-block partial sums added in block order, so results are deterministic. */
+typedef struct lg_mlp* mlp_t;
+int mlp_create(const float* params, int32_t n_params, mlp_t* out);
+/* Replace the parameters (host, SIM_MLP_N_PARAMS) and reset the Adam state. */
+int mlp_set_params(mlp_t m, const float* params, int32_t n_params);
+/* Copy the parameters to a host buffer (waits for the device). */
+int mlp_get_params(mlp_t m, float* params, int32_t n_params);
+/* d_y [n][3] = network(d_x) (device pointers). */
+int mlp_forward(mlp_t m, const float* d_x, float* d_y, int32_t n, void* hip_stream);
+/* One Adam step with learning rate lr on the batch; if loss is not null the batch loss
+ * before the step is copied to *loss (waits for the stream). */
+int mlp_train_step(mlp_t m, const float* d_x, const float* d_t, int32_t n, float lr, void* hip_stream,
+                   float* loss);
+/* Gradient [SIM_MLP_N_PARAMS] (host) and loss of the batch, parameters unchanged. */
+int mlp_gradient(mlp_t m, const float* d_x, const float* d_t, int32_t n, void* hip_stream, float* grad,
+                 float* loss);
+int mlp_destroy(mlp_t m);
+
 /* ---- host-only precompute inspection (no device needed) -------------------------
  * Run only the host precomputation of sim_create and keep its products. */
 typedef struct lg_host* lg_host_t;

@@ -9,6 +9,21 @@ outputs of (y - t)^2.  Parameters use the padded shapes of the GPU kernels:
 W1 (128, 16) whose last 4 input columns multiply zero features, W3 (16, 128) whose
 rows 3..15 are unused, b3 (16,).  Pins: the backward pass is checked against central
 differences of the loss.
+
+The learned warm start is not part of the paper; its inputs are built from quantities
+the paper defines: the contact frame and normal gap (App. A), the previous impulse
+re-expressed in the new frame (the plain warm start), and the Delassus diagonal K_jj
+that sets r_n = h^2 K_jj (Sec. 5.4).  Per contact, with l the mean rest edge length of
+the scene and x~ the predicted position:
+  f0     (n . x~ - d_n) / l                  normal gap at the predicted state
+  f1..3  n                                   contact normal (world)
+  f4..6  h C (v_t - u_obstacle) / l          relative velocity in the contact frame
+  f7..9  h^2 K_jj lambda_prev / l            previous impulse (contact frame), scaled
+  f10    log K_jj
+  f11    mu
+  f12..15 0
+and the target is h^2 K_jj lambda / l for the converged impulse lambda of the frame.
+Adam follows Kingma and Ba (2015), bias-corrected moments.
 """
 from __future__ import annotations
 
@@ -92,3 +107,88 @@ def bf16_round(a):
     u = a32.view(np.uint32).astype(np.uint64)
     r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
     return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+# ------------------------------------------------------------------ bf16 rounding points
+
+def _round_weights(p):
+    return {k: (bf16_round(v) if k.startswith("W") else np.asarray(v, np.float64)) for k, v in p.items()}
+
+
+def forward_bf16(p, X):
+    """The network with the device's rounding points: weights, inputs and the
+    activations h1, h2 rounded to bf16 (they are matrix-core operands); every sum and
+    the GELU exact (float64)."""
+    q = _round_weights(p)
+    x = bf16_round(pad_features(X))
+    z1 = x @ q["W1"].T + q["b1"]
+    h1 = bf16_round(gelu(z1))
+    z2 = h1 @ q["W2"].T + q["b2"]
+    h2 = bf16_round(gelu(z2))
+    y = h2 @ q["W3"].T + q["b3"]
+    return y[:, :3], (x, z1, h1, z2, h2)
+
+
+def grad_bf16(p, X, T):
+    """Gradient of the mean-squared loss with the device's rounding points: the forward
+    of forward_bf16, and dL/dy, dL/dz2, dL/dz1 rounded to bf16 (matrix-core operands);
+    the bias gradients sum those rounded values."""
+    y, (x, z1, h1, z2, h2) = forward_bf16(p, X)
+    q = _round_weights(p)
+    B = len(X)
+    dy = np.zeros((B, 16))
+    dy[:, :3] = 2.0 * (y - T) / (B * 3)
+    dy = bf16_round(dy)
+    dz2 = bf16_round((dy @ q["W3"]) * gelu_grad(z2))
+    dz1 = bf16_round((dz2 @ q["W2"]) * gelu_grad(z1))
+    return {"W3": dy.T @ h2, "b3": dy.sum(0), "W2": dz2.T @ h1, "b2": dz2.sum(0), "W1": dz1.T @ x,
+            "b1": dz1.sum(0)}
+
+
+# ------------------------------------------------------------------ warm-start data
+
+def mean_edge_length(rest, tets):
+    """Mean over tets of the six edge lengths at rest (an edge shared by k tets counts k
+    times)."""
+    rest = np.asarray(rest, np.float64)
+    tets = np.asarray(tets, np.int64)
+    pairs = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+    L = [np.linalg.norm(rest[tets[:, a]] - rest[tets[:, b]], axis=1) for a, b in pairs]
+    return float(np.mean(np.concatenate(L)))
+
+
+def features(C, d_n, mu, node, q_pred, v_t, obst_vel, lam_prev, K_diag, h, ell):
+    """Input features (c, 16) per the definition in the module docstring.
+
+    C (c,3,3) rows n, f1, f2; d_n (c,); mu (c,); node (c,) node per contact; q_pred,
+    v_t (n,3); obst_vel (c,3) obstacle velocity per contact; lam_prev (c,3) in the
+    contact frame; K_diag (c,) = K_jj."""
+    C = np.asarray(C, np.float64)
+    c = len(C)
+    F = np.zeros((c, 16))
+    if c == 0:
+        return F
+    xp = np.asarray(q_pred, np.float64)[node]
+    rel = np.asarray(v_t, np.float64)[node] - np.asarray(obst_vel, np.float64)
+    K_diag = np.asarray(K_diag, np.float64)
+    F[:, 0] = (np.einsum("ji,ji->j", C[:, 0, :], xp) - np.asarray(d_n)) / ell
+    F[:, 1:4] = C[:, 0, :]
+    F[:, 4:7] = h * np.einsum("jai,ji->ja", C, rel) / ell
+    F[:, 7:10] = (h * h * K_diag / ell)[:, None] * np.asarray(lam_prev, np.float64)
+    F[:, 10] = np.log(K_diag)
+    F[:, 11] = np.asarray(mu, np.float64)
+    return F
+
+
+def targets(lam, K_diag, h, ell):
+    """Scaled converged impulse h^2 K_jj lambda / l (c, 3)."""
+    return (h * h * np.asarray(K_diag, np.float64) / ell)[:, None] * np.asarray(lam, np.float64)
+
+
+def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update of flat parameters p with gradient g at step t >= 1."""
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mh = m / (1.0 - b1 ** t)
+    vh = v / (1.0 - b2 ** t)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v

@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblgsim_hip.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["precompute.cpp", "host_api.cpp", "k_elem.hip", "k_spmv.hip", "k_contact.hip", "k_cr.hip", "api.hip"]
+SOURCES = ["precompute.cpp", "host_api.cpp", "k_elem.hip", "k_spmv.hip", "k_contact.hip", "k_cr.hip", "k_mlp.hip",
+           "api.hip", "mlp_api.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-value", "-Wno-unused-result", f"-I{os.path.join(ROOT, 'include')}",
           f"-I{CSRC}"]

@@ -60,6 +60,9 @@ struct lgsim {
   int* h_pinned = nullptr;            // [4]: n_contacts, overflow, bad, spare
   float* h_res = nullptr;             // [NS]
   int iter_c = 0;                     // contact count of the current iterate state
+  bool has_model = false;             // learned warm-start parameters uploaded
+  bool record_pairs = false;          // compute contact features every frame
+  float* d_tgt = nullptr;             // [CMAX][3] scratch of sim_read_training_pairs
   std::vector<int32_t> iter_canon;    // internal contact index -> canonical position
   hipEvent_t ev[8] = {};
   std::vector<hipEvent_t> fev;        // per-frame timing events
@@ -337,6 +340,10 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   TRY(s->alloc(d.scene_node0, NS + 1));
   TRY(s->alloc(d.scene_obst0, NS + 1));
   TRY(s->alloc(d.scene_margin, NS));
+  TRY(s->alloc(d.ell, NS));
+  TRY(s->alloc(d.c_feat, 16 * (size_t)d.CMAX));
+  TRY(s->alloc(d.mlp_P, lg::kMlpParams));
+  TRY(s->alloc(s->d_tgt, 3 * (size_t)d.CMAX));
   TRY(s->alloc(d.obst, (size_t)lg::kMaxObstacles * NS));
   TRY(s->alloc(d.n_contacts, 4));
   TRY(s->alloc(d.overflow, 4));
@@ -432,6 +439,24 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   TRY(upload(s, d.chain_end, chain_end.data(), chain_end.size()));
   TRY(upload(s, d.scene_node0, scene_node0.data(), scene_node0.size()));
   TRY(upload(s, d.scene_margin, margins.data(), margins.size()));
+  {
+    // mean rest edge length per scene (scale of the learned warm start's features)
+    std::vector<double> ell(NS, 0.0);
+    for (int k = 0; k < NS; ++k) {
+      const auto& H = hs[k];
+      static const int E[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+      double sum = 0.0;
+      for (int t = 0; t < H.m; ++t)
+        for (const auto& e : E) {
+          const int a = H.tets[4 * t + e[0]], b = H.tets[4 * t + e[1]];
+          double l2 = 0.0;
+          for (int q = 0; q < 3; ++q) l2 += (H.rest[3 * a + q] - H.rest[3 * b + q]) * (H.rest[3 * a + q] - H.rest[3 * b + q]);
+          sum += std::sqrt(l2);
+        }
+      ell[k] = H.m > 0 ? sum / (6.0 * H.m) : 1.0;
+    }
+    TRY(upload(s, d.ell, ell.data(), ell.size()));
+  }
   // obstacles
   s->scene_obst0.assign(NS + 1, 0);
   s->obst.clear();
@@ -512,6 +537,8 @@ int frame_setup(lgsim* s) {
   lg::launch_collide(d, s->st);
   lg::launch_delassus(d, s->st);
   lg::launch_warm_start(d, s->st, 0);
+  if (s->record_pairs || (s->opt.warm == SIM_WARM_MLP && s->has_model)) lg::launch_mlp_features(d, s->st);
+  if (s->opt.warm == SIM_WARM_MLP && s->has_model) lg::launch_mlp_warm(d, s->st);
   lg::launch_force_ranges(d, s->st);
   s->iter_c = -1;  // known after the next synchronisation
   return check_launch("frame setup");
@@ -714,7 +741,6 @@ int create_common(int32_t count, const sim_mesh* meshes, const sim_material* mat
     lg::set_error("bad options");
     return fail(SIM_E_ARG);
   }
-  if (s->opt.warm == SIM_WARM_MLP) s->opt.warm = SIM_WARM_PREV;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) {
     lg::set_error("no HIP device");
@@ -849,6 +875,75 @@ int sim_set_solver(sim_t s, int32_t cr_iters, double cr_tol, int32_t cr_variant)
   return SIM_OK;
 }
 
+int sim_set_warm_model(sim_t s, const float* params, int32_t n_params) {
+  if (!s || !params || n_params != lg::kMlpParams) {
+    lg::set_error("sim_set_warm_model: expected " + std::to_string(lg::kMlpParams) + " parameters");
+    return SIM_E_ARG;
+  }
+  TRY(upload(s, s->d.mlp_P, params, (size_t)n_params));
+  HIPCHK(hipStreamSynchronize(s->st));
+  s->has_model = true;
+  return SIM_OK;
+}
+
+int sim_set_warm_mode(sim_t s, int32_t warm) {
+  if (!s || warm < SIM_WARM_ZERO || warm > SIM_WARM_MLP) {
+    lg::set_error("bad warm start mode");
+    return SIM_E_ARG;
+  }
+  s->opt.warm = warm;
+  s->d.warm = warm;
+  return SIM_OK;
+}
+
+int sim_record_training_pairs(sim_t s, int32_t on) {
+  if (!s) {
+    lg::set_error("null handle");
+    return SIM_E_ARG;
+  }
+  s->record_pairs = on != 0;
+  return SIM_OK;
+}
+
+int sim_read_training_pairs(sim_t s, int32_t* node, int32_t* obstacle, float* feat, float* target, int32_t cap,
+                            int32_t* n) {
+  if (!s || !n || cap < 0 || (cap > 0 && (!feat || !target))) {
+    lg::set_error("bad arguments");
+    return SIM_E_ARG;
+  }
+  if (!s->record_pairs && !(s->opt.warm == SIM_WARM_MLP && s->has_model)) {
+    lg::set_error("features are not recorded (sim_record_training_pairs)");
+    return SIM_E_STATE;
+  }
+  auto& d = s->d;
+  int c = 0;
+  HIPCHK(hipMemcpyAsync(&c, d.n_contacts, sizeof(int), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  c = std::min(c, d.CMAX);
+  *n = c;
+  if (c > cap) {
+    lg::set_error("capacity too small: " + std::to_string(c) + " contacts");
+    return SIM_E_CAPACITY;
+  }
+  if (c == 0) return SIM_OK;
+  std::vector<int> cn, co;
+  std::vector<int32_t> order;
+  TRY(sort_contacts_canonical(s, c, cn, co, order));
+  std::vector<float> f(16 * (size_t)c), t(3 * (size_t)c);
+  lg::launch_mlp_targets(d, s->d_tgt, s->st);
+  HIPCHK(hipMemcpyAsync(f.data(), d.c_feat, f.size() * sizeof(float), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipMemcpyAsync(t.data(), s->d_tgt, t.size() * sizeof(float), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  for (int k = 0; k < c; ++k) {
+    const int j = order[k];
+    if (node) node[k] = s->iperm_caller[cn[j]];
+    if (obstacle) obstacle[k] = co[j];
+    std::memcpy(feat + 16 * (size_t)k, f.data() + 16 * (size_t)j, 16 * sizeof(float));
+    std::memcpy(target + 3 * (size_t)k, t.data() + 3 * (size_t)j, 3 * sizeof(float));
+  }
+  return SIM_OK;
+}
+
 int sim_set_pin_motion(sim_t s, int32_t n_groups, const double* lin, const double* ang, const double* pivot) {
   if (!s || n_groups < 0 || (n_groups > 0 && (!lin || !ang || !pivot))) {
     lg::set_error("bad pin motion arguments");
@@ -881,6 +976,10 @@ int sim_step(sim_t s, int32_t frames, int32_t iters, sim_stats* stats) {
   if (!s || frames < 0 || iters < 0) {
     lg::set_error("bad arguments");
     return SIM_E_ARG;
+  }
+  if (s->opt.warm == SIM_WARM_MLP && !s->has_model) {
+    lg::set_error("learned warm start selected but no model set (sim_set_warm_model)");
+    return SIM_E_STATE;
   }
   for (int f = 0; f < frames; ++f) {
     const bool timed = stats != nullptr;

@@ -18,6 +18,9 @@ constexpr int kMaxObstacles = 64;
 constexpr int kDelTile = 16;      // Delassus tile (contacts x contacts)
 constexpr int kDelChunk = 64;     // Delassus depth chunk staged in LDS
 constexpr int kMaxCrIters = 1024;
+constexpr int kMlpParams = 20752;   // 16x128 + 128 + 128x128 + 128 + 16x128 + 16 (padded shapes)
+constexpr int kMlpMaxBlocks = 256;  // blocks of one training launch (64 samples each)
+constexpr int kMlpMaxBatch = 64 * kMlpMaxBlocks;
 constexpr int kCrMaxBlocks = 1024;  // blocks of the CR launch (partial sums)
 constexpr int kCrMaxBarriers = 2 * kMaxCrIters + 2;  // device-wide barriers of one CR launch
 
@@ -97,6 +100,10 @@ struct Dev {
   float *cr_prod;                  // per-(block, scene slot) partial sums of the CR launch
   unsigned *cr_sync;               // [kCrMaxBarriers + 1] arrival counters of the CR launch
   float cr_tol;                    // relative CR residual tolerance (0: fixed count)
+  // learned warm start
+  double *ell;                     // [NS] mean rest edge length per scene
+  float *c_feat;                   // [CMAX][16] features of the frame's contacts
+  float *mlp_P;                    // [kMlpParams] network parameters (float32 master copy)
   // frame state
   double *t;                       // [1] simulation time at frame start
   float *res;                      // [NS] NCP residual per scene
@@ -115,6 +122,14 @@ void launch_gather(const Dev& d, hipStream_t st);
 void launch_spmv_S(const Dev& d, hipStream_t st, const float* b, float* y);
 void launch_spmv_St(const Dev& d, hipStream_t st, const float* y, const float* base, float* u);
 void launch_contact_prep(const Dev& d, hipStream_t st);
+void launch_mlp_forward(const float* P, const float* X, float* Y, int n, hipStream_t st);
+int mlp_train_blocks(int n);
+void launch_mlp_train(const float* P, const float* X, const float* T, int n, float* partial, hipStream_t st);
+void launch_mlp_adam(float* P, float* M, float* V, const float* partial, int n, float lr, float b1, float b2,
+                     float eps, float c1, float c2, int update, float* grad_out, float* loss_out, hipStream_t st);
+void launch_mlp_features(const Dev& d, hipStream_t st);
+void launch_mlp_warm(const Dev& d, hipStream_t st);
+void launch_mlp_targets(const Dev& d, float* out, hipStream_t st);
 hipError_t launch_cr(const Dev& d, hipStream_t st, int cr_blocks, int variant);  // variant: SIM_CR_*
 void launch_apply_forces(const Dev& d, hipStream_t st);
 void launch_force_ranges(const Dev& d, hipStream_t st);

@@ -454,7 +454,7 @@ __global__ void k_warm_start(Dev d, int keep_lambda) {
   d.c_rf[j] = (float)d.h * kjj;
   if (keep_lambda) return;
   float l[3] = {0.0f, 0.0f, 0.0f};
-  if (d.warm == 1) {
+  if (d.warm >= 1) {  // previous frame (also the fallback and an input of the learned start)
     int pc = d.pc_count[0];
     int key_n = d.c_node[j], key_o = d.c_obst[j];
     int lo = 0, hi = pc;

@@ -17,6 +17,8 @@ LIB_NAME = "liblgsim_hip.so"
 LIB_PATH = os.path.join(_HERE, LIB_NAME)
 
 SIM_OK = 0
+SIM_WARM_ZERO, SIM_WARM_PREV, SIM_WARM_MLP = 0, 1, 2
+SIM_CR_TEXTBOOK, SIM_CR_PIPELINED = 0, 1
 ERRORS = {-1: "SIM_E_ARG", -2: "SIM_E_MESH", -3: "SIM_E_NOT_SPD", -4: "SIM_E_NOMEM",
           -5: "SIM_E_DEVICE", -6: "SIM_E_STATE", -7: "SIM_E_DIVERGED", -8: "SIM_E_CAPACITY"}
 
@@ -91,7 +93,18 @@ def load():
         "sim_read_state": [C.c_void_p, P(d), P(d), P(sim_contact), i32, P(i32)],
         "sim_read_state_device": [C.c_void_p, C.c_void_p, C.c_void_p],
         "sim_destroy": [C.c_void_p],
-        "sim_set_solver": [C.c_void_p, i32, d],
+        "sim_set_solver": [C.c_void_p, i32, d, i32],
+        "sim_set_warm_model": [C.c_void_p, P(C.c_float), i32],
+        "sim_set_warm_mode": [C.c_void_p, i32],
+        "sim_record_training_pairs": [C.c_void_p, i32],
+        "sim_read_training_pairs": [C.c_void_p, P(i32), P(i32), P(C.c_float), P(C.c_float), i32, P(i32)],
+        "mlp_create": [P(C.c_float), i32, P(C.c_void_p)],
+        "mlp_set_params": [C.c_void_p, P(C.c_float), i32],
+        "mlp_get_params": [C.c_void_p, P(C.c_float), i32],
+        "mlp_forward": [C.c_void_p, C.c_void_p, C.c_void_p, i32, C.c_void_p],
+        "mlp_train_step": [C.c_void_p, C.c_void_p, C.c_void_p, i32, C.c_float, C.c_void_p, P(C.c_float)],
+        "mlp_gradient": [C.c_void_p, C.c_void_p, C.c_void_p, i32, C.c_void_p, P(C.c_float), P(C.c_float)],
+        "mlp_destroy": [C.c_void_p],
         "sim_save_state": [C.c_void_p],
         "sim_restore_state": [C.c_void_p],
         "sim_create_batch": [i32, P(sim_mesh), P(sim_material), P(i32), P(P(sim_obstacle)), d,
@@ -130,6 +143,10 @@ def _check(rc):
 
 def _dp(a):
     return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float)) if a is not None else None
 
 
 def _ip(a):
@@ -290,6 +307,30 @@ class Sim:
     def set_solver(self, cr_iters, cr_tol=0.0, cr_variant=0):
         _check(_lib.sim_set_solver(self.h, int(cr_iters), float(cr_tol), int(cr_variant)))
 
+    # ---- learned warm start
+    def set_warm_model(self, params):
+        p = np.ascontiguousarray(params, np.float32)
+        _check(_lib.sim_set_warm_model(self.h, _fp(p), int(p.size)))
+
+    def set_warm_mode(self, warm):
+        _check(_lib.sim_set_warm_mode(self.h, int(warm)))
+
+    def record_training_pairs(self, on=True):
+        _check(_lib.sim_record_training_pairs(self.h, int(bool(on))))
+
+    def read_training_pairs(self, cap=None):
+        """(node, obstacle, features [c][16], scaled impulses [c][3]) of the last frame's
+        contacts, canonical order."""
+        cap = int(self.opt.max_contacts) if cap is None else cap
+        node = np.zeros(cap, np.int32)
+        obst = np.zeros(cap, np.int32)
+        feat = np.zeros((cap, 16), np.float32)
+        tgt = np.zeros((cap, 3), np.float32)
+        n = C.c_int32(0)
+        _check(_lib.sim_read_training_pairs(self.h, _ip(node), _ip(obst), _fp(feat), _fp(tgt), cap, C.byref(n)))
+        c = n.value
+        return node[:c].copy(), obst[:c].copy(), feat[:c].copy(), tgt[:c].copy()
+
     def save_state(self):
         _check(_lib.sim_save_state(self.h))
 
@@ -345,3 +386,67 @@ class Sim:
 
     def __del__(self):
         self.close()
+
+
+MLP_N_PARAMS = 20752
+MLP_MAX_BATCH = 16384
+
+
+def _stream_ptr():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Mlp:
+    """Trainer of the warm-start network (device-resident parameters and Adam state).
+    Batches are float32 torch tensors on the device: x [n][16], t [n][3]."""
+
+    def __init__(self, params):
+        load()
+        p = np.ascontiguousarray(params, np.float32)
+        h = C.c_void_p()
+        _check(_lib.mlp_create(_fp(p), int(p.size), C.byref(h)))
+        self.h = h
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, np.float32)
+        _check(_lib.mlp_set_params(self.h, _fp(p), int(p.size)))
+
+    def params(self):
+        p = np.zeros(MLP_N_PARAMS, np.float32)
+        _check(_lib.mlp_get_params(self.h, _fp(p), MLP_N_PARAMS))
+        return p
+
+    def forward(self, x):
+        import torch
+        assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.shape[1] == 16
+        y = torch.empty((x.shape[0], 3), dtype=torch.float32, device=x.device)
+        _check(_lib.mlp_forward(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), int(x.shape[0]),
+                                _stream_ptr()))
+        return y
+
+    def _batch(self, x, t):
+        import torch
+        assert x.is_cuda and t.is_cuda and x.dtype == torch.float32 and t.dtype == torch.float32
+        assert x.is_contiguous() and t.is_contiguous() and x.shape[1] == 16 and t.shape[1] == 3
+        assert x.shape[0] == t.shape[0]
+        return C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), int(x.shape[0])
+
+    def train_step(self, x, t, lr, want_loss=False):
+        xp, tp, n = self._batch(x, t)
+        loss = C.c_float(0.0)
+        _check(_lib.mlp_train_step(self.h, xp, tp, n, float(lr), _stream_ptr(),
+                                   C.byref(loss) if want_loss else None))
+        return float(loss.value) if want_loss else None
+
+    def gradient(self, x, t):
+        xp, tp, n = self._batch(x, t)
+        g = np.zeros(MLP_N_PARAMS, np.float32)
+        loss = C.c_float(0.0)
+        _check(_lib.mlp_gradient(self.h, xp, tp, n, _stream_ptr(), _fp(g), C.byref(loss)))
+        return g, float(loss.value)
+
+    def close(self):
+        if self.h:
+            _check(_lib.mlp_destroy(self.h))
+            self.h = None

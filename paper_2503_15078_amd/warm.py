@@ -1,0 +1,188 @@
+"""Learned warm start of the contact impulses: parameter initialisation, data from the
+solver itself, training on the device with the library's own kernels, and the
+comparison with the previous-frame warm start.
+
+The network, its 16 input features and its target (the frame's converged impulse
+scaled by h^2 K_jj / l) are defined in the library header next to sim_set_warm_model.
+Inputs and targets are standardised for training; the standardisation is folded into
+the first and last layers afterwards, so the device evaluates raw features.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import lgsim, scenes
+
+N_PARAMS = lgsim.MLP_N_PARAMS
+SHAPES = [("W1", (128, 16)), ("b1", (128,)), ("W2", (128, 128)), ("b2", (128,)), ("W3", (16, 128)),
+          ("b3", (16,))]
+N_FEAT = 12  # used inputs (16 with padding)
+N_OUT = 3
+
+
+def split(flat):
+    out, o = {}, 0
+    for k, shp in SHAPES:
+        n = int(np.prod(shp))
+        out[k] = np.asarray(flat[o:o + n], np.float64).reshape(shp)
+        o += n
+    return out
+
+
+def join(p):
+    return np.concatenate([np.asarray(p[k], np.float64).reshape(-1) for k, _ in SHAPES]).astype(np.float32)
+
+
+def init_params(seed=0):
+    """He-normal hidden layers, small output layer, zero biases; padding entries zero."""
+    rng = np.random.default_rng(seed)
+    p = {k: np.zeros(s) for k, s in SHAPES}
+    p["W1"][:, :N_FEAT] = rng.normal(0.0, np.sqrt(2.0 / N_FEAT), (128, N_FEAT))
+    p["W2"] = rng.normal(0.0, np.sqrt(2.0 / 128), (128, 128))
+    p["W3"][:N_OUT] = rng.normal(0.0, np.sqrt(0.1 / 128), (N_OUT, 128))
+    return join(p)
+
+
+def standardiser(feat, tgt):
+    """Per-feature mean/std of the used inputs and per-output std of the targets."""
+    mu = feat[:, :N_FEAT].mean(0)
+    sd = feat[:, :N_FEAT].std(0)
+    sd = np.where(sd > 1e-6, sd, 1.0)
+    ts = tgt.std(0)
+    ts = np.where(ts > 1e-9, ts, 1.0)
+    return mu, sd, ts
+
+
+def standardise(feat, tgt, mu, sd, ts):
+    x = np.zeros((len(feat), 16), np.float32)
+    x[:, :N_FEAT] = (feat[:, :N_FEAT] - mu) / sd
+    return x, (tgt / ts).astype(np.float32)
+
+
+def fold(flat, mu, sd, ts):
+    """Parameters acting on raw features and producing raw targets."""
+    p = split(flat)
+    W1 = p["W1"].copy()
+    W1[:, :N_FEAT] = p["W1"][:, :N_FEAT] / sd
+    b1 = p["b1"] - W1[:, :N_FEAT] @ mu
+    W3 = p["W3"].copy()
+    b3 = p["b3"].copy()
+    W3[:N_OUT] *= ts[:, None]
+    b3[:N_OUT] *= ts
+    return join({"W1": W1, "b1": b1, "W2": p["W2"], "b2": p["b2"], "W3": W3, "b3": b3})
+
+
+# ------------------------------------------------------------------ data
+def training_scenes(seeds):
+    """Config-2/3/4-style scenes: teaser-scale stars, twisted bars pressed into a plane
+    (mu in {0.2, 0.8}, E in {1e5, 1e6}), and a batch of small blobs."""
+    out = []
+    for s in seeds:
+        k = s % 4
+        if k in (0, 1):
+            out.append(("teaser", s, scenes.teaser_scene(s)))
+        elif k == 2:
+            out.append(("bar", s, scenes.twist_bar(s, model=2 + (s // 4) % 2, E=[1e5, 1e6][(s // 8) % 2],
+                                                    mu=[0.2, 0.8][(s // 16) % 2])))
+        else:
+            out.append(("blobs", s, scenes.batch_scenes(s, count=8)))
+    return out
+
+
+def generate(seeds, frames, cr_iters=300, cr_tol=1e-4, log=print):
+    """Run each scene to tolerance (NCP residual <= 1e-6 m) with the previous-frame warm
+    start and keep (features, converged impulse) of every frame that converged."""
+    feats, tgts = [], []
+    for kind, seed, sc in training_scenes(seeds):
+        t0 = time.perf_counter()
+        sim = lgsim.Sim(batch=sc, cr_iters=cr_iters, cr_tol=cr_tol) if kind == "blobs" else \
+            lgsim.Sim(sc, cr_iters=cr_iters, cr_tol=cr_tol)
+        sim.record_training_pairs(True)
+        kept = 0
+        for f in range(frames):
+            try:
+                st = sim.step(1, iters=0)
+            except lgsim.SimError as e:
+                log(f"  {kind} {seed}: stop at frame {f}: {e}")
+                break
+            if max(s["ncp"] for s in st) <= 1e-6 and st[0]["contacts"] > 0:
+                _, _, x, t = sim.read_training_pairs()
+                feats.append(x)
+                tgts.append(t)
+                kept += len(x)
+        sim.close()
+        log(f"  {kind} seed {seed}: {kept} samples in {time.perf_counter() - t0:.1f} s")
+    return np.concatenate(feats), np.concatenate(tgts)
+
+
+# ------------------------------------------------------------------ training
+def train(feat, tgt, epochs=30, batch=8192, lr=2e-3, seed=0, log=print):
+    """Adam on the device (library kernels); returns folded parameters and the history."""
+    import torch
+    mu, sd, ts = standardiser(feat, tgt)
+    x, t = standardise(feat, tgt, mu, sd, ts)
+    n = len(x)
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(n)
+    n_val = max(1, n // 20)
+    val, tr = perm[:n_val], perm[n_val:]
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(x[tr]).to(dev)
+    T = torch.from_numpy(t[tr]).to(dev)
+    Xv = torch.from_numpy(x[val]).to(dev)
+    Tv = torch.from_numpy(t[val]).to(dev)
+    net = lgsim.Mlp(init_params(seed))
+    steps_per_epoch = max(1, len(tr) // batch)
+    total = epochs * steps_per_epoch
+    hist = []
+    step = 0
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    for ep in range(epochs):
+        order = torch.randperm(len(tr), generator=g).to(dev)
+        for b in range(steps_per_epoch):
+            idx = order[b * batch:(b + 1) * batch]
+            rate = lr * 0.5 * (1.0 + np.cos(np.pi * step / total))  # cosine decay
+            net.train_step(X[idx].contiguous(), T[idx].contiguous(), rate)
+            step += 1
+        vl = val_loss(net, Xv, Tv)
+        hist.append(vl)
+        log(f"  epoch {ep + 1}/{epochs}: validation loss {vl:.4e} (standardised)")
+    params = fold(net.params(), mu, sd, ts)
+    net.close()
+    return params, {"val_loss": hist, "n_train": int(len(tr)), "n_val": int(n_val), "steps": step}
+
+
+def val_loss(net, Xv, Tv):
+    tot, n = 0.0, 0
+    for b in range(0, len(Xv), lgsim.MLP_MAX_BATCH):
+        xb, tb = Xv[b:b + lgsim.MLP_MAX_BATCH].contiguous(), Tv[b:b + lgsim.MLP_MAX_BATCH].contiguous()
+        _, loss = net.gradient(xb, tb)
+        tot += loss * len(xb)
+        n += len(xb)
+    return tot / max(n, 1)
+
+
+# ------------------------------------------------------------------ evaluation
+def compare(scene, params, frames, cr_iters=300, cr_tol=1e-4, cr_variant=0):
+    """Frames to NCP residual <= 1e-6 m from the same start with the previous-frame and
+    the learned warm start: per-frame iterations and ms (device-synchronised)."""
+    import torch
+    out = {}
+    for mode, name in ((lgsim.SIM_WARM_PREV, "plain"), (lgsim.SIM_WARM_MLP, "learned")):
+        sim = lgsim.Sim(scene, cr_iters=cr_iters, cr_tol=cr_tol, cr_variant=cr_variant)
+        sim.set_warm_model(params)
+        sim.set_warm_mode(mode)
+        its, ms, res = [], [], []
+        for _ in range(frames):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            st = sim.step(1, iters=0)[0]
+            torch.cuda.synchronize()
+            ms.append(1e3 * (time.perf_counter() - a))
+            its.append(st["iters"])
+            res.append(st["ncp"])
+        sim.close()
+        out[name] = {"iters": its, "ms": ms, "ncp": res}
+    return out

@@ -1,0 +1,183 @@
+"""GPU parity of the learned warm start against the FP64 oracle (through the C-ABI):
+the network's forward pass, its gradient, the Adam step, the per-contact features, the
+fallback to the previous-frame impulse, training, and the gain of the trained network.
+
+Tolerances.  The device rounds weights, inputs and activations to bf16 (8 significant
+bits) and accumulates in float32.  Forward: the first-order effect of rounding h1 and
+h2, |W3| (u |h2| + |gelu'(z2)| (|W2| u |h1|)) with u = 2^-8 (two roundings, doubled),
+bounds the gap to the exact network (the oracle's own pin checks the same bound).
+Gradients are compared with the oracle's form that takes the same bf16 rounding points
+(oracle.mlp.grad_bf16); what remains is float32 summation order and the odd bf16
+rounding that falls the other way, bounded per parameter block by 1e-2 of the block's
+largest entry."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+from oracle.sim import OracleSim
+from paper_2503_15078_amd import lgsim, scenes, warm
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+WEIGHTS = os.path.join(os.path.dirname(lgsim.__file__), "warm_mlp.npz")
+
+
+def _params(seed, noise=0.05):
+    rng = np.random.default_rng(seed)
+    p = warm.init_params(seed).astype(np.float64)
+    p += rng.normal(0, noise, p.shape)  # nonzero biases and output rows too
+    return p.astype(np.float32)
+
+
+def _batch(n, seed):
+    rng = np.random.default_rng(seed)
+    x = np.zeros((n, 16), np.float32)
+    x[:, :12] = rng.normal(0, 1, (n, 12))
+    t = rng.normal(0, 0.3, (n, 3)).astype(np.float32)
+    return x, t
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _forward_bound(p, X):
+    _, (x, z1, h1, z2, h2) = omlp.forward(p, X)
+    u = 2.0 ** -8
+    W1, W2, W3 = np.abs(p["W1"]), np.abs(p["W2"]), np.abs(p["W3"])
+    b = (np.abs(h2) @ W3.T + (np.abs(omlp.gelu_grad(z2)) * ((np.abs(h1) + np.abs(x) @ W1.T) @ W2.T)) @ W3.T) * u * 2
+    return b[:, :3] + 1e-5 * (np.abs(h2) @ W3.T)[:, :3]
+
+
+@pytest.mark.parametrize("n", [1, 77, 1000])
+def test_forward_matches_oracle(n):
+    flat = _params(n)
+    x, _ = _batch(n, 10 + n)
+    net = lgsim.Mlp(flat)
+    y = net.forward(_dev(x)).cpu().numpy().astype(np.float64)
+    net.close()
+    p = omlp.unflatten(flat.astype(np.float64))
+    # the oracle evaluates the bf16-representable weights and inputs the device uses
+    pb = {k: (omlp.bf16_round(v) if k.startswith("W") else v) for k, v in p.items()}
+    xb = omlp.bf16_round(x[:, :12])
+    ref, _ = omlp.forward(pb, xb)
+    assert np.all(np.abs(y - ref) <= _forward_bound(pb, xb)), np.abs(y - ref).max()
+    ref_b, _ = omlp.forward_bf16(p, x[:, :12])
+    print(f"n={n}: |y - exact| {np.abs(y - ref).max():.2e}, |y - bf16 points| {np.abs(y - ref_b).max():.2e}")
+
+
+@pytest.mark.parametrize("n", [64, 333, 4096])
+def test_gradient_matches_oracle(n):
+    flat = _params(100 + n)
+    x, t = _batch(n, 200 + n)
+    net = lgsim.Mlp(flat)
+    g, loss = net.gradient(_dev(x), _dev(t))
+    net.close()
+    p = omlp.unflatten(flat.astype(np.float64))
+    ref = omlp.grad_bf16(p, x[:, :12], t)
+    gd = omlp.unflatten(g.astype(np.float64))
+    yb, _ = omlp.forward_bf16(p, x[:, :12])
+    assert abs(loss - np.mean((yb - t) ** 2)) <= 1e-4 * max(1.0, abs(loss))
+    exact = omlp.grad(p, x[:, :12], t)
+    for k in omlp.ORDER:
+        scale = np.abs(ref[k]).max() + 1e-30
+        err = np.abs(gd[k] - ref[k]).max() / scale
+        print(f"n={n} {k}: rel gap to bf16-point oracle {err:.2e}, "
+              f"to exact {np.abs(gd[k] - exact[k]).max() / (np.abs(exact[k]).max() + 1e-30):.2e}")
+        assert err <= 1e-2, (k, err)
+
+
+def test_adam_step_matches_oracle():
+    flat = _params(7)
+    x, t = _batch(2048, 8)
+    net = lgsim.Mlp(flat)
+    X, T = _dev(x), _dev(t)
+    m = np.zeros(flat.size)
+    v = np.zeros(flat.size)
+    p = flat.astype(np.float64)
+    lr = 1e-3
+    for step in range(1, 4):
+        g, _ = net.gradient(X, T)      # the device gradient at the current parameters
+        net.train_step(X, T, lr)
+        p, m, v = omlp.adam_step(p, g.astype(np.float64), m, v, step, lr)
+        got = net.params().astype(np.float64)
+        # float32 parameters: the update agrees to float32 resolution of p and of the step
+        assert np.abs(got - p).max() <= 1e-6 * max(1.0, np.abs(p).max()) + 1e-3 * lr * step
+        p = got
+    net.close()
+
+
+def test_training_reduces_loss():
+    """A student of the same shape learns a random teacher network's outputs."""
+    rng = np.random.default_rng(3)
+    teacher = omlp.unflatten(_params(11, noise=0.2).astype(np.float64))
+    n = 8192
+    x = np.zeros((n, 16), np.float32)
+    x[:, :12] = rng.normal(0, 1, (n, 12))
+    t, _ = omlp.forward(teacher, x[:, :12])
+    t = t.astype(np.float32)
+    net = lgsim.Mlp(warm.init_params(0))
+    X, T = _dev(x), _dev(t)
+    l0 = net.gradient(X, T)[1]
+    for k in range(300):
+        net.train_step(X, T, 3e-3)
+    l1 = net.gradient(X, T)[1]
+    net.close()
+    print(f"loss {l0:.3e} -> {l1:.3e}")
+    assert l1 < 0.1 * l0
+
+
+def test_features_match_oracle():
+    """Features of the frame-14 contacts of a cube drop: the oracle evaluates their
+    definitions in float64 on the GPU's own float32 state and previous impulses."""
+    sc = scenes.cube_drop(0)
+    sim = lgsim.Sim(sc)
+    sim.record_training_pairs(True)
+    sim.step(13)
+    q_t, v_t, con = sim.read_state()
+    sim.step(1)
+    node, obst, feat, tgt = sim.read_training_pairs()
+    _, _, con1 = sim.read_state()
+    sim.close()
+    assert len(node) > 0
+    o = OracleSim(sc)
+    o.q, o.v, o.t = q_t.copy(), v_t.copy(), 13 * sc.h
+    o.prev = {(int(a), int(b)): np.asarray(C).T @ np.asarray(l)
+              for a, b, C, l in zip(con["node"], con["obst"], con["frame"], con["lam"])}
+    q0, q_pred, fc, lam = o.begin_frame()
+    assert np.array_equal(fc.node, node) and np.array_equal(fc.obst, obst)
+    ell = omlp.mean_edge_length(sc.rest, sc.tets)
+    ref = omlp.features(fc.C, fc.d_n, fc.mu, fc.node, q_pred, v_t, np.zeros((fc.c, 3)), lam,
+                        np.diagonal(fc.K), sc.h, ell)
+    err = np.abs(feat - ref) / np.maximum(1.0, np.abs(ref))
+    assert err.max() <= 1e-4, (np.unravel_index(err.argmax(), err.shape), err.max())
+    # targets: the frame's final impulses in the same scaling
+    ref_t = omlp.targets(con1["lam"], np.diagonal(fc.K), sc.h, ell)
+    assert np.abs(tgt - ref_t).max() <= 1e-4 * max(1.0, np.abs(ref_t).max())
+
+
+def test_non_finite_prediction_falls_back_to_previous_impulse():
+    sc = scenes.cube_drop(1)
+    bad = warm.init_params(0)
+    bad[-16:] = np.nan  # b3: every prediction is NaN
+    runs = []
+    for mode in (lgsim.SIM_WARM_PREV, lgsim.SIM_WARM_MLP):
+        sim = lgsim.Sim(sc)
+        sim.set_warm_model(bad)
+        sim.set_warm_mode(mode)
+        sim.step(20)
+        runs.append(sim.read_state())
+        sim.close()
+    np.testing.assert_array_equal(runs[0][0], runs[1][0])
+    np.testing.assert_array_equal(runs[0][2]["lam"], runs[1][2]["lam"])
+
+
+def test_mlp_mode_without_model_is_an_error():
+    sim = lgsim.Sim(scenes.cube_drop(0), warm=lgsim.SIM_WARM_MLP)
+    with pytest.raises(lgsim.SimError) as e:
+        sim.step(1)
+    assert e.value.code == -6
+    sim.close()
