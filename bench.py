@@ -11,12 +11,17 @@ from the same device-resident state each time so that every timed frame sees exa
 800 contacts.  value = ms per local-global iteration = frame time / 5 (as the paper's
 per-iteration figure, which includes the once-per-frame Schur complement).
 
-Also reported: per-phase times from HIP events recorded on the solver's stream during
-the timed frames, the roofline of the dominant kernel, ms/frame when iterating until
-the NCP residual is <= 1e-6 m, and the FP64 oracle timed on the host cores on one
-frame of the same state (cpu_baseline).
+Before timing, the library's autotuner picks the launch configuration (CR grid and
+form, S-pass segment length, element block size) on this state; timed frames replay
+a captured hipGraph.  Also reported: per-kernel times from HIP events on the solver's
+stream in an eagerly launched pass (graph replays hide kernel boundaries), the
+roofline of the dominant S-pass kernel, ms/frame when iterating until the NCP residual
+is <= 1e-6 m with the previous-frame and with the learned warm start, throughput of a
+64-scene batch, and the FP64 oracle timed on the host cores on one frame of the same
+state (cpu_baseline).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,7 +33,15 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 PAPER_MS_PER_ITER = 11.95  # Table 3, Gingerbread Man 19.5k, RTX 4090 + i9-13900KF (context only)
 ITERS = 5
-TOL_CR, TOL_CR_ITERS = 1e-3, 300
+TOL_CR, TOL_CR_ITERS, TOL_MAX_ITERS = 1e-3, 300, 100
+
+# HBM bytes per launch of the S^T pass at this workload from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch, averaged over the bench's launches), scaled by what the same
+# counters read for a plain float32 copy of 256 MiB (FETCH_SIZE reads half the bytes a
+# kernel fetches on this device: x2.0; WRITE_SIZE reads them exactly: x1.0).  Valid only
+# for the kernel source they were taken on.
+ST_COUNTERS = {"source": "paper_2503_15078_amd/csrc/k_spmv.hip", "sha256_16": "9da4d0e75f5fe7da",
+               "fetch_kib": 56640.878, "write_kib": 456.375, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def log(msg):
@@ -43,9 +56,18 @@ def algorithmic_bytes(n, nnz_s):
     return s_pass, st_pass
 
 
+def st_traffic():
+    path = os.path.join(ROOT, ST_COUNTERS["source"])
+    with open(path, "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()[:16]
+    if h != ST_COUNTERS["sha256_16"]:
+        return None
+    return 1024.0 * (ST_COUNTERS["fetch_kib"] * ST_COUNTERS["fetch_scale"] +
+                     ST_COUNTERS["write_kib"] * ST_COUNTERS["write_scale"])
+
+
 def cpu_baseline(scene):
     """The FP64 oracle as it stands, one frame of the same state (bounded sample)."""
-    import numpy as np
     from oracle.sim import OracleSim
     try:
         from threadpoolctl import threadpool_info
@@ -69,6 +91,95 @@ def cpu_baseline(scene):
                        f"SuperLU solves single-threaded, dense BLAS on {cores} threads")}
 
 
+def phase_pass(sim, frames):
+    """Per-phase ms per launch from HIP events of eagerly launched frames (each from the
+    saved state)."""
+    import numpy as np
+    sim.set_graph(False)
+    ph = np.zeros(8)
+    for _ in range(frames):
+        sim.restore_state()
+        st = sim.step(1, iters=ITERS, stats=True)
+        ph += np.asarray(st[0]["phases"])
+    sim.set_graph(True)
+    ph /= frames
+    ph[1:6] /= ITERS
+    return ph
+
+
+def warm_compare(sim, params):
+    """Frame to NCP residual <= 1e-6 m from the benchmark state with the previous-frame
+    warm start (none exists at this state: zero) and with the learned one."""
+    import torch
+    from paper_2503_15078_amd import lgsim
+    sim.set_warm_model(params)
+    out = {}
+    for mode, name in ((lgsim.SIM_WARM_PREV, "plain"), (lgsim.SIM_WARM_MLP, "learned")):
+        sim.set_warm_mode(mode)
+        sim.restore_state()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        s = sim.step(1, iters=0)[0]
+        torch.cuda.synchronize()
+        out[name] = {"ms_per_frame": round(1e3 * (time.perf_counter() - a), 3), "iters": int(s["iters"]),
+                     "ncp_res": float(s["ncp"])}
+    sim.set_warm_mode(lgsim.SIM_WARM_PREV)
+    return out
+
+
+def warm_drops(params, seeds=(1001, 1002, 1003), frames=60):
+    """Held-out config-1 cube drops, every frame to NCP residual <= 1e-6 m."""
+    import numpy as np
+    from paper_2503_15078_amd import scenes, warm
+    agg = {"plain": [[], []], "learned": [[], []]}
+    for s in seeds:
+        res = warm.compare(scenes.cube_drop(s), params, frames, cr_iters=TOL_CR_ITERS, cr_tol=TOL_CR,
+                           max_iters=TOL_MAX_ITERS)
+        for k, v in res.items():
+            agg[k][0] += v["ms"]
+            agg[k][1] += v["iters"]
+    out = {k: {"ms_per_frame": round(float(np.mean(v[0])), 4), "iters_per_frame": round(float(np.mean(v[1])), 3)}
+           for k, v in agg.items()}
+    out["workload"] = f"cube drops, seeds {list(seeds)}, {frames} frames each"
+    return out
+
+
+def batch_throughput(count, steps):
+    """A batch of `count` blobs (config 4) in one handle: scenes x iterations / s, and the
+    S-pass bandwidth at a size that does not fit the infinity cache."""
+    import torch
+    from paper_2503_15078_amd import lgsim, scenes
+    scs = scenes.batch_scenes(0, count=count)
+    t0 = time.perf_counter()
+    sim = lgsim.Sim(batch=scs, max_contacts=32768)
+    t_create = time.perf_counter() - t0
+    sim.save_state()
+    tune = sim.autotune(frames=1, iters=ITERS, allow_pipelined=True)
+    nnz = sum(lgsim.HostPrecompute(s).nnz_S for s in scs)
+    for _ in range(2):
+        sim.restore_state()
+        sim.step(1, iters=ITERS)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(steps):
+        sim.restore_state()
+        sim.step(1, iters=ITERS)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - a
+    ph = phase_pass(sim, 2)
+    n = sum(s.n for s in scs)
+    b_s, b_st = algorithmic_bytes(n, nnz)
+    out = {"metric": "scenes x L-G iterations / s", "value": round(count * ITERS * steps / dt, 1),
+           "scenes": count, "nodes": int(n), "tets": int(sum(len(s.tets) for s in scs)), "nnz_S": int(nnz),
+           "ms_per_frame": round(1e3 * dt / steps, 3), "create_s": round(t_create, 1), "launch": tune,
+           "S_pass_GBps": round(b_s / (ph[2] * 1e-3) / 1e9, 1),
+           "St_pass_GBps": round(b_st / (ph[5] * 1e-3) / 1e9, 1),
+           "St_pass_frac_of_hbm_peak": round(b_st / (ph[5] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "phases_ms_per_launch": [round(float(x), 5) for x in ph]}
+    sim.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,8 +187,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--tol-frames", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cr-variant", type=int, default=0, choices=[0, 1],
-                    help="form of the CR iteration: 0 textbook (two exchanges per step), 1 pipelined (one)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
+    ap.add_argument("--no-extras", action="store_true", help="skip the warm-start comparison and the batch")
+    ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the benchmark, run a plain float32 copy of 256 MiB three times "
                          "(reference kernel for scaling the HBM byte counters)")
@@ -100,30 +212,32 @@ def main():
     nnz_s = hp.nnz_S
     del hp
     log(f"n={sc.n} m={sc.m} nnz(S)={nnz_s}; creating solver")
-    sim = lgsim.Sim(sc, cr_variant=args.cr_variant)
+    sim = lgsim.Sim(sc)
     sim.save_state()
+    tune = sim.tuning() if args.no_tune else sim.autotune(frames=3, iters=ITERS, allow_pipelined=True)
+    log(f"launch configuration: {tune}")
 
-    def frame(stats=True, iters=ITERS):
+    def frame():
         sim.restore_state()
-        return sim.step(1, iters=iters, stats=stats)
+        sim.step(1, iters=ITERS)
 
     log("warmup")
     for _ in range(args.warmup):
-        st = frame()
-    contacts = st[0]["contacts"]
+        frame()
     torch.cuda.synchronize()
-    log(f"timed: {args.steps} frames, {contacts} contacts")
-    phases = np.zeros(8)
+    log(f"timed: {args.steps} frames")
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        st = frame()
-        phases += np.asarray(st[0]["phases"])
+        frame()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_frame = 1e3 * (t1 - t0) / args.steps
     ms_iter = ms_frame / ITERS
-    per_launch = phases / args.steps
-    per_launch[1:6] /= ITERS
+    sim.restore_state()
+    contacts = sim.step(1, iters=ITERS, stats=True)[0]["contacts"]
+
+    log("per-kernel pass (eager launches)")
+    per_launch = phase_pass(sim, max(5, args.steps // 4))
     names = ["frame_setup", "local_step_rhs", "S_pass", "contact_eval", "cr_and_force_update", "St_pass",
              "integrate", "residual"]
     phase_ms = {k: round(float(v), 5) for k, v in zip(names, per_launch)}
@@ -132,15 +246,16 @@ def main():
     dom = max(cand, key=lambda k: cand[k][0])
     dur_ms, nbytes = cand[dom]
     achieved = nbytes / (dur_ms * 1e-3) / 1e9
+    traffic = st_traffic() if dom == "St_pass" else None
     roofline = {"bound": "hbm", "kernel": {"S_pass": "k_spmv_S (+k_spmv_S_finish)", "St_pass": "k_spmv_St"}[dom],
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": round(traffic) if traffic else None,
                 "bytes_per_launch": int(nbytes), "avg_launch_ms": round(float(dur_ms), 5)}
 
     log("to-tolerance frames")
     # iterate until the NCP residual is <= 1e-6 m; the constraint solve runs CR to a
     # relative residual of TOL_CR (at most TOL_CR_ITERS iterations) instead of 10
-    sim.set_solver(TOL_CR_ITERS, TOL_CR, args.cr_variant)
+    sim.set_solver(TOL_CR_ITERS, TOL_CR, tune.get("cr_variant", 0))
     tol = []
     for _ in range(args.tol_frames):
         sim.restore_state()
@@ -149,7 +264,18 @@ def main():
         s = sim.step(1, iters=0, stats=True)[0]
         torch.cuda.synchronize()
         tol.append((1e3 * (time.perf_counter() - a), s["iters"], s["ncp"]))
+
+    extras = {}
+    weights = os.path.join(ROOT, "paper_2503_15078_amd", "warm_mlp.npz")
+    if not args.no_extras and os.path.exists(weights):
+        log("learned vs previous-frame warm start")
+        params = np.load(weights)["params"]
+        extras["warm_start_benchmark_state"] = warm_compare(sim, params)
+        extras["warm_start_held_out_drops"] = warm_drops(params)
     sim.close()
+    if not args.no_extras and args.batch_scenes > 0:
+        log(f"batch of {args.batch_scenes} scenes")
+        extras["batch"] = batch_throughput(args.batch_scenes, 10)
 
     out = {
         "metric": "ms/local-global iter @58.5k DoFs,800 contacts; ms/frame to NCP res<=1e-6",
@@ -168,15 +294,17 @@ def main():
                                 f"stable Neo-Hookean E=1e6 nu=0.45, h=0.01 s, {contacts} contacts, "
                                 f"{ITERS} L-G iterations/frame, 10 CR iterations; one step = one frame"),
                    "nodes": sc.n, "tets": sc.m, "contacts": contacts, "nnz_S": nnz_s,
-                   "iters_per_frame": ITERS, "cr_variant": ["textbook", "pipelined"][args.cr_variant]},
+                   "iters_per_frame": ITERS, "launch": tune, "graph_replay": True},
         "phases_ms_per_launch": phase_ms,
         "ms_per_frame_to_ncp_1e-6": round(float(np.median([t[0] for t in tol])), 3) if tol else None,
-        "to_tolerance_solver": f"CR to relative residual {TOL_CR} (at most {TOL_CR_ITERS} iterations)",
+        "to_tolerance_solver": (f"CR to relative residual {TOL_CR} (at most {TOL_CR_ITERS} iterations), "
+                                f"previous-frame warm start (zero at this state)"),
         "iters_to_ncp_1e-6": [int(t[1]) for t in tol],
         "ncp_res_reached": [float(t[2]) for t in tol],
         "paper_context_ms_per_iter": PAPER_MS_PER_ITER,
         "roofline": roofline,
     }
+    out.update(extras)
     if args.copy_probe:
         a = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
         b = torch.empty_like(a)

@@ -95,6 +95,7 @@ typedef struct {
   void* hip_stream;
   double cr_tol;           /* > 0: CR also stops once |r| <= cr_tol |r_0| (0: fixed count) */
   int32_t cr_variant;      /* SIM_CR_TEXTBOOK (default) or SIM_CR_PIPELINED */
+  int32_t graph;           /* 1 (default): fixed-iteration frames replay a captured hipGraph */
 } sim_options;
 
 /* Forms of the Conjugate Residual iteration; both give the same iterates in exact
@@ -155,6 +156,29 @@ int sim_create(const sim_mesh* mesh, const sim_material* mat, double h, const si
  * frames: at most cr_iters iterations (<= 1024), stopping early per scene once
  * |r| <= cr_tol |r_0| when cr_tol > 0, in the form cr_variant (SIM_CR_*). */
 int sim_set_solver(sim_t s, int32_t cr_iters, double cr_tol, int32_t cr_variant);
+
+/* Frames with a fixed iteration count are recorded once into a hipGraph (frame setup,
+ * the iterations, integration: one launch per frame) and replayed; the graph is
+ * re-recorded when a setting or the device state layout changes.  on = 0 launches the
+ * kernels one by one (needed for per-phase timing in sim_stats.ms_phase, which is zero
+ * for replayed frames). */
+int sim_set_graph(sim_t s, int32_t on);
+
+/* Launch configuration: CR blocks (one per CU at most), CR form (SIM_CR_*), S-pass
+ * segment length in floats (multiple of 4, >= 64), element-kernel block size (64, 128,
+ * 192 or 256 threads); ms_frame: the autotuner's measured time of the chosen one. */
+typedef struct {
+  int32_t cr_blocks, cr_variant, seg_floats, elem_block;
+  float ms_frame;
+} sim_tuning;
+int sim_get_tuning(sim_t s, sim_tuning* t);
+int sim_set_tuning(sim_t s, const sim_tuning* t);
+/* Autotuner: from the current state (restored afterwards), time `frames` frames of
+ * `iters` iterations for candidate configurations (segment length 1024/2048/4096,
+ * element block 64/128/256, then CR blocks 16..128, both CR forms if allow_pipelined)
+ * by coordinate search, keep the fastest and report it in *best.  The candidates that
+ * change rounding (segment length, CR form) stay within the parity tolerances. */
+int sim_autotune(sim_t s, int32_t frames, int32_t iters, int32_t allow_pipelined, sim_tuning* best);
 
 /* Replace the obstacle set (n >= 0; at most 64). */
 int sim_set_obstacles(sim_t s, int32_t n, const sim_obstacle* obs);

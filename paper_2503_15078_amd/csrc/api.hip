@@ -66,6 +66,13 @@ struct lgsim {
   std::vector<int32_t> iter_canon;    // internal contact index -> canonical position
   hipEvent_t ev[8] = {};
   std::vector<hipEvent_t> fev;        // per-frame timing events
+  // S-pass segmentation (host copies of the row layout, current segment length)
+  std::vector<int64_t> h_row_ptr;
+  std::vector<int32_t> h_row_lo4;
+  int seg_floats = 0;
+  // captured fixed-iteration frame
+  hipGraphExec_t gexec = nullptr;
+  std::vector<unsigned char> gkey;
   struct Snapshot {
     float *qt = nullptr, *vt = nullptr, *pc_world = nullptr;
     double* t = nullptr;
@@ -88,8 +95,19 @@ struct lgsim {
     p = static_cast<T*>(q);
     return SIM_OK;
   }
+  // release one tracked allocation (nullptr is ignored)
+  void release(void* p) {
+    if (!p) return;
+    for (size_t i = 0; i < allocs.size(); ++i)
+      if (allocs[i] == p) {
+        hipFree(p);
+        allocs.erase(allocs.begin() + (long)i);
+        return;
+      }
+  }
   ~lgsim() {
     if (st) hipStreamSynchronize(st);
+    if (gexec) hipGraphExecDestroy(gexec);
     for (void* p : allocs) hipFree(p);
     for (auto& e : ev)
       if (e) hipEventDestroy(e);
@@ -134,6 +152,56 @@ int push_obstacles(lgsim* s) {
 }
 
 // Build one handle from host precomputations of several scenes (concatenated).
+// Segments of the S pass: each row's stored range [lo4, hi4) is cut into pieces of at
+// most seg_floats floats, one wavefront each; rows of several pieces add their partial
+// sums in a second kernel.  Re-run with another length by the autotuner.
+int build_segments(lgsim* s, int seg_floats) {
+  auto& d = s->d;
+  const int N = d.N;
+  std::vector<int> seg_row, seg_col0, seg_len, long_row, long_seg0, long_nseg;
+  std::vector<int64_t> seg_off;
+  for (int i = 0; i < N; ++i) {
+    int64_t len = s->h_row_ptr[i + 1] - s->h_row_ptr[i];
+    int nseg = (int)((len + seg_floats - 1) / seg_floats);
+    if (nseg > 1) {
+      long_row.push_back(i);
+      long_seg0.push_back((int)seg_row.size());
+      long_nseg.push_back(nseg);
+    }
+    for (int q = 0; q < nseg; ++q) {
+      int64_t st = (int64_t)q * seg_floats;
+      seg_row.push_back(nseg > 1 ? -(i + 1) : i);
+      seg_off.push_back(s->h_row_ptr[i] + st);
+      seg_col0.push_back(s->h_row_lo4[i] + (int)st);
+      seg_len.push_back((int)std::min<int64_t>(seg_floats, len - st));
+    }
+  }
+  HIPCHK(hipStreamSynchronize(s->st));
+  for (void* p : {(void*)d.seg_row, (void*)d.seg_col0, (void*)d.seg_len, (void*)d.seg_off, (void*)d.long_row,
+                  (void*)d.long_seg0, (void*)d.long_nseg, (void*)d.partial})
+    s->release(p);
+  d.nseg = (int)seg_row.size();
+  d.nlong = (int)long_row.size();
+  TRY(s->alloc(d.seg_row, d.nseg));
+  TRY(s->alloc(d.seg_col0, d.nseg));
+  TRY(s->alloc(d.seg_len, d.nseg));
+  TRY(s->alloc(d.seg_off, d.nseg));
+  TRY(s->alloc(d.long_row, d.nlong));
+  TRY(s->alloc(d.long_seg0, d.nlong));
+  TRY(s->alloc(d.long_nseg, d.nlong));
+  TRY(s->alloc(d.partial, 3 * (size_t)d.nseg));
+  TRY(upload(s, d.seg_row, seg_row.data(), seg_row.size()));
+  TRY(upload(s, d.seg_col0, seg_col0.data(), seg_col0.size()));
+  TRY(upload(s, d.seg_len, seg_len.data(), seg_len.size()));
+  TRY(upload(s, d.seg_off, seg_off.data(), seg_off.size()));
+  TRY(upload(s, d.long_row, long_row.data(), long_row.size()));
+  TRY(upload(s, d.long_seg0, long_seg0.data(), long_seg0.size()));
+  TRY(upload(s, d.long_nseg, long_nseg.data(), long_nseg.size()));
+  HIPCHK(hipStreamSynchronize(s->st));
+  s->seg_floats = seg_floats;
+  return SIM_OK;
+}
+
 int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vector<sim_obstacle>>& obs) {
   auto& d = s->d;
   const int NS = (int)hs.size();
@@ -169,6 +237,7 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   d.cr_iters = s->opt.cr_iters;
   d.cr_tol = (float)s->opt.cr_tol;
   d.warm = s->opt.warm;
+  d.elem_block = lg::kBlock;
   s->perm_caller.resize(N);
   s->iperm_caller.resize(N);
   for (int k = 0; k < NS; ++k)
@@ -269,27 +338,8 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
     row_ptr[v + 1] += row_ptr[v];
     col_ptr[v + 1] += col_ptr[v];
   }
-  // segments of the S pass
-  std::vector<int> seg_row, seg_col0, seg_len, long_row, long_seg0, long_nseg;
-  std::vector<int64_t> seg_off;
-  for (int i = 0; i < N; ++i) {
-    int64_t len = row_ptr[i + 1] - row_ptr[i];
-    int nseg = (int)((len + kSegFloats - 1) / kSegFloats);
-    if (nseg > 1) {
-      long_row.push_back(i);
-      long_seg0.push_back((int)seg_row.size());
-      long_nseg.push_back(nseg);
-    }
-    for (int q = 0; q < nseg; ++q) {
-      int64_t st = (int64_t)q * kSegFloats;
-      seg_row.push_back(nseg > 1 ? -(i + 1) : i);
-      seg_off.push_back(row_ptr[i] + st);
-      seg_col0.push_back(row_lo4[i] + (int)st);
-      seg_len.push_back((int)std::min<int64_t>(kSegFloats, len - st));
-    }
-  }
-  d.nseg = (int)seg_row.size();
-  d.nlong = (int)long_row.size();
+  s->h_row_ptr = row_ptr;
+  s->h_row_lo4 = row_lo4;
 
   // ---- allocate
   const size_t NV = 3 * (size_t)N4;
@@ -322,14 +372,7 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   TRY(s->alloc(d.row_ptr, N + 1));
   TRY(s->alloc(d.row_lo4, N));
   TRY(s->alloc(d.row_val, (size_t)row_ptr[N]));
-  TRY(s->alloc(d.seg_row, d.nseg));
-  TRY(s->alloc(d.seg_col0, d.nseg));
-  TRY(s->alloc(d.seg_len, d.nseg));
-  TRY(s->alloc(d.seg_off, d.nseg));
-  TRY(s->alloc(d.long_row, d.nlong));
-  TRY(s->alloc(d.long_seg0, d.nlong));
-  TRY(s->alloc(d.long_nseg, d.nlong));
-  TRY(s->alloc(d.partial, 3 * (size_t)d.nseg));
+
   TRY(s->alloc(d.col_ptr, N + 1));
   TRY(s->alloc(d.col_val, (size_t)col_ptr[N]));
   TRY(s->alloc(d.parent, N));
@@ -424,13 +467,7 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   TRY(upload(s, d.row_ptr, row_ptr.data(), row_ptr.size()));
   TRY(upload(s, d.row_lo4, row_lo4.data(), row_lo4.size()));
   TRY(upload(s, d.row_val, row_val.data(), row_val.size()));
-  TRY(upload(s, d.seg_row, seg_row.data(), seg_row.size()));
-  TRY(upload(s, d.seg_col0, seg_col0.data(), seg_col0.size()));
-  TRY(upload(s, d.seg_len, seg_len.data(), seg_len.size()));
-  TRY(upload(s, d.seg_off, seg_off.data(), seg_off.size()));
-  TRY(upload(s, d.long_row, long_row.data(), long_row.size()));
-  TRY(upload(s, d.long_seg0, long_seg0.data(), long_seg0.size()));
-  TRY(upload(s, d.long_nseg, long_nseg.data(), long_nseg.size()));
+  TRY(build_segments(s, kSegFloats));
   TRY(upload(s, d.col_ptr, col_ptr.data(), col_ptr.size()));
   TRY(upload(s, d.col_val, col_val.data(), col_val.size()));
   TRY(upload(s, d.parent, parent.data(), parent.size()));
@@ -797,6 +834,7 @@ int sim_options_default(sim_options* o) {
   o->cr_iters = 10;
   o->cr_tol = 0.0;
   o->cr_variant = SIM_CR_TEXTBOOK;
+  o->graph = 1;
   o->warm = SIM_WARM_PREV;
   o->ncp_tol = 1e-6;
   o->max_iters = 200;
@@ -872,6 +910,120 @@ int sim_set_solver(sim_t s, int32_t cr_iters, double cr_tol, int32_t cr_variant)
   s->opt.cr_variant = cr_variant;
   s->d.cr_iters = cr_iters;
   s->d.cr_tol = (float)cr_tol;
+  return SIM_OK;
+}
+
+int sim_set_graph(sim_t s, int32_t on) {
+  if (!s) {
+    lg::set_error("null handle");
+    return SIM_E_ARG;
+  }
+  s->opt.graph = on != 0;
+  return SIM_OK;
+}
+
+int sim_get_tuning(sim_t s, sim_tuning* t) {
+  if (!s || !t) {
+    lg::set_error("bad arguments");
+    return SIM_E_ARG;
+  }
+  t->cr_blocks = s->cr_blocks;
+  t->cr_variant = s->opt.cr_variant;
+  t->seg_floats = s->seg_floats;
+  t->elem_block = s->d.elem_block;
+  t->ms_frame = 0.0f;
+  return SIM_OK;
+}
+
+int sim_set_tuning(sim_t s, const sim_tuning* t) {
+  if (!s || !t || t->seg_floats < 64 || t->seg_floats % 4 != 0 || t->elem_block < 64 || t->elem_block > lg::kBlock ||
+      t->elem_block % lg::kWave != 0 || (t->cr_variant != SIM_CR_TEXTBOOK && t->cr_variant != SIM_CR_PIPELINED)) {
+    lg::set_error("bad tuning");
+    return SIM_E_ARG;
+  }
+  const int need = (s->d.CMAX + 255) / 256;
+  if (t->cr_blocks < need || t->cr_blocks > lg::cr_max_blocks()) {
+    lg::set_error("cr_blocks must lie in [" + std::to_string(need) + ", " + std::to_string(lg::cr_max_blocks()) + "]");
+    return SIM_E_ARG;
+  }
+  if (t->seg_floats != s->seg_floats) TRY(build_segments(s, t->seg_floats));
+  s->cr_blocks = t->cr_blocks;
+  s->opt.cr_variant = t->cr_variant;
+  s->d.elem_block = t->elem_block;
+  return SIM_OK;
+}
+
+int sim_autotune(sim_t s, int32_t frames, int32_t iters, int32_t allow_pipelined, sim_tuning* best) {
+  if (!s || frames <= 0 || iters <= 0 || !best) {
+    lg::set_error("bad arguments");
+    return SIM_E_ARG;
+  }
+  TRY(sim_save_state(s));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  // time of `frames` frames from the saved state (each frame restarts from it), after one
+  // untimed frame that also captures the graph
+  auto measure = [&](const sim_tuning& t, float* ms) -> int {
+    TRY(sim_set_tuning(s, &t));
+    TRY(sim_restore_state(s));
+    TRY(sim_step(s, 1, iters, nullptr));
+    float total = 0.0f;
+    for (int f = 0; f < frames; ++f) {
+      TRY(sim_restore_state(s));
+      HIPCHK(hipEventRecord(e0, s->st));
+      TRY(sim_step(s, 1, iters, nullptr));
+      HIPCHK(hipEventRecord(e1, s->st));
+      HIPCHK(hipEventSynchronize(e1));
+      float m = 0.0f;
+      HIPCHK(hipEventElapsedTime(&m, e0, e1));
+      total += m;
+    }
+    *ms = total / frames;
+    return SIM_OK;
+  };
+  sim_tuning cur{};
+  TRY(sim_get_tuning(s, &cur));
+  float best_ms = 0.0f;
+  int rc = measure(cur, &best_ms);
+  // coordinate search: S-pass segment length, element block size, then the CR launch
+  auto try_cand = [&](sim_tuning c) -> int {
+    float m = 0.0f;
+    TRY(measure(c, &m));
+    if (m < best_ms) {
+      best_ms = m;
+      cur = c;
+    }
+    return SIM_OK;
+  };
+  for (int seg : {1024, 2048, 4096})
+    if (rc == SIM_OK && seg != cur.seg_floats) {
+      sim_tuning c = cur;
+      c.seg_floats = seg;
+      rc = try_cand(c);
+    }
+  for (int eb : {64, 128, 256})
+    if (rc == SIM_OK && eb != cur.elem_block) {
+      sim_tuning c = cur;
+      c.elem_block = eb;
+      rc = try_cand(c);
+    }
+  const int need = (s->d.CMAX + 255) / 256, most = lg::cr_max_blocks();
+  for (int v = 0; v <= (allow_pipelined ? 1 : 0); ++v)
+    for (int g : {16, 32, 48, 64, 96, 128})
+      if (rc == SIM_OK && g >= need && g <= most && !(v == cur.cr_variant && g == cur.cr_blocks)) {
+        sim_tuning c = cur;
+        c.cr_variant = v;
+        c.cr_blocks = g;
+        rc = try_cand(c);
+      }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != SIM_OK) return rc;
+  TRY(sim_set_tuning(s, &cur));
+  TRY(sim_restore_state(s));
+  cur.ms_frame = best_ms;
+  *best = cur;
   return SIM_OK;
 }
 
@@ -972,6 +1124,45 @@ int sim_set_pin_motion(sim_t s, int32_t n_groups, const double* lin, const doubl
   return upload(s, s->d.grp, grp.data(), grp.size());
 }
 
+namespace {
+
+// One fixed-iteration frame (setup, iters iterations, integration) replayed from a
+// hipGraph captured on the handle's stream; re-captured whenever the device state
+// descriptor or a launch setting differs from the captured one.
+int frame_by_graph(lgsim* s, int iters) {
+  std::vector<unsigned char> key(sizeof(lg::Dev) + 8 * sizeof(int));
+  std::memcpy(key.data(), &s->d, sizeof(lg::Dev));
+  const int extra[8] = {iters, s->cr_blocks, s->opt.cr_variant, s->opt.warm, (int)s->has_model, (int)s->record_pairs,
+                        s->seg_floats, s->d.elem_block};
+  std::memcpy(key.data() + sizeof(lg::Dev), extra, sizeof(extra));
+  if (!s->gexec || key != s->gkey) {
+    if (s->gexec) {
+      HIPCHK(hipGraphExecDestroy(s->gexec));
+      s->gexec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal));
+    int rc = frame_setup(s);
+    for (int k = 0; rc == SIM_OK && k < iters; ++k) rc = iteration(s, false, k);
+    if (rc == SIM_OK) rc = finish_frame(s);
+    hipError_t e = hipStreamEndCapture(s->st, &g);
+    if (rc != SIM_OK) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    HIPCHK(e);
+    e = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    HIPCHK(e);
+    s->gkey = key;
+  }
+  HIPCHK(hipGraphLaunch(s->gexec, s->st));
+  s->iter_c = -1;
+  return SIM_OK;
+}
+
+}  // namespace
+
 int sim_step(sim_t s, int32_t frames, int32_t iters, sim_stats* stats) {
   if (!s || frames < 0 || iters < 0) {
     lg::set_error("bad arguments");
@@ -990,6 +1181,25 @@ int sim_step(sim_t s, int32_t frames, int32_t iters, sim_stats* stats) {
         if (e) hipEventRecord(*e, s->st);
       }
     };
+    if (iters > 0 && s->opt.graph) {
+      TRY(frame_by_graph(s, iters));
+      int rc = frame_status(s);
+      if (rc != SIM_OK) return rc;
+      if (timed) {
+        lg::launch_residual(s->d, s->st);
+        HIPCHK(hipMemcpyAsync(s->h_res, s->d.res, sizeof(float) * s->d.NS, hipMemcpyDeviceToHost, s->st));
+        HIPCHK(hipStreamSynchronize(s->st));
+        double res = 0.0;
+        for (int q = 0; q < s->d.NS; ++q) res = std::max(res, (double)s->h_res[q]);
+        auto& st = stats[f];
+        st.iters_done = iters;
+        st.n_contacts = s->iter_c;
+        st.ncp_res = res;
+        st.ms_frame = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        for (int q = 0; q < 8; ++q) st.ms_phase[q] = 0.0f;  // not resolved inside a graph
+      }
+      continue;
+    }
     rec(0);
     TRY(frame_setup(s));
     rec(1);

@@ -39,6 +39,7 @@ struct Dev {
   int CMAX;                        // contact capacity (all scenes)
   int64_t KCAP;                    // Delassus storage capacity (floats)
   int nseg, nlong;                 // S-pass segments, multi-segment rows
+  int elem_block;                  // threads per block of the element kernel (64..256)
   double h;
   double g[3];
   int cr_iters;

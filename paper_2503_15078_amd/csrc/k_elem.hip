@@ -344,7 +344,8 @@ __global__ void __launch_bounds__(kBlock) k_element(Dev d) {
 }
 
 void launch_element(const Dev& d, hipStream_t st) {
-  hipLaunchKernelGGL(k_element, dim3((d.M + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d);
+  const int bs = d.elem_block > 0 ? d.elem_block : kBlock;
+  hipLaunchKernelGGL(k_element, dim3((d.M + bs - 1) / bs), dim3(bs), 0, st, d);
 }
 
 // ---------------------------------------------------------------- node gather

@@ -47,7 +47,13 @@ class sim_options(C.Structure):
     _fields_ = [("gravity", C.c_double * 3), ("pin_weight_scale", C.c_double),
                 ("contact_margin", C.c_double), ("cr_iters", C.c_int32), ("warm", C.c_int32),
                 ("ncp_tol", C.c_double), ("max_iters", C.c_int32), ("max_contacts", C.c_int32),
-                ("hip_stream", C.c_void_p), ("cr_tol", C.c_double), ("cr_variant", C.c_int32)]
+                ("hip_stream", C.c_void_p), ("cr_tol", C.c_double), ("cr_variant", C.c_int32),
+                ("graph", C.c_int32)]
+
+
+class sim_tuning(C.Structure):
+    _fields_ = [("cr_blocks", C.c_int32), ("cr_variant", C.c_int32), ("seg_floats", C.c_int32),
+                ("elem_block", C.c_int32), ("ms_frame", C.c_float)]
 
 
 class sim_obstacle(C.Structure):
@@ -95,6 +101,10 @@ def load():
         "sim_destroy": [C.c_void_p],
         "sim_set_solver": [C.c_void_p, i32, d, i32],
         "sim_set_warm_model": [C.c_void_p, P(C.c_float), i32],
+        "sim_set_graph": [C.c_void_p, i32],
+        "sim_get_tuning": [C.c_void_p, P(sim_tuning)],
+        "sim_set_tuning": [C.c_void_p, P(sim_tuning)],
+        "sim_autotune": [C.c_void_p, i32, i32, i32, P(sim_tuning)],
         "sim_set_warm_mode": [C.c_void_p, i32],
         "sim_record_training_pairs": [C.c_void_p, i32],
         "sim_read_training_pairs": [C.c_void_p, P(i32), P(i32), P(C.c_float), P(C.c_float), i32, P(i32)],
@@ -306,6 +316,27 @@ class Sim:
 
     def set_solver(self, cr_iters, cr_tol=0.0, cr_variant=0):
         _check(_lib.sim_set_solver(self.h, int(cr_iters), float(cr_tol), int(cr_variant)))
+
+    # ---- launch configuration
+    def set_graph(self, on):
+        _check(_lib.sim_set_graph(self.h, int(bool(on))))
+
+    def tuning(self):
+        t = sim_tuning()
+        _check(_lib.sim_get_tuning(self.h, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in sim_tuning._fields_}
+
+    def set_tuning(self, **kw):
+        t = sim_tuning()
+        _check(_lib.sim_get_tuning(self.h, C.byref(t)))
+        for k, v in kw.items():
+            setattr(t, k, v)
+        _check(_lib.sim_set_tuning(self.h, C.byref(t)))
+
+    def autotune(self, frames=3, iters=5, allow_pipelined=True):
+        t = sim_tuning()
+        _check(_lib.sim_autotune(self.h, int(frames), int(iters), int(bool(allow_pipelined)), C.byref(t)))
+        return {k: getattr(t, k) for k, _ in sim_tuning._fields_}
 
     # ---- learned warm start
     def set_warm_model(self, params):

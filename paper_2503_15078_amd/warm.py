@@ -76,44 +76,52 @@ def fold(flat, mu, sd, ts):
 
 # ------------------------------------------------------------------ data
 def training_scenes(seeds):
-    """Config-2/3/4-style scenes: teaser-scale stars, twisted bars pressed into a plane
-    (mu in {0.2, 0.8}, E in {1e5, 1e6}), and a batch of small blobs."""
+    """(kind, seed, scene, frames): config-1-style cube drops (model, E, mu, nodes and
+    drop height varied per seed; whole drops), the first frames of teaser-scale stars
+    (config 2) and of blobs resting on tilted planes (config 4).  Only frames whose NCP
+    residual reaches 1e-6 m contribute samples."""
     out = []
     for s in seeds:
+        rng = np.random.default_rng(s)
         k = s % 4
         if k in (0, 1):
-            out.append(("teaser", s, scenes.teaser_scene(s)))
+            sc = scenes.cube_drop(s, model=[1, 2][int(rng.integers(2))], nodes=int(rng.integers(4, 8)),
+                                  mu=float(rng.uniform(0.1, 0.9)), E=float(10 ** rng.uniform(4.5, 6)),
+                                  height=float(rng.uniform(0.01, 0.08)))
+            out.append(("cube", s, sc, 60))
         elif k == 2:
-            out.append(("bar", s, scenes.twist_bar(s, model=2 + (s // 4) % 2, E=[1e5, 1e6][(s // 8) % 2],
-                                                    mu=[0.2, 0.8][(s // 16) % 2])))
+            out.append(("teaser", s, scenes.teaser_scene(s), 2))
         else:
-            out.append(("blobs", s, scenes.batch_scenes(s, count=8)))
+            for i, b in enumerate(scenes.batch_scenes(s, count=4, hi=6000)):
+                out.append(("blob", 100 * s + i, b, 3))
     return out
 
 
-def generate(seeds, frames, cr_iters=300, cr_tol=1e-4, log=print):
-    """Run each scene to tolerance (NCP residual <= 1e-6 m) with the previous-frame warm
-    start and keep (features, converged impulse) of every frame that converged."""
+def generate(seeds, frames=None, cr_iters=300, cr_tol=1e-3, log=print):
+    """Run each scene frame by frame until the NCP residual is <= 1e-6 m (at most 100
+    iterations), with the previous-frame warm start, and keep (features, converged
+    impulse) of every frame that converged."""
     feats, tgts = [], []
-    for kind, seed, sc in training_scenes(seeds):
+    for kind, seed, sc, nf in training_scenes(seeds):
+        nf = nf if frames is None else min(nf, frames)
         t0 = time.perf_counter()
-        sim = lgsim.Sim(batch=sc, cr_iters=cr_iters, cr_tol=cr_tol) if kind == "blobs" else \
-            lgsim.Sim(sc, cr_iters=cr_iters, cr_tol=cr_tol)
+        sim = lgsim.Sim(sc, cr_iters=cr_iters, cr_tol=cr_tol, max_iters=100)
         sim.record_training_pairs(True)
-        kept = 0
-        for f in range(frames):
+        kept = conv = 0
+        for f in range(nf):
             try:
-                st = sim.step(1, iters=0)
+                st = sim.step(1, iters=0)[0]
             except lgsim.SimError as e:
                 log(f"  {kind} {seed}: stop at frame {f}: {e}")
                 break
-            if max(s["ncp"] for s in st) <= 1e-6 and st[0]["contacts"] > 0:
+            if st["ncp"] <= 1e-6 and st["contacts"] > 0:
                 _, _, x, t = sim.read_training_pairs()
                 feats.append(x)
                 tgts.append(t)
                 kept += len(x)
+                conv += 1
         sim.close()
-        log(f"  {kind} seed {seed}: {kept} samples in {time.perf_counter() - t0:.1f} s")
+        log(f"  {kind} seed {seed}: {conv}/{nf} frames converged, {kept} samples, {time.perf_counter() - t0:.1f} s")
     return np.concatenate(feats), np.concatenate(tgts)
 
 
@@ -165,13 +173,14 @@ def val_loss(net, Xv, Tv):
 
 
 # ------------------------------------------------------------------ evaluation
-def compare(scene, params, frames, cr_iters=300, cr_tol=1e-4, cr_variant=0):
-    """Frames to NCP residual <= 1e-6 m from the same start with the previous-frame and
-    the learned warm start: per-frame iterations and ms (device-synchronised)."""
+def compare(scene, params, frames, cr_iters=300, cr_tol=1e-3, max_iters=100, cr_variant=0):
+    """Frames to NCP residual <= 1e-6 m (at most max_iters iterations) from the same start
+    with the previous-frame and the learned warm start: per-frame iterations, ms
+    (device-synchronised) and residual reached."""
     import torch
     out = {}
     for mode, name in ((lgsim.SIM_WARM_PREV, "plain"), (lgsim.SIM_WARM_MLP, "learned")):
-        sim = lgsim.Sim(scene, cr_iters=cr_iters, cr_tol=cr_tol, cr_variant=cr_variant)
+        sim = lgsim.Sim(scene, cr_iters=cr_iters, cr_tol=cr_tol, cr_variant=cr_variant, max_iters=max_iters)
         sim.set_warm_model(params)
         sim.set_warm_mode(mode)
         its, ms, res = [], [], []

@@ -181,3 +181,33 @@ def test_mlp_mode_without_model_is_an_error():
         sim.step(1)
     assert e.value.code == -6
     sim.close()
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained warm-start weights in the package")
+def test_learned_warm_start_gain_on_held_out_drops():
+    """The trained network (trained on other seeds) against the previous-frame warm start
+    on held-out cube drops: fewer local-global iterations to NCP residual <= 1e-6 m in
+    total, and the oracle's float64 residual of the GPU's final state confirms the
+    convergence the GPU reports on sampled frames of the learned run."""
+    params = np.load(WEIGHTS)["params"]
+    total = {"plain": 0, "learned": 0}
+    for seed in (1001, 1002, 1003):
+        sc = scenes.cube_drop(seed)
+        for mode, name in ((lgsim.SIM_WARM_PREV, "plain"), (lgsim.SIM_WARM_MLP, "learned")):
+            sim = lgsim.Sim(sc, cr_iters=300, cr_tol=1e-3, max_iters=100)
+            sim.set_warm_model(params)
+            sim.set_warm_mode(mode)
+            o = OracleSim(sc)
+            judged = 0
+            for f in range(60):
+                q0, _, _ = sim.read_state()
+                st = sim.step(1, iters=0)[0]
+                total[name] += st["iters"]
+                if name == "learned" and st["contacts"] and st["ncp"] <= 1e-6 and f % 15 == 0:
+                    q1, _, con = sim.read_state()
+                    fc = o.contacts_from_keys(con["node"], con["obst"], q0)
+                    assert o.residual(fc, q1, q0, con["lam"]) <= 2e-6
+                    judged += 1
+            sim.close()
+    print(f"iterations over 3 held-out drops x 60 frames: {total}")
+    assert total["learned"] < total["plain"]
