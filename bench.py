@@ -190,6 +190,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--no-extras", action="store_true", help="skip the warm-start comparison and the batch")
     ap.add_argument("--batch-scenes", type=int, default=64)
+    ap.add_argument("--batch-only", action="store_true", help="only the batch measurement (for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the benchmark, run a plain float32 copy of 256 MiB three times "
                          "(reference kernel for scaling the HBM byte counters)")
@@ -206,6 +207,9 @@ def main():
     from paper_2503_15078_amd import lgsim, scenes
 
     torch.cuda.init()
+    if args.batch_only:
+        print(json.dumps({"batch": batch_throughput(args.batch_scenes, 10)}))
+        return
     log("building scene")
     sc = scenes.teaser_scene(0)
     hp = lgsim.HostPrecompute(sc)

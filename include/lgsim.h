@@ -175,7 +175,7 @@ int sim_get_tuning(sim_t s, sim_tuning* t);
 int sim_set_tuning(sim_t s, const sim_tuning* t);
 /* Autotuner: from the current state (restored afterwards), time `frames` frames of
  * `iters` iterations for candidate configurations (segment length 1024/2048/4096,
- * element block 64/128/256, then CR blocks 16..128, both CR forms if allow_pipelined)
+ * element block 64/128/256, then CR blocks 16..256, both CR forms if allow_pipelined)
  * by coordinate search, keep the fastest and report it in *best.  The candidates that
  * change rounding (segment length, CR form) stay within the parity tolerances. */
 int sim_autotune(sim_t s, int32_t frames, int32_t iters, int32_t allow_pipelined, sim_tuning* best);

@@ -1010,7 +1010,7 @@ int sim_autotune(sim_t s, int32_t frames, int32_t iters, int32_t allow_pipelined
     }
   const int need = (s->d.CMAX + 255) / 256, most = lg::cr_max_blocks();
   for (int v = 0; v <= (allow_pipelined ? 1 : 0); ++v)
-    for (int g : {16, 32, 48, 64, 96, 128})
+    for (int g : {16, 32, 48, 64, 96, 128, 192, 256})
       if (rc == SIM_OK && g >= need && g <= most && !(v == cur.cr_variant && g == cur.cr_blocks)) {
         sim_tuning c = cur;
         c.cr_variant = v;

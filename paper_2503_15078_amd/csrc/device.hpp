@@ -16,7 +16,7 @@ constexpr int kBlock = 256;
 constexpr int kWave = 64;
 constexpr int kMaxObstacles = 64;
 constexpr int kDelTile = 16;      // Delassus tile (contacts x contacts)
-constexpr int kDelChunk = 64;     // Delassus depth chunk staged in LDS
+constexpr int kDelChunk = 256;    // Delassus depth chunk staged in LDS
 constexpr int kMaxCrIters = 1024;
 constexpr int kMlpParams = 20752;   // 16x128 + 128 + 128x128 + 128 + 16x128 + 16 (padded shapes)
 constexpr int kMlpMaxBlocks = 256;  // blocks of one training launch (64 samples each)

@@ -399,14 +399,21 @@ __global__ void __launch_bounds__(kBlock) k_delassus_tiles(Dev d) {
     float acc[kPP];
     for (int r = 0; r < kPP; ++r) acc[r] = 0.0f;
     for (int base = 0; base < maxL; base += kDelChunk) {
-      for (int p = tid; p < kDelTile * kDelChunk; p += kBlock) {
-        int r = p / kDelChunk, q = p % kDelChunk;
-        int depthidx = base + q;  // 0 = root
-        float vj = 0.0f, vk = 0.0f;
-        if (r < nJ && depthidx <= dJ[r]) vj = d.col_val[cJ[r] + (dJ[r] - depthidx)];
-        if (r < nK && depthidx <= dK[r]) vk = d.col_val[cK[r] + (dK[r] - depthidx)];
-        PJ[r][q] = vj;
-        PK[r][q] = vk;
+      // all loads of the chunk issued before the LDS stores (one memory round trip)
+      constexpr int kPer = kDelTile * kDelChunk / kBlock;
+      float vj[kPer], vk[kPer];
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int p = tid + u * kBlock, r = p / kDelChunk, q = p % kDelChunk;
+        const int depthidx = base + q;  // 0 = root
+        vj[u] = (r < nJ && depthidx <= dJ[r]) ? d.col_val[cJ[r] + (dJ[r] - depthidx)] : 0.0f;
+        vk[u] = (r < nK && depthidx <= dK[r]) ? d.col_val[cK[r] + (dK[r] - depthidx)] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int p = tid + u * kBlock, r = p / kDelChunk, q = p % kDelChunk;
+        PJ[r][q] = vj[u];
+        PK[r][q] = vk[u];
       }
       __syncthreads();
       for (int r = 0; r < kPP; ++r) {

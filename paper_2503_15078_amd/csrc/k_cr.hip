@@ -256,9 +256,9 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
         if (q < 3 * nv) Zs[q * zpad + e] = v[q];
     }
   };
-  // Y_v,t = sum_k K_jk V_v,k for every owned row t and nv vectors.  staged: K and V in
-  // LDS, 16 lanes per row over float4 columns (16 rows per pass); else one wavefront per
-  // row with V_v,k component q at Vg[(3 v + q) CM + k] in global memory.
+  // Y_v,t = sum_k K_jk V_v,k for every owned row t and nv vectors, 16 lanes per row (16
+  // rows per pass).  staged: V in Zs; else V_v,k component q at Vg[(3 v + q) CM + k] in
+  // global memory.  K rows and V both in LDS: float4 over the padded columns.
   auto matvec_rows = [&](auto nv, bool staged, const float* Vg, float (*Y0)[kCrRows], float (*Y1)[kCrRows]) {
     constexpr int NV = decltype(nv)::value;
     if (k_in_lds && staged) {
@@ -292,19 +292,25 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
       __syncthreads();
       return;
     }
-    for (int t = wave; t < R; t += kBlock / kWave) {
+    // K rows from global memory (or unstaged V): 16 lanes per row, 16 rows in flight
+    const int grp = tid >> 4, gl = tid & 15;
+    for (int t = grp; t < R; t += kBlock / 16) {
       const int sl = row_slot[t], cs = sl_cs[sl], cnt = sl_ce[sl] - cs, pc = pad4(cnt);
       const int rrow = j0 + t - max(cs, j0);
       const float* Krow = k_in_lds ? Ks + sl_kb[sl] + rrow * pc : d.K + sl_koff[sl] + (int64_t)(j0 + t - cs) * cnt;
       float a[3 * NV];
+#pragma unroll
       for (int q = 0; q < 3 * NV; ++q) a[q] = 0.0f;
-      for (int k = lane; k < cnt; k += kWave) {
+#pragma unroll 4
+      for (int k = gl; k < cnt; k += 16) {
         const float kv = Krow[k];
 #pragma unroll
         for (int q = 0; q < 3 * NV; ++q) a[q] += kv * (staged ? Zs[q * zpad + sl_zb[sl] + k] : Vg[q * CM + cs + k]);
       }
-      for (int q = 0; q < 3 * NV; ++q) a[q] = wave_sum_cr(a[q]);
-      if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < 3 * NV; ++q)
+        for (int o = 8; o > 0; o >>= 1) a[q] += __shfl_xor(a[q], o, 16);
+      if (gl == 0) {
         for (int q = 0; q < 3; ++q) Y0[q][t] = a[q];
         if constexpr (NV == 2)
           for (int q = 0; q < 3; ++q) Y1[q][t] = a[3 + q];

@@ -349,17 +349,26 @@ void launch_element(const Dev& d, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------- node gather
-// b'_v = sum of the corner forces of v (fixed order) + h^2 w_pin (target - q~_v).
+// b'_v = sum of the corner forces of v + h^2 w_pin (target - q~_v).  Eight lanes per
+// node: lane l adds slots l, l+8, ... in order, then the eight partial sums are combined
+// by a fixed butterfly, so the result does not depend on timing.
+constexpr int kGatherLanes = 8;
 __global__ void k_gather(Dev d) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= d.N) return;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = gid / kGatherLanes, l = gid % kGatherLanes;
+  const bool ok = v < d.N;  // whole groups of 8 lanes share v, so the butterfly stays in range
   float acc[3] = {0.0f, 0.0f, 0.0f};
-  int e = d.g_ptr[v + 1];
-  for (int p = d.g_ptr[v]; p < e; ++p) {
-    int slot = d.g_slot[p];
-    int corner = slot / d.M, tet = slot - corner * d.M;
-    for (int c = 0; c < 3; ++c) acc[c] += d.fc[(corner * 3 + c) * d.M + tet];
+  if (ok) {
+    const int e = d.g_ptr[v + 1];
+    for (int p = d.g_ptr[v] + l; p < e; p += kGatherLanes) {
+      int slot = d.g_slot[p];
+      int corner = slot / d.M, tet = slot - corner * d.M;
+      for (int c = 0; c < 3; ++c) acc[c] += d.fc[(corner * 3 + c) * d.M + tet];
+    }
   }
+  for (int o = kGatherLanes / 2; o > 0; o >>= 1)
+    for (int c = 0; c < 3; ++c) acc[c] += __shfl_xor(acc[c], o, kGatherLanes);
+  if (!ok || l != 0) return;
   float w = d.pin_w[v];
   if (w != 0.0f)
     for (int c = 0; c < 3; ++c) acc[c] += w * (d.tgt[c * d.N4 + v] - d.qp[c * d.N4 + v]);
@@ -367,7 +376,8 @@ __global__ void k_gather(Dev d) {
 }
 
 void launch_gather(const Dev& d, hipStream_t st) {
-  hipLaunchKernelGGL(k_gather, dim3((d.N + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d);
+  const int64_t threads = (int64_t)d.N * kGatherLanes;
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, d);
 }
 
 // ---------------------------------------------------------------- finiteness check
