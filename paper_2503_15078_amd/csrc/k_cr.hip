@@ -178,7 +178,27 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
   const bool k_in_lds = sl_kb[nsl] <= kCrKFloats;
   const int zpad = sl_zb[nsl];
   const bool z_in_lds = 3 * NZ * zpad <= kCrZFloats;
-  if (k_in_lds && nsl == 1) {
+  if (k_in_lds && nsl == 1 && ((sl_ce[0] - sl_cs[0]) & 3) == 0 &&
+      ((sl_koff[0] + (int64_t)(j0 - sl_cs[0]) * (sl_ce[0] - sl_cs[0])) & 3) == 0) {
+    // one scene, rows a multiple of 4 long and 16-byte aligned: the padded layout is the
+    // global one, copied as float4 with eight loads in flight per thread
+    const int cnt = sl_ce[0] - sl_cs[0], total4 = R * cnt / 4;
+    const float4* src = reinterpret_cast<const float4*>(d.K + sl_koff[0] + (int64_t)(j0 - sl_cs[0]) * cnt);
+    float4* dst = reinterpret_cast<float4*>(Ks);
+    for (int base = 0; base < total4; base += 8 * kBlock) {
+      float4 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = base + tid + u * kBlock;
+        if (e < total4) v[u] = src[e];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = base + tid + u * kBlock;
+        if (e < total4) dst[e] = v[u];
+      }
+    }
+  } else if (k_in_lds && nsl == 1) {
     // one scene: the block's rows are contiguous in K; eight loads in flight per thread
     const int cs = sl_cs[0], cnt = sl_ce[0] - cs, pc = pad4(cnt), total = R * cnt;
     const float* src = d.K + sl_koff[0] + (int64_t)(j0 - cs) * cnt;

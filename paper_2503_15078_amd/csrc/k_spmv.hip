@@ -29,6 +29,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv_S(Dev d, const float* __restric
   const float4* __restrict__ by = reinterpret_cast<const float4*>(b + d.N4 + col0);
   const float4* __restrict__ bz = reinterpret_cast<const float4*>(b + 2 * d.N4 + col0);
   float ax = 0.0f, ay = 0.0f, az = 0.0f;
+#pragma unroll 4
   for (int q = lane; q < len4; q += kWave) {
     float4 s = S4[q];
     float4 x = bx[q], yy = by[q], z = bz[q];
@@ -90,6 +91,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv_St(Dev d, const float* __restri
   while (a != -1) {
     int e = __builtin_amdgcn_readfirstlane(d.chain_end[a]);
     int len = e - a + 1;
+#pragma unroll 4
     for (int k = lane; k < len; k += kWave) {
       float s = col[t + k];
       ax += s * y0[a + k];
