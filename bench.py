@@ -40,8 +40,8 @@ TOL_CR, TOL_CR_ITERS, TOL_MAX_ITERS = 1e-3, 300, 100
 # counters read for a plain float32 copy of 256 MiB (FETCH_SIZE reads half the bytes a
 # kernel fetches on this device: x2.0; WRITE_SIZE reads them exactly: x1.0).  Valid only
 # for the kernel source they were taken on.
-ST_COUNTERS = {"source": "paper_2503_15078_amd/csrc/k_spmv.hip", "sha256_16": "9da4d0e75f5fe7da",
-               "fetch_kib": 56640.878, "write_kib": 456.375, "fetch_scale": 2.0, "write_scale": 1.0}
+ST_COUNTERS = {"source": "paper_2503_15078_amd/csrc/k_spmv.hip", "sha256_16": "41d4e0a3af49d4f3",
+               "fetch_kib": 56527.168, "write_kib": 456.455, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def log(msg):
@@ -188,6 +188,8 @@ def main():
     ap.add_argument("--tol-frames", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
+    ap.add_argument("--launch", default=None,
+                    help="fixed launch configuration cr_blocks,cr_variant,seg_floats,elem_block (no autotuning)")
     ap.add_argument("--no-extras", action="store_true", help="skip the warm-start comparison and the batch")
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--batch-only", action="store_true", help="only the batch measurement (for profiling)")
@@ -218,7 +220,12 @@ def main():
     log(f"n={sc.n} m={sc.m} nnz(S)={nnz_s}; creating solver")
     sim = lgsim.Sim(sc)
     sim.save_state()
-    tune = sim.tuning() if args.no_tune else sim.autotune(frames=3, iters=ITERS, allow_pipelined=True)
+    if args.launch:
+        cb, cv, sf, eb = (int(x) for x in args.launch.split(","))
+        sim.set_tuning(cr_blocks=cb, cr_variant=cv, seg_floats=sf, elem_block=eb)
+        tune = sim.tuning()
+    else:
+        tune = sim.tuning() if args.no_tune else sim.autotune(frames=3, iters=ITERS, allow_pipelined=True)
     log(f"launch configuration: {tune}")
 
     def frame():
@@ -246,7 +253,12 @@ def main():
              "integrate", "residual"]
     phase_ms = {k: round(float(v), 5) for k, v in zip(names, per_launch)}
     b_s, b_st = algorithmic_bytes(sc.n, nnz_s)
-    cand = {"S_pass": (per_launch[2], b_s), "St_pass": (per_launch[5], b_st)}
+    # S-pass kernel durations for the roofline: back-to-back launches between one pair of
+    # HIP events on the solver's stream (per-launch events would add their own overhead)
+    sim.restore_state()
+    sim.step(1, iters=ITERS)
+    k_ms = {"S_pass": sim.time_kernel(0, 100), "St_pass": sim.time_kernel(1, 100)}
+    cand = {"S_pass": (k_ms["S_pass"], b_s), "St_pass": (k_ms["St_pass"], b_st)}
     dom = max(cand, key=lambda k: cand[k][0])
     dur_ms, nbytes = cand[dom]
     achieved = nbytes / (dur_ms * 1e-3) / 1e9
@@ -300,6 +312,7 @@ def main():
                    "nodes": sc.n, "tets": sc.m, "contacts": contacts, "nnz_S": nnz_s,
                    "iters_per_frame": ITERS, "launch": tune, "graph_replay": True},
         "phases_ms_per_launch": phase_ms,
+        "s_pass_kernels_ms": {k: round(v, 5) for k, v in k_ms.items()},
         "ms_per_frame_to_ncp_1e-6": round(float(np.median([t[0] for t in tol])), 3) if tol else None,
         "to_tolerance_solver": (f"CR to relative residual {TOL_CR} (at most {TOL_CR_ITERS} iterations), "
                                 f"previous-frame warm start (zero at this state)"),

@@ -913,6 +913,33 @@ int sim_set_solver(sim_t s, int32_t cr_iters, double cr_tol, int32_t cr_variant)
   return SIM_OK;
 }
 
+int sim_time_kernel(sim_t s, int32_t which, int32_t reps, float* ms_avg) {
+  if (!s || (which != 0 && which != 1) || reps <= 0 || !ms_avg) {
+    lg::set_error("bad arguments");
+    return SIM_E_ARG;
+  }
+  auto& d = s->d;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  auto launch = [&]() {
+    if (which == 0) lg::launch_spmv_S(d, s->st, d.b, d.tmp);  // reads b, writes scratch
+    else lg::launch_spmv_St(d, s->st, d.y, d.qp, d.tmp);      // reads y and q~, writes scratch
+  };
+  launch();
+  HIPCHK(hipEventRecord(e0, s->st));
+  for (int r = 0; r < reps; ++r) launch();
+  HIPCHK(hipEventRecord(e1, s->st));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.0f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  TRY(check_launch("timed kernel"));
+  *ms_avg = ms / reps;
+  return SIM_OK;
+}
+
 int sim_set_graph(sim_t s, int32_t on) {
   if (!s) {
     lg::set_error("null handle");

@@ -102,6 +102,7 @@ def load():
         "sim_set_solver": [C.c_void_p, i32, d, i32],
         "sim_set_warm_model": [C.c_void_p, P(C.c_float), i32],
         "sim_set_graph": [C.c_void_p, i32],
+        "sim_time_kernel": [C.c_void_p, i32, i32, P(C.c_float)],
         "sim_get_tuning": [C.c_void_p, P(sim_tuning)],
         "sim_set_tuning": [C.c_void_p, P(sim_tuning)],
         "sim_autotune": [C.c_void_p, i32, i32, i32, P(sim_tuning)],
@@ -320,6 +321,12 @@ class Sim:
     # ---- launch configuration
     def set_graph(self, on):
         _check(_lib.sim_set_graph(self.h, int(bool(on))))
+
+    def time_kernel(self, which, reps=50):
+        """Average ms of `reps` back-to-back launches of the S (0) or S^T (1) pass."""
+        ms = C.c_float(0.0)
+        _check(_lib.sim_time_kernel(self.h, int(which), int(reps), C.byref(ms)))
+        return float(ms.value)
 
     def tuning(self):
         t = sim_tuning()
