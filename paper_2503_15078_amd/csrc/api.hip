@@ -470,6 +470,53 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   TRY(build_segments(s, kSegFloats));
   TRY(upload(s, d.col_ptr, col_ptr.data(), col_ptr.size()));
   TRY(upload(s, d.col_val, col_val.data(), col_val.size()));
+  {
+    // S^T-pass copy of the columns: each chain run [a, e] of a column's ancestor path is
+    // stored from a multiple-of-4 position as the entries of nodes (a & ~3) .. (e | 3),
+    // zero outside [a, e], so the pass reads S values and y as aligned float4
+    std::vector<int64_t> colp_ptr(N + 1, 0);
+    for (int j = 0; j < N; ++j) {
+      int64_t tot = 0;
+      for (int a = j; a != -1;) {
+        const int e = chain_end[a];
+        tot += (int64_t)((e | 3) + 1 - (a & ~3));
+        a = parent[e];
+      }
+      colp_ptr[j + 1] = colp_ptr[j] + tot;
+    }
+    std::vector<float> colp_val((size_t)colp_ptr[N], 0.0f);
+    for (int j = 0; j < N; ++j) {
+      int64_t t = col_ptr[j], p = colp_ptr[j];
+      for (int a = j; a != -1;) {
+        const int e = chain_end[a], a4 = a & ~3;
+        for (int k = a; k <= e; ++k) colp_val[(size_t)(p + (k - a4))] = col_val[(size_t)(t + (k - a))];
+        t += e - a + 1;
+        p += (e | 3) + 1 - a4;
+        a = parent[e];
+      }
+    }
+    // the runs of every column, so the pass issues its loads without walking the tree
+    std::vector<int> run_ptr(N + 1, 0), run_a, run_e;
+    for (int j = 0; j < N; ++j) {
+      for (int a = j; a != -1;) {
+        const int e = chain_end[a];
+        run_a.push_back(a);
+        run_e.push_back(e);
+        a = parent[e];
+      }
+      run_ptr[j + 1] = (int)run_a.size();
+    }
+    TRY(s->alloc(d.run_ptr, N + 1));
+    TRY(s->alloc(d.run_a, run_a.size()));
+    TRY(s->alloc(d.run_e, run_e.size()));
+    TRY(upload(s, d.run_ptr, run_ptr.data(), run_ptr.size()));
+    TRY(upload(s, d.run_a, run_a.data(), run_a.size()));
+    TRY(upload(s, d.run_e, run_e.data(), run_e.size()));
+    TRY(s->alloc(d.colp_ptr, N + 1));
+    TRY(s->alloc(d.colp_val, (size_t)colp_ptr[N]));
+    TRY(upload(s, d.colp_ptr, colp_ptr.data(), colp_ptr.size()));
+    TRY(upload(s, d.colp_val, colp_val.data(), colp_val.size()));
+  }
   TRY(upload(s, d.parent, parent.data(), parent.size()));
   TRY(upload(s, d.lo, lo.data(), lo.size()));
   TRY(upload(s, d.depth, depth.data(), depth.size()));

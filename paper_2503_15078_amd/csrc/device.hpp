@@ -69,6 +69,10 @@ struct Dev {
   float *partial;                  // [3][nseg]
   int64_t *col_ptr;
   float *col_val;
+  int64_t *colp_ptr;               // [N+1] S^T-pass copy of the columns (multiples of 4)
+  float *colp_val;                 // runs stored from node a & ~3, zero outside the run
+  int *run_ptr;                    // [N+1] chain runs of each column's ancestor path
+  int *run_a, *run_e;              // first and last node of each run
   int *parent, *lo, *depth, *chain_end;
   int *frange;                     // [2][N] per-row contact range of the frame
   // scenes

@@ -74,32 +74,40 @@ void launch_spmv_S(const Dev& d, hipStream_t st, const float* b, float* y) {
 }
 
 // One wavefront per column j: u_j = base_j + sum over the ancestors i of j of
-// S_ij y_i.  The ancestor path is walked as chain runs [a, chain_end(a)], inside
-// which both the stored column values and y are contiguous.
+// S_ij y_i.  The ancestor path is a list of chain runs [a, e] (precomputed per column,
+// read with one vector load and broadcast lane by lane, so no load waits on the tree
+// walk); the pass reads the aligned copy of the columns (each run stored from node
+// a & ~3, zero-padded to whole 4-node groups), so S values and the three y coordinates
+// are loaded as 16-byte vectors.
 __global__ void __launch_bounds__(kBlock) k_spmv_St(Dev d, const float* __restrict__ y,
                                                     const float* __restrict__ base, float* __restrict__ u) {
   const int j = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
   const int lane = threadIdx.x & (kWave - 1);
   if (j >= d.N) return;
-  const float* __restrict__ col = d.col_val + d.col_ptr[j];
-  const float* __restrict__ y0 = y;
-  const float* __restrict__ y1 = y + d.N4;
-  const float* __restrict__ y2 = y + 2 * d.N4;
+  const float4* __restrict__ col = reinterpret_cast<const float4*>(d.colp_val + d.colp_ptr[j]);
+  const float4* __restrict__ y0 = reinterpret_cast<const float4*>(y);
+  const float4* __restrict__ y1 = reinterpret_cast<const float4*>(y + d.N4);
+  const float4* __restrict__ y2 = reinterpret_cast<const float4*>(y + 2 * d.N4);
+  const int rb = d.run_ptr[j], nr = d.run_ptr[j + 1] - rb;
   float ax = 0.0f, ay = 0.0f, az = 0.0f;
   int t = 0;
-  int a = j;
-  while (a != -1) {
-    int e = __builtin_amdgcn_readfirstlane(d.chain_end[a]);
-    int len = e - a + 1;
+  for (int c0 = 0; c0 < nr; c0 += kWave) {
+    const int my_a = c0 + lane < nr ? d.run_a[rb + c0 + lane] : 0;
+    const int my_e = c0 + lane < nr ? d.run_e[rb + c0 + lane] : 0;
+    const int nc = min(kWave, nr - c0);
+    for (int r = 0; r < nc; ++r) {
+      const int a4 = __builtin_amdgcn_readlane(my_a, r) >> 2;
+      const int n4 = (__builtin_amdgcn_readlane(my_e, r) >> 2) + 1 - a4;
 #pragma unroll 4
-    for (int k = lane; k < len; k += kWave) {
-      float s = col[t + k];
-      ax += s * y0[a + k];
-      ay += s * y1[a + k];
-      az += s * y2[a + k];
+      for (int q = lane; q < n4; q += kWave) {
+        const float4 s = col[t + q];
+        const float4 x = y0[a4 + q], yy = y1[a4 + q], z = y2[a4 + q];
+        ax += s.x * x.x + s.y * x.y + s.z * x.z + s.w * x.w;
+        ay += s.x * yy.x + s.y * yy.y + s.z * yy.z + s.w * yy.w;
+        az += s.x * z.x + s.y * z.y + s.z * z.z + s.w * z.w;
+      }
+      t += n4;
     }
-    t += len;
-    a = __builtin_amdgcn_readfirstlane(d.parent[e]);
   }
   ax = wave_sum(ax);
   ay = wave_sum(ay);
