@@ -128,7 +128,7 @@ def warm_compare(sim, params):
 
 
 def warm_drops(params, seeds=(1001, 1002, 1003), frames=60):
-    """Held-out config-1 cube drops, every frame to NCP residual <= 1e-6 m."""
+    """Held-out cube drops (5^3-node cubes), every frame to NCP residual <= 1e-6 m."""
     import numpy as np
     from paper_2503_15078_amd import scenes, warm
     agg = {"plain": [[], []], "learned": [[], []]}
@@ -145,7 +145,7 @@ def warm_drops(params, seeds=(1001, 1002, 1003), frames=60):
 
 
 def batch_throughput(count, steps):
-    """A batch of `count` blobs (config 4) in one handle: scenes x iterations / s, and the
+    """A batch of `count` blobs on tilted planes in one handle: scenes x iterations / s, and the
     S-pass bandwidth at a size that does not fit the infinity cache."""
     import torch
     from paper_2503_15078_amd import lgsim, scenes

@@ -231,7 +231,7 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   d.G = std::max(G, 1);
   d.NS = NS;
   d.CMAX = std::max(1, s->opt.max_contacts);
-  d.KCAP = std::min<int64_t>((int64_t)d.CMAX * d.CMAX, (int64_t)64 << 20);
+  d.KCAP = std::min<int64_t>((int64_t)d.CMAX * lg::kstride(d.CMAX), (int64_t)64 << 20);
   d.h = hs[0].h;
   for (int c = 0; c < 3; ++c) d.g[c] = s->opt.gravity[c];
   d.cr_iters = s->opt.cr_iters;
@@ -1558,14 +1558,15 @@ int sim_debug_delassus(sim_t s, double* K) {
   int c = s->iter_c;
   if (c == 0) return SIM_OK;
   auto& d = s->d;
-  std::vector<float> Kd((size_t)c * c);
+  const int ks = lg::kstride(c);
+  std::vector<float> Kd((size_t)c * ks);
   HIPCHK(hipMemcpyAsync(Kd.data(), d.K, sizeof(float) * Kd.size(), hipMemcpyDeviceToHost, s->st));
   HIPCHK(hipStreamSynchronize(s->st));
   std::vector<int> node, obst;
   std::vector<int32_t> order;
   TRY(sort_contacts_canonical(s, c, node, obst, order));
   for (int a = 0; a < c; ++a)
-    for (int b2 = 0; b2 < c; ++b2) K[(size_t)a * c + b2] = Kd[(size_t)order[a] * c + order[b2]];
+    for (int b2 = 0; b2 < c; ++b2) K[(size_t)a * c + b2] = Kd[(size_t)order[a] * ks + order[b2]];
   return SIM_OK;
 }
 

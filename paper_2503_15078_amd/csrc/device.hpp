@@ -16,6 +16,9 @@ constexpr int kBlock = 256;
 constexpr int kWave = 64;
 constexpr int kMaxObstacles = 64;
 constexpr int kDelTile = 16;      // Delassus tile (contacts x contacts)
+// Row stride of a scene's Delassus block: its contact count rounded up to 4 (rows are
+// 16-byte aligned; the pad entries are zero).
+__host__ __device__ inline int kstride(int cnt) { return (cnt + 3) & ~3; }
 constexpr int kDelChunk = 256;    // Delassus depth chunk staged in LDS
 constexpr int kMaxCrIters = 1024;
 constexpr int kMlpParams = 20752;   // 16x128 + 128 + 128x128 + 128 + 16x128 + 16 (padded shapes)

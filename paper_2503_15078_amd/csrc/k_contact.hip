@@ -246,7 +246,7 @@ __global__ void k_scene_offsets(Dev d) {
       d.k_off[s] = koff;
       d.tile_off[s] = toff;
       int cs = d.cs_off[s + 1] - d.cs_off[s];
-      koff += (int64_t)cs * cs;
+      koff += (int64_t)cs * kstride(cs);
       int T = (cs + kDelTile - 1) / kDelTile;
       toff += T * (T + 1) / 2;
     }
@@ -431,8 +431,8 @@ __global__ void __launch_bounds__(kBlock) k_delassus_tiles(Dev d) {
       if (a < nJ && b < nK) {
         int j = J0 + a - cs, k = K0 + b - cs;
         if (tj != tk || k >= j) {
-          d.K[ko + (int64_t)j * cnt + k] = acc[r];
-          d.K[ko + (int64_t)k * cnt + j] = acc[r];
+          d.K[ko + (int64_t)j * kstride(cnt) + k] = acc[r];
+          d.K[ko + (int64_t)k * kstride(cnt) + j] = acc[r];
         }
       }
     }
@@ -456,7 +456,9 @@ __global__ void k_warm_start(Dev d, int keep_lambda) {
   int s = d.c_scene[j];
   int cs = d.cs_off[s], cnt = d.cs_off[s + 1] - cs;
   if (d.k_off[d.NS] > d.KCAP) return;
-  float kjj = d.K[d.k_off[s] + (int64_t)(j - cs) * cnt + (j - cs)];
+  float* krow = d.K + d.k_off[s] + (int64_t)(j - cs) * kstride(cnt);
+  for (int k = cnt; k < kstride(cnt); ++k) krow[k] = 0.0f;  // pads of this row (storage is reused)
+  float kjj = krow[j - cs];
   d.c_rn[j] = (float)(d.h * d.h) * kjj;
   d.c_rf[j] = (float)d.h * kjj;
   if (keep_lambda) return;

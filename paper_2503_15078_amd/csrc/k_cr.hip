@@ -178,62 +178,27 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
   const bool k_in_lds = sl_kb[nsl] <= kCrKFloats;
   const int zpad = sl_zb[nsl];
   const bool z_in_lds = 3 * NZ * zpad <= kCrZFloats;
-  if (k_in_lds && nsl == 1 && ((sl_ce[0] - sl_cs[0]) & 3) == 0 &&
-      ((sl_koff[0] + (int64_t)(j0 - sl_cs[0]) * (sl_ce[0] - sl_cs[0])) & 3) == 0) {
-    // one scene, rows a multiple of 4 long and 16-byte aligned: the padded layout is the
-    // global one, copied as float4 with eight loads in flight per thread
-    const int cnt = sl_ce[0] - sl_cs[0], total4 = R * cnt / 4;
-    const float4* src = reinterpret_cast<const float4*>(d.K + sl_koff[0] + (int64_t)(j0 - sl_cs[0]) * cnt);
+  if (k_in_lds) {
+    // Global Delassus rows are stored padded to 4 with zero pads, like Ks: each slot's
+    // rows of this block form one contiguous, 16-byte aligned run in both, copied as
+    // float4 with eight loads in flight per thread
+    const int total4 = sl_kb[nsl] / 4;
     float4* dst = reinterpret_cast<float4*>(Ks);
     for (int base = 0; base < total4; base += 8 * kBlock) {
       float4 v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int e = base + tid + u * kBlock;
-        if (e < total4) v[u] = src[e];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = base + tid + u * kBlock;
-        if (e < total4) dst[e] = v[u];
-      }
-    }
-  } else if (k_in_lds && nsl == 1) {
-    // one scene: the block's rows are contiguous in K; eight loads in flight per thread
-    const int cs = sl_cs[0], cnt = sl_ce[0] - cs, pc = pad4(cnt), total = R * cnt;
-    const float* src = d.K + sl_koff[0] + (int64_t)(j0 - cs) * cnt;
-    const float inv = 1.0f / (float)cnt;
-    for (int base = 0; base < total; base += 8 * kBlock) {
-      float v[8];
-      int di[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = base + tid + u * kBlock;
-        int r = (int)((float)e * inv), k = e - r * cnt;
-        if (k >= cnt) {
-          ++r;
-          k -= cnt;
-        } else if (k < 0) {
-          --r;
-          k += cnt;
+        const int e4 = base + tid + u * kBlock;
+        if (e4 < total4) {
+          const int sl = nsl == 1 ? 0 : slot_of(sl_kb, nsl, 4 * e4);
+          const int cs = sl_cs[sl], pc = pad4(sl_ce[sl] - cs);
+          const int64_t src = sl_koff[sl] + (int64_t)(max(cs, j0) - cs) * pc + (4 * e4 - sl_kb[sl]);
+          v[u] = *reinterpret_cast<const float4*>(d.K + src);
         }
-        di[u] = r * pc + k;
-        v[u] = e < total ? src[e] : 0.0f;
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        if (base + tid + u * kBlock < total) Ks[di[u]] = v[u];
-    }
-    for (int e = tid; e < R * (pc - cnt); e += kBlock) Ks[(e / (pc - cnt)) * pc + cnt + e % (pc - cnt)] = 0.0f;
-  } else if (k_in_lds) {
-    // padded element e of Ks: slot, row within the slot, column; pads are zero
-    const int total = sl_kb[nsl];
-    for (int e = tid; e < total; e += kBlock) {
-      const int sl = slot_of(sl_kb, nsl, e);
-      const int cnt = sl_ce[sl] - sl_cs[sl], pc = pad4(cnt);
-      const int off = e - sl_kb[sl], r = off / pc, k = off - r * pc;
-      const int j = max(sl_cs[sl], j0) + r;
-      Ks[e] = k < cnt ? d.K[sl_koff[sl] + (int64_t)(j - sl_cs[sl]) * cnt + k] : 0.0f;
+        if (base + tid + u * kBlock < total4) dst[base + tid + u * kBlock] = v[u];
     }
   }
 
@@ -312,20 +277,35 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
       __syncthreads();
       return;
     }
-    // K rows from global memory (or unstaged V): 16 lanes per row, 16 rows in flight
+    // K rows from global memory (or unstaged V): 16 lanes per row, 16 rows in flight;
+    // rows are padded to 4 with zero pads and 16-byte aligned in both places
     const int grp = tid >> 4, gl = tid & 15;
     for (int t = grp; t < R; t += kBlock / 16) {
       const int sl = row_slot[t], cs = sl_cs[sl], cnt = sl_ce[sl] - cs, pc = pad4(cnt);
       const int rrow = j0 + t - max(cs, j0);
-      const float* Krow = k_in_lds ? Ks + sl_kb[sl] + rrow * pc : d.K + sl_koff[sl] + (int64_t)(j0 + t - cs) * cnt;
+      const float4* K4 = reinterpret_cast<const float4*>(k_in_lds ? Ks + sl_kb[sl] + rrow * pc
+                                                                  : d.K + sl_koff[sl] + (int64_t)(j0 + t - cs) * pc);
       float a[3 * NV];
 #pragma unroll
       for (int q = 0; q < 3 * NV; ++q) a[q] = 0.0f;
-#pragma unroll 4
-      for (int k = gl; k < cnt; k += 16) {
-        const float kv = Krow[k];
+#pragma unroll 2
+      for (int k4 = gl; k4 < pc / 4; k4 += 16) {
+        const float4 kv = K4[k4];
+        const int k = 4 * k4;
 #pragma unroll
-        for (int q = 0; q < 3 * NV; ++q) a[q] += kv * (staged ? Zs[q * zpad + sl_zb[sl] + k] : Vg[q * CM + cs + k]);
+        for (int q = 0; q < 3 * NV; ++q) {
+          float4 z;
+          if (staged) {
+            z = reinterpret_cast<const float4*>(Zs + q * zpad + sl_zb[sl])[k4];
+          } else {  // V beyond the scene's contacts meets a zero pad of K
+            const float* vg = Vg + q * CM + cs + k;
+            z.x = vg[0];
+            z.y = k + 1 < cnt ? vg[1] : 0.0f;
+            z.z = k + 2 < cnt ? vg[2] : 0.0f;
+            z.w = k + 3 < cnt ? vg[3] : 0.0f;
+          }
+          a[q] += kv.x * z.x + kv.y * z.y + kv.z * z.z + kv.w * z.w;
+        }
       }
 #pragma unroll
       for (int q = 0; q < 3 * NV; ++q)

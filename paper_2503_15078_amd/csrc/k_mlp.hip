@@ -301,7 +301,7 @@ __global__ void k_mlp_features(Dev d) {
   if (j >= c || d.k_off[d.NS] > d.KCAP) return;
   const int CM = d.CMAX, v = d.c_node[j], s = d.c_scene[j];
   const int cs = d.cs_off[s], cnt = d.cs_off[s + 1] - cs;
-  const float kjj = d.K[d.k_off[s] + (int64_t)(j - cs) * cnt + (j - cs)];
+  const float kjj = d.K[d.k_off[s] + (int64_t)(j - cs) * kstride(cnt) + (j - cs)];
   const double ell = d.ell[s];
   const double h = d.h;
   double xp[3], rel[3];
@@ -345,7 +345,7 @@ __global__ void __launch_bounds__(kBlock) k_mlp_warm(Dev d) {
     const f32x4 y = forward_tile(s, load_x(d.c_feat, j, c), z1, h1b, z2, h2b);
     if (lane < 16 && j < c) {
       const int sc = d.c_scene[j], cs = d.cs_off[sc], cnt = d.cs_off[sc + 1] - cs;
-      const float kjj = d.K[d.k_off[sc] + (int64_t)(j - cs) * cnt + (j - cs)];
+      const float kjj = d.K[d.k_off[sc] + (int64_t)(j - cs) * kstride(cnt) + (j - cs)];
       const float back = (float)(d.ell[sc] / (d.h * d.h * (double)kjj));
       float l[3] = {y[0] * back, y[1] * back, y[2] * back};
       if (isfinite(l[0]) && isfinite(l[1]) && isfinite(l[2])) {
@@ -369,7 +369,7 @@ __global__ void k_mlp_targets(Dev d, float* out) {
   const int c = min(d.n_contacts[0], d.CMAX);
   if (j >= c || d.k_off[d.NS] > d.KCAP) return;
   const int s = d.c_scene[j], cs = d.cs_off[s], cnt = d.cs_off[s + 1] - cs;
-  const float kjj = d.K[d.k_off[s] + (int64_t)(j - cs) * cnt + (j - cs)];
+  const float kjj = d.K[d.k_off[s] + (int64_t)(j - cs) * kstride(cnt) + (j - cs)];
   const double sc = d.h * d.h * (double)kjj / d.ell[s];
   for (int a = 0; a < 3; ++a) out[(int64_t)j * 3 + a] = (float)(sc * d.lam[a * d.CMAX + j]);
 }

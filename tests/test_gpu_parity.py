@@ -166,7 +166,7 @@ def test_contact_list_bit_exact_over_frames():
 
 
 def test_frame_trajectory_drop():
-    """60-frame drop (config 1 scene): the GPU trajectory stays within 1e-3 m of the
+    """60-frame drop of the small cube: the GPU trajectory stays within 1e-3 m of the
     oracle's and ends at rest on the ground."""
     sc = scenes.cube_drop(2, frames=60)
     sim = make_sim(sc)
