@@ -172,18 +172,23 @@ int sim_set_graph(sim_t s, int32_t on);
 
 /* Launch configuration: CR blocks (one per CU at most), CR form (SIM_CR_*), S-pass
  * segment length in floats (multiple of 4, >= 64), element-kernel block size (64, 128,
- * 192 or 256 threads); ms_frame: the autotuner's measured time of the chosen one. */
+ * 192 or 256 threads), the most rows of S that share one S-pass wavefront (consecutive
+ * rows stored from the same column quad) and the most columns that share one S^T-pass
+ * wavefront (consecutive columns of one elimination-tree chain), each 1, 2, 4 or 8;
+ * ms_frame: the autotuner's measured time of the chosen one. */
 typedef struct {
   int32_t cr_blocks, cr_variant, seg_floats, elem_block;
+  int32_t row_group, col_group;
   float ms_frame;
 } sim_tuning;
 int sim_get_tuning(sim_t s, sim_tuning* t);
 int sim_set_tuning(sim_t s, const sim_tuning* t);
 /* Autotuner: from the current state (restored afterwards), time `frames` frames of
- * `iters` iterations for candidate configurations (segment length 1024/2048/4096,
+ * `iters` iterations for candidate configurations (S-pass row group and S^T-pass column
+ * group 1/2/4/8, segment length 1024/2048/4096,
  * element block 64/128/256, then CR blocks 16..256, both CR forms if allow_pipelined)
  * by coordinate search, keep the fastest and report it in *best.  The candidates that
- * change rounding (segment length, CR form) stay within the parity tolerances. */
+ * change rounding (groups, segment length, CR form) stay within the parity tolerances. */
 int sim_autotune(sim_t s, int32_t frames, int32_t iters, int32_t allow_pipelined, sim_tuning* best);
 
 /* Replace the obstacle set (n >= 0; at most 64). */

@@ -69,6 +69,7 @@ struct lgsim {
   // S-pass segmentation (host copies of the row layout, current segment length)
   std::vector<int64_t> h_row_ptr;
   std::vector<int32_t> h_row_lo4;
+  std::vector<int32_t> h_chain_end;
   int seg_floats = 0;
   // captured fixed-iteration frame
   hipGraphExec_t gexec = nullptr;
@@ -151,57 +152,92 @@ int push_obstacles(lgsim* s) {
   return SIM_OK;
 }
 
-// Build one handle from host precomputations of several scenes (concatenated).
-// Segments of the S pass: each row's stored range [lo4, hi4) is cut into pieces of at
-// most seg_floats floats, one wavefront each; rows of several pieces add their partial
-// sums in a second kernel.  Re-run with another length by the autotuner.
-int build_segments(lgsim* s, int seg_floats) {
+// Column groups of the S^T pass: up to col_group consecutive columns of one chain share
+// every run of the first column's path except the start of the first run.
+int build_col_groups(lgsim* s, int col_group) {
   auto& d = s->d;
   const int N = d.N;
-  std::vector<int> seg_row, seg_col0, seg_len, long_row, long_seg0, long_nseg;
-  std::vector<int64_t> seg_off;
-  for (int i = 0; i < N; ++i) {
-    int64_t len = s->h_row_ptr[i + 1] - s->h_row_ptr[i];
-    int nseg = (int)((len + seg_floats - 1) / seg_floats);
+  std::vector<int> j0s, ngs;
+  for (int j = 0; j < N;) {
+    int ng = 1;
+    while (ng < col_group && j + ng < N && s->h_chain_end[j + ng] == s->h_chain_end[j]) ++ng;
+    j0s.push_back(j);
+    ngs.push_back(ng);
+    j += ng;
+  }
+  HIPCHK(hipStreamSynchronize(s->st));
+  s->release(d.stgrp_j0);
+  s->release(d.stgrp_ng);
+  d.n_stgrp = (int)j0s.size();
+  d.col_group = col_group;
+  TRY(s->alloc(d.stgrp_j0, j0s.size()));
+  TRY(s->alloc(d.stgrp_ng, ngs.size()));
+  TRY(upload(s, d.stgrp_j0, j0s.data(), j0s.size()));
+  TRY(upload(s, d.stgrp_ng, ngs.data(), ngs.size()));
+  HIPCHK(hipStreamSynchronize(s->st));
+  return SIM_OK;
+}
+
+// Segments of the S pass: consecutive rows stored from the same column quad (at most
+// row_group) form a group whose union range [lo4, hi4 of its last row) is cut into
+// pieces of at most seg_floats columns, one wavefront each, so each piece of b is loaded
+// once for the group; groups of several pieces add their partial sums in a second
+// kernel.  Re-run with another length by the autotuner.
+int build_segments(lgsim* s, int seg_floats, int row_group) {
+  auto& d = s->d;
+  const int N = d.N;
+  std::vector<int> seg_row, seg_ng, seg_q0, seg_len, long_row, long_seg0, long_nseg, long_ng;
+  for (int i = 0; i < N;) {
+    int ng = 1;
+    while (ng < row_group && i + ng < N && s->h_row_lo4[i + ng] == s->h_row_lo4[i]) ++ng;
+    // the last row of the group ends last (rows end at their own quad)
+    const int64_t len = s->h_row_ptr[i + ng] - s->h_row_ptr[i + ng - 1];
+    const int nseg = (int)((len + seg_floats - 1) / seg_floats);
     if (nseg > 1) {
       long_row.push_back(i);
       long_seg0.push_back((int)seg_row.size());
       long_nseg.push_back(nseg);
+      long_ng.push_back(ng);
     }
     for (int q = 0; q < nseg; ++q) {
-      int64_t st = (int64_t)q * seg_floats;
+      const int64_t st = (int64_t)q * seg_floats;
       seg_row.push_back(nseg > 1 ? -(i + 1) : i);
-      seg_off.push_back(s->h_row_ptr[i] + st);
-      seg_col0.push_back(s->h_row_lo4[i] + (int)st);
+      seg_ng.push_back(ng);
+      seg_q0.push_back((int)(st / 4));
       seg_len.push_back((int)std::min<int64_t>(seg_floats, len - st));
     }
+    i += ng;
   }
   HIPCHK(hipStreamSynchronize(s->st));
-  for (void* p : {(void*)d.seg_row, (void*)d.seg_col0, (void*)d.seg_len, (void*)d.seg_off, (void*)d.long_row,
-                  (void*)d.long_seg0, (void*)d.long_nseg, (void*)d.partial})
+  for (void* p : {(void*)d.seg_row, (void*)d.seg_ng, (void*)d.seg_q0, (void*)d.seg_len, (void*)d.long_row,
+                  (void*)d.long_seg0, (void*)d.long_nseg, (void*)d.long_ng, (void*)d.partial})
     s->release(p);
   d.nseg = (int)seg_row.size();
   d.nlong = (int)long_row.size();
   TRY(s->alloc(d.seg_row, d.nseg));
-  TRY(s->alloc(d.seg_col0, d.nseg));
+  TRY(s->alloc(d.seg_ng, d.nseg));
+  TRY(s->alloc(d.seg_q0, d.nseg));
   TRY(s->alloc(d.seg_len, d.nseg));
-  TRY(s->alloc(d.seg_off, d.nseg));
   TRY(s->alloc(d.long_row, d.nlong));
   TRY(s->alloc(d.long_seg0, d.nlong));
   TRY(s->alloc(d.long_nseg, d.nlong));
-  TRY(s->alloc(d.partial, 3 * (size_t)d.nseg));
+  TRY(s->alloc(d.long_ng, d.nlong));
+  d.row_group = row_group;
+  TRY(s->alloc(d.partial, 3 * (size_t)row_group * d.nseg));
   TRY(upload(s, d.seg_row, seg_row.data(), seg_row.size()));
-  TRY(upload(s, d.seg_col0, seg_col0.data(), seg_col0.size()));
+  TRY(upload(s, d.seg_ng, seg_ng.data(), seg_ng.size()));
+  TRY(upload(s, d.seg_q0, seg_q0.data(), seg_q0.size()));
   TRY(upload(s, d.seg_len, seg_len.data(), seg_len.size()));
-  TRY(upload(s, d.seg_off, seg_off.data(), seg_off.size()));
   TRY(upload(s, d.long_row, long_row.data(), long_row.size()));
   TRY(upload(s, d.long_seg0, long_seg0.data(), long_seg0.size()));
   TRY(upload(s, d.long_nseg, long_nseg.data(), long_nseg.size()));
+  TRY(upload(s, d.long_ng, long_ng.data(), long_ng.size()));
   HIPCHK(hipStreamSynchronize(s->st));
   s->seg_floats = seg_floats;
   return SIM_OK;
 }
 
+// Build one handle from host precomputations of several scenes (concatenated).
 int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vector<sim_obstacle>>& obs) {
   auto& d = s->d;
   const int NS = (int)hs.size();
@@ -467,7 +503,7 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   TRY(upload(s, d.row_ptr, row_ptr.data(), row_ptr.size()));
   TRY(upload(s, d.row_lo4, row_lo4.data(), row_lo4.size()));
   TRY(upload(s, d.row_val, row_val.data(), row_val.size()));
-  TRY(build_segments(s, kSegFloats));
+  TRY(build_segments(s, kSegFloats, 4));
   TRY(upload(s, d.col_ptr, col_ptr.data(), col_ptr.size()));
   TRY(upload(s, d.col_val, col_val.data(), col_val.size()));
   {
@@ -506,6 +542,8 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
       }
       run_ptr[j + 1] = (int)run_a.size();
     }
+    s->h_chain_end = chain_end;
+    TRY(build_col_groups(s, 4));
     TRY(s->alloc(d.run_ptr, N + 1));
     TRY(s->alloc(d.run_a, run_a.size()));
     TRY(s->alloc(d.run_e, run_e.size()));
@@ -1005,13 +1043,18 @@ int sim_get_tuning(sim_t s, sim_tuning* t) {
   t->cr_variant = s->opt.cr_variant;
   t->seg_floats = s->seg_floats;
   t->elem_block = s->d.elem_block;
+  t->row_group = s->d.row_group;
+  t->col_group = s->d.col_group;
   t->ms_frame = 0.0f;
   return SIM_OK;
 }
 
+static bool group_ok(int g) { return g == 1 || g == 2 || g == 4 || g == 8; }
+
 int sim_set_tuning(sim_t s, const sim_tuning* t) {
   if (!s || !t || t->seg_floats < 64 || t->seg_floats % 4 != 0 || t->elem_block < 64 || t->elem_block > lg::kBlock ||
-      t->elem_block % lg::kWave != 0 || (t->cr_variant != SIM_CR_TEXTBOOK && t->cr_variant != SIM_CR_PIPELINED)) {
+      t->elem_block % lg::kWave != 0 || (t->cr_variant != SIM_CR_TEXTBOOK && t->cr_variant != SIM_CR_PIPELINED) ||
+      !group_ok(t->row_group) || !group_ok(t->col_group)) {
     lg::set_error("bad tuning");
     return SIM_E_ARG;
   }
@@ -1020,7 +1063,9 @@ int sim_set_tuning(sim_t s, const sim_tuning* t) {
     lg::set_error("cr_blocks must lie in [" + std::to_string(need) + ", " + std::to_string(lg::cr_max_blocks()) + "]");
     return SIM_E_ARG;
   }
-  if (t->seg_floats != s->seg_floats) TRY(build_segments(s, t->seg_floats));
+  if (t->seg_floats != s->seg_floats || t->row_group != s->d.row_group)
+    TRY(build_segments(s, t->seg_floats, t->row_group));
+  if (t->col_group != s->d.col_group) TRY(build_col_groups(s, t->col_group));
   s->cr_blocks = t->cr_blocks;
   s->opt.cr_variant = t->cr_variant;
   s->d.elem_block = t->elem_block;
@@ -1060,7 +1105,8 @@ int sim_autotune(sim_t s, int32_t frames, int32_t iters, int32_t allow_pipelined
   TRY(sim_get_tuning(s, &cur));
   float best_ms = 0.0f;
   int rc = measure(cur, &best_ms);
-  // coordinate search: S-pass segment length, element block size, then the CR launch
+  // coordinate search: S / S^T group sizes, S-pass segment length, element block size,
+  // then the CR launch
   auto try_cand = [&](sim_tuning c) -> int {
     float m = 0.0f;
     TRY(measure(c, &m));
@@ -1070,6 +1116,18 @@ int sim_autotune(sim_t s, int32_t frames, int32_t iters, int32_t allow_pipelined
     }
     return SIM_OK;
   };
+  for (int g : {1, 2, 4, 8})
+    if (rc == SIM_OK && g != cur.row_group) {
+      sim_tuning c = cur;
+      c.row_group = g;
+      rc = try_cand(c);
+    }
+  for (int g : {1, 2, 4, 8})
+    if (rc == SIM_OK && g != cur.col_group) {
+      sim_tuning c = cur;
+      c.col_group = g;
+      rc = try_cand(c);
+    }
   for (int seg : {1024, 2048, 4096})
     if (rc == SIM_OK && seg != cur.seg_floats) {
       sim_tuning c = cur;

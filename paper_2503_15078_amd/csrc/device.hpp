@@ -20,6 +20,7 @@ constexpr int kDelTile = 16;      // Delassus tile (contacts x contacts)
 // 16-byte aligned; the pad entries are zero).
 __host__ __device__ inline int kstride(int cnt) { return (cnt + 3) & ~3; }
 constexpr int kDelChunk = 256;    // Delassus depth chunk staged in LDS
+constexpr int kMaxGroup = 8;      // S-pass rows / S^T-pass columns per wavefront, at most
 constexpr int kMaxCrIters = 1024;
 constexpr int kMlpParams = 20752;   // 16x128 + 128 + 128x128 + 128 + 16x128 + 16 (padded shapes)
 constexpr int kMlpMaxBlocks = 256;  // blocks of one training launch (64 samples each)
@@ -66,16 +67,21 @@ struct Dev {
   int64_t *row_ptr;
   int *row_lo4;
   float *row_val;
-  int *seg_row, *seg_col0, *seg_len;
-  int64_t *seg_off;
-  int *long_row, *long_seg0, *long_nseg;
-  float *partial;                  // [3][nseg]
+  int row_group, col_group;        // group size limits of the S and S^T passes (1, 2, 4, 8)
+  // S-pass segments: a group of up to row_group consecutive rows stored from the same
+  // column quad, cut along its columns; seg_row = first row (-(row + 1) if the group has
+  // several segments), seg_q0 = first quad of the segment, seg_len = its floats per row
+  int *seg_row, *seg_ng, *seg_q0, *seg_len;
+  int *long_row, *long_seg0, *long_nseg, *long_ng;
+  float *partial;                  // [3][row_group][nseg]
   int64_t *col_ptr;
   float *col_val;
   int64_t *colp_ptr;               // [N+1] S^T-pass copy of the columns (multiples of 4)
   float *colp_val;                 // runs stored from node a & ~3, zero outside the run
   int *run_ptr;                    // [N+1] chain runs of each column's ancestor path
   int *run_a, *run_e;              // first and last node of each run
+  int n_stgrp;                     // S^T-pass groups: up to col_group consecutive columns
+  int *stgrp_j0, *stgrp_ng;        // of one chain (first column, count)
   int *parent, *lo, *depth, *chain_end;
   int *frange;                     // [2][N] per-row contact range of the frame
   // scenes

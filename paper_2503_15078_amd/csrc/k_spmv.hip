@@ -13,116 +13,178 @@ __device__ inline float wave_sum(float v) {
   return v;
 }
 
-// One wavefront per row segment.  Row i is stored over columns [lo4_i, hi4_i) in
-// 16-byte groups, so S and the three b coordinates are read as aligned float4.
-// Single-segment rows write y directly; segments of long rows write partial sums.
+__device__ inline float dot4(const float4& s, const float4& x) {
+  return s.x * x.x + s.y * x.y + s.z * x.z + s.w * x.w;
+}
+
+// One wavefront per segment of a row group.  Row i is stored over columns
+// [lo4_i, hi4_i) in 16-byte groups; the rows of a group share lo4, so one float4 of
+// each b coordinate serves every row of the group and only the S values are per row.
+// Rows end at their own quad (the last row of a group ends last); quads beyond a row's
+// end count as zero.  Single-segment groups write y directly; the others write partial
+// sums per row.
+template <int G>
 __global__ void __launch_bounds__(kBlock) k_spmv_S(Dev d, const float* __restrict__ b, float* __restrict__ y) {
   const int wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
   const int lane = threadIdx.x & (kWave - 1);
   if (wave >= d.nseg) return;
-  const int row = d.seg_row[wave];
-  const int64_t off = d.seg_off[wave];
-  const int col0 = d.seg_col0[wave];
-  const int len4 = d.seg_len[wave] >> 2;
-  const float4* __restrict__ S4 = reinterpret_cast<const float4*>(d.row_val + off);
+  const int r = d.seg_row[wave];
+  const int i0 = r >= 0 ? r : -r - 1;
+  const int ng = d.seg_ng[wave], q0 = d.seg_q0[wave];
+  const int nq = d.seg_len[wave] >> 2;
+  const int col0 = d.row_lo4[i0] + 4 * q0;
+  const float4* S4[G];
+  int n4[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int64_t p = g < ng ? d.row_ptr[i0 + g] : 0;
+    n4[g] = g < ng ? min(nq, (int)((d.row_ptr[i0 + g + 1] - p) >> 2) - q0) : 0;
+    S4[g] = reinterpret_cast<const float4*>(d.row_val + p + 4 * (int64_t)q0);
+  }
   const float4* __restrict__ bx = reinterpret_cast<const float4*>(b + col0);
   const float4* __restrict__ by = reinterpret_cast<const float4*>(b + d.N4 + col0);
   const float4* __restrict__ bz = reinterpret_cast<const float4*>(b + 2 * d.N4 + col0);
-  float ax = 0.0f, ay = 0.0f, az = 0.0f;
-#pragma unroll 4
-  for (int q = lane; q < len4; q += kWave) {
-    float4 s = S4[q];
-    float4 x = bx[q], yy = by[q], z = bz[q];
-    ax += s.x * x.x + s.y * x.y + s.z * x.z + s.w * x.w;
-    ay += s.x * yy.x + s.y * yy.y + s.z * yy.z + s.w * yy.w;
-    az += s.x * z.x + s.y * z.y + s.z * z.z + s.w * z.w;
+  float acc[G][3];
+#pragma unroll
+  for (int g = 0; g < G; ++g) acc[g][0] = acc[g][1] = acc[g][2] = 0.0f;
+#pragma unroll(G <= 2 ? 4 : 2)
+  for (int q = lane; q < nq; q += kWave) {
+    const float4 x = bx[q], yy = by[q], z = bz[q];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (n4[g] > 0) {  // uniform: the row has quads in this segment
+        float4 sv = S4[g][min(q, n4[g] - 1)];
+        if (q >= n4[g]) sv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        acc[g][0] += dot4(sv, x);
+        acc[g][1] += dot4(sv, yy);
+        acc[g][2] += dot4(sv, z);
+      }
+    }
   }
-  ax = wave_sum(ax);
-  ay = wave_sum(ay);
-  az = wave_sum(az);
-  if (lane == 0) {
-    if (row >= 0) {
-      y[row] = ax;
-      y[d.N4 + row] = ay;
-      y[2 * d.N4 + row] = az;
-    } else {
-      d.partial[wave] = ax;
-      d.partial[d.nseg + wave] = ay;
-      d.partial[2 * d.nseg + wave] = az;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    if (g < ng) {
+      const float ax = wave_sum(acc[g][0]), ay = wave_sum(acc[g][1]), az = wave_sum(acc[g][2]);
+      if (lane == 0) {
+        if (r >= 0) {
+          y[i0 + g] = ax;
+          y[d.N4 + i0 + g] = ay;
+          y[2 * d.N4 + i0 + g] = az;
+        } else {
+          d.partial[(0 * G + g) * (int64_t)d.nseg + wave] = ax;
+          d.partial[(1 * G + g) * (int64_t)d.nseg + wave] = ay;
+          d.partial[(2 * G + g) * (int64_t)d.nseg + wave] = az;
+        }
+      }
     }
   }
 }
 
-// Rows longer than one segment: y_i = sum of their partials, in segment order.
+// Row groups of several segments: y_i = sum of the row's partials, in segment order.
 __global__ void k_spmv_S_finish(Dev d, float* __restrict__ y) {
-  int l = blockIdx.x * blockDim.x + threadIdx.x;
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= d.nlong) return;
-  int s0 = d.long_seg0[l], ns = d.long_nseg[l], row = d.long_row[l];
-  for (int c = 0; c < 3; ++c) {
-    float a = 0.0f;
-    for (int s = 0; s < ns; ++s) a += d.partial[c * d.nseg + s0 + s];
-    y[c * d.N4 + row] = a;
-  }
+  const int s0 = d.long_seg0[l], ns = d.long_nseg[l], i0 = d.long_row[l], ng = d.long_ng[l];
+  for (int g = 0; g < ng; ++g)
+    for (int c = 0; c < 3; ++c) {
+      const float* p = d.partial + (c * d.row_group + g) * (int64_t)d.nseg + s0;
+      float a = 0.0f;
+      for (int k = 0; k < ns; ++k) a += p[k];
+      y[c * d.N4 + i0 + g] = a;
+    }
 }
 
 void launch_spmv_S(const Dev& d, hipStream_t st, const float* b, float* y) {
-  int waves_per_block = kBlock / kWave;
-  hipLaunchKernelGGL(k_spmv_S, dim3((d.nseg + waves_per_block - 1) / waves_per_block), dim3(kBlock), 0, st,
-                     d, b, y);
+  const dim3 grid((d.nseg + kBlock / kWave - 1) / (kBlock / kWave));
+  switch (d.row_group) {
+    case 1: hipLaunchKernelGGL(k_spmv_S<1>, grid, dim3(kBlock), 0, st, d, b, y); break;
+    case 2: hipLaunchKernelGGL(k_spmv_S<2>, grid, dim3(kBlock), 0, st, d, b, y); break;
+    case 4: hipLaunchKernelGGL(k_spmv_S<4>, grid, dim3(kBlock), 0, st, d, b, y); break;
+    default: hipLaunchKernelGGL(k_spmv_S<8>, grid, dim3(kBlock), 0, st, d, b, y); break;
+  }
   if (d.nlong > 0)
     hipLaunchKernelGGL(k_spmv_S_finish, dim3((d.nlong + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d, y);
 }
 
-// One wavefront per column j: u_j = base_j + sum over the ancestors i of j of
-// S_ij y_i.  The ancestor path is a list of chain runs [a, e] (precomputed per column,
-// read with one vector load and broadcast lane by lane, so no load waits on the tree
-// walk); the pass reads the aligned copy of the columns (each run stored from node
+// One wavefront per group of up to G consecutive columns j0 .. j0 + ng - 1 of one
+// chain: u_j = base_j + sum over the ancestors i of j of S_ij y_i.  The columns' ancestor
+// paths are the chain runs [a, e] of column j0's path (precomputed, read with one vector
+// load and broadcast lane by lane), except that column j0 + g starts its first run at
+// its own node.  Each column is read from its aligned copy (every run stored from node
 // a & ~3, zero-padded to whole 4-node groups), so S values and the three y coordinates
-// are loaded as 16-byte vectors.
+// are 16-byte loads, and one float4 of each y coordinate serves every column of the
+// group.
+template <int G>
 __global__ void __launch_bounds__(kBlock) k_spmv_St(Dev d, const float* __restrict__ y,
                                                     const float* __restrict__ base, float* __restrict__ u) {
-  const int j = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  const int w = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
   const int lane = threadIdx.x & (kWave - 1);
-  if (j >= d.N) return;
-  const float4* __restrict__ col = reinterpret_cast<const float4*>(d.colp_val + d.colp_ptr[j]);
+  if (w >= d.n_stgrp) return;
+  const int j0 = d.stgrp_j0[w], ng = d.stgrp_ng[w];
   const float4* __restrict__ y0 = reinterpret_cast<const float4*>(y);
   const float4* __restrict__ y1 = reinterpret_cast<const float4*>(y + d.N4);
   const float4* __restrict__ y2 = reinterpret_cast<const float4*>(y + 2 * d.N4);
-  const int rb = d.run_ptr[j], nr = d.run_ptr[j + 1] - rb;
-  float ax = 0.0f, ay = 0.0f, az = 0.0f;
-  int t = 0;
+  // column g's quad index for quad q of the current run is q + off[g]; in the first run
+  // its copy starts ((j0 + g) >> 2) - (j0 >> 2) quads later (quads before it are zero)
+  const float4* col[G];
+  int off[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    col[g] = reinterpret_cast<const float4*>(d.colp_val + d.colp_ptr[g < ng ? j0 + g : j0]);
+    off[g] = -(((j0 + g) >> 2) - (j0 >> 2));
+  }
+  const int rb = d.run_ptr[j0], nr = d.run_ptr[j0 + 1] - rb;
+  float acc[G][3];
+#pragma unroll
+  for (int g = 0; g < G; ++g) acc[g][0] = acc[g][1] = acc[g][2] = 0.0f;
   for (int c0 = 0; c0 < nr; c0 += kWave) {
     const int my_a = c0 + lane < nr ? d.run_a[rb + c0 + lane] : 0;
     const int my_e = c0 + lane < nr ? d.run_e[rb + c0 + lane] : 0;
     const int nc = min(kWave, nr - c0);
-    for (int r = 0; r < nc; ++r) {
-      const int a4 = __builtin_amdgcn_readlane(my_a, r) >> 2;
-      const int n4 = (__builtin_amdgcn_readlane(my_e, r) >> 2) + 1 - a4;
-#pragma unroll 4
+    for (int rr = 0; rr < nc; ++rr) {
+      const int a4 = __builtin_amdgcn_readlane(my_a, rr) >> 2;
+      const int n4 = (__builtin_amdgcn_readlane(my_e, rr) >> 2) + 1 - a4;
+#pragma unroll(G <= 2 ? 4 : 2)
       for (int q = lane; q < n4; q += kWave) {
-        const float4 s = col[t + q];
         const float4 x = y0[a4 + q], yy = y1[a4 + q], z = y2[a4 + q];
-        ax += s.x * x.x + s.y * x.y + s.z * x.z + s.w * x.w;
-        ay += s.x * yy.x + s.y * yy.y + s.z * yy.z + s.w * yy.w;
-        az += s.x * z.x + s.y * z.y + s.z * z.z + s.w * z.w;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          if (g < ng) {
+            const int qq = q + off[g];
+            float4 sv = col[g][max(qq, 0)];
+            if (qq < 0) sv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            acc[g][0] += dot4(sv, x);
+            acc[g][1] += dot4(sv, yy);
+            acc[g][2] += dot4(sv, z);
+          }
+        }
       }
-      t += n4;
+#pragma unroll
+      for (int g = 0; g < G; ++g) off[g] += n4;
     }
   }
-  ax = wave_sum(ax);
-  ay = wave_sum(ay);
-  az = wave_sum(az);
-  if (lane == 0) {
-    u[j] = (base ? base[j] : 0.0f) + ax;
-    u[d.N4 + j] = (base ? base[d.N4 + j] : 0.0f) + ay;
-    u[2 * d.N4 + j] = (base ? base[2 * d.N4 + j] : 0.0f) + az;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    if (g < ng) {
+      const float ax = wave_sum(acc[g][0]), ay = wave_sum(acc[g][1]), az = wave_sum(acc[g][2]);
+      if (lane == 0) {
+        const int j = j0 + g;
+        u[j] = (base ? base[j] : 0.0f) + ax;
+        u[d.N4 + j] = (base ? base[d.N4 + j] : 0.0f) + ay;
+        u[2 * d.N4 + j] = (base ? base[2 * d.N4 + j] : 0.0f) + az;
+      }
+    }
   }
 }
 
 void launch_spmv_St(const Dev& d, hipStream_t st, const float* y, const float* base, float* u) {
-  int waves_per_block = kBlock / kWave;
-  hipLaunchKernelGGL(k_spmv_St, dim3((d.N + waves_per_block - 1) / waves_per_block), dim3(kBlock), 0, st, d,
-                     y, base, u);
+  const dim3 grid((d.n_stgrp + kBlock / kWave - 1) / (kBlock / kWave));
+  switch (d.col_group) {
+    case 1: hipLaunchKernelGGL(k_spmv_St<1>, grid, dim3(kBlock), 0, st, d, y, base, u); break;
+    case 2: hipLaunchKernelGGL(k_spmv_St<2>, grid, dim3(kBlock), 0, st, d, y, base, u); break;
+    case 4: hipLaunchKernelGGL(k_spmv_St<4>, grid, dim3(kBlock), 0, st, d, y, base, u); break;
+    default: hipLaunchKernelGGL(k_spmv_St<8>, grid, dim3(kBlock), 0, st, d, y, base, u); break;
+  }
 }
 
 // y_i += sum over contacts k whose node lies in the subtree [lo_i, i] of row i of

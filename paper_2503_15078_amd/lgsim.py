@@ -53,7 +53,8 @@ class sim_options(C.Structure):
 
 class sim_tuning(C.Structure):
     _fields_ = [("cr_blocks", C.c_int32), ("cr_variant", C.c_int32), ("seg_floats", C.c_int32),
-                ("elem_block", C.c_int32), ("ms_frame", C.c_float)]
+                ("elem_block", C.c_int32), ("row_group", C.c_int32), ("col_group", C.c_int32),
+                ("ms_frame", C.c_float)]
 
 
 class sim_obstacle(C.Structure):

@@ -87,7 +87,8 @@ def test_autotune_keeps_results_within_tolerance():
 
 def test_bad_tuning_is_rejected():
     sim = lgsim.Sim(scenes.cube_drop(0))
-    for kw in ({"seg_floats": 30}, {"elem_block": 100}, {"cr_blocks": 100000}, {"cr_variant": 7}):
+    for kw in ({"seg_floats": 30}, {"elem_block": 100}, {"cr_blocks": 100000}, {"cr_variant": 7},
+               {"row_group": 3}, {"col_group": 16}, {"row_group": 0}):
         with pytest.raises(lgsim.SimError) as e:
             sim.set_tuning(**kw)
         assert e.value.code == -1

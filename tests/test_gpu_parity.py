@@ -53,6 +53,29 @@ def test_global_solve(mk):
     sim.close()
 
 
+@pytest.mark.parametrize("row_group,col_group,seg", [(1, 1, 2048), (2, 8, 64), (8, 2, 256), (4, 4, 1024),
+                                                     (8, 8, 64)])
+def test_global_solve_group_sizes(row_group, col_group, seg):
+    """S and S^T passes with every row/column group size and segment lengths down to 64
+    floats (groups cut into many pieces), on a batch of three blobs so that groups meet
+    scene boundaries: each scene's part of u = S^T S b is the oracle's solve of its part."""
+    scs = scenes.batch_scenes(5, count=3, lo=300, hi=1500)
+    sim = lgsim.Sim(batch=scs)
+    sim.set_tuning(row_group=row_group, col_group=col_group, seg_floats=seg)
+    t = sim.tuning()
+    assert (t["row_group"], t["col_group"], t["seg_floats"]) == (row_group, col_group, seg)
+    rng = np.random.default_rng(row_group * 10 + col_group)
+    n = sum(s.n for s in scs)
+    b = f32(rng.standard_normal((n, 3)))
+    u = sim.global_solve(b)
+    sim.close()
+    off = 0
+    for sc in scs:
+        ref = OracleSim(sc).solve(b[off:off + sc.n])
+        assert rel_inf(u[off:off + sc.n], ref) <= 1e-5, (row_group, col_group, seg)
+        off += sc.n
+
+
 @pytest.mark.parametrize("model", [0, 1, 2, 3])
 def test_rhs_local_step(model):
     sc = scenes.twist_bar(0, model=model, nodes=(20, 6, 6), E=1e6)
