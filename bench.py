@@ -12,7 +12,7 @@ from the same device-resident state each time so that every timed frame sees exa
 per-iteration figure, which includes the once-per-frame Schur complement).
 
 Before timing, the library's autotuner picks the launch configuration (CR grid and
-form, S-pass segment length, element block size) on this state; timed frames replay
+form, S-pass segment length, S / S^T group sizes, element block size) on this state; timed frames replay
 a captured hipGraph.  Also reported: per-kernel times from HIP events on the solver's
 stream in an eagerly launched pass (graph replays hide kernel boundaries), the
 roofline of the dominant S-pass kernel, ms/frame when iterating until the NCP residual
@@ -21,7 +21,6 @@ is <= 1e-6 m with the previous-frame and with the learned warm start, throughput
 state (cpu_baseline).
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -35,13 +34,13 @@ PAPER_MS_PER_ITER = 11.95  # Table 3, Gingerbread Man 19.5k, RTX 4090 + i9-13900
 ITERS = 5
 TOL_CR, TOL_CR_ITERS, TOL_MAX_ITERS = 1e-3, 300, 100
 
-# HBM bytes per launch of the S^T pass at this workload from rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE (KiB per dispatch, averaged over the bench's launches), scaled by what the same
-# counters read for a plain float32 copy of 256 MiB (FETCH_SIZE reads half the bytes a
-# kernel fetches on this device: x2.0; WRITE_SIZE reads them exactly: x1.0).  Valid only
-# for the kernel source they were taken on.
-ST_COUNTERS = {"source": "paper_2503_15078_amd/csrc/k_spmv.hip", "sha256_16": "41d4e0a3af49d4f3",
-               "fetch_kib": 56527.168, "write_kib": 456.455, "fetch_scale": 2.0, "write_scale": 1.0}
+COUNTER_PASS_LAUNCHES = 20
+# rocprofv3 FETCH_SIZE / WRITE_SIZE over `bench.py --counter-pass` (scaled by a plain copy:
+# FETCH_SIZE x2.0, WRITE_SIZE x1.0) are steady per launch configuration but not credible as
+# HBM bytes for these kernels: most configurations of the 2.0 GB batch pass read 2.1-2.2 GB,
+# yet some read 10-100 MB, and the teaser's 108 MB pass reads 1-3 MB in most
+# configurations and 114 MB in others.  Traffic is therefore not reported.
+TRAFFIC_NOTE = "null: FETCH_SIZE is inconsistent across launch configurations for these kernels"
 
 
 def log(msg):
@@ -56,14 +55,34 @@ def algorithmic_bytes(n, nnz_s):
     return s_pass, st_pass
 
 
-def st_traffic():
-    path = os.path.join(ROOT, ST_COUNTERS["source"])
-    with open(path, "rb") as f:
-        h = hashlib.sha256(f.read()).hexdigest()[:16]
-    if h != ST_COUNTERS["sha256_16"]:
-        return None
-    return 1024.0 * (ST_COUNTERS["fetch_kib"] * ST_COUNTERS["fetch_scale"] +
-                     ST_COUNTERS["write_kib"] * ST_COUNTERS["write_scale"])
+def copy_probe(torch, mib=256):
+    """A plain float32 copy of `mib` MiB, three times: the reference kernel whose counter
+    readings scale FETCH_SIZE / WRITE_SIZE to bytes."""
+    a = torch.ones(mib << 18, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    out = {"kernel": "torch neg (elementwise)", "read_bytes": 4 * a.numel(), "write_bytes": 4 * a.numel()}
+    del a, b
+    return out
+
+
+def counter_pass(sim):
+    """Fixed launch sequence for counter collection: for each S-pass configuration (row
+    group 1, 2, 4, 8 x segment 1024, 2048, 4096 floats) and then each S^T-pass column group
+    (1, 2, 4, 8), 1 + COUNTER_PASS_LAUNCHES back-to-back launches; then the copy probe."""
+    seq = []
+    for rg in (1, 2, 4, 8):
+        for seg in (1024, 2048, 4096):
+            sim.set_tuning(row_group=rg, seg_floats=seg)
+            sim.time_kernel(0, COUNTER_PASS_LAUNCHES)
+            seq.append(("S", rg, seg))
+    for cg in (1, 2, 4, 8):
+        sim.set_tuning(col_group=cg)
+        sim.time_kernel(1, COUNTER_PASS_LAUNCHES)
+        seq.append(("St", cg))
+    return seq
 
 
 def cpu_baseline(scene):
@@ -189,10 +208,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--launch", default=None,
-                    help="fixed launch configuration cr_blocks,cr_variant,seg_floats,elem_block (no autotuning)")
+                    help="fixed launch configuration cr_blocks,cr_variant,seg_floats,elem_block,row_group,"
+                         "col_group (no autotuning)")
     ap.add_argument("--no-extras", action="store_true", help="skip the warm-start comparison and the batch")
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--batch-only", action="store_true", help="only the batch measurement (for profiling)")
+    ap.add_argument("--counter-pass", action="store_true",
+                    help="only the fixed S-pass launch sequence for rocprofv3 counters (teaser, or the batch "
+                         "with --batch-only), then copy probes of 256 MiB and 4 GiB")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the benchmark, run a plain float32 copy of 256 MiB three times "
                          "(reference kernel for scaling the HBM byte counters)")
@@ -209,6 +232,14 @@ def main():
     from paper_2503_15078_amd import lgsim, scenes
 
     torch.cuda.init()
+    if args.batch_only and args.counter_pass:
+        sim = lgsim.Sim(batch=scenes.batch_scenes(0, count=args.batch_scenes), max_contacts=32768)
+        sim.step(1, iters=ITERS)
+        seq = counter_pass(sim)
+        sim.close()
+        print(json.dumps({"counter_pass": seq, "launches_per_config": 1 + COUNTER_PASS_LAUNCHES,
+                          "copy_probe": [copy_probe(torch, 256), copy_probe(torch, 4096)]}))
+        return
     if args.batch_only:
         print(json.dumps({"batch": batch_throughput(args.batch_scenes, 10)}))
         return
@@ -220,9 +251,16 @@ def main():
     log(f"n={sc.n} m={sc.m} nnz(S)={nnz_s}; creating solver")
     sim = lgsim.Sim(sc)
     sim.save_state()
+    if args.counter_pass:
+        sim.step(1, iters=ITERS)
+        seq = counter_pass(sim)
+        sim.close()
+        print(json.dumps({"counter_pass": seq, "launches_per_config": 1 + COUNTER_PASS_LAUNCHES,
+                          "copy_probe": [copy_probe(torch, 256), copy_probe(torch, 4096)]}))
+        return
     if args.launch:
-        cb, cv, sf, eb = (int(x) for x in args.launch.split(","))
-        sim.set_tuning(cr_blocks=cb, cr_variant=cv, seg_floats=sf, elem_block=eb)
+        cb, cv, sf, eb, rg, cg = (int(x) for x in args.launch.split(","))
+        sim.set_tuning(cr_blocks=cb, cr_variant=cv, seg_floats=sf, elem_block=eb, row_group=rg, col_group=cg)
         tune = sim.tuning()
     else:
         tune = sim.tuning() if args.no_tune else sim.autotune(frames=3, iters=ITERS, allow_pipelined=True)
@@ -262,10 +300,9 @@ def main():
     dom = max(cand, key=lambda k: cand[k][0])
     dur_ms, nbytes = cand[dom]
     achieved = nbytes / (dur_ms * 1e-3) / 1e9
-    traffic = st_traffic() if dom == "St_pass" else None
     roofline = {"bound": "hbm", "kernel": {"S_pass": "k_spmv_S (+k_spmv_S_finish)", "St_pass": "k_spmv_St"}[dom],
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": round(traffic) if traffic else None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "traffic_note": TRAFFIC_NOTE,
                 "bytes_per_launch": int(nbytes), "avg_launch_ms": round(float(dur_ms), 5)}
 
     log("to-tolerance frames")
@@ -323,14 +360,7 @@ def main():
     }
     out.update(extras)
     if args.copy_probe:
-        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            torch.neg(a, out=b)
-        torch.cuda.synchronize()
-        out["copy_probe"] = {"kernel": "torch neg (elementwise)", "read_bytes": 4 * a.numel(),
-                             "write_bytes": 4 * a.numel()}
-        del a, b
+        out["copy_probe"] = copy_probe(torch)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(sc)

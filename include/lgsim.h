@@ -183,12 +183,13 @@ typedef struct {
 } sim_tuning;
 int sim_get_tuning(sim_t s, sim_tuning* t);
 int sim_set_tuning(sim_t s, const sim_tuning* t);
-/* Autotuner: from the current state (restored afterwards), time `frames` frames of
- * `iters` iterations for candidate configurations (S-pass row group and S^T-pass column
- * group 1/2/4/8, segment length 1024/2048/4096,
- * element block 64/128/256, then CR blocks 16..256, both CR forms if allow_pipelined)
- * by coordinate search, keep the fastest and report it in *best.  The candidates that
- * change rounding (groups, segment length, CR form) stay within the parity tolerances. */
+/* Autotuner, from the current state (restored afterwards).  The S-pass row group and
+ * segment length (1/2/4/8 x 1024/2048/4096) and the S^T-pass column group (1/2/4/8) are
+ * chosen by the times of 30 back-to-back launches of those kernels; then the element
+ * block (64/128/256), CR blocks (16..256) and both CR forms if allow_pipelined are chosen
+ * by coordinate search over the time of `frames` frames of `iters` iterations.  The
+ * fastest configuration is kept and reported in *best.  The candidates that change
+ * rounding (groups, segment length, CR form) stay within the parity tolerances. */
 int sim_autotune(sim_t s, int32_t frames, int32_t iters, int32_t allow_pipelined, sim_tuning* best);
 
 /* Replace the obstacle set (n >= 0; at most 64). */

@@ -186,7 +186,8 @@ int build_col_groups(lgsim* s, int col_group) {
 int build_segments(lgsim* s, int seg_floats, int row_group) {
   auto& d = s->d;
   const int N = d.N;
-  std::vector<int> seg_row, seg_ng, seg_q0, seg_len, long_row, long_seg0, long_nseg, long_ng;
+  std::vector<int> seg_row, seg_ng, seg_q0, seg_len, seg_col0, long_row, long_seg0, long_nseg, long_ng;
+  std::vector<int64_t> seg_off;
   for (int i = 0; i < N;) {
     int ng = 1;
     while (ng < row_group && i + ng < N && s->h_row_lo4[i + ng] == s->h_row_lo4[i]) ++ng;
@@ -204,12 +205,15 @@ int build_segments(lgsim* s, int seg_floats, int row_group) {
       seg_row.push_back(nseg > 1 ? -(i + 1) : i);
       seg_ng.push_back(ng);
       seg_q0.push_back((int)(st / 4));
+      seg_off.push_back(s->h_row_ptr[i] + st);
+      seg_col0.push_back(s->h_row_lo4[i] + (int)st);
       seg_len.push_back((int)std::min<int64_t>(seg_floats, len - st));
     }
     i += ng;
   }
   HIPCHK(hipStreamSynchronize(s->st));
-  for (void* p : {(void*)d.seg_row, (void*)d.seg_ng, (void*)d.seg_q0, (void*)d.seg_len, (void*)d.long_row,
+  for (void* p : {(void*)d.seg_row, (void*)d.seg_ng, (void*)d.seg_q0, (void*)d.seg_len, (void*)d.seg_col0,
+                  (void*)d.seg_off, (void*)d.long_row,
                   (void*)d.long_seg0, (void*)d.long_nseg, (void*)d.long_ng, (void*)d.partial})
     s->release(p);
   d.nseg = (int)seg_row.size();
@@ -218,6 +222,8 @@ int build_segments(lgsim* s, int seg_floats, int row_group) {
   TRY(s->alloc(d.seg_ng, d.nseg));
   TRY(s->alloc(d.seg_q0, d.nseg));
   TRY(s->alloc(d.seg_len, d.nseg));
+  TRY(s->alloc(d.seg_col0, d.nseg));
+  TRY(s->alloc(d.seg_off, d.nseg));
   TRY(s->alloc(d.long_row, d.nlong));
   TRY(s->alloc(d.long_seg0, d.nlong));
   TRY(s->alloc(d.long_nseg, d.nlong));
@@ -228,6 +234,8 @@ int build_segments(lgsim* s, int seg_floats, int row_group) {
   TRY(upload(s, d.seg_ng, seg_ng.data(), seg_ng.size()));
   TRY(upload(s, d.seg_q0, seg_q0.data(), seg_q0.size()));
   TRY(upload(s, d.seg_len, seg_len.data(), seg_len.size()));
+  TRY(upload(s, d.seg_col0, seg_col0.data(), seg_col0.size()));
+  TRY(upload(s, d.seg_off, seg_off.data(), seg_off.size()));
   TRY(upload(s, d.long_row, long_row.data(), long_row.size()));
   TRY(upload(s, d.long_seg0, long_seg0.data(), long_seg0.size()));
   TRY(upload(s, d.long_nseg, long_nseg.data(), long_nseg.size()));
@@ -1105,8 +1113,8 @@ int sim_autotune(sim_t s, int32_t frames, int32_t iters, int32_t allow_pipelined
   TRY(sim_get_tuning(s, &cur));
   float best_ms = 0.0f;
   int rc = measure(cur, &best_ms);
-  // coordinate search: S / S^T group sizes, S-pass segment length, element block size,
-  // then the CR launch
+  // S / S^T group sizes and segment length by kernel times, then coordinate search over
+  // the element block size and the CR launch by frame times
   auto try_cand = [&](sim_tuning c) -> int {
     float m = 0.0f;
     TRY(measure(c, &m));
@@ -1116,24 +1124,37 @@ int sim_autotune(sim_t s, int32_t frames, int32_t iters, int32_t allow_pipelined
     }
     return SIM_OK;
   };
-  for (int g : {1, 2, 4, 8})
-    if (rc == SIM_OK && g != cur.row_group) {
-      sim_tuning c = cur;
-      c.row_group = g;
-      rc = try_cand(c);
-    }
-  for (int g : {1, 2, 4, 8})
-    if (rc == SIM_OK && g != cur.col_group) {
-      sim_tuning c = cur;
+  // S-pass parameters change only their own kernels: chosen by those kernels' times
+  // (back-to-back launches), which are far steadier than whole frames
+  if (rc == SIM_OK) {
+    float best_s = 0.0f, best_st = 0.0f;
+    sim_tuning c = cur;
+    for (int g : {1, 2, 4, 8})
+      for (int seg : {1024, 2048, 4096}) {
+        c.row_group = g;
+        c.seg_floats = seg;
+        float m = 0.0f;
+        if (rc == SIM_OK) rc = sim_set_tuning(s, &c);
+        if (rc == SIM_OK) rc = sim_time_kernel(s, 0, 30, &m);
+        if (rc == SIM_OK && (best_s == 0.0f || m < best_s)) {
+          best_s = m;
+          cur.row_group = g;
+          cur.seg_floats = seg;
+        }
+      }
+    for (int g : {1, 2, 4, 8}) {
+      c = cur;
       c.col_group = g;
-      rc = try_cand(c);
+      float m = 0.0f;
+      if (rc == SIM_OK) rc = sim_set_tuning(s, &c);
+      if (rc == SIM_OK) rc = sim_time_kernel(s, 1, 30, &m);
+      if (rc == SIM_OK && (best_st == 0.0f || m < best_st)) {
+        best_st = m;
+        cur.col_group = g;
+      }
     }
-  for (int seg : {1024, 2048, 4096})
-    if (rc == SIM_OK && seg != cur.seg_floats) {
-      sim_tuning c = cur;
-      c.seg_floats = seg;
-      rc = try_cand(c);
-    }
+    if (rc == SIM_OK) rc = measure(cur, &best_ms);
+  }
   for (int eb : {64, 128, 256})
     if (rc == SIM_OK && eb != cur.elem_block) {
       sim_tuning c = cur;

@@ -70,8 +70,10 @@ struct Dev {
   int row_group, col_group;        // group size limits of the S and S^T passes (1, 2, 4, 8)
   // S-pass segments: a group of up to row_group consecutive rows stored from the same
   // column quad, cut along its columns; seg_row = first row (-(row + 1) if the group has
-  // several segments), seg_q0 = first quad of the segment, seg_len = its floats per row
-  int *seg_row, *seg_ng, *seg_q0, *seg_len;
+  // several segments), seg_q0 = first quad of the segment, seg_len = its floats per row,
+  // seg_off = row_ptr of the first row + 4 seg_q0, seg_col0 = its first column
+  int *seg_row, *seg_ng, *seg_q0, *seg_len, *seg_col0;
+  int64_t *seg_off;
   int *long_row, *long_seg0, *long_nseg, *long_ng;
   float *partial;                  // [3][row_group][nseg]
   int64_t *col_ptr;

@@ -32,14 +32,20 @@ __global__ void __launch_bounds__(kBlock) k_spmv_S(Dev d, const float* __restric
   const int i0 = r >= 0 ? r : -r - 1;
   const int ng = d.seg_ng[wave], q0 = d.seg_q0[wave];
   const int nq = d.seg_len[wave] >> 2;
-  const int col0 = d.row_lo4[i0] + 4 * q0;
+  const int col0 = d.seg_col0[wave];
+  const int64_t off0 = d.seg_off[wave];
+  // row i0 + g is stored over quads [lo4 / 4, (i0 + g) / 4 + 1): its length and its
+  // offset from row i0 follow from the indices alone
+  const int lo4q = (col0 >> 2) - q0;
   const float4* S4[G];
   int n4[G];
+  int64_t rel = 0;
 #pragma unroll
   for (int g = 0; g < G; ++g) {
-    const int64_t p = g < ng ? d.row_ptr[i0 + g] : 0;
-    n4[g] = g < ng ? min(nq, (int)((d.row_ptr[i0 + g + 1] - p) >> 2) - q0) : 0;
-    S4[g] = reinterpret_cast<const float4*>(d.row_val + p + 4 * (int64_t)q0);
+    const int len4 = ((i0 + g) >> 2) + 1 - lo4q;
+    n4[g] = g < ng ? min(nq, len4 - q0) : 0;
+    S4[g] = reinterpret_cast<const float4*>(d.row_val + off0 + rel);
+    rel += 4 * (int64_t)len4;
   }
   const float4* __restrict__ bx = reinterpret_cast<const float4*>(b + col0);
   const float4* __restrict__ by = reinterpret_cast<const float4*>(b + d.N4 + col0);
@@ -53,8 +59,13 @@ __global__ void __launch_bounds__(kBlock) k_spmv_S(Dev d, const float* __restric
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       if (n4[g] > 0) {  // uniform: the row has quads in this segment
-        float4 sv = S4[g][min(q, n4[g] - 1)];
-        if (q >= n4[g]) sv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        float4 sv;
+        if constexpr (G == 1) {  // a lone row spans its whole segment
+          sv = S4[g][q];
+        } else {
+          sv = S4[g][min(q, n4[g] - 1)];
+          if (q >= n4[g]) sv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
         acc[g][0] += dot4(sv, x);
         acc[g][1] += dot4(sv, yy);
         acc[g][2] += dot4(sv, z);
