@@ -307,8 +307,10 @@ __global__ void k_adjacent_lca(Dev d) {
 // The column paths of both contacts are staged root-aligned in LDS in chunks; a pair
 // accumulates only over its common prefix (its common ancestors).
 __global__ void __launch_bounds__(kBlock) k_delassus_tiles(Dev d) {
-  __shared__ float PJ[kDelTile][kDelChunk + 1];
-  __shared__ float PK[kDelTile][kDelChunk + 1];
+  // rows padded by 4 floats: 16-byte aligned, and the 16 rows of a float4 read start in
+  // distinct bank groups
+  __shared__ __align__(16) float PJ[kDelTile][kDelChunk + 4];
+  __shared__ __align__(16) float PK[kDelTile][kDelChunk + 4];
   __shared__ int LJK[kDelTile][kDelTile];
   __shared__ int sufJ[kDelTile], preK[kDelTile];
   __shared__ int dJ[kDelTile], dK[kDelTile];
@@ -417,10 +419,16 @@ __global__ void __launch_bounds__(kBlock) k_delassus_tiles(Dev d) {
       }
       __syncthreads();
       for (int r = 0; r < kPP; ++r) {
-        int L = LJK[a][b0 + r] - base;
-        int lim = min(L, kDelChunk);
+        const int L = LJK[a][b0 + r] - base;
+        const int lim = min(L, kDelChunk), lim4 = max(lim, 0) >> 2;
+        const float4* pj = reinterpret_cast<const float4*>(&PJ[a][0]);
+        const float4* pk = reinterpret_cast<const float4*>(&PK[b0 + r][0]);
         float sacc = 0.0f;
-        for (int q = 0; q < lim; ++q) sacc += PJ[a][q] * PK[b0 + r][q];
+        for (int q = 0; q < lim4; ++q) {
+          const float4 x = pj[q], y = pk[q];
+          sacc += x.x * y.x + x.y * y.y + x.z * y.z + x.w * y.w;
+        }
+        for (int q = 4 * lim4; q < lim; ++q) sacc += PJ[a][q] * PK[b0 + r][q];
         acc[r] += sacc;
       }
       __syncthreads();

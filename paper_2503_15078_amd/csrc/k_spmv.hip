@@ -92,17 +92,25 @@ __global__ void __launch_bounds__(kBlock) k_spmv_S(Dev d, const float* __restric
 }
 
 // Row groups of several segments: y_i = sum of the row's partials, in segment order.
+// One thread per (group, coordinate, row of the group); the first eight partials are
+// loaded together before the ordered sum.
 __global__ void k_spmv_S_finish(Dev d, float* __restrict__ y) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= d.nlong) return;
-  const int s0 = d.long_seg0[l], ns = d.long_nseg[l], i0 = d.long_row[l], ng = d.long_ng[l];
-  for (int g = 0; g < ng; ++g)
-    for (int c = 0; c < 3; ++c) {
-      const float* p = d.partial + (c * d.row_group + g) * (int64_t)d.nseg + s0;
-      float a = 0.0f;
-      for (int k = 0; k < ns; ++k) a += p[k];
-      y[c * d.N4 + i0 + g] = a;
-    }
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int G = d.row_group;
+  if (t >= d.nlong * 3 * G) return;
+  const int l = t / (3 * G), c = (t / G) % 3, g = t % G;
+  if (g >= d.long_ng[l]) return;
+  const int s0 = d.long_seg0[l], ns = d.long_nseg[l], i0 = d.long_row[l];
+  const float* p = d.partial + (c * G + g) * (int64_t)d.nseg + s0;
+  float v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = k < ns ? p[k] : 0.0f;
+  float a = v[0];
+#pragma unroll
+  for (int k = 1; k < 8; ++k)
+    if (k < ns) a += v[k];
+  for (int k = 8; k < ns; ++k) a += p[k];
+  y[c * d.N4 + i0 + g] = a;
 }
 
 void launch_spmv_S(const Dev& d, hipStream_t st, const float* b, float* y) {
@@ -114,7 +122,8 @@ void launch_spmv_S(const Dev& d, hipStream_t st, const float* b, float* y) {
     default: hipLaunchKernelGGL(k_spmv_S<8>, grid, dim3(kBlock), 0, st, d, b, y); break;
   }
   if (d.nlong > 0)
-    hipLaunchKernelGGL(k_spmv_S_finish, dim3((d.nlong + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d, y);
+    hipLaunchKernelGGL(k_spmv_S_finish, dim3((d.nlong * 3 * d.row_group + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                       st, d, y);
 }
 
 // One wavefront per group of up to G consecutive columns j0 .. j0 + ng - 1 of one
