@@ -326,6 +326,14 @@ def main():
         extras["warm_start_benchmark_state"] = warm_compare(sim, params)
         extras["warm_start_held_out_drops"] = warm_drops(params)
     sim.close()
+    if not args.no_extras:
+        log("stick-sliding precision (NCP rows x preconditioner)")
+        from paper_2503_15078_amd import stick_slide
+        extras["stick_slide_precision"] = {
+            "test": ("stiff block (E=1e8) on a 10 deg slope, mu* = tan 10 deg, 10 L-G / 24 CR iterations, 40 frames; "
+                     "precision = smallest offset from mu* above which sliding (>= 0.5 x analytic velocity) "
+                     "and sticking (< 0.1 x) are both classified correctly"),
+            **{k: stick_slide.scan(k)["precision"] for k in stick_slide.CONFIGS}}
     if not args.no_extras and args.batch_scenes > 0:
         log(f"batch of {args.batch_scenes} scenes")
         extras["batch"] = batch_throughput(args.batch_scenes, 10)

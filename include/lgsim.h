@@ -82,7 +82,9 @@ typedef struct {
 /* Options.  cr_iters: Conjugate Residual iterations per L-G iteration (Sec. 7.1: 10).
  * warm: initial impulse of a frame (SIM_WARM_*).  ncp_tol/max_iters: stopping rule of
  * sim_step with iters == 0.  max_contacts: contact capacity (device buffers).
- * hip_stream: a hipStream_t to enqueue on (null: the library creates its own). */
+ * hip_stream: a hipStream_t to enqueue on (null: the library creates its own).
+ * ncp / precond: NCP function and complementarity preconditioner of the contact rows
+ * (SIM_NCP_*, SIM_PRECOND_*; the defaults are the method's). */
 typedef struct {
   double gravity[3];
   double pin_weight_scale; /* h^2 w_pin = 1e3 * scale * [A_n]_vv                */
@@ -96,6 +98,8 @@ typedef struct {
   double cr_tol;           /* > 0: CR also stops once |r| <= cr_tol |r_0| (0: fixed count) */
   int32_t cr_variant;      /* SIM_CR_TEXTBOOK (default) or SIM_CR_PIPELINED */
   int32_t graph;           /* 1 (default): fixed-iteration frames replay a captured hipGraph */
+  int32_t ncp;             /* SIM_NCP_FB (default) or SIM_NCP_MINMAP */
+  int32_t precond;         /* SIM_PRECOND_DELASSUS (default) or SIM_PRECOND_MASS */
 } sim_options;
 
 /* Forms of the Conjugate Residual iteration; both give the same iterates in exact
@@ -106,6 +110,18 @@ typedef struct {
  * synchronisation, with a relative accuracy floor near 1e-4 of the solution when run
  * to convergence (fine for a fixed handful of steps or a loose tolerance). */
 enum { SIM_CR_TEXTBOOK = 0, SIM_CR_PIPELINED = 1 };
+/* NCP functions of the contact rows (App. B): Fischer-Burmeister (the method's) or the
+ * minimum map.  Min-map rows: phi_n = delta_n with omega_n = 1, E_n = 0 where
+ * delta_n <= r_n lambda_n, else phi_n = r_n lambda_n with omega_n = 0, E_n = r_n; friction
+ * rows with lambda_n > 0 (and mu > 0): omega_f = 1 and E_f = 0 while
+ * |vdot_f| <= r_f (mu lambda_n - |lambda_f|), else E_f = (|vdot_f| - r_f (mu lambda_n -
+ * |lambda_f|)) / (mu lambda_n); otherwise omega_f = 0, E_f = 1. */
+enum { SIM_NCP_FB = 0, SIM_NCP_MINMAP = 1 };
+/* Complementarity preconditioner (Sec. 5.4): r_n = h^2 W_jj, r_f = h W_jj from the
+ * Delassus diagonal (the method's), or the mass-inverse form r_n = h^2 / m_v,
+ * r_f = h / m_v that Sec. 7's stick-sliding test compares against (m_v: lumped mass of
+ * the contact node). */
+enum { SIM_PRECOND_DELASSUS = 0, SIM_PRECOND_MASS = 1 };
 
 /* Obstacles (App. A: analytic contact partners).  geom by type:
  *   HALFSPACE [px,py,pz, nx,ny,nz]        solid where n.(x-p) < 0

@@ -1,11 +1,13 @@
-"""Contacts: obstacle distances, frames, Fischer-Burmeister terms, NCP residual (FP64).
+"""Contacts: obstacle distances, frames, Fischer-Burmeister and minimum-map terms, NCP
+residual (FP64).
 
 Paper: Sec. 3.2 (linearised constraints along n and tangents f built by
 Gram-Schmidt; Signorini-Coulomb conditions), App. A (constraint
 linearisation; interpenetration computed from positions only:
 delta_n = H_n q - d_n, h delta_dot_f = H_f (q - q_t) - h d_f), App. B
-(Fischer-Burmeister NCP functions and their derivatives), Sec. 5.4
-(complementarity preconditioner r from the Delassus diagonal).
+(Fischer-Burmeister and minimum-map NCP functions and their derivatives), Sec. 5.4
+(complementarity preconditioner r from the Delassus diagonal, or from the mass
+inverse as in the comparison of Sec. 7, stick-sliding test).
 
 Readings where the paper is silent:
 * detection: pair (v, o) is a contact iff min(sdf_o(x_t), sdf_o(x~)) < margin,
@@ -172,6 +174,37 @@ def friction_terms(vdot_f, lam_n, lam_f, r_f, mu):
         Ef_act = np.where(den != 0.0, num / np.where(den != 0.0, den, 1.0) * r_f, 0.0)
     omega = np.where(active, 1.0, 0.0)
     Ef = np.where(active, Ef_act, 1.0)
+    phi = omega[:, None] * vdot_f + Ef[:, None] * lam_f
+    return omega, Ef, phi
+
+
+def normal_terms_minmap(delta_n, lam_n, r_n):
+    """App. B minimum-map normal row: phi_n = delta_n with omega_n = 1, E_n = 0 where
+    delta_n <= r_n lam_n (ties included), else phi_n = r_n lam_n with omega_n = 0, E_n = r_n."""
+    first = delta_n <= r_n * lam_n
+    phi = np.where(first, delta_n, r_n * lam_n)
+    omega = np.where(first, 1.0, 0.0)
+    E = np.where(first, 0.0, r_n)
+    return phi, omega, E
+
+
+def friction_terms_minmap(vdot_f, lam_n, lam_f, r_f, mu):
+    """App. B minimum-map friction rows: phi_f = omega_f vdot_f + E_f lambda_f.
+
+    lambda_n <= 0: omega_f = 0, E_f = 1 (drives lambda_f to 0).  lambda_n > 0: omega_f = 1
+    and E_f = 0 while |vdot_f| <= r_f (mu lambda_n - |lambda_f|) (stick), else
+    E_f = (|vdot_f| - r_f (mu lambda_n - |lambda_f|)) / (mu lambda_n) (slide).  Reading
+    shared with the FB rows: mu = 0 (the cone is the point lambda_f = 0) is inactive.
+    """
+    s = np.sqrt((vdot_f ** 2).sum(1))
+    lf = np.sqrt((lam_f ** 2).sum(1))
+    gamma = mu * lam_n - lf
+    active = (lam_n > 0.0) & (mu > 0.0)
+    slide = s > r_f * gamma
+    with np.errstate(divide="ignore", invalid="ignore"):
+        Ef_slide = (s - r_f * gamma) / np.where(active, mu * lam_n, 1.0)
+    Ef = np.where(active, np.where(slide, Ef_slide, 0.0), 1.0)
+    omega = np.where(active, 1.0, 0.0)
     phi = omega[:, None] * vdot_f + Ef[:, None] * lam_f
     return omega, Ef, phi
 

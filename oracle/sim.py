@@ -11,7 +11,10 @@ Paper: Algorithm 4 (unified GPU-friendly pipeline), with
   q = A^-1 (b + h^2 J^T lambda);
 * Sec. 5.3: J = Omega H with the indicators of App. B, Schur term Omega W Omega
   with the Delassus operator W = H A^-1 H^T formed once per frame;
-* Sec. 5.4: preconditioner r_n = h^2 W_jj (normal), r_f = h W_jj (friction);
+* Sec. 5.4: preconditioner r_n = h^2 W_jj (normal), r_f = h W_jj (friction); the
+  ablation of Sec. 7 (stick-sliding test) uses the mass inverse instead,
+  r_n = h^2 / m_v, r_f = h / m_v (precond="mass");
+* App. B: Fischer-Burmeister rows (default) or minimum-map rows (ncp="minmap");
 * App. A: delta_n = H_n q - d_n, h delta_dot_f = H_f (q - q_t) - h d_f.
 
 The global step is the plain definition u = A^-1 rhs, by a sparse LU
@@ -58,7 +61,10 @@ class FrameContacts:
 
 
 class OracleSim:
-    def __init__(self, scene, cr_iters=None, pin_weight_scale=None, margin=None):
+    def __init__(self, scene, cr_iters=None, pin_weight_scale=None, margin=None, ncp="fb", precond="delassus"):
+        if ncp not in ("fb", "minmap") or precond not in ("delassus", "mass"):
+            raise OracleError("ncp must be 'fb' or 'minmap', precond 'delassus' or 'mass'")
+        self.ncp, self.precond = ncp, precond
         self.scene = scene
         self.h = float(scene.h)
         self.g = np.asarray(scene.gravity, np.float64)
@@ -148,8 +154,13 @@ class OracleSim:
             gap[j] = d
         K, W = self.delassus(node, C)
         Wd = np.diagonal(W)
-        r_n = self.h * self.h * Wd[0::3] if c else np.zeros(0)
-        r_f = self.h * 0.5 * (Wd[1::3] + Wd[2::3]) if c else np.zeros(0)
+        if self.precond == "mass":
+            # [H M^-1 H^T]_jj of a unit row at node v is 1 / m_v
+            r_n = self.h * self.h / self.mass[node]
+            r_f = self.h / self.mass[node]
+        else:
+            r_n = self.h * self.h * Wd[0::3] if c else np.zeros(0)
+            r_f = self.h * 0.5 * (Wd[1::3] + Wd[2::3]) if c else np.zeros(0)
         return FrameContacts(node, obst, C, d_n, d_f, mu, K, W, r_n, r_f, gap)
 
     def delassus(self, node, C):
@@ -188,8 +199,12 @@ class OracleSim:
         delta_n = np.einsum("ji,ji->j", n, x) - fc.d_n
         hvf = np.einsum("jai,ji->ja", f, x - xt) - h * fc.d_f
         vdot_f = hvf / h
-        phi_n, om_n, E_n = ct.normal_terms(delta_n, lam[:, 0], fc.r_n)
-        om_f, E_f, phi_f = ct.friction_terms(vdot_f, lam[:, 0], lam[:, 1:], fc.r_f, fc.mu)
+        if self.ncp == "minmap":
+            phi_n, om_n, E_n = ct.normal_terms_minmap(delta_n, lam[:, 0], fc.r_n)
+            om_f, E_f, phi_f = ct.friction_terms_minmap(vdot_f, lam[:, 0], lam[:, 1:], fc.r_f, fc.mu)
+        else:
+            phi_n, om_n, E_n = ct.normal_terms(delta_n, lam[:, 0], fc.r_n)
+            om_f, E_f, phi_f = ct.friction_terms(vdot_f, lam[:, 0], lam[:, 1:], fc.r_f, fc.mu)
         Hq = np.einsum("jai,ji->ja", fc.C, x)                       # (c,3)
         hv = np.empty((fc.c, 3))
         hv[:, 0] = -phi_n + om_n * Hq[:, 0]

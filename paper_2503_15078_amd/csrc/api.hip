@@ -281,6 +281,8 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   d.cr_iters = s->opt.cr_iters;
   d.cr_tol = (float)s->opt.cr_tol;
   d.warm = s->opt.warm;
+  d.ncp = s->opt.ncp;
+  d.precond = s->opt.precond;
   d.elem_block = lg::kBlock;
   s->perm_caller.resize(N);
   s->iperm_caller.resize(N);
@@ -293,12 +295,13 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
 
   // ---- node arrays
   const int N4 = d.N4;
-  std::vector<float> qt(3 * (size_t)N4, 0.0f), vt(3 * (size_t)N4, 0.0f), pinw(N, 0.0f);
+  std::vector<float> qt(3 * (size_t)N4, 0.0f), vt(3 * (size_t)N4, 0.0f), pinw(N, 0.0f), inv_mass(N, 0.0f);
   std::vector<int> node_scene(N, 0);
   for (int k = 0; k < NS; ++k)
     for (int o = 0; o < hs[k].n; ++o) {
       int gi = s->scenes[k].node0 + hs[k].perm[o];
       node_scene[gi] = k;
+      inv_mass[gi] = (float)(1.0 / hs[k].mass[o]);
       for (int c = 0; c < 3; ++c) {
         qt[c * (size_t)N4 + gi] = (float)hs[k].init[3 * (size_t)o + c];
         vt[c * (size_t)N4 + gi] = (float)hs[k].vel[3 * (size_t)o + c];
@@ -398,6 +401,7 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   TRY(s->alloc(d.tmp, NV));
   TRY(s->alloc(d.iperm_caller, N));
   TRY(s->alloc(d.pin_w, N));
+  TRY(s->alloc(d.inv_mass, N));
   TRY(s->alloc(d.node_scene, N));
   TRY(s->alloc(d.g_ptr, N + 1));
   TRY(s->alloc(d.g_slot, 4 * (size_t)M));
@@ -494,6 +498,7 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   TRY(upload(s, d.qt, qt.data(), qt.size()));
   TRY(upload(s, d.vt, vt.data(), vt.size()));
   TRY(upload(s, d.pin_w, pinw.data(), pinw.size()));
+  TRY(upload(s, d.inv_mass, inv_mass.data(), inv_mass.size()));
   TRY(upload(s, d.node_scene, node_scene.data(), node_scene.size()));
   TRY(upload(s, d.iperm_caller, s->iperm_caller.data(), s->iperm_caller.size()));
   TRY(upload(s, d.g_ptr, g_ptr.data(), g_ptr.size()));
@@ -867,7 +872,9 @@ int create_common(int32_t count, const sim_mesh* meshes, const sim_material* mat
   if (s->opt.cr_iters < 0 || s->opt.cr_iters > lg::kMaxCrIters || !(s->opt.cr_tol >= 0.0) ||
       (s->opt.cr_variant != SIM_CR_TEXTBOOK && s->opt.cr_variant != SIM_CR_PIPELINED) ||
       s->opt.max_contacts <= 0 || s->opt.max_iters <= 0 || !(s->opt.ncp_tol > 0.0) ||
-      s->opt.warm < 0 || s->opt.warm > 2 || !(s->opt.contact_margin >= 0.0)) {
+      s->opt.warm < 0 || s->opt.warm > 2 || !(s->opt.contact_margin >= 0.0) ||
+      (s->opt.ncp != SIM_NCP_FB && s->opt.ncp != SIM_NCP_MINMAP) ||
+      (s->opt.precond != SIM_PRECOND_DELASSUS && s->opt.precond != SIM_PRECOND_MASS)) {
     lg::set_error("bad options");
     return fail(SIM_E_ARG);
   }
@@ -928,6 +935,8 @@ int sim_options_default(sim_options* o) {
   o->cr_tol = 0.0;
   o->cr_variant = SIM_CR_TEXTBOOK;
   o->graph = 1;
+  o->ncp = SIM_NCP_FB;
+  o->precond = SIM_PRECOND_DELASSUS;
   o->warm = SIM_WARM_PREV;
   o->ncp_tol = 1e-6;
   o->max_iters = 200;

@@ -48,6 +48,7 @@ struct Dev {
   double g[3];
   int cr_iters;
   int warm;
+  int ncp, precond;                // SIM_NCP_*, SIM_PRECOND_*
   // nodes
   float *qt, *vt, *qp, *q, *b, *y, *tgt, *pin_w, *tmp;
   int *node_scene;
@@ -119,6 +120,7 @@ struct Dev {
   // learned warm start
   double *ell;                     // [NS] mean rest edge length per scene
   float *c_feat;                   // [CMAX][16] features of the frame's contacts
+  float *inv_mass;                 // [N] 1 / lumped mass (mass-inverse preconditioner)
   float *mlp_P;                    // [kMlpParams] network parameters (float32 master copy)
   // frame state
   double *t;                       // [1] simulation time at frame start

@@ -467,6 +467,7 @@ __global__ void k_warm_start(Dev d, int keep_lambda) {
   float* krow = d.K + d.k_off[s] + (int64_t)(j - cs) * kstride(cnt);
   for (int k = cnt; k < kstride(cnt); ++k) krow[k] = 0.0f;  // pads of this row (storage is reused)
   float kjj = krow[j - cs];
+  if (d.precond == 1) kjj = d.inv_mass[d.c_node[j]];  // [H M^-1 H^T]_jj = 1 / m_v
   d.c_rn[j] = (float)(d.h * d.h) * kjj;
   d.c_rf[j] = (float)d.h * kjj;
   if (keep_lambda) return;
@@ -538,6 +539,37 @@ __device__ FBTerms fb_terms(float dn, const float vf[2], const float l[3], float
   return t;
 }
 
+// App. B, minimum-map rows.  Normal: phi_n = delta_n (omega_n = 1, E_n = 0) where
+// delta_n <= r_n lambda_n, else r_n lambda_n (omega_n = 0, E_n = r_n).  Friction with
+// lambda_n > 0 and mu > 0: omega_f = 1, E_f = 0 while |vdot_f| <= r_f (mu lambda_n -
+// |lambda_f|) (stick), else E_f = (|vdot_f| - r_f (mu lambda_n - |lambda_f|)) /
+// (mu lambda_n) (slide); otherwise inactive (omega_f = 0, E_f = 1) as in the FB rows.
+__device__ FBTerms minmap_terms(float dn, const float vf[2], const float l[3], float rn, float rf, float mu) {
+  FBTerms t;
+  if (dn <= rn * l[0]) {
+    t.phi_n = dn;
+    t.om_n = 1.0f;
+    t.E_n = 0.0f;
+  } else {
+    t.phi_n = rn * l[0];
+    t.om_n = 0.0f;
+    t.E_n = rn;
+  }
+  const float s = sqrtf(vf[0] * vf[0] + vf[1] * vf[1]);
+  const float lf = sqrtf(l[1] * l[1] + l[2] * l[2]);
+  const float gam = mu * l[0] - lf;
+  if (l[0] > 0.0f && mu > 0.0f) {
+    t.om_f = 1.0f;
+    t.E_f = s > rf * gam ? (s - rf * gam) / (mu * l[0]) : 0.0f;
+  } else {
+    t.om_f = 0.0f;
+    t.E_f = 1.0f;
+  }
+  t.phi_f[0] = t.om_f * vf[0] + t.E_f * l[1];
+  t.phi_f[1] = t.om_f * vf[1] + t.E_f * l[2];
+  return t;
+}
+
 // One wavefront per contact: u_v = q~_v + (S^T y)_v along the ancestor path of v
 // (the unconstrained solve A^-1 b at the contact node), then Omega, E~, the h vector
 // (Sec. 5.2) and X = C^T (Omega lambda) for the W Omega lambda term of J A^-1 g.
@@ -592,7 +624,8 @@ __global__ void __launch_bounds__(kBlock) k_contact_prep(Dev d) {
     hvf[r] = C[r + 1][0] * (x[0] - xt[0]) + C[r + 1][1] * (x[1] - xt[1]) + C[r + 1][2] * (x[2] - xt[2]) -
              h * d.c_df[r * CM + j];
   float vf[2] = {hvf[0] / h, hvf[1] / h};
-  FBTerms f = fb_terms(dn, vf, l, d.c_rn[j], d.c_rf[j], d.c_mu[j]);
+  FBTerms f = d.ncp == 1 ? minmap_terms(dn, vf, l, d.c_rn[j], d.c_rf[j], d.c_mu[j])
+                         : fb_terms(dn, vf, l, d.c_rn[j], d.c_rf[j], d.c_mu[j]);
   float om[3] = {f.om_n, f.om_f, f.om_f};
   d.Om[j] = om[0];
   d.Om[CM + j] = om[1];

@@ -25,14 +25,14 @@ def oracle_state_after(scene, frames, iters=None):
 
 
 def iterate_pair(sim_factory, scene, q_t, v_t, q_k, t, node, obst, lam, k=1, cr="fixed", cr_iters=None,
-                 gpu_cr_iters=None):
+                 gpu_cr_iters=None, sim_opt=None, oracle_opt=None):
     """k iterations from the same state on the GPU and in the oracle.
 
     cr="fixed": both run the scene's (or cr_iters) CR iterations; cr="exact": the oracle
     solves the Schur system exactly and the GPU runs gpu_cr_iters iterations (converged
     mode).  Returns (q_gpu, lam_gpu, q_oracle, lam_oracle, oracle, fc)."""
     q_t, v_t, q_k, lam = f32(q_t), f32(v_t), f32(q_k), f32(lam)
-    opt = {}
+    opt = dict(sim_opt or {})
     if gpu_cr_iters is not None:
         opt["cr_iters"] = gpu_cr_iters
     elif cr_iters is not None:
@@ -41,7 +41,7 @@ def iterate_pair(sim_factory, scene, q_t, v_t, q_k, t, node, obst, lam, k=1, cr=
     sim.set_iterate_state(q_t, v_t, q_k, t, node, obst, lam)
     sim.run_iterations(k)
     qg, lg = sim.read_iterate(len(node))
-    o = OracleSim(scene, cr_iters=cr_iters)
+    o = OracleSim(scene, cr_iters=cr_iters, **(oracle_opt or {}))
     o.t = t
     q_pred = o.predict(q_t, v_t)
     fc = o.contacts_from_keys(node, obst, q_t)
