@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
+#include "path_sums.hpp"
 
 namespace lg {
 
@@ -571,7 +572,7 @@ __device__ FBTerms minmap_terms(float dn, const float vf[2], const float l[3], f
 }
 
 // One wavefront per contact: u_v = q~_v + (S^T y)_v along the ancestor path of v
-// (the unconstrained solve A^-1 b at the contact node), then Omega, E~, the h vector
+// (column_path_sums; the unconstrained solve A^-1 b at the contact node), then Omega, E~, the h vector
 // (Sec. 5.2) and X = C^T (Omega lambda) for the W Omega lambda term of J A^-1 g.
 __global__ void __launch_bounds__(kBlock) k_contact_prep(Dev d) {
   const int j = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
@@ -580,25 +581,10 @@ __global__ void __launch_bounds__(kBlock) k_contact_prep(Dev d) {
   if (blockIdx.x == 0)  // barrier counters of the CR launch that follows
     for (int k = threadIdx.x; k <= min(2 * d.cr_iters + 2, kCrMaxBarriers); k += blockDim.x) d.cr_sync[k] = 0u;
   if (j >= c) return;
-  const int v = d.c_node[j];
-  const float* col = d.col_val + d.col_ptr[v];
-  float ax = 0.0f, ay = 0.0f, az = 0.0f;
-  int t = 0, a = v;
-  while (a != -1) {
-    int e = __builtin_amdgcn_readfirstlane(d.chain_end[a]);
-    int len = e - a + 1;
-    for (int k = lane; k < len; k += kWave) {
-      float s = col[t + k];
-      ax += s * d.y[a + k];
-      ay += s * d.y[d.N4 + a + k];
-      az += s * d.y[2 * d.N4 + a + k];
-    }
-    t += len;
-    a = __builtin_amdgcn_readfirstlane(d.parent[e]);
-  }
-  ax = wave_sum_c(ax);
-  ay = wave_sum_c(ay);
-  az = wave_sum_c(az);
+  const int v = __builtin_amdgcn_readfirstlane(d.c_node[j]);
+  float acc[1][3];
+  column_path_sums<1>(d, d.y, v, 1, lane, acc);
+  const float ax = wave_sum_c(acc[0][0]), ay = wave_sum_c(acc[0][1]), az = wave_sum_c(acc[0][2]);
   if (lane != 0) return;
   const int CM = d.CMAX;
   const float h = (float)d.h;
