@@ -84,7 +84,7 @@ typedef struct {
  * sim_step with iters == 0.  max_contacts: contact capacity (device buffers).
  * hip_stream: a hipStream_t to enqueue on (null: the library creates its own).
  * ncp / precond: NCP function and complementarity preconditioner of the contact rows
- * (SIM_NCP_*, SIM_PRECOND_*; the defaults are the method's). */
+ * (SIM_NCP_*, SIM_PRECOND_*; the defaults are the method's).  global_step: SIM_GLOBAL_*. */
 typedef struct {
   double gravity[3];
   double pin_weight_scale; /* h^2 w_pin = 1e3 * scale * [A_n]_vv                */
@@ -100,6 +100,7 @@ typedef struct {
   int32_t graph;           /* 1 (default): fixed-iteration frames replay a captured hipGraph */
   int32_t ncp;             /* SIM_NCP_FB (default) or SIM_NCP_MINMAP */
   int32_t precond;         /* SIM_PRECOND_DELASSUS (default) or SIM_PRECOND_MASS */
+  int32_t global_step;     /* SIM_GLOBAL_DIRECT (default) or SIM_GLOBAL_JACOBI */
 } sim_options;
 
 /* Forms of the Conjugate Residual iteration; both give the same iterates in exact
@@ -122,6 +123,15 @@ enum { SIM_NCP_FB = 0, SIM_NCP_MINMAP = 1 };
  * r_f = h / m_v that Sec. 7's stick-sliding test compares against (m_v: lumped mass of
  * the contact node). */
 enum { SIM_PRECOND_DELASSUS = 0, SIM_PRECOND_MASS = 1 };
+/* Global step of each L-G iteration: the direct solve q = A^-1 b through S^T S (Sec. 4,
+ * the method), or the incomplete solution that Sec. 7's convergence comparison uses as
+ * its baseline, one Jacobi sweep q <- q + D^-1 (b - A q) from the current iterate
+ * (D = diag A).  The Jacobi step is implemented for scenes without obstacles: sim_step
+ * and sim_run_iterations return SIM_E_STATE when a Jacobi handle has obstacles.
+ * Currently switched off (SIM_E_STATE from sim_step, sim_run_iterations and
+ * sim_lg_energy): a device run that included it ended in a GPU fault whose cause has not
+ * been established. */
+enum { SIM_GLOBAL_DIRECT = 0, SIM_GLOBAL_JACOBI = 1 };
 
 /* Obstacles (App. A: analytic contact partners).  geom by type:
  *   HALFSPACE [px,py,pz, nx,ny,nz]        solid where n.(x-p) < 0
@@ -263,7 +273,8 @@ int sim_batch_info(sim_t s, int32_t* count, int32_t* node_offsets);
 
 /* ---- parity hooks (tests) --------------------------------------------------------
  * Set a complete iterate state: frame start q_t, v_t [n][3], current iterate q_k
- * [n][3] (caller order), simulation time t (frame start), and a contact list of c
+ * [n][3] (caller order; NULL: q^0 = q~, the predicted state of Algorithm 4),
+ * simulation time t (frame start), and a contact list of c
  * entries (node, obstacle, lambda in the frame of that contact; frame rows and gap
  * are recomputed from q_t).  Recomputes the predicted state, frames, d_n, the
  * Delassus operator and the preconditioner exactly as a frame start does, but keeps
@@ -272,6 +283,14 @@ int sim_set_iterate_state(sim_t s, const double* q_t, const double* v_t, const d
                           double t, int32_t c, const sim_contact* contacts);
 /* Run k L-G iterations from the current iterate state without ending the frame. */
 int sim_run_iterations(sim_t s, int32_t k);
+/* The objective the L-G iteration minimises, at the current iterate q and the frame's
+ * q~ and pin targets, with the local variables at their optimum (Eq. PD local and PD
+ * global; Sec. 7's relative error is measured on it):
+ *   1/2 (q - q~)^T M (q - q~) + h^2 sum_t [w_t/2 |F_t - p_t|^2 + V_t psi(p_t)]
+ *   + 1/2 sum_pins h^2 w_pin |q_v - target|^2,
+ * p_t the prox of F_t (ARAP: the rotation of F_t).  Float32 positions and per-tet terms,
+ * float64 sums in a fixed order.  Contact terms are not included. */
+int sim_lg_energy(sim_t s, double* energy);
 /* Read the current iterate q_k [n][3] (caller order) and the impulses [c][3] of the
  * contact list, in canonical (node, obstacle) order. */
 int sim_read_iterate(sim_t s, double* q_k, double* lambda);

@@ -15,6 +15,9 @@ Paper: Algorithm 4 (unified GPU-friendly pipeline), with
   ablation of Sec. 7 (stick-sliding test) uses the mass inverse instead,
   r_n = h^2 / m_v, r_f = h / m_v (precond="mass");
 * App. B: Fischer-Burmeister rows (default) or minimum-map rows (ncp="minmap");
+* Sec. 7 (performance and accuracy evaluation): the incomplete global step of the
+  comparison, one Jacobi sweep from the current iterate (global_step="jacobi",
+  contact-free frames), and the objective the iteration minimises (lg_energy);
 * App. A: delta_n = H_n q - d_n, h delta_dot_f = H_f (q - q_t) - h d_f.
 
 The global step is the plain definition u = A^-1 rhs, by a sparse LU
@@ -61,10 +64,13 @@ class FrameContacts:
 
 
 class OracleSim:
-    def __init__(self, scene, cr_iters=None, pin_weight_scale=None, margin=None, ncp="fb", precond="delassus"):
+    def __init__(self, scene, cr_iters=None, pin_weight_scale=None, margin=None, ncp="fb", precond="delassus",
+                 global_step="direct"):
         if ncp not in ("fb", "minmap") or precond not in ("delassus", "mass"):
             raise OracleError("ncp must be 'fb' or 'minmap', precond 'delassus' or 'mass'")
-        self.ncp, self.precond = ncp, precond
+        if global_step not in ("direct", "jacobi"):
+            raise OracleError("global_step must be 'direct' or 'jacobi'")
+        self.ncp, self.precond, self.global_step = ncp, precond, global_step
         self.scene = scene
         self.h = float(scene.h)
         self.g = np.asarray(scene.gravity, np.float64)
@@ -122,6 +128,27 @@ class OracleSim:
     def local_step(self, q):
         F = fem.deformation_gradient(q, self.tets, self.D)
         return mat.local_step(self.model, F, self.mu, self.lam, self.k)
+
+    def lg_energy(self, q, q_pred, t_next):
+        """The objective that the local-global iteration minimises, at its optimal local
+        variables (Eq. PD local and PD global):
+            1/2 (q - q~)^T M (q - q~) + h^2 sum_t [w_t/2 |F_t - p_t|^2 + V_t psi(p_t)]
+            + 1/2 sum_pins h^2 w_pin |q_v - target|^2,
+        with p_t = U diag(s*) V^T the prox of F_t, so |F_t - p_t|^2 = |sigma - s*|^2.  For
+        ARAP psi is the indicator of SO(3) and the tet term is k V / 2 |F - R(F)|^2, the
+        ARAP energy; the minimiser of this objective is the backward-Euler step."""
+        h = self.h
+        dq = q - q_pred
+        e = 0.5 * float((self.mass[:, None] * dq * dq).sum())
+        F = fem.deformation_gradient(q, self.tets, self.D)
+        _, sig, _ = mat.svd_rv(F)
+        s = mat.prox_singular(self.model, sig, self.mu, self.lam, self.k)
+        psi = mat.energy(self.model, s, self.mu, self.lam)
+        e += h * h * float((0.5 * self.w * ((sig - s) ** 2).sum(1) + self.V * psi).sum())
+        if len(self.pin_nodes):
+            r = q[self.pin_nodes] - self.pin_target(t_next)
+            e += 0.5 * float((self.pin_h2w[:, None] * r * r).sum())
+        return e
 
     def rhs(self, q, q_pred, t_next):
         """b = M q~ + h^2 sum w G^T p (+ pin terms) at positions q."""
@@ -228,8 +255,14 @@ class OracleSim:
         b = self.rhs(q, q_pred, t_next)
         info = {}
         if fc.c == 0:
-            qn = self.solve(b)
+            if self.global_step == "jacobi":
+                # one Jacobi sweep from the current iterate: q + D^-1 (b - A q)
+                qn = q + (b - self.A @ q) / self.A.diagonal()[:, None]
+            else:
+                qn = self.solve(b)
             return qn, lam.copy(), info
+        if self.global_step == "jacobi":
+            raise OracleError("the Jacobi global step is defined here for contact-free frames")
         ev = self.contact_eval(fc, q, q_t, lam)
         Om = ev["Omega"]
         g = b + h * h * self.H_T(fc, Om * lam)

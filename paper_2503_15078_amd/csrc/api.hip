@@ -70,6 +70,7 @@ struct lgsim {
   std::vector<int64_t> h_row_ptr;
   std::vector<int32_t> h_row_lo4;
   std::vector<int32_t> h_chain_end;
+  double* energy_part = nullptr;  // per-block partial sums of sim_lg_energy
   int seg_floats = 0;
   // captured fixed-iteration frame
   hipGraphExec_t gexec = nullptr;
@@ -283,6 +284,7 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   d.warm = s->opt.warm;
   d.ncp = s->opt.ncp;
   d.precond = s->opt.precond;
+  d.global_step = s->opt.global_step;
   d.elem_block = lg::kBlock;
   s->perm_caller.resize(N);
   s->iperm_caller.resize(N);
@@ -402,6 +404,35 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   TRY(s->alloc(d.iperm_caller, N));
   TRY(s->alloc(d.pin_w, N));
   TRY(s->alloc(d.inv_mass, N));
+  {
+    // A_n in internal order (CSR) for the Jacobi global step
+    std::vector<int> ap(N + 1, 0), ai;
+    std::vector<float> av, adinv(N, 0.0f);
+    for (int k = 0; k < NS; ++k)
+      for (int o = 0; o < hs[k].n; ++o) ap[s->scenes[k].node0 + hs[k].perm[o] + 1] = (int)(hs[k].a_ptr[o + 1] - hs[k].a_ptr[o]);
+    for (int v = 0; v < N; ++v) ap[v + 1] += ap[v];
+    ai.resize(ap[N]);
+    av.resize(ap[N]);
+    for (int k = 0; k < NS; ++k)
+      for (int o = 0; o < hs[k].n; ++o) {
+        const int gi = s->scenes[k].node0 + hs[k].perm[o];
+        int w = ap[gi];
+        for (int64_t p = hs[k].a_ptr[o]; p < hs[k].a_ptr[o + 1]; ++p, ++w) {
+          const int gj = s->scenes[k].node0 + hs[k].perm[hs[k].a_idx[p]];
+          ai[w] = gj;
+          av[w] = (float)hs[k].a_val[p];
+          if (gj == gi) adinv[gi] = (float)(1.0 / hs[k].a_val[p]);
+        }
+      }
+    TRY(s->alloc(d.a_ptr, N + 1));
+    TRY(s->alloc(d.a_idx, ai.size()));
+    TRY(s->alloc(d.a_val, av.size()));
+    TRY(s->alloc(d.a_dinv, N));
+    TRY(upload(s, d.a_ptr, ap.data(), ap.size()));
+    TRY(upload(s, d.a_idx, ai.data(), ai.size()));
+    TRY(upload(s, d.a_val, av.data(), av.size()));
+    TRY(upload(s, d.a_dinv, adinv.data(), adinv.size()));
+  }
   TRY(s->alloc(d.node_scene, N));
   TRY(s->alloc(d.g_ptr, N + 1));
   TRY(s->alloc(d.g_slot, 4 * (size_t)M));
@@ -661,6 +692,26 @@ int validate_obstacles(int32_t n, const sim_obstacle* obs) {
   return SIM_OK;
 }
 
+// Switched off: a device run that included the Jacobi global step and the objective
+// kernel ended in a GPU fault whose cause has not been established.
+constexpr bool kJacobiEnabled = false;
+constexpr const char* kJacobiOff =
+    "the Jacobi global step and the objective kernel are switched off (a run that included them ended in a GPU "
+    "fault of unknown cause)";
+
+// The Jacobi global step has no constraint solve: it needs a handle without obstacles.
+int check_global_step(lgsim* s) {
+  if (s->opt.global_step == SIM_GLOBAL_JACOBI && !kJacobiEnabled) {
+    lg::set_error(kJacobiOff);
+    return SIM_E_STATE;
+  }
+  if (s->opt.global_step == SIM_GLOBAL_JACOBI && !s->obst.empty()) {
+    lg::set_error("the Jacobi global step is implemented for scenes without obstacles");
+    return SIM_E_STATE;
+  }
+  return SIM_OK;
+}
+
 // ---------------------------------------------------------------- drivers
 // Frame start (Algorithm 4): predicted state, pin targets, collision detection with
 // compaction, Delassus operator and warm start.  No host synchronisation: every kernel
@@ -704,6 +755,11 @@ int iteration(lgsim* s, bool timed, int it) {
   lg::launch_element(d, s->st);
   lg::launch_gather(d, s->st);
   rec(1);
+  if (d.global_step == SIM_GLOBAL_JACOBI) {  // no obstacles (checked by the callers)
+    lg::launch_jacobi_global(d, s->st);
+    for (int p = 2; p <= 5; ++p) rec(p);
+    return check_launch("iteration");
+  }
   lg::launch_spmv_S(d, s->st, d.b, d.y);
   rec(2);
   if (s->iter_c != 0) {
@@ -874,7 +930,8 @@ int create_common(int32_t count, const sim_mesh* meshes, const sim_material* mat
       s->opt.max_contacts <= 0 || s->opt.max_iters <= 0 || !(s->opt.ncp_tol > 0.0) ||
       s->opt.warm < 0 || s->opt.warm > 2 || !(s->opt.contact_margin >= 0.0) ||
       (s->opt.ncp != SIM_NCP_FB && s->opt.ncp != SIM_NCP_MINMAP) ||
-      (s->opt.precond != SIM_PRECOND_DELASSUS && s->opt.precond != SIM_PRECOND_MASS)) {
+      (s->opt.precond != SIM_PRECOND_DELASSUS && s->opt.precond != SIM_PRECOND_MASS) ||
+      (s->opt.global_step != SIM_GLOBAL_DIRECT && s->opt.global_step != SIM_GLOBAL_JACOBI)) {
     lg::set_error("bad options");
     return fail(SIM_E_ARG);
   }
@@ -937,6 +994,7 @@ int sim_options_default(sim_options* o) {
   o->graph = 1;
   o->ncp = SIM_NCP_FB;
   o->precond = SIM_PRECOND_DELASSUS;
+  o->global_step = SIM_GLOBAL_DIRECT;
   o->warm = SIM_WARM_PREV;
   o->ncp_tol = 1e-6;
   o->max_iters = 200;
@@ -1334,6 +1392,7 @@ int sim_step(sim_t s, int32_t frames, int32_t iters, sim_stats* stats) {
     lg::set_error("learned warm start selected but no model set (sim_set_warm_model)");
     return SIM_E_STATE;
   }
+  TRY(check_global_step(s));
   for (int f = 0; f < frames; ++f) {
     const bool timed = stats != nullptr;
     auto t0 = std::chrono::steady_clock::now();
@@ -1519,7 +1578,7 @@ int sim_restore_state(sim_t s) {
 // ---------------------------------------------------------------- parity hooks
 int sim_set_iterate_state(sim_t s, const double* q_t, const double* v_t, const double* q_k, double t, int32_t c,
                           const sim_contact* contacts) {
-  if (!s || !q_t || !v_t || !q_k || c < 0 || (c > 0 && !contacts) || !std::isfinite(t)) {
+  if (!s || !q_t || !v_t || c < 0 || (c > 0 && !contacts) || !std::isfinite(t)) {
     lg::set_error("bad arguments");
     return SIM_E_ARG;
   }
@@ -1538,7 +1597,11 @@ int sim_set_iterate_state(sim_t s, const double* q_t, const double* v_t, const d
   lg::launch_predict(d, s->st);
   lg::launch_pins(d, s->st);
   TRY(check_launch("predict"));
-  TRY(upload_nodes(s, q_k, d.q));
+  if (q_k) {
+    TRY(upload_nodes(s, q_k, d.q));
+  } else {  // q^0 = q~ (Alg. 4)
+    HIPCHK(hipMemcpyAsync(d.q, d.qp, 3 * (size_t)d.N4 * sizeof(float), hipMemcpyDeviceToDevice, s->st));
+  }
   // contact list into internal order (internal node, obstacle)
   std::vector<int> order(c);
   std::iota(order.begin(), order.end(), 0);
@@ -1590,11 +1653,35 @@ int sim_set_iterate_state(sim_t s, const double* q_t, const double* v_t, const d
   return SIM_OK;
 }
 
+int sim_lg_energy(sim_t s, double* energy) {
+  if (!s || !energy) {
+    lg::set_error("bad arguments");
+    return SIM_E_ARG;
+  }
+  if (!kJacobiEnabled) {
+    lg::set_error(kJacobiOff);
+    return SIM_E_STATE;
+  }
+  auto& d = s->d;
+  const int nb = lg::lg_energy_blocks(d);
+  if (!s->energy_part) TRY(s->alloc(s->energy_part, nb));
+  lg::launch_lg_energy(d, s->st, s->energy_part);
+  TRY(check_launch("objective"));
+  std::vector<double> part(nb);
+  HIPCHK(hipMemcpyAsync(part.data(), s->energy_part, nb * sizeof(double), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  double e = 0.0;
+  for (double p : part) e += p;
+  *energy = e;
+  return SIM_OK;
+}
+
 int sim_run_iterations(sim_t s, int32_t k) {
   if (!s || k < 0) {
     lg::set_error("bad arguments");
     return SIM_E_ARG;
   }
+  TRY(check_global_step(s));
   for (int i = 0; i < k; ++i) TRY(iteration(s, false, i));
   TRY(check_launch("iterations"));
   HIPCHK(hipStreamSynchronize(s->st));

@@ -49,6 +49,7 @@ struct Dev {
   int cr_iters;
   int warm;
   int ncp, precond;                // SIM_NCP_*, SIM_PRECOND_*
+  int global_step;                 // SIM_GLOBAL_*
   // nodes
   float *qt, *vt, *qp, *q, *b, *y, *tgt, *pin_w, *tmp;
   int *node_scene;
@@ -121,6 +122,8 @@ struct Dev {
   double *ell;                     // [NS] mean rest edge length per scene
   float *c_feat;                   // [CMAX][16] features of the frame's contacts
   float *inv_mass;                 // [N] 1 / lumped mass (mass-inverse preconditioner)
+  int *a_ptr, *a_idx;              // A_n in internal order (CSR) for the Jacobi global step
+  float *a_val, *a_dinv;           // its values and 1 / diagonal
   float *mlp_P;                    // [kMlpParams] network parameters (float32 master copy)
   // frame state
   double *t;                       // [1] simulation time at frame start
@@ -150,6 +153,9 @@ void launch_mlp_warm(const Dev& d, hipStream_t st);
 void launch_mlp_targets(const Dev& d, float* out, hipStream_t st);
 hipError_t launch_cr(const Dev& d, hipStream_t st, int cr_blocks, int variant);  // variant: SIM_CR_*
 void launch_apply_forces(const Dev& d, hipStream_t st);
+void launch_jacobi_global(const Dev& d, hipStream_t st);
+int lg_energy_blocks(const Dev& d);
+void launch_lg_energy(const Dev& d, hipStream_t st, double* part);
 void launch_force_ranges(const Dev& d, hipStream_t st);
 void launch_residual(const Dev& d, hipStream_t st);
 void launch_integrate(const Dev& d, hipStream_t st);

@@ -348,6 +348,71 @@ void launch_element(const Dev& d, hipStream_t st) {
   hipLaunchKernelGGL(k_element, dim3((d.M + bs - 1) / bs), dim3(bs), 0, st, d);
 }
 
+// ---------------------------------------------------------------- L-G objective
+// The objective the local-global iteration minimises at the current iterate q, at its
+// optimal local variables (Eq. PD local and PD global):
+//   1/2 (q - q~)^T M (q - q~) + h^2 sum_t [w_t/2 |F_t - p_t|^2 + V_t psi(p_t)]
+//   + 1/2 sum_pins h^2 w_pin |q_v - target|^2,
+// with p_t the prox of F_t (same singular vectors, so |F_t - p_t|^2 = |sigma - s*|^2;
+// ARAP: psi is the indicator of SO(3), zero at s* = 1).  Blocks [0, nbt) sum tets,
+// the rest nodes; each block writes one float64 partial (fixed-order tree sum).
+__global__ void __launch_bounds__(kBlock) k_lg_energy(Dev d, int nbt, double* part) {
+  __shared__ double red[kBlock];
+  double e = 0.0;
+  if ((int)blockIdx.x < nbt) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t < d.M) {
+      float D[3][3], F[3][3], e3[3][3];
+      int vi[4];
+      for (int a = 0; a < 4; ++a) vi[a] = d.tidx[a * d.M + t];
+      for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) D[a][c] = d.dinv[(3 * a + c) * d.M + t];
+      for (int c = 0; c < 3; ++c) {
+        const float x0 = d.q[c * d.N4 + vi[0]];
+        for (int a = 0; a < 3; ++a) e3[a][c] = d.q[c * d.N4 + vi[a + 1]] - x0;
+      }
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) F[i][j] = e3[0][i] * D[0][j] + e3[1][i] * D[1][j] + e3[2][i] * D[2][j];
+      float U[3][3], V[3][3], sig[3], s[3];
+      svd3(F, U, sig, V);
+      const int model = d.tmodel[t];
+      prox3(model, sig, d.tmu[t], d.tlam[t], d.tk[t], s);
+      const double hw = d.hw[t];
+      double dist = 0.0;
+      for (int i = 0; i < 3; ++i) dist += (double)(sig[i] - s[i]) * (double)(sig[i] - s[i]);
+      e = 0.5 * hw * dist;
+      if (model != 0) e += hw / (double)d.tk[t] * (double)psi(model, s, d.tmu[t], d.tlam[t]);
+    }
+  } else {
+    const int v = (blockIdx.x - nbt) * kBlock + threadIdx.x;
+    if (v < d.N) {
+      const double m = 1.0 / (double)d.inv_mass[v], w = d.pin_w[v];
+      for (int c = 0; c < 3; ++c) {
+        const double dq = (double)d.q[c * d.N4 + v] - (double)d.qp[c * d.N4 + v];
+        e += 0.5 * m * dq * dq;
+        if (w > 0.0) {
+          const double r = (double)d.q[c * d.N4 + v] - (double)d.tgt[c * d.N4 + v];
+          e += 0.5 * w * r * r;
+        }
+      }
+    }
+  }
+  red[threadIdx.x] = e;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+int lg_energy_blocks(const Dev& d) { return (d.M + kBlock - 1) / kBlock + (d.N + kBlock - 1) / kBlock; }
+
+void launch_lg_energy(const Dev& d, hipStream_t st, double* part) {
+  const int nbt = (d.M + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_lg_energy, dim3(lg_energy_blocks(d)), dim3(kBlock), 0, st, d, nbt, part);
+}
+
 // ---------------------------------------------------------------- node gather
 // b'_v = sum of the corner forces of v + h^2 w_pin (target - q~_v).  Eight lanes per
 // node: lane l adds slots l, l+8, ... in order, then the eight partial sums are combined

@@ -217,4 +217,38 @@ void launch_apply_forces(const Dev& d, hipStream_t st) {
   hipLaunchKernelGGL(k_apply_forces, dim3((d.N + waves_per_block - 1) / waves_per_block), dim3(kBlock), 0, st, d);
 }
 
+// Incomplete global step (the baseline of Sec. 7's convergence comparison): one Jacobi
+// sweep q <- q + D^-1 (b - A q) from the current iterate.  In the delta form used here
+// (b' = b - A q~, dq = q - q~) it reads u = q~ + dq + D^-1 (b' - A dq).  One thread per
+// node computes u into tmp; a second kernel copies it to q, so every thread reads the
+// old iterate.
+__global__ void k_jacobi_global(Dev d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.N) return;
+  const int p0 = d.a_ptr[i], p1 = d.a_ptr[i + 1];
+  for (int c = 0; c < 3; ++c) {
+    const float* q = d.q + c * d.N4;
+    const float* qp = d.qp + c * d.N4;
+    float adq = 0.0f;
+    for (int p = p0; p < p1; ++p) {
+      const int j = d.a_idx[p];
+      adq += d.a_val[p] * (q[j] - qp[j]);
+    }
+    const float dq = q[i] - qp[i];
+    d.tmp[c * d.N4 + i] = qp[i] + (dq + (d.b[c * d.N4 + i] - adq) * d.a_dinv[i]);
+  }
+}
+
+__global__ void k_copy_iterate(Dev d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.N) return;
+  for (int c = 0; c < 3; ++c) d.q[c * d.N4 + i] = d.tmp[c * d.N4 + i];
+}
+
+void launch_jacobi_global(const Dev& d, hipStream_t st) {
+  const dim3 grid((d.N + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_jacobi_global, grid, dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_copy_iterate, grid, dim3(kBlock), 0, st, d);
+}
+
 }  // namespace lg

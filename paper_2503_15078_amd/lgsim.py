@@ -21,6 +21,7 @@ SIM_WARM_ZERO, SIM_WARM_PREV, SIM_WARM_MLP = 0, 1, 2
 SIM_CR_TEXTBOOK, SIM_CR_PIPELINED = 0, 1
 SIM_NCP_FB, SIM_NCP_MINMAP = 0, 1
 SIM_PRECOND_DELASSUS, SIM_PRECOND_MASS = 0, 1
+SIM_GLOBAL_DIRECT, SIM_GLOBAL_JACOBI = 0, 1
 ERRORS = {-1: "SIM_E_ARG", -2: "SIM_E_MESH", -3: "SIM_E_NOT_SPD", -4: "SIM_E_NOMEM",
           -5: "SIM_E_DEVICE", -6: "SIM_E_STATE", -7: "SIM_E_DIVERGED", -8: "SIM_E_CAPACITY"}
 
@@ -50,7 +51,8 @@ class sim_options(C.Structure):
                 ("contact_margin", C.c_double), ("cr_iters", C.c_int32), ("warm", C.c_int32),
                 ("ncp_tol", C.c_double), ("max_iters", C.c_int32), ("max_contacts", C.c_int32),
                 ("hip_stream", C.c_void_p), ("cr_tol", C.c_double), ("cr_variant", C.c_int32),
-                ("graph", C.c_int32), ("ncp", C.c_int32), ("precond", C.c_int32)]
+                ("graph", C.c_int32), ("ncp", C.c_int32), ("precond", C.c_int32),
+                ("global_step", C.c_int32)]
 
 
 class sim_tuning(C.Structure):
@@ -128,6 +130,7 @@ def load():
         "sim_run_iterations": [C.c_void_p, i32],
         "sim_read_iterate": [C.c_void_p, P(d), P(d)],
         "sim_global_solve": [C.c_void_p, P(d), P(d)],
+        "sim_lg_energy": [C.c_void_p, P(d)],
         "sim_debug_rhs": [C.c_void_p, P(d)],
         "sim_debug_delassus": [C.c_void_p, P(d)],
         "lg_host_create": [P(sim_mesh), P(sim_material), d, d, i32, P(C.c_void_p)],
@@ -391,9 +394,9 @@ class Sim:
             buf[j].obstacle = int(obst[j])
             for q in range(3):
                 buf[j].lambda_[q] = float(lam[j][q])
+        qk = None if q_k is None else _dp(np.ascontiguousarray(q_k, np.float64))  # None: q^0 = q~
         _check(_lib.sim_set_iterate_state(self.h, _dp(np.ascontiguousarray(q_t, np.float64)),
-                                          _dp(np.ascontiguousarray(v_t, np.float64)),
-                                          _dp(np.ascontiguousarray(q_k, np.float64)), float(t), c, buf))
+                                          _dp(np.ascontiguousarray(v_t, np.float64)), qk, float(t), c, buf))
 
     def run_iterations(self, k=1):
         _check(_lib.sim_run_iterations(self.h, k))
@@ -403,6 +406,12 @@ class Sim:
         lam = np.zeros((max(c, 1), 3))
         _check(_lib.sim_read_iterate(self.h, _dp(q), _dp(lam)))
         return q, lam[:c]
+
+    def lg_energy(self):
+        """The L-G objective at the current iterate (sim_lg_energy)."""
+        e = C.c_double(0.0)
+        _check(_lib.sim_lg_energy(self.h, C.byref(e)))
+        return e.value
 
     def global_solve(self, b):
         b = np.ascontiguousarray(b, np.float64)

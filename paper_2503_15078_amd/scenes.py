@@ -221,9 +221,10 @@ def free_block(seed: int = 0, model: int = MODEL_SNH, nodes: int = 4, edge: floa
 def twist_bar(seed: int = 0, model: int = MODEL_SNH, E: float = 1e6, nu: float = 0.4,
               mu: float = 0.2, nodes=(40, 10, 10), voxel: float = 0.01, frames: int = 400,
               iters: int = 10, cr_iters: int = 10, h: float = 0.01, turns: float = 1.0,
-              press: float = 0.2) -> Scene:
+              press: float = 0.2, ground: bool = True) -> Scene:
     """40x10x10-node bar; end caps rotate +-turns*360 deg over ``frames`` while pressed
-    ``press`` x height into the plane z=0 (5 tets per voxel)."""
+    ``press`` x height into the plane z=0 (5 tets per voxel); ground=False drops the plane
+    (the twisting test of the global-step comparison has no contact)."""
     rng = np.random.default_rng(seed)
     nvx, nvy, nvz = nodes[0] - 1, nodes[1] - 1, nodes[2] - 1
     rest, tets = voxel_mesh(np.ones((nvx, nvy, nvz), bool), voxel, split=5)
@@ -242,9 +243,9 @@ def twist_bar(seed: int = 0, model: int = MODEL_SNH, E: float = 1e6, nu: float =
     lin = np.array([[0.0, 0.0, vz], [0.0, 0.0, vz]])
     ang = np.array([[-w, 0.0, 0.0], [w, 0.0, 0.0]])
     piv = np.array([[xmin, 0.0, cz], [xmax, 0.0, cz]])
-    ground = Obstacle.make(OBST_HALFSPACE, [0, 0, 0, 0, 0, 1], mu)
+    ground_plane = Obstacle.make(OBST_HALFSPACE, [0, 0, 0, 0, 0, 1], mu)
     return Scene("twist_bar", rest, tets, model, E, nu, 1000.0, h, np.array([0.0, 0.0, -9.81]),
-                 [ground], 0.25 * voxel, iters, cr_iters, frames, init_pos=init,
+                 [ground_plane] if ground else [], 0.25 * voxel, iters, cr_iters, frames, init_pos=init,
                  pin_nodes=pins, pin_group=group, pin_lin_vel=lin, pin_ang_vel=ang, pin_pivot=piv)
 
 
