@@ -183,10 +183,11 @@ int sim_create(const sim_mesh* mesh, const sim_material* mat, double h, const si
  * |r| <= cr_tol |r_0| when cr_tol > 0, in the form cr_variant (SIM_CR_*). */
 int sim_set_solver(sim_t s, int32_t cr_iters, double cr_tol, int32_t cr_variant);
 
-/* Measurement: average duration (ms) of `reps` back-to-back launches of one global-step
- * pass on the handle's stream between a single pair of HIP events, on the current
- * buffers (which = 0: y = S b, which = 1: u = q~ + S^T y; the result goes to a scratch
- * buffer, the state is unchanged). */
+/* Measurement: average duration (ms) of `reps` back-to-back launches of one kernel pass
+ * on the handle's stream between a single pair of HIP events, on the current buffers
+ * (which = 0: y = S b, which = 1: u = q~ + S^T y, the result going to a scratch buffer;
+ * which = 2: the local step at the current iterate, rewriting its per-tet corner forces
+ * with the same values).  The state is unchanged. */
 int sim_time_kernel(sim_t s, int32_t which, int32_t reps, float* ms_avg);
 
 /* Frames with a fixed iteration count are recorded once into a hipGraph (frame setup,

@@ -1074,7 +1074,7 @@ int sim_set_solver(sim_t s, int32_t cr_iters, double cr_tol, int32_t cr_variant)
 }
 
 int sim_time_kernel(sim_t s, int32_t which, int32_t reps, float* ms_avg) {
-  if (!s || (which != 0 && which != 1) || reps <= 0 || !ms_avg) {
+  if (!s || which < 0 || which > 2 || reps <= 0 || !ms_avg) {
     lg::set_error("bad arguments");
     return SIM_E_ARG;
   }
@@ -1084,7 +1084,8 @@ int sim_time_kernel(sim_t s, int32_t which, int32_t reps, float* ms_avg) {
   HIPCHK(hipEventCreate(&e1));
   auto launch = [&]() {
     if (which == 0) lg::launch_spmv_S(d, s->st, d.b, d.tmp);  // reads b, writes scratch
-    else lg::launch_spmv_St(d, s->st, d.y, d.qp, d.tmp);      // reads y and q~, writes scratch
+    else if (which == 1) lg::launch_spmv_St(d, s->st, d.y, d.qp, d.tmp);  // reads y and q~, writes scratch
+    else lg::launch_element(d, s->st);  // corner forces of the current iterate (same values)
   };
   launch();
   HIPCHK(hipEventRecord(e0, s->st));

@@ -329,7 +329,8 @@ class Sim:
         _check(_lib.sim_set_graph(self.h, int(bool(on))))
 
     def time_kernel(self, which, reps=50):
-        """Average ms of `reps` back-to-back launches of the S (0) or S^T (1) pass."""
+        """Average ms of `reps` back-to-back launches of the S pass (0), the S^T pass (1) or
+        the local step (2) on the current buffers (sim_time_kernel)."""
         ms = C.c_float(0.0)
         _check(_lib.sim_time_kernel(self.h, int(which), int(reps), C.byref(ms)))
         return float(ms.value)

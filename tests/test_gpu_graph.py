@@ -93,3 +93,28 @@ def test_bad_tuning_is_rejected():
             sim.set_tuning(**kw)
         assert e.value.code == -1
     sim.close()
+
+
+def test_time_kernel_leaves_the_state_unchanged():
+    """Back-to-back timing launches of the S pass, the S^T pass and the local step between
+    two iterations change nothing: the next iterate is bit-identical to an untimed run."""
+    sc = scenes.cube_drop(0)
+    runs = []
+    for timed in (False, True):
+        sim = lgsim.Sim(sc)
+        sim.step(14)
+        q_t, v_t, con = sim.read_state()
+        sim.set_iterate_state(q_t, v_t, None, 14 * sc.h, con["node"], con["obst"], con["lam"])
+        sim.run_iterations(1)
+        if timed:
+            for which in (0, 1, 2):
+                assert sim.time_kernel(which, 5) > 0.0
+        sim.run_iterations(1)
+        runs.append(sim.read_iterate(len(con["node"])))
+        sim.close()
+    np.testing.assert_array_equal(runs[0][0], runs[1][0])
+    np.testing.assert_array_equal(runs[0][1], runs[1][1])
+    sim = lgsim.Sim(sc)
+    with pytest.raises(lgsim.SimError):
+        sim.time_kernel(3, 1)
+    sim.close()
