@@ -293,6 +293,19 @@ class Sim:
             _check(lib.sim_set_pin_motion(h, len(lin), _dp(lin), _dp(ang), _dp(piv)))
         del groups
 
+    def set_obstacles(self, obstacles):
+        """Replace the obstacle set (single-scene handles), e.g. to move obstacles between
+        frames."""
+        obs = (sim_obstacle * max(1, len(obstacles)))()
+        for k, ob in enumerate(obstacles):
+            obs[k].type = ob.type
+            for q in range(10):
+                obs[k].geom[q] = float(ob.geom[q])
+            obs[k].mu = ob.mu
+            for q in range(3):
+                obs[k].vel[q] = float(ob.vel[q])
+        _check(_lib.sim_set_obstacles(self.h, len(obstacles), obs))
+
     def step(self, frames=1, iters=None, stats=True):
         iters = self.scenes[0].iters if iters is None else iters
         st = (sim_stats * frames)() if stats else None

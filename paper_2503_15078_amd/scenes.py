@@ -14,7 +14,7 @@ Mesh recipes
   voxelised and extruded (the teaser-scale "gingerbread" stand-in);
 * a 40x10x10-node bar (twist/compression sweep);
 * seeded voxel blobs (unions of spheres) sized to a target node count;
-* a small cube (drop and incline tests).
+* a small cube (drop, incline and conveyor tests; moving planes).
 
 Obstacle encoding (``Obstacle.type``):
   0 half-space  geom = [px,py,pz, nx,ny,nz]           solid where n.(x-p) < 0
@@ -199,6 +199,26 @@ def incline_block(mu: float, theta_deg: float = 10.0, nodes: int = 4, edge: floa
     vel[:, 0] = slide_speed
     return Scene("incline", rest, tets, model, E, nu, 1000.0, h, g, [ground], 0.25 * voxel,
                  iters, cr_iters, frames, init_pos=rest.copy(), init_vel=vel)
+
+
+def conveyor_block(mu: float = 0.8, belt=(0.2, 0.0, 0.0), nodes: int = 3, edge: float = 0.1, E: float = 1e5,
+                   nu: float = 0.3, model: int = MODEL_COROT, h: float = 0.01, frames: int = 40,
+                   iters: int = 10, cr_iters: int = 24) -> Scene:
+    """Block at rest on the plane z=0 whose surface moves with velocity ``belt`` (a
+    conveyor: the obstacle velocity enters the friction rows).  Static friction carries
+    the block up to belt speed when mu g is large enough."""
+    nv = nodes - 1
+    voxel = edge / nv
+    rest, tets = voxel_mesh(np.ones((nv, nv, nv), bool), voxel, split=5)
+    ground = Obstacle.make(OBST_HALFSPACE, [0, 0, 0, 0, 0, 1], mu, vel=belt)
+    return Scene("conveyor", rest, tets, model, E, nu, 1000.0, h, np.array([0.0, 0.0, -9.81]), [ground],
+                 0.25 * voxel, iters, cr_iters, frames, init_pos=rest.copy())
+
+
+def moving_plane(z: float, mu: float = 0.5, vel=(0.0, 0.0, 0.0)) -> Obstacle:
+    """The half-space below z (normal +z), moving with ``vel`` (geometry updated by the
+    caller every frame)."""
+    return Obstacle.make(OBST_HALFSPACE, [0, 0, z, 0, 0, 1], mu, vel=vel)
 
 
 def free_block(seed: int = 0, model: int = MODEL_SNH, nodes: int = 4, edge: float = 0.1,
