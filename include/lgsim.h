@@ -137,6 +137,11 @@ enum { SIM_GLOBAL_DIRECT = 0, SIM_GLOBAL_JACOBI = 1 };
  *   HALFSPACE [px,py,pz, nx,ny,nz]        solid where n.(x-p) < 0
  *   BOX       [cx,cy,cz, hx,hy,hz]        axis-aligned box, half extents
  *   CYLINDER  [ax,ay,az, bx,by,bz, r]     capped cylinder
+ *   BINDING   [px,py,pz, cx,cy,cz, e, v]  bilateral row at node v (caller order, within
+ *                                         its scene): c.x_v = c.p^ with compliance e >= 0
+ *                                         (Sec. 3.2 binding contact, App. A bilateral items:
+ *                                         phi_b = delta_b + e lambda_b; e = 0 hard), active
+ *                                         at every frame, no friction (mu, vel ignored)
  * mu is the Coulomb coefficient; vel is the obstacle velocity u^ entering d_f. */
 typedef struct {
   int32_t type;

@@ -30,7 +30,7 @@ import math
 
 import numpy as np
 
-HALFSPACE, BOX, CYLINDER = 0, 1, 2
+HALFSPACE, BOX, CYLINDER, BINDING = 0, 1, 2, 3
 INV_SQRT2 = 1.0 / math.sqrt(2.0)
 
 
@@ -112,6 +112,26 @@ def tangent_basis(n):
     return f1, f2
 
 
+def binding_frame(geom, x_t):
+    """A bilateral (binding) constraint (Sec. 3.2, binding contact; App. A, bilateral items):
+    geom = [p^ (3), direction c (3), compliance e, node].  Its row is n = c / |c| with the
+    Gram-Schmidt tangents, d_b = n . p^, and its gap n . x_t - d_b; it is active at every
+    frame for its node."""
+    c = np.asarray(geom[3:6], np.float64)
+    nrm = tuple(float(v) for v in c / math.sqrt(float(c @ c)))
+    f1, f2 = tangent_basis(nrm)
+    d_n = float(np.dot(nrm, np.asarray(geom[0:3], np.float64)))
+    return nrm, f1, f2, d_n, float(np.dot(nrm, x_t)) - d_n
+
+
+def binding_terms(delta_n, lam, comp):
+    """Bilateral rows: phi_b = delta_b + e lambda_b with omega_b = 1, E_b = e (e = 0: hard;
+    e > 0: a quadratic potential of stiffness 1/e), and the tangent rows inactive
+    (omega = 0, E = 1, driving lambda_f to 0)."""
+    phi_n = delta_n + comp * lam[:, 0]
+    return phi_n, np.ones_like(delta_n), comp.copy()
+
+
 def detect(q_t, q_pred, obstacles, margin):
     """Contact list in canonical (node, obstacle) order.
 
@@ -121,6 +141,18 @@ def detect(q_t, q_pred, obstacles, margin):
     nodes, obs, frames, dn, gaps, mus, vels = [], [], [], [], [], [], []
     for v in range(len(q_t)):
         for o, ob in enumerate(obstacles):
+            if ob.type == BINDING:
+                if v != int(ob.geom[7]):
+                    continue
+                nrm, f1, f2, d_n, gap = binding_frame(ob.geom, q_t[v])
+                nodes.append(v)
+                obs.append(o)
+                frames.append([nrm, f1, f2])
+                dn.append(d_n)
+                gaps.append(gap)
+                mus.append(0.0)
+                vels.append(np.zeros(3))
+                continue
             d_t, nrm = sdf_normal(ob.type, ob.geom, q_t[v])
             d_p, _ = sdf_normal(ob.type, ob.geom, q_pred[v])
             if min(d_t, d_p) < margin:
@@ -209,7 +241,7 @@ def friction_terms_minmap(vdot_f, lam_n, lam_f, r_f, mu):
     return omega, Ef, phi
 
 
-def ncp_residual(delta_n, vdot_f, lam, r_n, r_f, mu, h):
+def ncp_residual(delta_n, vdot_f, lam, r_n, r_f, mu, h, comp=None):
     """Max-norm NCP residual in metres (reading of the Signorini-Coulomb conditions).
 
     Per contact: |FB(delta_n, r_n lam_n)|; if lam_n > 0: h |FB(s, r_f gamma)| and,
@@ -230,4 +262,7 @@ def ncp_residual(delta_n, vdot_f, lam, r_n, r_f, mu, h):
     e_dir = np.where(lf > 0, h * np.sqrt((dirv ** 2).sum(1)), 0.0)
     e_off = h * r_f * lf
     res = np.maximum(res, np.where(act, np.maximum(t_act, e_dir), e_off))
+    if comp is not None:  # bilateral rows: |delta_b + e lambda_b| and the inactive tangents
+        b = comp >= 0.0
+        res = np.where(b, np.maximum(np.abs(delta_n + comp * lam_n), e_off), res)
     return float(res.max())

@@ -57,6 +57,7 @@ class FrameContacts:
     r_n: np.ndarray
     r_f: np.ndarray
     gap: np.ndarray
+    comp: np.ndarray = None  # compliance e of bilateral rows, -1 for unilateral contacts
 
     @property
     def c(self):
@@ -169,8 +170,14 @@ class OracleSim:
         d_f = np.zeros((c, 2))
         mu = np.zeros(c)
         gap = np.zeros(c)
+        comp = np.full(c, -1.0)
         for j in range(c):
             ob = self.obstacles[obst[j]]
+            if ob.type == ct.BINDING:
+                nrm, f1, f2, d_n[j], gap[j] = ct.binding_frame(ob.geom, q_t[node[j]])
+                C[j] = [nrm, f1, f2]
+                comp[j] = float(ob.geom[6])
+                continue
             d, nrm = ct.sdf_normal(ob.type, ob.geom, q_t[node[j]])
             f1, f2 = ct.tangent_basis(nrm)
             C[j] = [nrm, f1, f2]
@@ -188,7 +195,7 @@ class OracleSim:
         else:
             r_n = self.h * self.h * Wd[0::3] if c else np.zeros(0)
             r_f = self.h * 0.5 * (Wd[1::3] + Wd[2::3]) if c else np.zeros(0)
-        return FrameContacts(node, obst, C, d_n, d_f, mu, K, W, r_n, r_f, gap)
+        return FrameContacts(node, obst, C, d_n, d_f, mu, K, W, r_n, r_f, gap, comp)
 
     def delassus(self, node, C):
         """K = B^T A_n^-1 B by multi-RHS solves; W_(j,k) = K_jk C_j C_k^T (A = A_n (x) I3)."""
@@ -232,6 +239,13 @@ class OracleSim:
         else:
             phi_n, om_n, E_n = ct.normal_terms(delta_n, lam[:, 0], fc.r_n)
             om_f, E_f, phi_f = ct.friction_terms(vdot_f, lam[:, 0], lam[:, 1:], fc.r_f, fc.mu)
+        if fc.comp is not None and np.any(fc.comp >= 0.0):
+            b = fc.comp >= 0.0
+            pb, ob_, eb = ct.binding_terms(delta_n[b], lam[b], fc.comp[b])
+            phi_n, om_n, E_n = phi_n.copy(), om_n.copy(), E_n.copy()
+            phi_n[b], om_n[b], E_n[b] = pb, ob_, eb
+            om_f, E_f, phi_f = om_f.copy(), E_f.copy(), phi_f.copy()
+            om_f[b], E_f[b], phi_f[b] = 0.0, 1.0, lam[b, 1:]
         Hq = np.einsum("jai,ji->ja", fc.C, x)                       # (c,3)
         hv = np.empty((fc.c, 3))
         hv[:, 0] = -phi_n + om_n * Hq[:, 0]
@@ -292,7 +306,7 @@ class OracleSim:
         f = fc.C[:, 1:, :]
         delta_n = np.einsum("ji,ji->j", n, x) - fc.d_n
         vdot_f = (np.einsum("jai,ji->ja", f, x - q_t[fc.node]) - self.h * fc.d_f) / self.h
-        return ct.ncp_residual(delta_n, vdot_f, lam, fc.r_n, fc.r_f, fc.mu, self.h)
+        return ct.ncp_residual(delta_n, vdot_f, lam, fc.r_n, fc.r_f, fc.mu, self.h, fc.comp)
 
     # ---------------------------------------------------------------- frames
     def begin_frame(self):

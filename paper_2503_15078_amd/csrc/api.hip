@@ -246,6 +246,8 @@ int build_segments(lgsim* s, int seg_floats, int row_group) {
   return SIM_OK;
 }
 
+int obstacle_dev(lgsim* s, int k, const sim_obstacle& o, lg::ObstacleDev& od);
+
 // Build one handle from host precomputations of several scenes (concatenated).
 int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vector<sim_obstacle>>& obs) {
   auto& d = s->d;
@@ -464,6 +466,7 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   TRY(s->alloc(d.scene_margin, NS));
   TRY(s->alloc(d.ell, NS));
   TRY(s->alloc(d.c_feat, 16 * (size_t)d.CMAX));
+  TRY(s->alloc(d.c_comp, d.CMAX));
   TRY(s->alloc(d.mlp_P, lg::kMlpParams));
   TRY(s->alloc(s->d_tgt, 3 * (size_t)d.CMAX));
   TRY(s->alloc(d.obst, (size_t)lg::kMaxObstacles * NS));
@@ -631,11 +634,7 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
     if (k < (int)obs.size())
       for (auto& o : obs[k]) {
         lg::ObstacleDev od{};
-        od.type = o.type;
-        od.scene = k;
-        std::memcpy(od.geom, o.geom, sizeof(od.geom));
-        od.mu = o.mu;
-        std::memcpy(od.vel, o.vel, sizeof(od.vel));
+        TRY(obstacle_dev(s, k, o, od));
         s->obst.push_back(od);
       }
   }
@@ -664,6 +663,27 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   return SIM_OK;
 }
 
+// Device form of an obstacle of scene k; a binding's node (caller order, scene-local) is
+// replaced by its internal index, and it carries no friction or surface velocity.
+int obstacle_dev(lgsim* s, int k, const sim_obstacle& o, lg::ObstacleDev& od) {
+  od.type = o.type;
+  od.scene = k;
+  std::memcpy(od.geom, o.geom, sizeof(od.geom));
+  od.mu = o.mu;
+  std::memcpy(od.vel, o.vel, sizeof(od.vel));
+  if (o.type == 3) {
+    const int node = (int)o.geom[7];
+    if (node < 0 || node >= s->scenes[k].n) {
+      lg::set_error("binding node out of range");
+      return SIM_E_ARG;
+    }
+    od.geom[7] = (double)s->perm_caller[s->scenes[k].caller0 + node];
+    od.mu = 0.0;
+    od.vel[0] = od.vel[1] = od.vel[2] = 0.0;
+  }
+  return SIM_OK;
+}
+
 int validate_obstacles(int32_t n, const sim_obstacle* obs) {
   if (n < 0 || n > lg::kMaxObstacles || (n > 0 && !obs)) {
     lg::set_error("bad obstacle count");
@@ -671,7 +691,7 @@ int validate_obstacles(int32_t n, const sim_obstacle* obs) {
   }
   for (int i = 0; i < n; ++i) {
     const auto& o = obs[i];
-    if (o.type < 0 || o.type > 2 || !(o.mu >= 0.0)) {
+    if (o.type < 0 || o.type > 3 || !(o.mu >= 0.0)) {
       lg::set_error("bad obstacle " + std::to_string(i));
       return SIM_E_ARG;
     }
@@ -682,6 +702,11 @@ int validate_obstacles(int32_t n, const sim_obstacle* obs) {
       }
     if (o.type == 0 && o.geom[3] * o.geom[3] + o.geom[4] * o.geom[4] + o.geom[5] * o.geom[5] == 0.0) {
       lg::set_error("half-space with zero normal");
+      return SIM_E_ARG;
+    }
+    if (o.type == 3 && (o.geom[3] * o.geom[3] + o.geom[4] * o.geom[4] + o.geom[5] * o.geom[5] == 0.0 ||
+                        !(o.geom[6] >= 0.0) || !(o.geom[7] >= 0.0) || o.geom[7] != std::floor(o.geom[7]))) {
+      lg::set_error("binding needs a non-zero direction, a compliance >= 0 and a node index");
       return SIM_E_ARG;
     }
     if (o.type == 2 && (!(o.geom[6] > 0.0) || (o.geom[0] == o.geom[3] && o.geom[1] == o.geom[4] && o.geom[2] == o.geom[5]))) {
@@ -1045,16 +1070,13 @@ int sim_set_obstacles(sim_t s, int32_t n, const sim_obstacle* obs) {
     return SIM_E_STATE;
   }
   TRY(validate_obstacles(n, obs));
-  s->obst.clear();
+  std::vector<lg::ObstacleDev> next;
   for (int i = 0; i < n; ++i) {
     lg::ObstacleDev od{};
-    od.type = obs[i].type;
-    od.scene = 0;
-    std::memcpy(od.geom, obs[i].geom, sizeof(od.geom));
-    od.mu = obs[i].mu;
-    std::memcpy(od.vel, obs[i].vel, sizeof(od.vel));
-    s->obst.push_back(od);
+    TRY(obstacle_dev(s, 0, obs[i], od));
+    next.push_back(od);
   }
+  s->obst = next;
   s->scene_obst0 = {0, n};
   return push_obstacles(s);
 }

@@ -121,6 +121,7 @@ struct Dev {
   // learned warm start
   double *ell;                     // [NS] mean rest edge length per scene
   float *c_feat;                   // [CMAX][16] features of the frame's contacts
+  float *c_comp;                   // [CMAX] compliance e of bilateral (binding) rows, -1: unilateral
   float *inv_mass;                 // [N] 1 / lumped mass (mass-inverse preconditioner)
   int *a_ptr, *a_idx;              // A_n in internal order (CSR) for the Jacobi global step
   float *a_val, *a_dinv;           // its values and 1 / diagonal

@@ -111,9 +111,11 @@ __device__ double sdf64(const ObstacleDev& ob, const double x[3], double nrm[3])
   return da;
 }
 
-// contact predicate: min(sdf(q_t), sdf(q~)) < margin with q~ = (q_t + h v_t) + (h h) g in float64
+// contact predicate: min(sdf(q_t), sdf(q~)) < margin with q~ = (q_t + h v_t) + (h h) g in float64;
+// a binding (type 3) is active for its own node (internal index in geom[7]) at every frame
 __device__ bool in_contact(const Dev& d, const ObstacleDev& ob, int v, double margin) {
 #pragma clang fp contract(off)
+  if (ob.type == 3) return v == (int)ob.geom[7];
   double xt[3], xp[3], nrm[3];
   double hh = d.h * d.h;
   for (int c = 0; c < 3; ++c) {
@@ -126,13 +128,29 @@ __device__ bool in_contact(const Dev& d, const ObstacleDev& ob, int v, double ma
 }
 
 // frame rows (n, f1, f2) at q_t, d_n = n . (x_t - sdf n), d_f = f . u^, gap = sdf(x_t)
+// (binding, Sec. 3.2 and App. A bilateral items: n = c / |c|, d_b = n . p^, gap n . x_t - d_b,
+// no friction, compliance e in c_comp)
 __device__ void write_contact_frame(const Dev& d, int j, int v, const ObstacleDev& ob) {
 #pragma clang fp contract(off)
   double xt[3], n[3], f1[3], f2[3];
   for (int c = 0; c < 3; ++c) xt[c] = (double)d.qt[c * d.N4 + v];
-  double dist = sdf64(ob, xt, n);
+  double dist;
+  double ph[3];
+  if (ob.type == 3) {
+    const double* g = ob.geom;
+    const double cn = sqrt(g[3] * g[3] + g[4] * g[4] + g[5] * g[5]);
+    for (int c = 0; c < 3; ++c) {
+      n[c] = g[3 + c] / cn;
+      ph[c] = g[c];
+    }
+    dist = (n[0] * xt[0] + n[1] * xt[1] + n[2] * xt[2]) - (n[0] * ph[0] + n[1] * ph[1] + n[2] * ph[2]);
+    d.c_comp[j] = (float)g[6];
+  } else {
+    dist = sdf64(ob, xt, n);
+    for (int c = 0; c < 3; ++c) ph[c] = xt[c] - dist * n[c];
+    d.c_comp[j] = -1.0f;
+  }
   tangents64(n, f1, f2);
-  double ph[3] = {xt[0] - dist * n[0], xt[1] - dist * n[1], xt[2] - dist * n[2]};
   const double* rows[3] = {n, f1, f2};
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c) {
@@ -144,7 +162,7 @@ __device__ void write_contact_frame(const Dev& d, int j, int v, const ObstacleDe
   d.c_dn64[j] = dn;
   d.c_df[j] = (float)(f1[0] * ob.vel[0] + f1[1] * ob.vel[1] + f1[2] * ob.vel[2]);
   d.c_df[d.CMAX + j] = (float)(f2[0] * ob.vel[0] + f2[1] * ob.vel[1] + f2[2] * ob.vel[2]);
-  d.c_mu[j] = (float)ob.mu;
+  d.c_mu[j] = ob.type == 3 ? 0.0f : (float)ob.mu;
   d.c_gap[j] = dist;
 }
 
@@ -612,6 +630,16 @@ __global__ void __launch_bounds__(kBlock) k_contact_prep(Dev d) {
   float vf[2] = {hvf[0] / h, hvf[1] / h};
   FBTerms f = d.ncp == 1 ? minmap_terms(dn, vf, l, d.c_rn[j], d.c_rf[j], d.c_mu[j])
                          : fb_terms(dn, vf, l, d.c_rn[j], d.c_rf[j], d.c_mu[j]);
+  const float comp = d.c_comp[j];
+  if (comp >= 0.0f) {  // bilateral row: phi_b = delta_b + e lambda_b; tangent rows inactive
+    f.phi_n = dn + comp * l[0];
+    f.om_n = 1.0f;
+    f.E_n = comp;
+    f.om_f = 0.0f;
+    f.E_f = 1.0f;
+    f.phi_f[0] = l[1];
+    f.phi_f[1] = l[2];
+  }
   float om[3] = {f.om_n, f.om_f, f.om_f};
   d.Om[j] = om[0];
   d.Om[CM + j] = om[1];
@@ -665,7 +693,10 @@ __global__ void k_residual(Dev d) {
   float res = fabsf(dn + a - sqrtf(dn * dn + a * a));
   float s = sqrtf(vf[0] * vf[0] + vf[1] * vf[1]);
   float lf = sqrtf(l[1] * l[1] + l[2] * l[2]);
-  if (l[0] > 0.0f) {
+  const float comp = d.c_comp[j];
+  if (comp >= 0.0f) {  // bilateral row and its inactive tangent rows
+    res = fmaxf(fabsf(dn + comp * l[0]), h * rf * lf);
+  } else if (l[0] > 0.0f) {
     float b = rf * (mu * l[0] - lf);
     res = fmaxf(res, h * fabsf(s + b - sqrtf(s * s + b * b)));
     if (lf > 0.0f) {

@@ -20,6 +20,8 @@ Obstacle encoding (``Obstacle.type``):
   0 half-space  geom = [px,py,pz, nx,ny,nz]           solid where n.(x-p) < 0
   1 box         geom = [cx,cy,cz, hx,hy,hz]           axis-aligned solid box
   2 cylinder    geom = [ax,ay,az, bx,by,bz, radius]   capped cylinder, axis a->b
+  3 binding     geom = [px,py,pz, cx,cy,cz, e, node]  bilateral row c . x_node = c . p
+                                                      with compliance e (0: hard)
 """
 from __future__ import annotations
 
@@ -30,7 +32,7 @@ from typing import List, Optional
 import numpy as np
 
 MODEL_ARAP, MODEL_COROT, MODEL_SNH, MODEL_MR = 0, 1, 2, 3
-OBST_HALFSPACE, OBST_BOX, OBST_CYLINDER = 0, 1, 2
+OBST_HALFSPACE, OBST_BOX, OBST_CYLINDER, OBST_BINDING = 0, 1, 2, 3
 
 
 @dataclasses.dataclass
@@ -219,6 +221,26 @@ def moving_plane(z: float, mu: float = 0.5, vel=(0.0, 0.0, 0.0)) -> Obstacle:
     """The half-space below z (normal +z), moving with ``vel`` (geometry updated by the
     caller every frame)."""
     return Obstacle.make(OBST_HALFSPACE, [0, 0, z, 0, 0, 1], mu, vel=vel)
+
+
+def hanging_block(e_z: float = 0.0, nodes: int = 3, edge: float = 0.1, E: float = 1e5, nu: float = 0.3,
+                  model: int = MODEL_COROT, h: float = 0.01, frames: int = 40, iters: int = 10,
+                  cr_iters: int = 24, swing: float = 0.0) -> Scene:
+    """Block hanging from its top corner by bilateral (binding) rows: along x and y hard,
+    along z with compliance e_z (0: a hard point anchor, > 0: a vertical spring of
+    stiffness 1/e_z).  swing: initial sideways speed of every node (m/s)."""
+    nv = nodes - 1
+    voxel = edge / nv
+    rest, tets = voxel_mesh(np.ones((nv, nv, nv), bool), voxel, split=5)
+    top = int(np.argmax(rest @ np.array([1.0, 1.0, 1.0])))
+    p = rest[top]
+    binds = [Obstacle.make(OBST_BINDING, [p[0], p[1], p[2], 1, 0, 0, 0.0, top], 0.0),
+             Obstacle.make(OBST_BINDING, [p[0], p[1], p[2], 0, 1, 0, 0.0, top], 0.0),
+             Obstacle.make(OBST_BINDING, [p[0], p[1], p[2], 0, 0, 1, e_z, top], 0.0)]
+    vel = np.zeros_like(rest)
+    vel[:, 1] = swing
+    return Scene("hanging", rest, tets, model, E, nu, 1000.0, h, np.array([0.0, 0.0, -9.81]), binds,
+                 0.25 * voxel, iters, cr_iters, frames, init_pos=rest.copy(), init_vel=vel)
 
 
 def free_block(seed: int = 0, model: int = MODEL_SNH, nodes: int = 4, edge: float = 0.1,
