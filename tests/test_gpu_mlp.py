@@ -211,3 +211,19 @@ def test_learned_warm_start_gain_on_held_out_drops():
             sim.close()
     print(f"iterations over 3 held-out drops x 60 frames: {total}")
     assert total["learned"] < total["plain"]
+
+
+def test_learned_start_keeps_previous_impulse_of_bindings():
+    """Binding rows keep the previous-frame impulse under the learned warm start (their
+    impulse has no sign or cone to project onto): the trajectory of a block hanging from
+    bindings is the same with any network."""
+    sc = scenes.hanging_block(e_z=1e-4, swing=0.3)
+    runs = []
+    for mode in (lgsim.SIM_WARM_PREV, lgsim.SIM_WARM_MLP):
+        sim = lgsim.Sim(sc)
+        sim.set_warm_model(_params(5, noise=0.5))
+        sim.set_warm_mode(mode)
+        sim.step(10)
+        runs.append(sim.read_state())
+        sim.close()
+    np.testing.assert_array_equal(runs[0][0], runs[1][0])
