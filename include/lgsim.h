@@ -47,7 +47,7 @@ enum {
 };
 
 enum { SIM_ARAP = 0, SIM_COROT = 1, SIM_STABLE_NH = 2, SIM_MOONEY_RIVLIN = 3 };
-enum { SIM_OBST_HALFSPACE = 0, SIM_OBST_BOX = 1, SIM_OBST_CYLINDER = 2 };
+enum { SIM_OBST_HALFSPACE = 0, SIM_OBST_BOX = 1, SIM_OBST_CYLINDER = 2, SIM_OBST_BINDING = 3 };
 enum { SIM_WARM_ZERO = 0, SIM_WARM_PREV = 1, SIM_WARM_MLP = 2 };
 
 typedef struct lgsim* sim_t; /* opaque, library-owned */
