@@ -107,7 +107,9 @@ __device__ void svd3(const float F[3][3], float U[3][3], float s[3], float V[3][
       S[i][j] = F[0][i] * F[0][j] + F[1][i] * F[1][j] + F[2][i] * F[2][j];
       V[i][j] = (i == j) ? 1.0f : 0.0f;
     }
-  for (int sweep = 0; sweep < 6; ++sweep) {
+  // four cyclic sweeps: on float32 3x3 matrices the eigenvalues are then within float32
+  // rounding (~3e-7 relative) of an exact SVD, as with more sweeps
+  for (int sweep = 0; sweep < 4; ++sweep) {
     jacobi_rot(S, V, 0, 1);
     jacobi_rot(S, V, 0, 2);
     jacobi_rot(S, V, 1, 2);
