@@ -84,7 +84,8 @@ typedef struct {
  * sim_step with iters == 0.  max_contacts: contact capacity (device buffers).
  * hip_stream: a hipStream_t to enqueue on (null: the library creates its own).
  * ncp / precond: NCP function and complementarity preconditioner of the contact rows
- * (SIM_NCP_*, SIM_PRECOND_*; the defaults are the method's).  global_step: SIM_GLOBAL_*. */
+ * (SIM_NCP_*, SIM_PRECOND_*; the defaults are the method's).  global_step: SIM_GLOBAL_*.
+ * lg_form: SIM_LG_*. */
 typedef struct {
   double gravity[3];
   double pin_weight_scale; /* h^2 w_pin = 1e3 * scale * [A_n]_vv                */
@@ -101,6 +102,7 @@ typedef struct {
   int32_t ncp;             /* SIM_NCP_FB (default) or SIM_NCP_MINMAP */
   int32_t precond;         /* SIM_PRECOND_DELASSUS (default) or SIM_PRECOND_MASS */
   int32_t global_step;     /* SIM_GLOBAL_DIRECT (default) or SIM_GLOBAL_JACOBI */
+  int32_t lg_form;         /* SIM_LG_PD (default) or SIM_LG_ADMM */
 } sim_options;
 
 /* Forms of the Conjugate Residual iteration; both give the same iterates in exact
@@ -132,6 +134,15 @@ enum { SIM_PRECOND_DELASSUS = 0, SIM_PRECOND_MASS = 1 };
  * sim_lg_energy): a device run that included it ended in a GPU fault whose cause has not
  * been established. */
 enum { SIM_GLOBAL_DIRECT = 0, SIM_GLOBAL_JACOBI = 1 };
+/* Local-global form: projective dynamics (the local step projects F_t = G_t q), or
+ * ADMM-PD, the paper's other implementation (local step of the cited ADMM-PD method):
+ * per-tet dual variables u_t, zero at every frame start; the local step takes
+ * p_t = prox(F_t + u_t), updates u_t += F_t - p_t, and the global step uses p_t - u_t.
+ * ADMM-PD's converged iterate is stationary for the hyperelastic incremental potential
+ * itself; PD's minimises its quadratic-penalty relaxation.  ARAP takes its energy
+ * mu |F - R|^2 (prox s* = (sigma + 1) / 2) in the ADMM form instead of the SO(3)
+ * indicator of the PD form. */
+enum { SIM_LG_PD = 0, SIM_LG_ADMM = 1 };
 
 /* Obstacles (App. A: analytic contact partners).  geom by type:
  *   HALFSPACE [px,py,pz, nx,ny,nz]        solid where n.(x-p) < 0
@@ -192,7 +203,8 @@ int sim_set_solver(sim_t s, int32_t cr_iters, double cr_tol, int32_t cr_variant)
  * on the handle's stream between a single pair of HIP events, on the current buffers
  * (which = 0: y = S b, which = 1: u = q~ + S^T y, the result going to a scratch buffer;
  * which = 2: the local step at the current iterate, rewriting its per-tet corner forces
- * with the same values).  The state is unchanged. */
+ * with the same values; SIM_E_STATE for ADMM-PD handles, whose local step updates the
+ * duals).  The state is unchanged. */
 int sim_time_kernel(sim_t s, int32_t which, int32_t reps, float* ms_avg);
 
 /* Frames with a fixed iteration count are recorded once into a hipGraph (frame setup,

@@ -15,6 +15,8 @@ Paper: Algorithm 4 (unified GPU-friendly pipeline), with
   ablation of Sec. 7 (stick-sliding test) uses the mass inverse instead,
   r_n = h^2 / m_v, r_f = h / m_v (precond="mass");
 * App. B: Fischer-Burmeister rows (default) or minimum-map rows (ncp="minmap");
+* ADMM-PD local step (lg_form="admm"; the paper's implementations are PD and ADMM-PD):
+  dual variables per tet, reset at every frame start;
 * Sec. 7 (performance and accuracy evaluation): the incomplete global step of the
   comparison, one Jacobi sweep from the current iterate (global_step="jacobi",
   contact-free frames), and the objective the iteration minimises (lg_energy);
@@ -66,11 +68,15 @@ class FrameContacts:
 
 class OracleSim:
     def __init__(self, scene, cr_iters=None, pin_weight_scale=None, margin=None, ncp="fb", precond="delassus",
-                 global_step="direct"):
+                 global_step="direct", lg_form="pd"):
         if ncp not in ("fb", "minmap") or precond not in ("delassus", "mass"):
             raise OracleError("ncp must be 'fb' or 'minmap', precond 'delassus' or 'mass'")
         if global_step not in ("direct", "jacobi"):
             raise OracleError("global_step must be 'direct' or 'jacobi'")
+        if lg_form not in ("pd", "admm"):
+            raise OracleError("lg_form must be 'pd' or 'admm'")
+        self.lg_form = lg_form
+        self.dual = None  # ADMM-PD dual variables per tet (m,3,3), zero at every frame start
         self.ncp, self.precond, self.global_step = ncp, precond, global_step
         self.scene = scene
         self.h = float(scene.h)
@@ -130,6 +136,25 @@ class OracleSim:
         F = fem.deformation_gradient(q, self.tets, self.D)
         return mat.local_step(self.model, F, self.mu, self.lam, self.k)
 
+    def potential(self, q, q_pred, t_next):
+        """The backward-Euler incremental potential of the hyperelastic energy itself:
+            1/2 (q - q~)^T M (q - q~) + h^2 sum_t V_t psi(F_t) + 1/2 sum_pins h^2 w_pin |q_v - target|^2
+        (psi on the signed singular values; ARAP: w_t / (2 V_t) |F - R(F)|^2).  ADMM-PD's
+        converged iterate is stationary for it; PD's minimises a relaxation of it."""
+        h = self.h
+        dq = q - q_pred
+        e = 0.5 * float((self.mass[:, None] * dq * dq).sum())
+        F = fem.deformation_gradient(q, self.tets, self.D)
+        _, sig, _ = mat.svd_rv(F)
+        psi = mat.energy(self.model, sig, self.mu, self.lam)
+        arap = self.model == mat.ARAP
+        psi = np.where(arap, 0.5 * self.k * ((sig - 1.0) ** 2).sum(1), psi)
+        e += h * h * float((self.V * psi).sum())
+        if len(self.pin_nodes):
+            r = q[self.pin_nodes] - self.pin_target(t_next)
+            e += 0.5 * float((self.pin_h2w[:, None] * r * r).sum())
+        return e
+
     def lg_energy(self, q, q_pred, t_next):
         """The objective that the local-global iteration minimises, at its optimal local
         variables (Eq. PD local and PD global):
@@ -152,8 +177,26 @@ class OracleSim:
         return e
 
     def rhs(self, q, q_pred, t_next):
-        """b = M q~ + h^2 sum w G^T p (+ pin terms) at positions q."""
-        P = self.local_step(q)
+        """b = M q~ + h^2 sum w G^T p (+ pin terms) at positions q.
+
+        ADMM-PD (lg_form="admm", the local step of the cited ADMM-PD method): with duals
+        u_t, p_t = prox(F_t + u_t), then u_t += F_t - p_t, and the global step takes
+        p_t - u_t in place of p_t."""
+        if self.lg_form == "admm":
+            F = fem.deformation_gradient(q, self.tets, self.D)
+            if self.dual is None:
+                self.dual = np.zeros_like(F)
+            U, sig, Vt = mat.svd_rv(F + self.dual)
+            s = mat.prox_singular(self.model, sig, self.mu, self.lam, self.k)
+            # ARAP in ADMM form: the energy mu |F - R|^2 (PD weight w = 2 mu V) instead of
+            # the SO(3) indicator, whose prox is s* = (sigma + 1) / 2
+            arap = self.model == mat.ARAP
+            s[arap] = 0.5 * (sig[arap] + 1.0)
+            Pz = np.einsum("tij,tj,tjk->tik", U, s, Vt)
+            self.dual = self.dual + F - Pz
+            P = Pz - self.dual
+        else:
+            P = self.local_step(q)
         b = self.mass[:, None] * q_pred + self.h * self.h * fem.elastic_rhs(self.n, self.tets, self.D, self.w, P)
         if len(self.pin_nodes):
             np.add.at(b, self.pin_nodes, self.pin_h2w[:, None] * self.pin_target(t_next))
@@ -310,6 +353,7 @@ class OracleSim:
 
     # ---------------------------------------------------------------- frames
     def begin_frame(self):
+        self.dual = None
         q_t = self.q
         q_pred = self.predict()
         node, obst = self.detect(q_t, q_pred)

@@ -287,6 +287,7 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   d.ncp = s->opt.ncp;
   d.precond = s->opt.precond;
   d.global_step = s->opt.global_step;
+  d.lg_form = s->opt.lg_form;
   d.elem_block = lg::kBlock;
   s->perm_caller.resize(N);
   s->iperm_caller.resize(N);
@@ -450,6 +451,7 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   TRY(s->alloc(d.tk, M));
   TRY(s->alloc(d.tmodel, M));
   TRY(s->alloc(d.fc, 12 * (size_t)M));
+  TRY(s->alloc(d.dual, s->opt.lg_form == SIM_LG_ADMM ? 9 * (size_t)M : 1));
   TRY(s->alloc(d.row_ptr, N + 1));
   TRY(s->alloc(d.row_lo4, N));
   TRY(s->alloc(d.row_val, (size_t)row_ptr[N]));
@@ -745,6 +747,7 @@ int frame_setup(lgsim* s) {
   auto& d = s->d;
   lg::launch_predict(d, s->st);
   lg::launch_pins(d, s->st);
+  lg::launch_zero_dual(d, s->st);
   lg::launch_collide(d, s->st);
   lg::launch_delassus(d, s->st);
   lg::launch_warm_start(d, s->st, 0);
@@ -956,7 +959,8 @@ int create_common(int32_t count, const sim_mesh* meshes, const sim_material* mat
       s->opt.warm < 0 || s->opt.warm > 2 || !(s->opt.contact_margin >= 0.0) ||
       (s->opt.ncp != SIM_NCP_FB && s->opt.ncp != SIM_NCP_MINMAP) ||
       (s->opt.precond != SIM_PRECOND_DELASSUS && s->opt.precond != SIM_PRECOND_MASS) ||
-      (s->opt.global_step != SIM_GLOBAL_DIRECT && s->opt.global_step != SIM_GLOBAL_JACOBI)) {
+      (s->opt.global_step != SIM_GLOBAL_DIRECT && s->opt.global_step != SIM_GLOBAL_JACOBI) ||
+      (s->opt.lg_form != SIM_LG_PD && s->opt.lg_form != SIM_LG_ADMM)) {
     lg::set_error("bad options");
     return fail(SIM_E_ARG);
   }
@@ -1020,6 +1024,7 @@ int sim_options_default(sim_options* o) {
   o->ncp = SIM_NCP_FB;
   o->precond = SIM_PRECOND_DELASSUS;
   o->global_step = SIM_GLOBAL_DIRECT;
+  o->lg_form = SIM_LG_PD;
   o->warm = SIM_WARM_PREV;
   o->ncp_tol = 1e-6;
   o->max_iters = 200;
@@ -1099,6 +1104,10 @@ int sim_time_kernel(sim_t s, int32_t which, int32_t reps, float* ms_avg) {
   if (!s || which < 0 || which > 2 || reps <= 0 || !ms_avg) {
     lg::set_error("bad arguments");
     return SIM_E_ARG;
+  }
+  if (which == 2 && s->opt.lg_form == SIM_LG_ADMM) {
+    lg::set_error("the ADMM-PD local step updates its dual variables: not timed in isolation");
+    return SIM_E_STATE;
   }
   auto& d = s->d;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1619,6 +1628,7 @@ int sim_set_iterate_state(sim_t s, const double* q_t, const double* v_t, const d
   TRY(upload(s, d.t, &t, 1));
   lg::launch_predict(d, s->st);
   lg::launch_pins(d, s->st);
+  lg::launch_zero_dual(d, s->st);
   TRY(check_launch("predict"));
   if (q_k) {
     TRY(upload_nodes(s, q_k, d.q));

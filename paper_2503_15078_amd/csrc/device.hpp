@@ -50,6 +50,7 @@ struct Dev {
   int warm;
   int ncp, precond;                // SIM_NCP_*, SIM_PRECOND_*
   int global_step;                 // SIM_GLOBAL_*
+  int lg_form;                     // SIM_LG_* (1: ADMM-PD duals in the local step)
   // nodes
   float *qt, *vt, *qp, *q, *b, *y, *tgt, *pin_w, *tmp;
   int *node_scene;
@@ -65,6 +66,7 @@ struct Dev {
   float *hw, *tmu, *tlam, *tk;     // h^2 w, mu, lambda, k
   unsigned char *tmodel;
   float *fc;                       // [12][M] corner forces
+  float *dual;                     // [9][M] ADMM-PD dual variables (row-major 3x3 per tet)
   // S storage
   int64_t *row_ptr;
   int *row_lo4;
@@ -140,6 +142,7 @@ void launch_frames_for_list(const Dev& d, hipStream_t st);
 void launch_delassus(const Dev& d, hipStream_t st);
 void launch_warm_start(const Dev& d, hipStream_t st, int keep_lambda);
 void launch_element(const Dev& d, hipStream_t st);
+void launch_zero_dual(const Dev& d, hipStream_t st);
 void launch_gather(const Dev& d, hipStream_t st);
 void launch_spmv_S(const Dev& d, hipStream_t st, const float* b, float* y);
 void launch_spmv_St(const Dev& d, hipStream_t st, const float* y, const float* base, float* u);

@@ -324,15 +324,33 @@ __global__ void __launch_bounds__(kBlock) k_element(Dev d) {
       F[i][j] = e[0][i] * D[0][j] + e[1][i] * D[1][j] + e[2][i] * D[2][j];
       Fp[i][j] = ep[0][i] * D[0][j] + ep[1][i] * D[1][j] + ep[2][i] * D[2][j];
     }
+  // ADMM-PD: project F + u (u the tet's dual), then u += F - p and the global step takes
+  // p - u; PD projects F itself
+  const bool admm = d.lg_form == 1;
+  float Fz[3][3], du[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      du[i][j] = admm ? d.dual[(3 * i + j) * d.M + t] : 0.0f;
+      Fz[i][j] = F[i][j] + du[i][j];
+    }
   float U[3][3], V[3][3], sig[3], s[3];
-  svd3(F, U, sig, V);
+  svd3(Fz, U, sig, V);
   int model = d.tmodel[t];
-  prox3(model, sig, d.tmu[t], d.tlam[t], d.tk[t], s);
+  if (admm && model == 0) {  // ARAP's energy mu |F - R|^2 (weight w = 2 mu V): s* = (sigma + 1) / 2
+    for (int i = 0; i < 3; ++i) s[i] = 0.5f * (sig[i] + 1.0f);
+  } else {
+    prox3(model, sig, d.tmu[t], d.tlam[t], d.tk[t], s);
+  }
   float hw = d.hw[t];
   float P[3][3];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
       float pij = U[i][0] * s[0] * V[j][0] + U[i][1] * s[1] * V[j][1] + U[i][2] * s[2] * V[j][2];
+      if (admm) {
+        const float un = du[i][j] + F[i][j] - pij;
+        d.dual[(3 * i + j) * d.M + t] = un;
+        pij -= un;
+      }
       P[i][j] = hw * (pij - Fp[i][j]);
     }
   float f0[3] = {0.0f, 0.0f, 0.0f};
@@ -343,6 +361,18 @@ __global__ void __launch_bounds__(kBlock) k_element(Dev d) {
       f0[c] -= fa;
     }
   for (int c = 0; c < 3; ++c) d.fc[c * d.M + t] = f0[c];
+}
+
+__global__ void k_zero_dual(Dev d) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= d.M) return;
+  for (int q = 0; q < 9; ++q) d.dual[q * d.M + t] = 0.0f;
+}
+
+// ADMM-PD duals start every frame at zero (a kernel, so that captured frames clear them)
+void launch_zero_dual(const Dev& d, hipStream_t st) {
+  if (d.lg_form != 1) return;
+  hipLaunchKernelGGL(k_zero_dual, dim3((d.M + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d);
 }
 
 void launch_element(const Dev& d, hipStream_t st) {

@@ -22,6 +22,7 @@ SIM_CR_TEXTBOOK, SIM_CR_PIPELINED = 0, 1
 SIM_NCP_FB, SIM_NCP_MINMAP = 0, 1
 SIM_PRECOND_DELASSUS, SIM_PRECOND_MASS = 0, 1
 SIM_GLOBAL_DIRECT, SIM_GLOBAL_JACOBI = 0, 1
+SIM_LG_PD, SIM_LG_ADMM = 0, 1
 ERRORS = {-1: "SIM_E_ARG", -2: "SIM_E_MESH", -3: "SIM_E_NOT_SPD", -4: "SIM_E_NOMEM",
           -5: "SIM_E_DEVICE", -6: "SIM_E_STATE", -7: "SIM_E_DIVERGED", -8: "SIM_E_CAPACITY"}
 
@@ -52,7 +53,7 @@ class sim_options(C.Structure):
                 ("ncp_tol", C.c_double), ("max_iters", C.c_int32), ("max_contacts", C.c_int32),
                 ("hip_stream", C.c_void_p), ("cr_tol", C.c_double), ("cr_variant", C.c_int32),
                 ("graph", C.c_int32), ("ncp", C.c_int32), ("precond", C.c_int32),
-                ("global_step", C.c_int32)]
+                ("global_step", C.c_int32), ("lg_form", C.c_int32)]
 
 
 class sim_tuning(C.Structure):
