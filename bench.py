@@ -128,12 +128,13 @@ def phase_pass(sim, frames):
 
 def warm_compare(sim, params):
     """Frame to NCP residual <= 1e-6 m from the benchmark state with the previous-frame
-    warm start (none exists at this state: zero) and with the learned one."""
+    warm start (none exists at this state: zero), the learned one on every contact and the
+    learned one on persisting contacts only (every contact is new at this state: zero)."""
     import torch
-    from paper_2503_15078_amd import lgsim
+    from paper_2503_15078_amd import lgsim, warm
     sim.set_warm_model(params)
     out = {}
-    for mode, name in ((lgsim.SIM_WARM_PREV, "plain"), (lgsim.SIM_WARM_MLP, "learned")):
+    for mode, name in warm.MODES:
         sim.set_warm_mode(mode)
         sim.restore_state()
         torch.cuda.synchronize()
@@ -150,7 +151,7 @@ def warm_drops(params, seeds=(1001, 1002, 1003), frames=60):
     """Held-out cube drops (5^3-node cubes), every frame to NCP residual <= 1e-6 m."""
     import numpy as np
     from paper_2503_15078_amd import scenes, warm
-    agg = {"plain": [[], []], "learned": [[], []]}
+    agg = {name: [[], []] for _, name in warm.MODES}
     for s in seeds:
         res = warm.compare(scenes.cube_drop(s), params, frames, cr_iters=TOL_CR_ITERS, cr_tol=TOL_CR,
                            max_iters=TOL_MAX_ITERS)

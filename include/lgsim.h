@@ -48,7 +48,7 @@ enum {
 
 enum { SIM_ARAP = 0, SIM_COROT = 1, SIM_STABLE_NH = 2, SIM_MOONEY_RIVLIN = 3 };
 enum { SIM_OBST_HALFSPACE = 0, SIM_OBST_BOX = 1, SIM_OBST_CYLINDER = 2, SIM_OBST_BINDING = 3 };
-enum { SIM_WARM_ZERO = 0, SIM_WARM_PREV = 1, SIM_WARM_MLP = 2 };
+enum { SIM_WARM_ZERO = 0, SIM_WARM_PREV = 1, SIM_WARM_MLP = 2, SIM_WARM_MLP_PERSIST = 3 };
 
 typedef struct lgsim* sim_t; /* opaque, library-owned */
 
@@ -334,6 +334,9 @@ int sim_debug_delassus(sim_t s, double* K);
  *   f11 mu, f12..15 0
  * and its output y gives lambda = y l / (h^2 K_jj), projected onto the friction cone;
  * a contact whose prediction is not finite keeps the previous-frame impulse.
+ * SIM_WARM_MLP predicts every contact; SIM_WARM_MLP_PERSIST only contacts with a
+ * non-zero previous-frame impulse (new or released contacts start at zero, as with
+ * the previous-frame start).
  * Parameters: float32, SIM_MLP_N_PARAMS values in the order W1 [128][16], b1 [128],
  * W2 [128][128], b2 [128], W3 [16][128] (rows 3..15 unused), b3 [16]; the device uses
  * bf16 copies of the weights and bf16 activations with float32 accumulation. */

@@ -751,8 +751,9 @@ int frame_setup(lgsim* s) {
   lg::launch_collide(d, s->st);
   lg::launch_delassus(d, s->st);
   lg::launch_warm_start(d, s->st, 0);
-  if (s->record_pairs || (s->opt.warm == SIM_WARM_MLP && s->has_model)) lg::launch_mlp_features(d, s->st);
-  if (s->opt.warm == SIM_WARM_MLP && s->has_model) lg::launch_mlp_warm(d, s->st);
+  const bool learned = (s->opt.warm == SIM_WARM_MLP || s->opt.warm == SIM_WARM_MLP_PERSIST) && s->has_model;
+  if (s->record_pairs || learned) lg::launch_mlp_features(d, s->st);
+  if (learned) lg::launch_mlp_warm(d, s->st);
   lg::launch_force_ranges(d, s->st);
   s->iter_c = -1;  // known after the next synchronisation
   return check_launch("frame setup");
@@ -956,7 +957,7 @@ int create_common(int32_t count, const sim_mesh* meshes, const sim_material* mat
   if (s->opt.cr_iters < 0 || s->opt.cr_iters > lg::kMaxCrIters || !(s->opt.cr_tol >= 0.0) ||
       (s->opt.cr_variant != SIM_CR_TEXTBOOK && s->opt.cr_variant != SIM_CR_PIPELINED) ||
       s->opt.max_contacts <= 0 || s->opt.max_iters <= 0 || !(s->opt.ncp_tol > 0.0) ||
-      s->opt.warm < 0 || s->opt.warm > 2 || !(s->opt.contact_margin >= 0.0) ||
+      s->opt.warm < 0 || s->opt.warm > SIM_WARM_MLP_PERSIST || !(s->opt.contact_margin >= 0.0) ||
       (s->opt.ncp != SIM_NCP_FB && s->opt.ncp != SIM_NCP_MINMAP) ||
       (s->opt.precond != SIM_PRECOND_DELASSUS && s->opt.precond != SIM_PRECOND_MASS) ||
       (s->opt.global_step != SIM_GLOBAL_DIRECT && s->opt.global_step != SIM_GLOBAL_JACOBI) ||
@@ -1291,7 +1292,7 @@ int sim_set_warm_model(sim_t s, const float* params, int32_t n_params) {
 }
 
 int sim_set_warm_mode(sim_t s, int32_t warm) {
-  if (!s || warm < SIM_WARM_ZERO || warm > SIM_WARM_MLP) {
+  if (!s || warm < SIM_WARM_ZERO || warm > SIM_WARM_MLP_PERSIST) {
     lg::set_error("bad warm start mode");
     return SIM_E_ARG;
   }
@@ -1315,7 +1316,7 @@ int sim_read_training_pairs(sim_t s, int32_t* node, int32_t* obstacle, float* fe
     lg::set_error("bad arguments");
     return SIM_E_ARG;
   }
-  if (!s->record_pairs && !(s->opt.warm == SIM_WARM_MLP && s->has_model)) {
+  if (!s->record_pairs && !((s->opt.warm == SIM_WARM_MLP || s->opt.warm == SIM_WARM_MLP_PERSIST) && s->has_model)) {
     lg::set_error("features are not recorded (sim_record_training_pairs)");
     return SIM_E_STATE;
   }
@@ -1420,7 +1421,7 @@ int sim_step(sim_t s, int32_t frames, int32_t iters, sim_stats* stats) {
     lg::set_error("bad arguments");
     return SIM_E_ARG;
   }
-  if (s->opt.warm == SIM_WARM_MLP && !s->has_model) {
+  if ((s->opt.warm == SIM_WARM_MLP || s->opt.warm == SIM_WARM_MLP_PERSIST) && !s->has_model) {
     lg::set_error("learned warm start selected but no model set (sim_set_warm_model)");
     return SIM_E_STATE;
   }

@@ -349,7 +349,8 @@ __global__ void __launch_bounds__(kBlock) k_mlp_warm(Dev d) {
       const float kjj = d.K[d.k_off[sc] + (int64_t)(j - cs) * kstride(cnt) + (j - cs)];
       const float back = (float)(d.ell[sc] / (d.h * d.h * (double)kjj));
       float l[3] = {y[0] * back, y[1] * back, y[2] * back};
-      if (isfinite(l[0]) && isfinite(l[1]) && isfinite(l[2]) && !(d.c_comp[j] >= 0.0f)) {
+      const bool fresh = d.warm == 3 && d.lam[j] == 0.0f && d.lam[CM + j] == 0.0f && d.lam[2 * CM + j] == 0.0f;
+      if (isfinite(l[0]) && isfinite(l[1]) && isfinite(l[2]) && !(d.c_comp[j] >= 0.0f) && !fresh) {
         const float mu = d.c_mu[j];
         l[0] = fmaxf(l[0], 0.0f);
         const float lf = sqrtf(l[1] * l[1] + l[2] * l[2]), cap = mu * l[0];

@@ -17,7 +17,7 @@ LIB_NAME = "liblgsim_hip.so"
 LIB_PATH = os.path.join(_HERE, LIB_NAME)
 
 SIM_OK = 0
-SIM_WARM_ZERO, SIM_WARM_PREV, SIM_WARM_MLP = 0, 1, 2
+SIM_WARM_ZERO, SIM_WARM_PREV, SIM_WARM_MLP, SIM_WARM_MLP_PERSIST = 0, 1, 2, 3
 SIM_CR_TEXTBOOK, SIM_CR_PIPELINED = 0, 1
 SIM_NCP_FB, SIM_NCP_MINMAP = 0, 1
 SIM_PRECOND_DELASSUS, SIM_PRECOND_MASS = 0, 1

@@ -20,6 +20,8 @@ SHAPES = [("W1", (128, 16)), ("b1", (128,)), ("W2", (128, 128)), ("b2", (128,)),
           ("b3", (16,))]
 N_FEAT = 12  # used inputs (16 with padding)
 N_OUT = 3
+MODES = ((lgsim.SIM_WARM_PREV, "plain"), (lgsim.SIM_WARM_MLP, "learned"),
+         (lgsim.SIM_WARM_MLP_PERSIST, "learned_persist"))
 
 
 def split(flat):
@@ -175,11 +177,12 @@ def val_loss(net, Xv, Tv):
 # ------------------------------------------------------------------ evaluation
 def compare(scene, params, frames, cr_iters=300, cr_tol=1e-3, max_iters=100, cr_variant=0):
     """Frames to NCP residual <= 1e-6 m (at most max_iters iterations) from the same start
-    with the previous-frame and the learned warm start: per-frame iterations, ms
-    (device-synchronised) and residual reached."""
+    with the previous-frame warm start ("plain"), the learned one on every contact
+    ("learned") and the learned one on persisting contacts only ("learned_persist"):
+    per-frame iterations, ms (device-synchronised) and residual reached."""
     import torch
     out = {}
-    for mode, name in ((lgsim.SIM_WARM_PREV, "plain"), (lgsim.SIM_WARM_MLP, "learned")):
+    for mode, name in MODES:
         sim = lgsim.Sim(scene, cr_iters=cr_iters, cr_tol=cr_tol, cr_variant=cr_variant, max_iters=max_iters)
         sim.set_warm_model(params)
         sim.set_warm_mode(mode)

@@ -187,30 +187,53 @@ def test_mlp_mode_without_model_is_an_error():
 def test_learned_warm_start_gain_on_held_out_drops():
     """The trained network (trained on other seeds) against the previous-frame warm start
     on held-out cube drops: fewer local-global iterations to NCP residual <= 1e-6 m in
-    total, and the oracle's float64 residual of the GPU's final state confirms the
-    convergence the GPU reports on sampled frames of the learned run."""
+    total, on every contact and on persisting contacts only, and the oracle's float64
+    residual of the GPU's final state confirms the convergence the GPU reports on sampled
+    frames of the learned runs."""
     params = np.load(WEIGHTS)["params"]
-    total = {"plain": 0, "learned": 0}
+    total = {name: 0 for _, name in warm.MODES}
     for seed in (1001, 1002, 1003):
         sc = scenes.cube_drop(seed)
-        for mode, name in ((lgsim.SIM_WARM_PREV, "plain"), (lgsim.SIM_WARM_MLP, "learned")):
+        for mode, name in warm.MODES:
             sim = lgsim.Sim(sc, cr_iters=300, cr_tol=1e-3, max_iters=100)
             sim.set_warm_model(params)
             sim.set_warm_mode(mode)
             o = OracleSim(sc)
-            judged = 0
             for f in range(60):
                 q0, _, _ = sim.read_state()
                 st = sim.step(1, iters=0)[0]
                 total[name] += st["iters"]
-                if name == "learned" and st["contacts"] and st["ncp"] <= 1e-6 and f % 15 == 0:
+                if name != "plain" and st["contacts"] and st["ncp"] <= 1e-6 and f % 15 == 0:
                     q1, _, con = sim.read_state()
                     fc = o.contacts_from_keys(con["node"], con["obst"], q0)
                     assert o.residual(fc, q1, q0, con["lam"]) <= 2e-6
-                    judged += 1
             sim.close()
     print(f"iterations over 3 held-out drops x 60 frames: {total}")
     assert total["learned"] < total["plain"]
+    assert total["learned_persist"] < total["plain"]
+
+
+def test_persisting_mode_leaves_new_contacts_at_the_plain_start():
+    """On persisting contacts only, the network predicts nothing for a contact that has no
+    previous impulse: a frame whose contacts are all new (the teaser's first contact) runs
+    exactly as with the previous-frame warm start, whatever the network; a frame after it,
+    whose contacts persist, does not."""
+    sc = scenes.teaser_scene(0)
+    runs = []
+    for mode in (lgsim.SIM_WARM_PREV, lgsim.SIM_WARM_MLP_PERSIST):
+        sim = lgsim.Sim(sc, cr_iters=100, cr_tol=1e-3, max_iters=20)
+        sim.set_warm_model(_params(7, noise=0.5))
+        sim.set_warm_mode(mode)
+        st0 = sim.step(1, iters=0)[0]
+        first = sim.read_state()
+        st1 = sim.step(1, iters=0)[0]
+        runs.append((st0, first, st1, sim.read_state()))
+        sim.close()
+    assert runs[0][0]["contacts"] > 0
+    assert runs[0][0]["iters"] == runs[1][0]["iters"]
+    np.testing.assert_array_equal(runs[0][1][0], runs[1][1][0])
+    np.testing.assert_array_equal(runs[0][1][2]["lam"], runs[1][1][2]["lam"])
+    assert not np.array_equal(runs[0][3][2]["lam"], runs[1][3][2]["lam"])
 
 
 def test_learned_start_keeps_previous_impulse_of_bindings():
