@@ -89,7 +89,18 @@ struct lgsim {
       lg::set_error("hipMalloc failed (" + std::to_string(bytes) + " bytes)");
       return SIM_E_NOMEM;
     }
-    if (hipMemset(q, 0, bytes) != hipSuccess) {
+    // Zero on the handle's own stream and wait for it: the stream is non-blocking, so a
+    // fill on the null stream would be unordered with the uploads that follow on it and
+    // could land after them.  Never called while the stream is being captured.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (st && (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)) {
+      hipFree(q);
+      lg::set_error("device allocation during stream capture");
+      return SIM_E_STATE;
+    }
+    if ((st ? hipMemsetAsync(q, 0, bytes, st) : hipMemset(q, 0, bytes)) != hipSuccess ||
+        (st ? hipStreamSynchronize(st) : hipDeviceSynchronize()) != hipSuccess) {
+      hipFree(q);
       lg::set_error("hipMemset failed");
       return SIM_E_DEVICE;
     }

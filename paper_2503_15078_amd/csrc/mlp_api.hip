@@ -76,8 +76,11 @@ int mlp_create(const float* params, int32_t n_params, mlp_t* out) {
     lg::set_error("mlp_create: device allocation failed");
     return SIM_E_NOMEM;
   }
+  // the null-stream fills are waited for: training runs on the caller's stream, which may
+  // be non-blocking and so unordered with them
   if (hipMemcpy(m->P, params, np * 4, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemset(m->M, 0, np * 4) != hipSuccess || hipMemset(m->V, 0, np * 4) != hipSuccess) {
+      hipMemset(m->M, 0, np * 4) != hipSuccess || hipMemset(m->V, 0, np * 4) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
     release(m);
     lg::set_error("mlp_create: upload failed");
     return SIM_E_DEVICE;
@@ -91,9 +94,11 @@ int mlp_set_params(mlp_t m, const float* params, int32_t n_params) {
     lg::set_error("bad arguments");
     return SIM_E_ARG;
   }
+  MCHK(hipDeviceSynchronize());  // no training step of the caller's stream still reads them
   MCHK(hipMemcpy(m->P, params, (size_t)n_params * 4, hipMemcpyHostToDevice));
   MCHK(hipMemset(m->M, 0, (size_t)n_params * 4));
   MCHK(hipMemset(m->V, 0, (size_t)n_params * 4));
+  MCHK(hipDeviceSynchronize());
   m->step = 0;
   return SIM_OK;
 }
