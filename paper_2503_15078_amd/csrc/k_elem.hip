@@ -54,12 +54,20 @@ void launch_pins(const Dev& d, hipStream_t st) {
 // Rotation-variant SVD F = U diag(s) V^T with det U = det V = +1: cyclic Jacobi on
 // F^T F for V, columns of B = F V sorted by norm, then a Givens QR of B for U and s
 // (the smallest singular value carries the sign of det F).
+// Reciprocal, reciprocal square root and square root by the hardware's approximations
+// (about 1 ulp) instead of the correctly rounded sequences: the local step is a long
+// dependent chain per tet, and float32 rounding of these steps is far inside the
+// tolerance of the method.
+__device__ inline float rcp1(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline float rsq1(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline float sqrt1(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 __device__ inline void jacobi_rot(float S[3][3], float V[3][3], int p, int q) {
   float apq = S[p][q];
   if (fabsf(apq) <= 1e-30f) return;
-  float theta = (S[q][q] - S[p][p]) / (2.0f * apq);
-  float t = copysignf(1.0f, theta) / (fabsf(theta) + sqrtf(theta * theta + 1.0f));
-  float c = 1.0f / sqrtf(t * t + 1.0f), s = t * c;
+  float theta = (S[q][q] - S[p][p]) * (0.5f * rcp1(apq));
+  float t = copysignf(rcp1(fabsf(theta) + sqrt1(theta * theta + 1.0f)), theta);
+  float c = rsq1(t * t + 1.0f), s = t * c;
   int r = 3 - p - q;
   float srp = S[r][p], srq = S[r][q];
   S[p][p] -= t * apq;
@@ -76,11 +84,12 @@ __device__ inline void jacobi_rot(float S[3][3], float V[3][3], int p, int q) {
 
 __device__ inline void givens_rows(float B[3][3], float U[3][3], int i, int k, int col) {
   float a = B[i][col], b = B[k][col];
-  float r = sqrtf(a * a + b * b);
+  float r2 = a * a + b * b;
   float c = 1.0f, s = 0.0f;
-  if (r > 0.0f) {
-    c = a / r;
-    s = b / r;
+  if (r2 > 1e-35f) {  // a pair below ~3e-18 is left as it is
+    float ir = rsq1(r2);
+    c = a * ir;
+    s = b * ir;
   }
   for (int j = 0; j < 3; ++j) {
     float bi = B[i][j], bk = B[k][j];
@@ -157,7 +166,7 @@ __device__ float psi(int model, const float s[3], float mu, float lam) {
     return mu * (a * a + b * b + c * c) + 0.5f * lam * (J - 1.0f) * (J - 1.0f);
   }
   if (model == 2) {
-    float alpha = 1.0f + 0.75f * mu / lam;
+    float alpha = 1.0f + 0.75f * mu * rcp1(lam);
     return 0.5f * mu * (I1 - 3.0f) + 0.5f * lam * (J - alpha) * (J - alpha) - 0.5f * mu * logf(I1 + 1.0f);
   }
   float q0 = s[0] * s[0], q1 = s[1] * s[1], q2 = s[2] * s[2];
@@ -181,9 +190,9 @@ __device__ void psi_grad_hess(int model, const float s[3], float mu, float lam, 
     return;
   }
   if (model == 2) {
-    float alpha = 1.0f + 0.75f * mu / lam;
+    float alpha = 1.0f + 0.75f * mu * rcp1(lam);
     float I1 = s[0] * s[0] + s[1] * s[1] + s[2] * s[2];
-    float qi = 1.0f / (I1 + 1.0f);
+    float qi = rcp1(I1 + 1.0f);
     for (int i = 0; i < 3; ++i) {
       g[i] = mu * s[i] + lam * (J - alpha) * Ji[i] - mu * qi * s[i];
       for (int j = 0; j < 3; ++j)
@@ -226,21 +235,22 @@ __device__ void psi_grad_hess(int model, const float s[3], float mu, float lam, 
 }
 
 __device__ inline bool chol3_solve(const float K[3][3], float tau, const float rhs[3], float x[3]) {
+  // pivots below 1e-30 count as failures (the caller then shifts the diagonal)
   float a00 = K[0][0] + tau, a11 = K[1][1] + tau, a22 = K[2][2] + tau;
-  if (!(a00 > 0.0f)) return false;
-  float l00 = sqrtf(a00);
-  float l10 = K[1][0] / l00, l20 = K[2][0] / l00;
+  if (!(a00 > 1e-30f)) return false;
+  float i00 = rsq1(a00);
+  float l10 = K[1][0] * i00, l20 = K[2][0] * i00;
   float d1 = a11 - l10 * l10;
-  if (!(d1 > 0.0f)) return false;
-  float l11 = sqrtf(d1);
-  float l21 = (K[2][1] - l20 * l10) / l11;
+  if (!(d1 > 1e-30f)) return false;
+  float i11 = rsq1(d1);
+  float l21 = (K[2][1] - l20 * l10) * i11;
   float d2 = a22 - l20 * l20 - l21 * l21;
-  if (!(d2 > 0.0f)) return false;
-  float l22 = sqrtf(d2);
-  float z0 = rhs[0] / l00, z1 = (rhs[1] - l10 * z0) / l11, z2 = (rhs[2] - l20 * z0 - l21 * z1) / l22;
-  x[2] = z2 / l22;
-  x[1] = (z1 - l21 * x[2]) / l11;
-  x[0] = (z0 - l10 * x[1] - l20 * x[2]) / l00;
+  if (!(d2 > 1e-30f)) return false;
+  float i22 = rsq1(d2);
+  float z0 = rhs[0] * i00, z1 = (rhs[1] - l10 * z0) * i11, z2 = (rhs[2] - l20 * z0 - l21 * z1) * i22;
+  x[2] = z2 * i22;
+  x[1] = (z1 - l21 * x[2]) * i11;
+  x[0] = (z0 - l10 * x[1] - l20 * x[2]) * i00;
   return true;
 }
 
