@@ -167,7 +167,7 @@ __device__ float psi(int model, const float s[3], float mu, float lam) {
   }
   if (model == 2) {
     float alpha = 1.0f + 0.75f * mu * rcp1(lam);
-    return 0.5f * mu * (I1 - 3.0f) + 0.5f * lam * (J - alpha) * (J - alpha) - 0.5f * mu * logf(I1 + 1.0f);
+    return 0.5f * mu * (I1 - 3.0f) + 0.5f * lam * (J - alpha) * (J - alpha) - 0.5f * mu * __logf(I1 + 1.0f);
   }
   float q0 = s[0] * s[0], q1 = s[1] * s[1], q2 = s[2] * s[2];
   float I2 = q0 * q1 + q0 * q2 + q1 * q2;
@@ -265,6 +265,8 @@ __device__ void prox3(int model, const float sig[3], float mu, float lam, float 
     return;
   }
   float scale = fmaxf(1.0f, fmaxf(fabsf(sig[0]), fmaxf(fabsf(sig[1]), fabsf(sig[2]))));
+  float f0 = 0.0f;  // objective at s
+  bool have_f0 = false;
   for (int it = 0; it < 8; ++it) {
     float g[3], H[3][3];
     psi_grad_hess(model, s, mu, lam, g, H);
@@ -284,10 +286,10 @@ __device__ void prox3(int model, const float sig[3], float mu, float lam, float 
     }
     if (!ok) break;
     float slope = g[0] * dx[0] + g[1] * dx[1] + g[2] * dx[2];
-    float f0 = psi(model, s, mu, lam);
-    {
+    if (!have_f0) {  // later iterations start from the accepted line-search value
       float a = s[0] - sig[0], b = s[1] - sig[1], c = s[2] - sig[2];
-      f0 += 0.5f * k * (a * a + b * b + c * c);
+      f0 = psi(model, s, mu, lam) + 0.5f * k * (a * a + b * b + c * c);
+      have_f0 = true;
     }
     float t = 1.0f;
     bool acc = false;
@@ -299,6 +301,7 @@ __device__ void prox3(int model, const float sig[3], float mu, float lam, float 
         s[0] = tr[0];
         s[1] = tr[1];
         s[2] = tr[2];
+        f0 = f1;
         acc = true;
         break;
       }
