@@ -228,17 +228,26 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
       }
       return;
     }
-    for (int e = tid; e < zpad; e += kBlock) {
-      const int sl = slot_of(sl_zb, nsl, e);
-      const int k = e - sl_zb[sl] + sl_cs[sl];
-      const bool ok = k < sl_ce[sl];
-      float v[6];
+    // several scenes: four elements per thread, all loads of a round issued before the stores
+    for (int base = 0; base < zpad; base += 4 * kBlock) {
+      float v[4][6];
 #pragma unroll
-      for (int q = 0; q < 6; ++q)
-        if (q < 3 * nv) v[q] = ok ? Vg[q * CM + k] : 0.0f;
+      for (int u = 0; u < 4; ++u) {
+        const int e = base + tid + u * kBlock;
+        const int sl = e < zpad ? slot_of(sl_zb, nsl, e) : 0;
+        const int k = e - sl_zb[sl] + sl_cs[sl];
+        const bool ok = e < zpad && k < sl_ce[sl];
 #pragma unroll
-      for (int q = 0; q < 6; ++q)
-        if (q < 3 * nv) Zs[q * zpad + e] = v[q];
+        for (int q = 0; q < 6; ++q) v[u][q] = (q < 3 * nv && ok) ? Vg[q * CM + k] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = base + tid + u * kBlock;
+        if (e < zpad)
+#pragma unroll
+          for (int q = 0; q < 6; ++q)
+            if (q < 3 * nv) Zs[q * zpad + e] = v[u][q];
+      }
     }
   };
   // Y_v,t = sum_k K_jk V_v,k for every owned row t and nv vectors, 16 lanes per row (16
@@ -288,23 +297,37 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
       float a[3 * NV];
 #pragma unroll
       for (int q = 0; q < 3 * NV; ++q) a[q] = 0.0f;
-#pragma unroll 2
-      for (int k4 = gl; k4 < pc / 4; k4 += 16) {
-        const float4 kv = K4[k4];
-        const int k = 4 * k4;
+      // four quads of K per lane loaded together (fewer round trips per row
+      // when K comes from global memory; eight spill to scratch); each lane still adds its
+      // quads in column order
+      constexpr int U = 4;
+      const int n4 = pc / 4;
+      for (int base = gl; base < n4; base += 16 * U) {
+        float4 kv[U];
 #pragma unroll
-        for (int q = 0; q < 3 * NV; ++q) {
-          float4 z;
-          if (staged) {
-            z = reinterpret_cast<const float4*>(Zs + q * zpad + sl_zb[sl])[k4];
-          } else {  // V beyond the scene's contacts meets a zero pad of K
-            const float* vg = Vg + q * CM + cs + k;
-            z.x = vg[0];
-            z.y = k + 1 < cnt ? vg[1] : 0.0f;
-            z.z = k + 2 < cnt ? vg[2] : 0.0f;
-            z.w = k + 3 < cnt ? vg[3] : 0.0f;
+        for (int u = 0; u < U; ++u) {
+          const int k4 = base + 16 * u;
+          kv[u] = k4 < n4 ? K4[k4] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int k4 = base + 16 * u;
+          const int k = 4 * k4;
+#pragma unroll
+          for (int q = 0; q < 3 * NV; ++q) {
+            if (k4 >= n4) continue;
+            float4 z;
+            if (staged) {
+              z = reinterpret_cast<const float4*>(Zs + q * zpad + sl_zb[sl])[k4];
+            } else {  // V beyond the scene's contacts meets a zero pad of K
+              const float* vg = Vg + q * CM + cs + k;
+              z.x = vg[0];
+              z.y = k + 1 < cnt ? vg[1] : 0.0f;
+              z.z = k + 2 < cnt ? vg[2] : 0.0f;
+              z.w = k + 3 < cnt ? vg[3] : 0.0f;
+            }
+            a[q] += kv[u].x * z.x + kv[u].y * z.y + kv[u].z * z.z + kv[u].w * z.w;
           }
-          a[q] += kv.x * z.x + kv.y * z.y + kv.z * z.z + kv.w * z.w;
         }
       }
 #pragma unroll

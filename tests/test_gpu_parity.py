@@ -128,6 +128,34 @@ def test_delassus_and_preconditioner():
     sim.close()
 
 
+def test_teaser_iteration_with_delassus_rows_from_global_memory():
+    """The constraint solve on the fewest blocks the contact capacity allows (8 for 2048):
+    100 rows of 800 Delassus entries per block exceed a block's LDS, so the products stream
+    K rows from global memory.  One iteration at teaser scale against the oracle's exact
+    solve, to the same bounds as at the autotuned grid."""
+    sc = scenes.teaser_scene(0)
+    o = OracleSim(sc)
+    q_t = f32(sc.q0())
+    v_t = f32(sc.v0())
+    node, obst = o.detect(q_t, o.predict(q_t, v_t))
+    assert len(node) == 800
+    lam = np.zeros((len(node), 3))
+    q_k = o.predict(q_t, v_t)
+
+    def mk(s, **kw):
+        sim = make_sim(s, **kw)
+        sim.set_tuning(cr_blocks=8)
+        assert sim.tuning()["cr_blocks"] == 8
+        return sim
+
+    qg, lg_, qo, lo, o2, _ = iterate_pair(mk, sc, q_t, v_t, q_k, 0.0, node, obst, lam, k=1, cr="exact",
+                                          gpu_cr_iters=1000)
+    assert rel_inf(qg, qo) <= 1e-5
+    lam_scale = max(np.abs(lo).max(), 1e-3 * o2.mass.sum() * 9.81)
+    bound = max(1e-4, impulse_rounding_bound(o2, lam_scale))
+    assert rel_inf(lg_, lo, lam_scale) <= bound, (rel_inf(lg_, lo, lam_scale), bound)
+
+
 @pytest.mark.parametrize("frames", [12, 20, 40])
 def test_one_iteration_with_contacts(frames):
     """Positions with the paper's 10 CR iterations on both sides; impulses with the
@@ -272,15 +300,21 @@ def test_frames_to_tolerance_judged_by_oracle(variant):
     sim.close()
 
 
-def test_batch_equals_single_scenes():
+@pytest.mark.parametrize("cr_blocks", [None, 8])
+def test_batch_equals_single_scenes(cr_blocks):
     """A batch runs every scene as its own handle would, up to float32 summation order:
     rows of S are padded on batch-global 4-column groups, and the constraint solver splits
     a scene's contacts over a different set of blocks, so its per-scene sums are added in
     another order.  Such differences (a few ulp per iteration) grow through contact
-    changes over 15 frames; the bound is 5e-5 of the scene size."""
+    changes over 15 frames; the bound is 5e-5 of the scene size.  With the fewest CR blocks
+    the contact capacity allows (8), blocks hold the contacts of two scenes, which takes
+    the constraint solver's several-scene staging path."""
     scs = [scenes.cube_drop(s) for s in range(3)]
     scs[1].model = 2
     batch = lgsim.Sim(batch=scs)
+    if cr_blocks is not None:
+        batch.set_tuning(cr_blocks=cr_blocks)
+        assert batch.tuning()["cr_blocks"] == cr_blocks
     singles = [make_sim(s) for s in scs]
     batch.step(15)
     qb, vb, _ = batch.read_state()
