@@ -50,6 +50,11 @@ struct lgsim {
   lg::Dev d{};
   hipStream_t st = nullptr;
   bool own_stream = false;
+  // side stream of the frame set-up: the Delassus operator and the warm start run there
+  // while the first iteration's local step and S pass run on st (default priority)
+  hipStream_t st2 = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  bool setup_forked = false;
   std::vector<void*> allocs;
   std::vector<SceneMeta> scenes;
   std::vector<int32_t> iperm_caller;  // internal node -> caller node (global)
@@ -120,6 +125,12 @@ struct lgsim {
   }
   ~lgsim() {
     if (st) hipStreamSynchronize(st);
+    if (st2) {
+      hipStreamSynchronize(st2);
+      hipStreamDestroy(st2);
+    }
+    if (fork_ev) hipEventDestroy(fork_ev);
+    if (join_ev) hipEventDestroy(join_ev);
     if (gexec) hipGraphExecDestroy(gexec);
     for (void* p : allocs) hipFree(p);
     for (auto& e : ev)
@@ -754,20 +765,42 @@ int check_global_step(lgsim* s) {
 // Frame start (Algorithm 4): predicted state, pin targets, collision detection with
 // compaction, Delassus operator and warm start.  No host synchronisation: every kernel
 // reads the contact count from device memory and grids are sized by capacity.
-int frame_setup(lgsim* s) {
+// With fork, the steps after detection (Delassus operator, warm start, force ranges) run
+// on the side stream; they read only what detection and the predicted state wrote, and
+// the first iteration's local step, gather and S pass touch none of their outputs, so the
+// two overlap.  join_setup makes the handle's stream wait for them before the contact
+// evaluation of the first iteration.
+int frame_setup(lgsim* s, bool fork) {
   auto& d = s->d;
   lg::launch_predict(d, s->st);
   lg::launch_pins(d, s->st);
   lg::launch_zero_dual(d, s->st);
   lg::launch_collide(d, s->st);
-  lg::launch_delassus(d, s->st);
-  lg::launch_warm_start(d, s->st, 0);
+  hipStream_t cs = s->st;
+  if (fork) {
+    HIPCHK(hipEventRecord(s->fork_ev, s->st));
+    HIPCHK(hipStreamWaitEvent(s->st2, s->fork_ev, 0));
+    cs = s->st2;
+  }
+  lg::launch_delassus(d, cs);
+  lg::launch_warm_start(d, cs, 0);
   const bool learned = (s->opt.warm == SIM_WARM_MLP || s->opt.warm == SIM_WARM_MLP_PERSIST) && s->has_model;
-  if (s->record_pairs || learned) lg::launch_mlp_features(d, s->st);
-  if (learned) lg::launch_mlp_warm(d, s->st);
-  lg::launch_force_ranges(d, s->st);
+  if (s->record_pairs || learned) lg::launch_mlp_features(d, cs);
+  if (learned) lg::launch_mlp_warm(d, cs);
+  lg::launch_force_ranges(d, cs);
+  if (fork) {
+    HIPCHK(hipEventRecord(s->join_ev, s->st2));
+    s->setup_forked = true;
+  }
   s->iter_c = -1;  // known after the next synchronisation
   return check_launch("frame setup");
+}
+
+int join_setup(lgsim* s) {
+  if (!s->setup_forked) return SIM_OK;
+  s->setup_forked = false;
+  HIPCHK(hipStreamWaitEvent(s->st, s->join_ev, 0));
+  return SIM_OK;
 }
 
 // Timing events of one frame: [0] frame start, [1] setup done, then 6 per iteration,
@@ -796,11 +829,13 @@ int iteration(lgsim* s, bool timed, int it) {
   lg::launch_gather(d, s->st);
   rec(1);
   if (d.global_step == SIM_GLOBAL_JACOBI) {  // no obstacles (checked by the callers)
+    TRY(join_setup(s));
     lg::launch_jacobi_global(d, s->st);
     for (int p = 2; p <= 5; ++p) rec(p);
     return check_launch("iteration");
   }
   lg::launch_spmv_S(d, s->st, d.b, d.y);
+  TRY(join_setup(s));
   rec(2);
   if (s->iter_c != 0) {
     lg::launch_contact_prep(d, s->st);
@@ -865,6 +900,7 @@ int clear_flag(lgsim* s, int* dflag) {
 // frame is dropped and the state stays at the frame start).
 int finish_frame(lgsim* s) {
   auto& d = s->d;
+  TRY(join_setup(s));
   lg::launch_check_finite(d, s->st);
   lg::launch_integrate(d, s->st);
   TRY(check_launch("integrate"));
@@ -989,6 +1025,12 @@ int create_common(int32_t count, const sim_mesh* meshes, const sim_material* mat
       return fail(SIM_E_DEVICE);
     }
     s->own_stream = true;
+  }
+  if (hipStreamCreateWithFlags(&s->st2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&s->fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&s->join_ev, hipEventDisableTiming) != hipSuccess) {
+    lg::set_error("stream creation failed");
+    return fail(SIM_E_DEVICE);
   }
   std::vector<lg::HostScene> hs(count);
   try {
@@ -1406,8 +1448,9 @@ int frame_by_graph(lgsim* s, int iters) {
     }
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal));
-    int rc = frame_setup(s);
+    int rc = frame_setup(s, true);
     for (int k = 0; rc == SIM_OK && k < iters; ++k) rc = iteration(s, false, k);
+    if (rc != SIM_OK) (void)join_setup(s);  // no side-stream work left outside the capture
     if (rc == SIM_OK) rc = finish_frame(s);
     hipError_t e = hipStreamEndCapture(s->st, &g);
     if (rc != SIM_OK) {
@@ -1466,7 +1509,7 @@ int sim_step(sim_t s, int32_t frames, int32_t iters, sim_stats* stats) {
       continue;
     }
     rec(0);
-    TRY(frame_setup(s));
+    TRY(frame_setup(s, !timed));  // the per-phase timing pass keeps one stream
     rec(1);
     int k = 0;
     double res = 0.0;
