@@ -37,6 +37,31 @@ def test_graph_replay_matches_eager_launches(variant):
         np.testing.assert_array_equal(la, lb)
 
 
+@pytest.mark.parametrize("iters", [None, 0])
+def test_side_stream_setup_matches_one_stream(iters):
+    """Untimed eager frames run the Delassus operator and the warm start on the side
+    stream, overlapping the first iteration; timed frames keep one stream.  Both give the
+    same states bit for bit after every frame, with the scene's fixed iteration count and
+    with iterations to the NCP tolerance."""
+    sc = scenes.cube_drop(1)
+    runs = []
+    for stats in (True, False):
+        sim = lgsim.Sim(sc, max_iters=40)
+        sim.set_graph(False)
+        out = []
+        for f in range(25):
+            sim.step(1, iters=iters, stats=stats)
+            q, v, con = sim.read_state()
+            out.append((q, v, con["lam"].copy()))
+        sim.close()
+        runs.append(out)
+    assert sum(len(x[2]) for x in runs[0]) > 0
+    for (qa, va, la), (qb, vb, lb) in zip(*runs):
+        np.testing.assert_array_equal(qa, qb)
+        np.testing.assert_array_equal(va, vb)
+        np.testing.assert_array_equal(la, lb)
+
+
 def test_graph_recaptured_after_setting_change():
     sc = scenes.cube_drop(2)
     ref = lgsim.Sim(sc)
