@@ -222,8 +222,8 @@ def main():
                          "(reference kernel for scaling the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; a scene batch is the unit of work and "
-                                   "multi-GPU sharding is described in DESIGN.md but not implemented",
+        print(json.dumps({"error": "the solver runs on one GPU; a scene batch is the unit of work and "
+                                   "multi-GPU sharding is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
