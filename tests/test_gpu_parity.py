@@ -13,7 +13,7 @@ import pytest
 from oracle import fem
 from oracle.sim import OracleSim
 from paper_2503_15078_amd import lgsim, scenes
-from tests.parity_util import f32, impulse_rounding_bound, iterate_pair, oracle_state_after, rel_inf
+from tests.parity_util import f32, impulse_rounding_bound, iterate_pair, oracle_state_after, rel_inf, ulp_sensitivity
 
 pytestmark = pytest.mark.gpu
 
@@ -154,6 +154,44 @@ def test_teaser_iteration_with_delassus_rows_from_global_memory():
     lam_scale = max(np.abs(lo).max(), 1e-3 * o2.mass.sum() * 9.81)
     bound = max(1e-4, impulse_rounding_bound(o2, lam_scale))
     assert rel_inf(lg_, lo, lam_scale) <= bound, (rel_inf(lg_, lo, lam_scale), bound)
+
+
+def test_smallest_mesh_iteration_and_contact_list():
+    """Degenerate size: one voxel (8 nodes, 5 tets), so S is one dense 8x8 block and the
+    four bottom contacts fill a quarter of one Delassus tile.  One iteration against the
+    oracle's exact solve, and the contact list over 30 frames of the drop bit for bit.
+
+    The cube rests on the plane here, where the iteration map amplifies rounding of the
+    contact state strongly: the oracle's own impulses move by ulp_sensitivity (a few 1e-5)
+    when its float32 inputs move by one ulp.  The device rounds that state to float32
+    several times before the Fischer-Burmeister evaluation (prediction, the S and S^T
+    passes, the path sums, the frame products), so the impulse bound allows 16 such
+    roundings on top of the right-hand-side bound; positions keep 1e-5."""
+    sc = scenes.cube_drop(4, nodes=2)
+    o, q_t, v_t, t, fc, lam = oracle_state_after(sc, 12)
+    assert fc.c == 4
+    q_k = o.predict(q_t, v_t)
+    qg, lg_, qo, lo, o2, _ = iterate_pair(make_sim, sc, q_t, v_t, q_k, t, fc.node, fc.obst, lam, k=1,
+                                          cr="exact", gpu_cr_iters=100)
+    assert rel_inf(qg, qo) <= 1e-5
+    lam_scale = max(np.abs(lo).max(), 1e-3 * o2.mass.sum() * 9.81)
+    sens = ulp_sensitivity(sc, t, fc, q_t, v_t, lam)
+    bound = max(1e-4, impulse_rounding_bound(o2, lam_scale), 16.0 * sens)
+    print(f"impulse gap {rel_inf(lg_, lo, lam_scale):.2e}, one-ulp sensitivity {sens:.2e}, bound {bound:.2e}")
+    assert rel_inf(lg_, lo, lam_scale) <= bound, (rel_inf(lg_, lo, lam_scale), bound)
+    sim = make_sim(sc)
+    od = OracleSim(sc)
+    seen = 0
+    for f in range(30):
+        q, v, _ = sim.read_state()
+        node, obst = od.detect(q, od.predict(q, v))
+        st = sim.step(1)
+        _, _, con = sim.read_state()
+        assert st[0]["contacts"] == len(node)
+        assert np.array_equal(con["node"], node) and np.array_equal(con["obst"], obst)
+        seen += len(node)
+    assert seen > 0
+    sim.close()
 
 
 @pytest.mark.parametrize("frames", [12, 20, 40])
