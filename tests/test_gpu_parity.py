@@ -366,6 +366,44 @@ def test_batch_equals_single_scenes(cr_blocks):
     batch.close()
 
 
+def test_batch_with_a_contact_free_scene():
+    """Ragged batch: a contact-free spinning block between two drops, so the contact ranges
+    of the Delassus tiles and of the constraint solver skip the middle scene; every scene
+    runs as its own handle would, to the bound of the batch test above."""
+    scs = [scenes.cube_drop(0), scenes.free_block(4, h=1.0 / 60.0, spin=1.0), scenes.cube_drop(2)]
+    batch = lgsim.Sim(batch=scs)
+    singles = [make_sim(s) for s in scs]
+    contacts = 0
+    for f in range(15):
+        contacts += batch.step(1)[0]["contacts"]
+    assert contacts > 0
+    qb, _, _ = batch.read_state()
+    off = 0
+    for s, sim in zip(scs, singles):
+        sim.step(15)
+        q, _, _ = sim.read_state()
+        assert np.abs(qb[off:off + s.n] - q).max() <= 5e-5 * np.abs(q).max()
+        off += s.n
+        sim.close()
+    batch.close()
+
+
+def test_contact_capacity_boundary():
+    """The resting cube has exactly 25 contacts (its bottom face): with a capacity of 25 every
+    frame runs, with 24 the first frame that detects 25 reports the capacity error."""
+    sc = scenes.cube_drop(0)
+    sim = make_sim(sc, max_contacts=25)
+    sim.step(30)
+    _, _, con = sim.read_state()
+    assert len(con["node"]) == 25
+    sim.close()
+    sim = make_sim(sc, max_contacts=24)
+    with pytest.raises(lgsim.SimError) as e:
+        sim.step(30)
+    assert e.value.code == -8
+    sim.close()
+
+
 def test_device_readback_into_torch():
     torch = pytest.importorskip("torch")
     sc = scenes.cube_drop(0)
