@@ -333,6 +333,7 @@ __global__ void __launch_bounds__(kBlock) k_delassus_tiles(Dev d) {
   __shared__ int LJK[kDelTile][kDelTile];
   __shared__ int sufJ[kDelTile], preK[kDelTile];
   __shared__ int dJ[kDelTile], dK[kDelTile];
+  __shared__ int adJ[kDelTile], adK[kDelTile];
   __shared__ int64_t cJ[kDelTile], cK[kDelTile];
   __shared__ int red[kBlock];
   __shared__ int maxL;
@@ -353,21 +354,36 @@ __global__ void __launch_bounds__(kBlock) k_delassus_tiles(Dev d) {
     int J0 = cs + tj * kDelTile, K0 = cs + tk * kDelTile;
     int nJ = min(kDelTile, cs + cnt - J0), nK = min(kDelTile, cs + cnt - K0);
     int tid = threadIdx.x;
+    // the adjacent-pair depths inside both contact ranges, ad[J0 .. J0+nJ-2] and
+    // ad[K0 .. K0+nK-2], staged once (cross-scene pairs as -1); with the column data
     if (tid < kDelTile) {
-      int j = J0 + tid, k = K0 + tid;
+      const int j = J0 + tid;
+      adJ[tid] = tid < nJ - 1 ? max(d.ad[j], -1) : (1 << 30);
       if (tid < nJ) {
         dJ[tid] = d.depth[d.c_node[j]];
         cJ[tid] = d.col_ptr[d.c_node[j]];
+      }
+    } else if (tid < 2 * kDelTile) {
+      const int r = tid - kDelTile, k = K0 + r;
+      adK[r] = r < nK - 1 ? max(d.ad[k], -1) : (1 << 30);
+      if (r < nK) {
+        dK[r] = d.depth[d.c_node[k]];
+        cK[r] = d.col_ptr[d.c_node[k]];
+      }
+    }
+    __syncthreads();
+    if (tid < kDelTile) {
+      if (tid < nJ) {
         int m = 1 << 30;
-        for (int q = j; q < J0 + nJ - 1 && tj != tk; ++q) m = min(m, d.ad[q] < 0 ? -1 : d.ad[q]);
+        for (int q = tid; q < nJ - 1 && tj != tk; ++q) m = min(m, adJ[q]);
         sufJ[tid] = m;  // min ad[j .. J0+nJ-2] (off-diagonal tiles only)
       }
-      if (tid < nK) {
-        dK[tid] = d.depth[d.c_node[k]];
-        cK[tid] = d.col_ptr[d.c_node[k]];
+    } else if (tid < 2 * kDelTile) {
+      const int r = tid - kDelTile;
+      if (r < nK) {
         int m = 1 << 30;
-        for (int q = K0; q < k; ++q) m = min(m, d.ad[q] < 0 ? -1 : d.ad[q]);
-        preK[tid] = m;  // min ad[K0 .. k-1]
+        for (int q = 0; q < r; ++q) m = min(m, adK[q]);
+        preK[r] = m;  // min ad[K0 .. k-1]
       }
     }
     // min over the gap ad[J0+nJ-1 .. K0-1] (includes the boundary pair)
@@ -392,7 +408,7 @@ __global__ void __launch_bounds__(kBlock) k_delassus_tiles(Dev d) {
             L = dJ[a] + 1;
           } else if (k > j) {
             int m = 1 << 30;
-            for (int q = j; q < k; ++q) m = min(m, d.ad[q] < 0 ? -1 : d.ad[q]);
+            for (int q = a; q < b; ++q) m = min(m, adJ[q]);  // min ad[j .. k-1]
             L = m + 1;
           }
         } else {
