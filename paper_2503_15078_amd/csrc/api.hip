@@ -90,19 +90,18 @@ struct lgsim {
   int alloc(T*& p, size_t count) {
     void* q = nullptr;
     size_t bytes = std::max<size_t>(1, count) * sizeof(T);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;  // never while capturing
+    if (st && (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)) {
+      lg::set_error("device allocation during stream capture");
+      return SIM_E_STATE;
+    }
     if (hipMalloc(&q, bytes) != hipSuccess) {
       lg::set_error("hipMalloc failed (" + std::to_string(bytes) + " bytes)");
       return SIM_E_NOMEM;
     }
     // Zero on the handle's own stream and wait for it: the stream is non-blocking, so a
     // fill on the null stream would be unordered with the uploads that follow on it and
-    // could land after them.  Never called while the stream is being captured.
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (st && (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)) {
-      hipFree(q);
-      lg::set_error("device allocation during stream capture");
-      return SIM_E_STATE;
-    }
+    // could land after them.
     if ((st ? hipMemsetAsync(q, 0, bytes, st) : hipMemset(q, 0, bytes)) != hipSuccess ||
         (st ? hipStreamSynchronize(st) : hipDeviceSynchronize()) != hipSuccess) {
       hipFree(q);
