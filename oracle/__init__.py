@@ -19,6 +19,8 @@ Modules
   sparse_inverse elimination tree and L^-1 on small matrices               (Sec. 4.2, Theorem 1)
   sim            the frame / iteration loop of Algorithm 4
   brute_ncp      brute-force solutions of small contact problems (pins only)
+  selfcontact    surface triangles, vertex-triangle self-contacts, multi-node rows
+                 and their Delassus block                                 (Sec. 6, Sec. 3.2, App. A)
 
 Pinning status of each function is stated in its docstring; functions with
 no independent pin say "parity unpinned".

@@ -1,0 +1,128 @@
+"""Pins of the self-contact oracle (oracle/selfcontact.py) against geometry and mechanics
+that fix its results independently: closed-form surfaces and barycentric coordinates,
+hand-placed contacts, Newton's third law and zero torque of the contact pair, and the
+Delassus block against the dense product H (A_n (x) I3)^-1 H^T."""
+import numpy as np
+import pytest
+
+from oracle import selfcontact as scx
+from paper_2503_15078_amd import scenes
+
+# two separate tets: the top one's lowest vertex (4) hovers 0.005 above the bottom one's
+# upward face (0, 1, 2), over the point (0.2, 0.2, 0)
+STACK = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, -1],
+                  [0.2, 0.2, 0.005], [0.2, 0.2, 1], [1, 0.2, 1], [0.2, 1, 1]], float)
+STACK_TETS = np.array([[0, 1, 2, 3], [4, 5, 6, 7]])
+
+
+def test_single_tet_surface_is_outward():
+    X = STACK[:4]
+    tris = scx.surface_triangles(STACK_TETS[:1], X)
+    assert len(tris) == 4
+    centre = X.mean(0)
+    for t in tris:
+        n, _ = scx.triangle_frame(*X[t])
+        assert np.dot(n, X[t].mean(0) - centre) > 0.0
+
+
+def test_one_voxel_cube_surface():
+    """Five-tet split of a cube: 20 tet faces, 4 interior (shared), 12 on the boundary,
+    covering the six square faces (area 6 e^2), all outward."""
+    sc = scenes.cube_drop(0, nodes=2)
+    tris = scx.surface_triangles(sc.tets, sc.rest)
+    assert len(tris) == 12
+    e = np.ptp(sc.rest[:, 0])
+    centre = sc.rest.mean(0)
+    area = 0.0
+    for t in tris:
+        n, a = scx.triangle_frame(*sc.rest[t])
+        area += a
+        assert np.dot(n, sc.rest[t].mean(0) - centre) > 0.0
+    assert area == pytest.approx(6.0 * e * e, rel=1e-12)
+
+
+def test_projection_closed_forms():
+    a, b, c = np.array([0.0, 0, 0]), np.array([1.0, 0, 0]), np.array([0.0, 1, 0])
+    w, d = scx.project(np.array([1 / 3, 1 / 3, 0.2]), a, b, c)
+    np.testing.assert_allclose(w, [1 / 3, 1 / 3, 1 / 3], atol=1e-15)
+    assert d == pytest.approx(0.2)
+    w, d = scx.project(np.array([0.5, 0.5, -0.1]), a, b, c)
+    np.testing.assert_allclose(w, [0.0, 0.5, 0.5], atol=1e-15)
+    assert d == pytest.approx(-0.1)
+    w, _ = scx.project(np.array([1.0, 1.0, 0.0]), a, b, c)
+    assert w[0] == pytest.approx(-1.0) and w.sum() == pytest.approx(1.0)
+
+
+def test_convex_body_at_rest_has_no_self_contacts():
+    """Every vertex touches its own triangles (excluded) and lies a full edge inside the
+    opposite faces (beyond the depth), so a convex cube at rest has none."""
+    sc = scenes.cube_drop(0, nodes=2)
+    tris = scx.surface_triangles(sc.tets, sc.rest)
+    assert scx.detect_self(sc.rest, sc.rest, tris, margin=0.01, depth=0.05) == []
+
+
+def test_hand_placed_contact():
+    tris = scx.surface_triangles(STACK_TETS, STACK)
+    pairs = scx.detect_self(STACK, STACK, tris, margin=0.01, depth=0.05)
+    assert len(pairs) == 1 and pairs[0][0] == 4
+    assert sorted(tris[pairs[0][1]]) == [0, 1, 2]
+    rows = scx.SelfRows(pairs, tris, STACK)
+    # the weights reproduce the foot point (0.2, 0.2, 0); the gap is the hover height
+    p = -(rows.signs[0, 1:, None] * STACK[rows.nodes[0, 1:]]).sum(0)
+    np.testing.assert_allclose(p, [0.2, 0.2, 0.0], atol=1e-15)
+    assert rows.gap[0] == pytest.approx(0.005)
+    np.testing.assert_allclose(rows.C[0, 0], [0.0, 0.0, 1.0], atol=1e-15)
+    # beyond the margin, or the far side beyond the depth: no contact
+    far = STACK.copy()
+    far[4, 2] = 0.02
+    assert scx.detect_self(far, far, tris, margin=0.01, depth=0.05) == []
+    deep = STACK.copy()
+    deep[4, 2] = -0.06
+    assert scx.detect_self(deep, deep, tris, margin=0.01, depth=0.05) == []
+    # approaching: out of the margin at x_t, inside it at the predicted state
+    pred = far.copy()
+    pred[4, 2] = 0.004
+    assert scx.detect_self(far, pred, tris, margin=0.01, depth=0.05) == [(4, pairs[0][1])]
+
+
+def test_contact_pair_forces_balance():
+    """Newton's third law for any impulse (the weights sum to one), and zero torque when
+    the vertex lies on the triangle (its lever arm equals the foot point's)."""
+    X = STACK.copy()
+    X[4, 2] = 0.0
+    tris = scx.surface_triangles(STACK_TETS, STACK)
+    rows = scx.SelfRows([(4, int(np.flatnonzero([sorted(t) == [0, 1, 2] for t in tris])[0]))], tris, X)
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        lam = rng.normal(size=(1, 3))
+        f = rows.H_T(lam, len(X))
+        np.testing.assert_allclose(f.sum(0), 0.0, atol=1e-14)
+        np.testing.assert_allclose(np.cross(X, f).sum(0), 0.0, atol=1e-14)
+        assert np.abs(f).max() > 0.1
+
+
+def test_delassus_equals_dense_product():
+    """K and W of multi-node rows against H (A_n (x) I3)^-1 H^T with a dense inverse, for an
+    arbitrary SPD A_n and rows sharing nodes."""
+    rng = np.random.default_rng(3)
+    n = 8
+    G = rng.normal(size=(n, n))
+    A = G @ G.T + n * np.eye(n)
+    tris = scx.surface_triangles(STACK_TETS, STACK)
+    X = STACK.copy()
+    pairs = scx.detect_self(X, X, tris, margin=0.01, depth=0.05)
+    # a second row on the same triangle, from the top tet's vertex 5 placed under the face
+    X2 = X.copy()
+    X2[5] = [0.1, 0.3, -0.002]
+    t = pairs[0][1]
+    rows = scx.SelfRows([pairs[0], (5, t)], tris, X2)
+    K, W = rows.delassus(lambda B: np.linalg.solve(A, B), n)
+    Hm = rows.H(n)
+    W_dense = Hm @ np.kron(np.linalg.inv(A), np.eye(3)) @ Hm.T
+    np.testing.assert_allclose(W, W_dense, rtol=1e-12, atol=1e-14)
+    Ai = np.linalg.inv(A)
+    for j in range(2):
+        for k in range(2):
+            ref = sum(rows.signs[j, a] * rows.signs[k, b] * Ai[rows.nodes[j, a], rows.nodes[k, b]]
+                      for a in range(4) for b in range(4))
+            assert K[j, k] == pytest.approx(ref, rel=1e-12)
