@@ -126,3 +126,36 @@ def test_delassus_equals_dense_product():
             ref = sum(rows.signs[j, a] * rows.signs[k, b] * Ai[rows.nodes[j, a], rows.nodes[k, b]]
                       for a in range(4) for b in range(4))
             assert K[j, k] == pytest.approx(ref, rel=1e-12)
+
+
+def test_frictionless_self_contact_brute_force_and_momentum():
+    """One frictionless self-contact in the affine frame problem y = a + h^2 W lambda
+    (App. A): the brute-force NCP solution is the closed form -a_n / (h^2 K_jj); the
+    corrected positions q = u + A^-1 h^2 H^T lambda close the linearised gap, and the
+    correction carries no linear momentum (the pair's impulses cancel and the elastic
+    part of A is translation invariant)."""
+    from oracle import brute_ncp
+    from oracle.sim import OracleSim
+    tets = np.array([[0, 2, 1, 3], [4, 5, 6, 7]], np.int32)  # positively oriented
+    sc = scenes.Scene("stack", STACK.copy(), tets, scenes.MODEL_COROT, 1e5, 0.3, 1000.0, 0.01,
+                      np.zeros(3), [], 0.01, 1, 10, 1)
+    o = OracleSim(sc)
+    n, h = len(STACK), sc.h
+    tris = scx.surface_triangles(tets, STACK)
+    pairs = scx.detect_self(STACK, STACK, tris, margin=0.01, depth=0.05)
+    rows = scx.SelfRows(pairs, tris, STACK)
+    K, W = rows.delassus(o.lu.solve, n)
+    u = STACK.copy()
+    u[4:, 2] -= 0.007  # the top tet moved down: vertex 4 ends 2 mm below the face
+    a = (np.einsum("jab,jb->ja", rows.C, np.einsum("ja,jab->jb", rows.signs, u[rows.nodes]))).reshape(-1)
+    assert a[0] == pytest.approx(-0.002, abs=1e-12)
+    sols = brute_ncp.solve_all(a, h * h * W, np.zeros(1))
+    assert len(sols) == 1
+    lam = np.asarray(sols[0]).reshape(1, 3)
+    assert lam[0, 0] == pytest.approx(0.002 / (h * h * K[0, 0]), rel=1e-9)
+    np.testing.assert_allclose(lam[0, 1:], 0.0, atol=1e-12)
+    q = u + o.lu.solve(h * h * rows.H_T(lam, n))
+    gap = rows.C[0, 0] @ (rows.signs[0] @ q[rows.nodes[0]])
+    assert gap == pytest.approx(0.0, abs=1e-12)
+    p = (o.mass[:, None] * (q - u)).sum(0)
+    assert np.abs(p).max() <= 1e-12 * o.mass.sum() * 0.002
