@@ -159,3 +159,47 @@ def test_frictionless_self_contact_brute_force_and_momentum():
     assert gap == pytest.approx(0.0, abs=1e-12)
     p = (o.mass[:, None] * (q - u)).sum(0)
     assert np.abs(p).max() <= 1e-12 * o.mass.sum() * 0.002
+
+
+@pytest.mark.parametrize("mu,mode", [(2.0, "stick"), (0.05, "slide")])
+def test_frictional_self_contact_brute_force(mu, mode):
+    """The top tet pushed 7 mm down and 3 mm sideways into the bottom one's face: the
+    brute-force Signorini-Coulomb solution is unique, closes the gap, and either sticks
+    (no relative tangential motion, impulse inside the cone) or slides (impulse on the cone
+    boundary, opposing the relative motion); the pair's impulses leave linear momentum
+    unchanged in both cases."""
+    from oracle import brute_ncp
+    from oracle.sim import OracleSim
+    tets = np.array([[0, 2, 1, 3], [4, 5, 6, 7]], np.int32)
+    sc = scenes.Scene("stack", STACK.copy(), tets, scenes.MODEL_COROT, 1e5, 0.3, 1000.0, 0.01,
+                      np.zeros(3), [], 0.01, 1, 10, 1)
+    o = OracleSim(sc)
+    n, h = len(STACK), sc.h
+    tris = scx.surface_triangles(tets, STACK)
+    rows = scx.SelfRows(scx.detect_self(STACK, STACK, tris, margin=0.01, depth=0.05), tris, STACK)
+    K, W = rows.delassus(o.lu.solve, n)
+    u = STACK.copy()
+    u[4:, 2] -= 0.007
+    u[4:, 0] += 0.003
+    rel = lambda x: np.einsum("ja,jab->jb", rows.signs, x[rows.nodes])  # x_v - p(x)
+    a = np.einsum("jab,jb->ja", rows.C, rel(u))
+    a[:, 1:] = np.einsum("jab,jb->ja", rows.C[:, 1:], rel(u - STACK))  # h delta_dot_f at u
+    a = a.reshape(-1)
+    # impulses are O(400) here: the mode checks take an absolute 1e-8 (2e-11 relative),
+    # which the sliding mode's root finder reaches from 36 starting angles
+    sols = brute_ncp.solve_all(a, h * h * W, np.array([mu]), tol=1e-8, n_starts=36)
+    assert len(sols) == 1
+    lam = np.asarray(sols[0])
+    y = a + h * h * W @ lam
+    assert lam[0] > 0.0 and y[0] == pytest.approx(0.0, abs=1e-12)
+    lf, yf = lam[1:], y[1:]
+    if mode == "stick":
+        np.testing.assert_allclose(yf, 0.0, atol=1e-12)
+        assert np.linalg.norm(lf) < mu * lam[0]
+    else:
+        assert np.linalg.norm(yf) > 1e-6
+        assert np.linalg.norm(lf) == pytest.approx(mu * lam[0], rel=1e-8)
+        assert np.dot(lf, yf) == pytest.approx(-np.linalg.norm(lf) * np.linalg.norm(yf), rel=1e-6)
+    q = u + o.lu.solve(h * h * rows.H_T(lam.reshape(1, 3), n))
+    p = (o.mass[:, None] * (q - u)).sum(0)
+    assert np.abs(p).max() <= 1e-12 * o.mass.sum() * 0.002
