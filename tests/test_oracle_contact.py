@@ -227,3 +227,78 @@ def test_incline_stick_slide(delta):
         assert abs(v) < 0.01 * v_slide
     else:
         assert abs(v - v_slide) < 0.1 * v_slide
+
+
+# ---- NCP residual (reading of the Signorini-Coulomb conditions, Sec. 3.2 and App. B) at
+# states off the solution: each case isolates one term and states its value worked out by
+# hand from the definitions (FB(a, b) = a + b - sqrt(a^2 + b^2), s = |vdot_f|,
+# gamma = mu lambda_n - |lambda_f|), so a dropped term, a missing h or a wrong sign fails.
+H_STEP = 0.01
+
+
+def _res(dn, vf, lam, rn=0.5, rf=0.1, mu=0.5, comp=None):
+    return ct.ncp_residual(np.array([dn], float), np.array([vf], float), np.array([lam], float),
+                           np.array([rn]), np.array([rf]), np.array([mu]), H_STEP,
+                           None if comp is None else np.array([comp], float))
+
+
+def test_ncp_residual_normal_term():
+    # penetration with no impulse: FB(-0.01, 0) = -0.01 - 0.01
+    assert _res(-0.01, [0.0, 0.0], [0.0, 0.0, 0.0]) == pytest.approx(0.02, rel=1e-14)
+    # separated with an impulse: FB(0.003, 0.5 * 0.008) = 0.007 - 0.005
+    assert _res(0.003, [0.0, 0.0], [0.008, 0.0, 0.0]) == pytest.approx(0.002, rel=1e-12)
+    # complementary pairs are zero
+    assert _res(0.0, [0.0, 0.0], [0.01, 0.0, 0.0]) == 0.0
+    assert _res(0.02, [0.0, 0.0], [0.0, 0.0, 0.0]) == 0.0
+
+
+def test_ncp_residual_friction_fb_term():
+    # active contact (delta_n = 0, lambda_n = 4 > 0), slip s = 0.5 inside the cone with no
+    # friction impulse: h FB(0.5, r_f gamma) with r_f gamma = 0.1 * (0.5 * 4) = 0.2
+    expect = H_STEP * (0.7 - math.sqrt(0.25 + 0.04))
+    assert _res(0.0, [0.3, 0.4], [4.0, 0.0, 0.0]) == pytest.approx(expect, rel=1e-13)
+    # sticking on the cone interior with zero slip: zero
+    assert _res(0.0, [0.0, 0.0], [4.0, 0.5, -0.5]) == 0.0
+
+
+def test_ncp_residual_direction_term():
+    # sliding on the cone boundary (|lambda_f| = mu lambda_n = 1, so FB(s, 0) = 0), but the
+    # friction impulse is perpendicular to the slip instead of opposing it:
+    # h |vdot_f + s lambda_f / |lambda_f|| = h |(0, 0.5) + 0.5 (1, 0)| = h sqrt(0.5)
+    assert _res(0.0, [0.0, 0.5], [2.0, 1.0, 0.0]) == pytest.approx(H_STEP * math.sqrt(0.5), rel=1e-13)
+    # opposing the slip, as Coulomb's law requires: zero
+    assert _res(0.0, [-0.5, 0.0], [2.0, 1.0, 0.0]) == 0.0
+
+
+def test_ncp_residual_off_cone_term():
+    # no normal impulse (separated, delta_n > 0) but a friction impulse: h r_f |lambda_f|
+    assert _res(0.01, [0.2, 0.0], [0.0, 0.3, -0.4]) == pytest.approx(H_STEP * 0.1 * 0.5, rel=1e-13)
+    # negative normal impulse also counts as inactive (and its FB term is its own value):
+    # FB(0.01, 0.5 * -0.002) = 0.009 - sqrt(1e-4 + 1e-6)
+    fbn = 0.009 - math.sqrt(1e-4 + 1e-6)
+    got = _res(0.01, [0.0, 0.0], [-0.002, 0.3, -0.4])
+    assert got == pytest.approx(max(abs(fbn), H_STEP * 0.1 * 0.5), rel=1e-12)
+
+
+def test_ncp_residual_binding_row():
+    # bilateral row of compliance e = 0.2: |delta_b + e lambda_b| = |0.01 - 0.2 * 0.01|, and
+    # its tangent impulses are off-cone terms h r_f |lambda_f|
+    assert _res(0.01, [0.0, 0.0], [-0.01, 0.0, 0.0], comp=0.2) == pytest.approx(0.008, rel=1e-12)
+    assert _res(0.01, [0.0, 0.0], [-0.01, 0.0, 0.6], comp=0.2) == pytest.approx(0.008, rel=1e-12)
+    assert _res(0.0, [0.0, 0.0], [0.0, 8.0, 6.0], comp=0.0) == pytest.approx(H_STEP * 0.1 * 10.0, rel=1e-13)
+    # a hard binding (e = 0) pulled 0.01 off its line: |delta_b| (a unilateral row would
+    # give |FB(-0.01, 0)| = 0.02)
+    assert _res(-0.01, [0.0, 0.0], [0.0, 0.0, 0.0], comp=0.0) == pytest.approx(0.01, rel=1e-14)
+    # the bilateral residual replaces the unilateral one (which would be 0.02 here)
+    assert _res(-0.01, [0.0, 0.0], [0.05, 0.0, 0.0], comp=0.2) == pytest.approx(0.0, abs=1e-15)
+
+
+def test_ncp_residual_is_the_max_over_contacts():
+    dn = np.array([-0.01, 0.0, 0.01])
+    vf = np.array([[0.0, 0.0], [0.0, 0.5], [0.2, 0.0]])
+    lam = np.array([[0.0, 0.0, 0.0], [2.0, 1.0, 0.0], [0.0, 0.3, -0.4]])
+    one = np.ones(3)
+    got = ct.ncp_residual(dn, vf, lam, 0.5 * one, 0.1 * one, 0.5 * one, H_STEP)
+    assert got == pytest.approx(0.02, rel=1e-14)
+    got = ct.ncp_residual(dn[1:], vf[1:], lam[1:], 0.5 * one[1:], 0.1 * one[1:], 0.5 * one[1:], H_STEP)
+    assert got == pytest.approx(H_STEP * math.sqrt(0.5), rel=1e-13)
