@@ -236,12 +236,21 @@ int sim_set_tuning(sim_t s, const sim_tuning* t);
  * rounding (groups, segment length, CR form) stay within the parity tolerances. */
 int sim_autotune(sim_t s, int32_t frames, int32_t iters, int32_t allow_pipelined, sim_tuning* best);
 
-/* Replace the obstacle set (n >= 0; at most 64). */
+/* Replace the obstacle set of a single-scene handle (n >= 0; at most 64), e.g. to move
+ * obstacles between frames.  Obstacles are the analytic contact partners of App. A (their
+ * surface velocity enters the friction rows as h d_f) plus the bilateral rows of Sec. 3.2
+ * (binding type).  obs is borrowed for the call and copied.  SIM_E_ARG for a bad count,
+ * type, non-finite geometry, a zero normal, a degenerate cylinder or a binding node out of
+ * range; SIM_E_STATE on a batch handle.  Takes effect at the next frame start. */
 int sim_set_obstacles(sim_t s, int32_t n, const sim_obstacle* obs);
 
-/* Rigid motion of each pin group: target(t) = pivot + lin_vel t + R(ang_vel t)(x0 - pivot),
- * x0 the pinned node's initial position.  Arrays [n_groups][3]; n_groups must cover
- * every group index used by the mesh. */
+/* Rigid motion of each pin group (the moving positional constraints of Sec. 3.3's local
+ * step, e.g. the twisted ends of Sec. 7's bar): target(t) = pivot + lin_vel t +
+ * R(ang_vel t)(x0 - pivot), x0 the pinned node's initial position, R the rotation by the
+ * vector ang_vel t.  Arrays [n_groups][3], borrowed and copied; n_groups must cover every
+ * group index used by the mesh (SIM_E_ARG), non-finite values are SIM_E_ARG, a batch
+ * handle is SIM_E_STATE.  The pin weights stay those fixed at creation (they are part of
+ * the constant system matrix of Sec. 4); only targets move. */
 int sim_set_pin_motion(sim_t s, int32_t n_groups, const double* lin_vel, const double* ang_vel,
                        const double* pivot);
 
@@ -252,9 +261,13 @@ int sim_set_pin_motion(sim_t s, int32_t n_groups, const double* lin_vel, const d
  * SIM_E_DIVERGED (non-finite state; rolled back), SIM_E_DEVICE. */
 int sim_step(sim_t s, int32_t frames, int32_t iters, sim_stats* stats);
 
-/* Copy the state to the host: xyz/vel [n][3] in caller order (each may be null), and
- * the last frame's contacts in canonical (node, obstacle) order into contacts[cap]
- * (may be null); *n_contacts (may be null) receives the total count. */
+/* Copy the state to the host: q_t and v_t of Algorithm 4 after the last frame, xyz/vel
+ * [n][3] float64 in caller order (each may be null), and the last frame's contacts in
+ * canonical (node, obstacle) order into contacts[cap] (may be null): frame rows n, f1, f2
+ * (Sec. 3.2), the impulse lambda in that frame and the float64 gap at the frame start;
+ * *n_contacts (may be null) receives the total count (more than cap is not an error: the
+ * first cap are copied).  Buffers are caller-owned; the call synchronises the handle's
+ * stream. */
 int sim_read_state(sim_t s, double* xyz, double* vel, sim_contact* contacts, int32_t cap,
                    int32_t* n_contacts);
 
@@ -281,8 +294,10 @@ const char* sim_last_error(void);
  * Build a batch solver from several scene descriptions.  Scenes are concatenated:
  * the block-diagonal system has one elimination forest, so every kernel of
  * Algorithm 4 runs once per stage for all scenes, and the Conjugate Residual solves
- * run per scene inside one cooperative launch.  All scenes share h and options.
- * obstacles[i] / n_obstacles[i] describe scene i. */
+ * run per scene inside one persistent launch.  All scenes share h and options.
+ * obstacles[i] / n_obstacles[i] describe scene i.  count must lie in [1, 256] (the
+ * constraint solver keeps per-scene slots in fixed on-chip tables): SIM_E_ARG otherwise,
+ * before any device work. */
 int sim_create_batch(int32_t count, const sim_mesh* meshes, const sim_material* mats,
                      const int32_t* n_obstacles, const sim_obstacle* const* obstacles, double h,
                      const sim_options* opt, sim_t* out);

@@ -17,9 +17,15 @@ Readings where the paper is silent:
 * a pair (v, T) is a candidate iff v is a surface vertex that is not a corner of T;
   it is a contact iff, at x_t and at x~, the orthogonal projection of x_v onto the plane
   of T falls inside T (all barycentric weights >= 0), the signed distance along T's
-  outward normal exceeds -depth at x_t (v is not on the far side of the body), and the
-  smaller of the two states' distances is below margin (the obstacle predicate of the
-  main contact model, applied to the triangle plane);
+  outward normal exceeds -margin at x_t (v is outside the body at the frame start up to
+  the contact margin: an intersection-free state has every vertex outside, the band keeps
+  a slightly penetrated vertex in contact, and it is far thinner than any wall, so the far
+  side of the body never qualifies), v faces
+  T at x_t (the sum of the area-weighted outward normals of v's surface triangles has a
+  negative dot product with T's normal: the two surfaces are opposed, which excludes
+  vertices next to a convex edge, whose projection falls on the perpendicular face just
+  below its plane), and the smaller of the two states' distances is below margin (the
+  obstacle predicate of the main contact model, applied to the triangle plane);
 * the row's frame, weights and d_n are taken at x_t: n the outward unit normal of T,
   tangents as for obstacle rows, d_n = 0 (the gap is n . (x_v - p));
 * canonical order: (vertex id, triangle id).
@@ -74,25 +80,47 @@ def project(x, xa, xb, xc):
     return np.array([wa, wb, wc]) / tot, dist
 
 
-def detect_self(q_t, q_pred, tris, margin, depth):
-    """Vertex-triangle self-contacts: list of (v, triangle index) in canonical order."""
+def vertex_normals(x, tris):
+    """Sum over each vertex's surface triangles of their area-weighted outward normals
+    (the cross product of two edges), at positions x; zero for non-surface vertices."""
+    out = np.zeros_like(np.asarray(x, np.float64))
+    for a, b, c in tris:
+        nrm = np.cross(x[b] - x[a], x[c] - x[a])
+        out[a] += nrm
+        out[b] += nrm
+        out[c] += nrm
+    return out
+
+
+def detect_self(q_t, q_pred, tris, margin):
+    """Vertex-triangle self-contacts: list of (v, triangle index) in canonical order.
+
+    Each vertex is tested against every triangle (vectorised over triangles)."""
+    tris = np.asarray(tris, np.int64).reshape(-1, 3)
     verts = np.unique(tris)
+    vn = vertex_normals(q_t, tris)
+    geo = []
+    for q in (q_t, q_pred):
+        xa, xb, xc = q[tris[:, 0]], q[tris[:, 1]], q[tris[:, 2]]
+        nrm = np.cross(xb - xa, xc - xa)
+        nrm = nrm / np.linalg.norm(nrm, axis=1)[:, None]
+        geo.append((xa, xb, xc, nrm))
     out = []
     for v in verts:
-        for ti, tri in enumerate(tris):
-            if v in tri:
-                continue
-            ok = True
-            dists = []
-            for q in (q_t, q_pred):
-                w, dist = project(q[v], q[tri[0]], q[tri[1]], q[tri[2]])
-                if np.any(w < 0.0):
-                    ok = False
-                    break
-                dists.append(dist)
-            if not ok or not dists[0] > -depth or min(dists) >= margin:
-                continue
-            out.append((int(v), int(ti)))
+        keep = ~np.any(tris == v, axis=1) & (geo[0][3] @ vn[v] < 0.0)
+        dists = []
+        for q, (xa, xb, xc, nrm) in zip((q_t, q_pred), geo):
+            x = q[v]
+            dist = np.einsum("ti,ti->t", nrm, x - xa)
+            p = x - dist[:, None] * nrm
+            wa = np.einsum("ti,ti->t", nrm, np.cross(xb - p, xc - p))
+            wb = np.einsum("ti,ti->t", nrm, np.cross(xc - p, xa - p))
+            wc = np.einsum("ti,ti->t", nrm, np.cross(xa - p, xb - p))
+            tot = wa + wb + wc
+            keep &= (wa / tot >= 0.0) & (wb / tot >= 0.0) & (wc / tot >= 0.0)
+            dists.append(dist)
+        keep &= (dists[0] > -margin) & (np.minimum(dists[0], dists[1]) < margin)
+        out.extend((int(v), int(ti)) for ti in np.flatnonzero(keep))
     return out
 
 

@@ -849,7 +849,7 @@ int iteration(lgsim* s, bool timed, int it) {
   lg::launch_spmv_St(d, s->st, d.y, d.qp, d.q);
   rec(5);
   if (cr_err != hipSuccess) {
-    lg::set_error(std::string("cooperative CR launch failed: ") + hipGetErrorString(cr_err));
+    lg::set_error(std::string("CR launch failed: ") + hipGetErrorString(cr_err));
     return SIM_E_DEVICE;
   }
   return check_launch("iteration");
@@ -984,6 +984,10 @@ int create_common(int32_t count, const sim_mesh* meshes, const sim_material* mat
                   const sim_options* opt, const std::vector<std::vector<sim_obstacle>>& obs, sim_t* out) {
   if (!meshes || !mats || !out || count <= 0) {
     lg::set_error("null argument");
+    return SIM_E_ARG;
+  }
+  if (count > lg::kMaxScenes) {
+    lg::set_error("at most " + std::to_string(lg::kMaxScenes) + " scenes per handle");
     return SIM_E_ARG;
   }
   *out = nullptr;

@@ -26,6 +26,9 @@ constexpr int kMlpParams = 20752;   // 16x128 + 128 + 128x128 + 128 + 16x128 + 1
 constexpr int kMlpMaxBlocks = 256;  // blocks of one training launch (64 samples each)
 constexpr int kMlpMaxBatch = 64 * kMlpMaxBlocks;
 constexpr int kCrMaxBlocks = 1024;  // blocks of the CR launch (partial sums)
+// scenes of one handle: a CR block keeps a slot per scene between its first and last
+// contact (empty scenes included), in LDS tables of this many entries
+constexpr int kMaxScenes = 256;
 constexpr int kCrMaxBarriers = 2 * kMaxCrIters + 2;  // device-wide barriers of one CR launch
 
 struct ObstacleDev {

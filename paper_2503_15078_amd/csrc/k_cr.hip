@@ -45,6 +45,8 @@ constexpr int kCrZFloats = 3 * 2048;  // gathered (padded) Z of the touched scen
 constexpr int kCrRows = 256;          // max contacts per block
 constexpr int kCrSlots = 4;           // partial sums per (block, scene slot)
 constexpr unsigned kCrSpinLimit = 1u << 21;  // polls before a barrier wait is abandoned
+// a block's scene slots span at most every scene of the handle
+static_assert(kMaxScenes <= kCrRows, "scene slot tables of a CR block");
 
 __device__ inline float wave_sum_cr(float v) {
   for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);

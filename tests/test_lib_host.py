@@ -114,3 +114,12 @@ def test_host_pin_weights_match_oracle():
     o = OracleSim(sc)
     A = hp.dense_A()
     np.testing.assert_allclose(np.diag(A)[perm], o.A.diagonal(), rtol=1e-12)
+
+
+def test_batch_beyond_scene_slots_is_refused():
+    """A handle holds at most 256 scenes (the constraint solver's per-scene slot tables):
+    257 is refused with SIM_E_ARG before any device work, so this runs without a GPU."""
+    sc = _tiny((2, 2, 2))
+    with pytest.raises(lgsim.SimError) as e:
+        lgsim.Sim(batch=[sc] * 257)
+    assert e.value.code == -1 and "256 scenes" in str(e.value)  # SIM_E_ARG

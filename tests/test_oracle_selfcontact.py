@@ -55,15 +55,55 @@ def test_projection_closed_forms():
 
 def test_convex_body_at_rest_has_no_self_contacts():
     """Every vertex touches its own triangles (excluded) and lies a full edge inside the
-    opposite faces (beyond the depth), so a convex cube at rest has none."""
+    opposite faces (further inside than the margin), so a convex cube at rest has none."""
     sc = scenes.cube_drop(0, nodes=2)
     tris = scx.surface_triangles(sc.tets, sc.rest)
-    assert scx.detect_self(sc.rest, sc.rest, tris, margin=0.01, depth=0.05) == []
+    assert scx.detect_self(sc.rest, sc.rest, tris, margin=0.01) == []
+
+
+@pytest.mark.parametrize("case", ["cube5", "star"])
+def test_meshes_at_rest_have_no_self_contacts(case):
+    """At rest no vertex faces another part of the surface within the margin.  The 5^3-node
+    cube has vertices one layer from every convex edge, whose projections fall on the
+    perpendicular face a voxel below its plane (excluded as not facing it and deeper than
+    the margin); a star-profile mesh (the teaser's shape, fewer nodes) adds concave
+    corners between its arms, thin walls and staircase steps."""
+    if case == "cube5":
+        sc = scenes.cube_drop(0)
+        rest, tets, margin = sc.rest, sc.tets, sc.margin
+    else:
+        rest, tets = scenes.star_profile_mesh(0, target=(2000, 2400), layers=6)[:2]
+        margin = 0.25 * 0.01
+    tris = scx.surface_triangles(tets, rest)
+    assert len(tris) > 100
+    assert scx.detect_self(rest, rest, tris, margin=margin) == []
+
+
+def test_facing_rule():
+    """A vertex just outside a face but next to it across a convex edge (its own surface
+    normal perpendicular to the face's) is not a contact; the same point on a separate body
+    whose surface faces the face is."""
+    tris = scx.surface_triangles(STACK_TETS, STACK)
+    vn = scx.vertex_normals(STACK, tris)
+    t = int(np.flatnonzero([sorted(tr) == [0, 1, 2] for tr in tris])[0])
+    n, _ = scx.triangle_frame(*STACK[tris[t]])
+    assert vn[4] @ n < 0.0  # the hovering vertex faces the bottom tet's top face
+    X = STACK.copy()
+    X[4:] += [0.0, 0.0, 0.001]
+    X[4] = [0.2, 0.2, 0.003]
+    assert (4, t) in scx.detect_self(X, X, tris, margin=0.01)
+    # turn the top tet a quarter turn about vertex 4 (y axis): vertex 4's surface normal
+    # becomes horizontal, perpendicular to the face it still hovers over
+    Y = STACK.copy()
+    Y[5:] = Y[4] + (STACK[5:] - STACK[4])[:, [2, 1, 0]] * [1.0, 1.0, -1.0]
+    vy = scx.vertex_normals(Y, tris)
+    assert abs(vy[4] @ n) <= 1e-15 and abs(vy[4][0]) > 0.1
+    assert (4, t) not in scx.detect_self(Y, Y, tris, margin=0.01)
 
 
 def test_hand_placed_contact():
     tris = scx.surface_triangles(STACK_TETS, STACK)
-    pairs = scx.detect_self(STACK, STACK, tris, margin=0.01, depth=0.05)
+    pairs = scx.detect_self(STACK, STACK, tris, margin=0.01)
     assert len(pairs) == 1 and pairs[0][0] == 4
     assert sorted(tris[pairs[0][1]]) == [0, 1, 2]
     rows = scx.SelfRows(pairs, tris, STACK)
@@ -72,17 +112,17 @@ def test_hand_placed_contact():
     np.testing.assert_allclose(p, [0.2, 0.2, 0.0], atol=1e-15)
     assert rows.gap[0] == pytest.approx(0.005)
     np.testing.assert_allclose(rows.C[0, 0], [0.0, 0.0, 1.0], atol=1e-15)
-    # beyond the margin, or the far side beyond the depth: no contact
+    # beyond the margin, or inside the body by more than the margin: no contact
     far = STACK.copy()
     far[4, 2] = 0.02
-    assert scx.detect_self(far, far, tris, margin=0.01, depth=0.05) == []
+    assert scx.detect_self(far, far, tris, margin=0.01) == []
     deep = STACK.copy()
-    deep[4, 2] = -0.06
-    assert scx.detect_self(deep, deep, tris, margin=0.01, depth=0.05) == []
+    deep[4, 2] = -0.011  # further inside than the margin
+    assert scx.detect_self(deep, deep, tris, margin=0.01) == []
     # approaching: out of the margin at x_t, inside it at the predicted state
     pred = far.copy()
     pred[4, 2] = 0.004
-    assert scx.detect_self(far, pred, tris, margin=0.01, depth=0.05) == [(4, pairs[0][1])]
+    assert scx.detect_self(far, pred, tris, margin=0.01) == [(4, pairs[0][1])]
 
 
 def test_contact_pair_forces_balance():
@@ -110,7 +150,7 @@ def test_delassus_equals_dense_product():
     A = G @ G.T + n * np.eye(n)
     tris = scx.surface_triangles(STACK_TETS, STACK)
     X = STACK.copy()
-    pairs = scx.detect_self(X, X, tris, margin=0.01, depth=0.05)
+    pairs = scx.detect_self(X, X, tris, margin=0.01)
     # a second row on the same triangle, from the top tet's vertex 5 placed under the face
     X2 = X.copy()
     X2[5] = [0.1, 0.3, -0.002]
@@ -142,7 +182,7 @@ def test_frictionless_self_contact_brute_force_and_momentum():
     o = OracleSim(sc)
     n, h = len(STACK), sc.h
     tris = scx.surface_triangles(tets, STACK)
-    pairs = scx.detect_self(STACK, STACK, tris, margin=0.01, depth=0.05)
+    pairs = scx.detect_self(STACK, STACK, tris, margin=0.01)
     rows = scx.SelfRows(pairs, tris, STACK)
     K, W = rows.delassus(o.lu.solve, n)
     u = STACK.copy()
@@ -176,7 +216,7 @@ def test_frictional_self_contact_brute_force(mu, mode):
     o = OracleSim(sc)
     n, h = len(STACK), sc.h
     tris = scx.surface_triangles(tets, STACK)
-    rows = scx.SelfRows(scx.detect_self(STACK, STACK, tris, margin=0.01, depth=0.05), tris, STACK)
+    rows = scx.SelfRows(scx.detect_self(STACK, STACK, tris, margin=0.01), tris, STACK)
     K, W = rows.delassus(o.lu.solve, n)
     u = STACK.copy()
     u[4:, 2] -= 0.007
