@@ -180,6 +180,32 @@ def cube_drop(seed: int = 0, model: int = MODEL_COROT, nodes: int = 5, edge: flo
                  init_pos=init)
 
 
+def cube_on_obstacle(kind: str, seed: int = 0, mu: float = 0.5, frames: int = 40) -> Scene:
+    """The 5x5x5-node drop cube (0.1 m, x, y in [0, 0.1]) falling onto a slab or a capped
+    cylinder instead of the ground plane (App. A's analytic partners), placed so that
+    every branch of their distance functions holds contacts:
+    * "slab": a box whose top face is z = 0 and whose +x side face is at x = 0.07, so the
+      cube lands across the slab's edge (inside points, the edge and the side face);
+    * "cylinder_side": a horizontal capped cylinder along y, radius 0.03, top line z = 0
+      at x = 0.05, its cap at y = 0.097, just inside the cube's last node row (curved
+      side, cap and rim);
+    * "cylinder_cap": a vertical capped cylinder of radius 0.046 under the cube's centre,
+      its upper cap at z = 0 (the cap face, and its rim edge just inside the cube's edge
+      midpoints; the cube's corners overhang)."""
+    sc = cube_drop(seed, mu=mu, frames=frames)
+    if kind == "slab":
+        ob = Obstacle.make(OBST_BOX, [0.0, 0.05, -0.02, 0.07, 0.2, 0.02], mu)
+    elif kind == "cylinder_side":
+        ob = Obstacle.make(OBST_CYLINDER, [0.05, -0.2, -0.03, 0.05, 0.097, -0.03, 0.03], mu)
+    elif kind == "cylinder_cap":
+        ob = Obstacle.make(OBST_CYLINDER, [0.05, 0.05, -0.3, 0.05, 0.05, 0.0, 0.046], mu)
+    else:
+        raise ValueError(kind)
+    sc.name = f"cube_on_{kind}"
+    sc.obstacles = [ob]
+    return sc
+
+
 def incline_block(mu: float, theta_deg: float = 10.0, nodes: int = 4, edge: float = 0.1,
                   E: float = 1e8, nu: float = 0.3, model: int = MODEL_COROT, h: float = 0.01,
                   frames: int = 60, iters: int = 10, cr_iters: int = 24,

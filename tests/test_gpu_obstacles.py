@@ -1,0 +1,83 @@
+"""GPU parity of collision detection and the contact iteration against slab (box) and
+capped-cylinder obstacles (App. A's analytic partners, Sec. 6 collision detection).
+
+The cube drop falls onto each obstacle, placed so that its contacts cover every branch of
+the obstacle's distance function: a slab's inside points, edge and side face; a cylinder's
+curved side, caps and rims.  Each frame, the oracle's float64 predicate on the GPU's own
+float32 state must select exactly the GPU's contact list (node, obstacle, order), and the
+frame rows must equal the oracle's float64 frames rounded to float32.  At frames with
+contacts, one iteration from the same state must match the oracle (positions 1e-5, impulses
+with the constraint system solved to convergence on both sides)."""
+import numpy as np
+import pytest
+
+from oracle import contact as ct
+from oracle.sim import OracleSim
+from paper_2503_15078_amd import lgsim, scenes
+from tests.parity_util import f32, iterate_pair, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+KINDS = ["slab", "cylinder_side", "cylinder_cap"]
+
+
+def _branch(ob, x):
+    """Which piece of the obstacle surface is nearest to x (for coverage only)."""
+    g = np.asarray(ob.geom, float)
+    if ob.type == ct.BOX:
+        q = np.abs(x - g[:3]) - g[3:6]
+        return "inside" if np.all(q <= 0) else ("face" if np.sum(q > 0) == 1 else "edge")
+    e = g[3:6] - g[:3]
+    L = np.linalg.norm(e)
+    u = e / L
+    t = (x - g[:3]) @ u
+    rho = np.linalg.norm((x - g[:3]) - t * u)
+    dr, da = rho - g[6], max(-t, t - L)
+    if dr > 0 and da > 0:
+        return "rim"
+    return "side" if (dr > 0 or (da <= 0 and dr > da)) else "cap"
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_contact_lists_and_frames_bit_exact(kind):
+    sc = scenes.cube_on_obstacle(kind)
+    sim = lgsim.Sim(sc)
+    o = OracleSim(sc)
+    ob = sc.obstacles[0]
+    seen, branches = 0, set()
+    for f in range(40):
+        q, v, _ = sim.read_state()
+        node, obst = o.detect(q, o.predict(q, v))
+        st = sim.step(1)
+        _, _, con = sim.read_state()
+        assert st[0]["contacts"] == len(node), (kind, f)
+        assert np.array_equal(con["node"], node) and np.array_equal(con["obst"], obst), (kind, f)
+        if len(node):
+            fc = o.contacts_from_keys(node, obst, q)
+            np.testing.assert_array_equal(con["frame"].reshape(-1, 3, 3), fc.C.astype(np.float32).astype(np.float64))
+            branches |= {_branch(ob, q[v]) for v in node}
+        seen += len(node)
+    sim.close()
+    want = {"slab": {"inside", "face", "edge"}, "cylinder_side": {"side", "rim"},
+            "cylinder_cap": {"cap", "rim"}}[kind]
+    assert seen > 100 and want <= branches, (kind, seen, branches)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("frames", [8, 20])
+def test_one_iteration_on_obstacle(kind, frames):
+    sc = scenes.cube_on_obstacle(kind)
+    o = OracleSim(sc)
+    o.step(frames)
+    q_t, q_pred, fc, lam = o.begin_frame()
+    assert fc.c > 0
+    q_k = o.predict(q_t, o.v)
+    qg, lg_, qo, lo, o2, _ = iterate_pair(lgsim.Sim, sc, q_t, o.v, q_k, o.t, fc.node, fc.obst, lam, k=1)
+    assert rel_inf(qg, qo) <= 1e-5, (kind, frames, rel_inf(qg, qo))
+    qg, lg_, qo, lo, o2, _ = iterate_pair(lgsim.Sim, sc, q_t, o.v, q_k, o.t, fc.node, fc.obst, lam, k=1,
+                                          cr="exact", gpu_cr_iters=200)
+    assert rel_inf(qg, qo) <= 1e-5
+    lam_scale = max(np.abs(lo).max(), 1e-3 * o2.mass.sum() * 9.81)
+    gap = rel_inf(lg_, lo, lam_scale)
+    print(f"{kind} frame {frames}: {fc.c} contacts, positions {rel_inf(qg, qo):.2e}, impulses {gap:.2e}")
+    assert gap <= 1e-4, (kind, frames, gap)
