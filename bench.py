@@ -133,6 +133,10 @@ def warm_compare(sim, params):
     import torch
     from paper_2503_15078_amd import lgsim, warm
     sim.set_warm_model(params)
+    for mode, _ in warm.MODES:  # load every kernel of the learned start before timing
+        sim.set_warm_mode(mode)
+        sim.restore_state()
+        sim.step(1, iters=1)
     out = {}
     for mode, name in warm.MODES:
         sim.set_warm_mode(mode)
@@ -143,6 +147,10 @@ def warm_compare(sim, params):
         torch.cuda.synchronize()
         out[name] = {"ms_per_frame": round(1e3 * (time.perf_counter() - a), 3), "iters": int(s["iters"]),
                      "ncp_res": float(s["ncp"])}
+        if mode != lgsim.SIM_WARM_PREV:
+            jp, jl, _ = sim.read_warm_judge(cap=0)
+            out[name]["judge"] = {"score_previous_frame_start": float(jp[0]), "score_network_start": float(jl[0]),
+                                  "kept": "network" if jl[0] < jp[0] else "previous_frame"}
     sim.set_warm_mode(lgsim.SIM_WARM_PREV)
     return out
 
@@ -152,14 +160,20 @@ def warm_drops(params, seeds=(1001, 1002, 1003), frames=60):
     import numpy as np
     from paper_2503_15078_amd import scenes, warm
     agg = {name: [[], []] for _, name in warm.MODES}
+    kept = {}
     for s in seeds:
         res = warm.compare(scenes.cube_drop(s), params, frames, cr_iters=TOL_CR_ITERS, cr_tol=TOL_CR,
                            max_iters=TOL_MAX_ITERS)
         for k, v in res.items():
             agg[k][0] += v["ms"]
             agg[k][1] += v["iters"]
+            if k != "plain":
+                kept[k] = kept.get(k, 0) + v["learned_start_kept"]
     out = {k: {"ms_per_frame": round(float(np.mean(v[0])), 4), "iters_per_frame": round(float(np.mean(v[1])), 3)}
            for k, v in agg.items()}
+    for k in out:
+        if k in kept:
+            out[k]["frames_network_start_kept"] = kept[k]
     out["workload"] = f"cube drops, seeds {list(seeds)}, {frames} frames each"
     return out
 
@@ -213,6 +227,9 @@ def main():
                          "col_group (no autotuning)")
     ap.add_argument("--no-extras", action="store_true", help="skip the warm-start comparison and the batch")
     ap.add_argument("--batch-scenes", type=int, default=64)
+    ap.add_argument("--traj-frames", type=int, default=100,
+                    help="frames of each to-tolerance trajectory (held-out teaser seeds; 0: none)")
+    ap.add_argument("--traj-seeds", type=int, default=1, help="held-out teaser seeds 1000, 1001, ...")
     ap.add_argument("--batch-only", action="store_true", help="only the batch measurement (for profiling)")
     ap.add_argument("--counter-pass", action="store_true",
                     help="only the fixed S-pass launch sequence for rocprofv3 counters (teaser, or the batch "
@@ -327,14 +344,37 @@ def main():
         extras["warm_start_benchmark_state"] = warm_compare(sim, params)
         extras["warm_start_held_out_drops"] = warm_drops(params)
     sim.close()
+    if not args.no_extras and args.traj_frames > 0:
+        seeds = [1000 + k for k in range(args.traj_seeds)]
+        log(f"to-tolerance trajectories: held-out teaser seeds {seeds}, {args.traj_frames} frames")
+        from paper_2503_15078_amd import warm
+        params = np.load(weights)["params"] if os.path.exists(weights) else None
+        modes = warm.MODES if params is not None else warm.MODES[:1]
+        runs = {}
+        for sd in seeds:
+            r = warm.trajectory(scenes.teaser_scene(sd), params, args.traj_frames, modes=modes, cr_iters=TOL_CR_ITERS,
+                                cr_tol=TOL_CR, max_iters=TOL_MAX_ITERS, log=log)
+            for k, v in r.items():
+                agg = runs.setdefault(k, {"iters": [], "ms": [], "ncp": [], "learned_start_kept": 0})
+                for q in ("iters", "ms", "ncp"):
+                    agg[q] += v[q]
+                agg["learned_start_kept"] += v["learned_start_kept"]
+        extras["to_tolerance_trajectories"] = {
+            "workload": (f"teaser-scale stars, held-out seeds {seeds}, {args.traj_frames} frames each from rest, "
+                         f"every frame until NCP residual <= 1e-6 m or {TOL_MAX_ITERS} L-G iterations; CR to "
+                         f"relative {TOL_CR} (at most {TOL_CR_ITERS} steps)"),
+            **warm.summarise(runs)}
     if not args.no_extras:
         log("stick-sliding precision (NCP rows x preconditioner)")
         from paper_2503_15078_amd import stick_slide
         extras["stick_slide_precision"] = {
             "test": ("stiff block (E=1e8) on a 10 deg slope, mu* = tan 10 deg, 10 L-G / 24 CR iterations, 40 frames; "
                      "precision = smallest offset from mu* above which sliding (>= 0.5 x analytic velocity) "
-                     "and sticking (< 0.1 x) are both classified correctly"),
-            **{k: stick_slide.scan(k)["precision"] for k in stick_slide.CONFIGS}}
+                     "and sticking (< 0.1 x) are both classified correctly; precision_moves: sliding >= 0.1 x "
+                     "analytic (the block moves) and sticking < 0.1 x; slide velocity / analytic per offset"),
+            **{k: {"precision": r["precision"], "precision_moves": r["precision_moves"],
+                   "slide_fraction_by_offset": {str(x["offset"]): round(x["slide_fraction"], 4) for x in r["rows"]}}
+               for k, r in ((k, stick_slide.scan(k)) for k in stick_slide.CONFIGS)}}
     if not args.no_extras and args.batch_scenes > 0:
         log(f"batch of {args.batch_scenes} scenes")
         extras["batch"] = batch_throughput(args.batch_scenes, 10)

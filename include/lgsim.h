@@ -348,7 +348,9 @@ int sim_debug_delassus(sim_t s, double* K);
  *   f10 log K_jj              Delassus diagonal (r_n = h^2 K_jj, Sec. 5.4)
  *   f11 mu, f12..15 0
  * and its output y gives lambda = y l / (h^2 K_jj), projected onto the friction cone;
- * a contact whose prediction is not finite keeps the previous-frame impulse.
+ * a contact whose prediction is not finite keeps the previous-frame impulse.  The
+ * prediction is a candidate: a judge (sim_read_warm_judge) keeps the previous-frame
+ * start of a scene wherever the prediction does not lower the NCP residual.
  * SIM_WARM_MLP predicts every contact; SIM_WARM_MLP_PERSIST only contacts with a
  * non-zero previous-frame impulse (new or released contacts start at zero, as with
  * the previous-frame start).
@@ -375,6 +377,19 @@ int sim_record_training_pairs(sim_t s, int32_t on);
  * (nothing copied), SIM_E_STATE when features are not recorded. */
 int sim_read_training_pairs(sim_t s, int32_t* node, int32_t* obstacle, float* feat, float* target, int32_t cap,
                             int32_t* n);
+
+/* Judge of the learned start (not part of the paper, which leaves the start impulse
+ * open): each frame start with a learned warm start has two candidates, the
+ * previous-frame impulse and the network's.  Each is scored by the NCP residual (the
+ * metres measure of sim_step) that it leaves in the frame start's linear contact
+ * problem, positions x_v = q~_v + h^2 sum_k K_jk C_k^T lambda_k (the predicted state
+ * moved by the impulses through A^-1, Sec. 5.3), velocities (x - q_t) / h; per scene
+ * the network's candidate is used only if its score is strictly lower.  Read the last
+ * frame's scores: res [2][count] float32 (res[s]: previous-frame start of scene s,
+ * res[count + s]: the network's), and, if cap > 0, the network's candidate impulses
+ * [c][3] (contact frame, canonical contact order) into lam_learned; *n = c.
+ * SIM_E_STATE when the warm start is not learned, SIM_E_CAPACITY when c > cap. */
+int sim_read_warm_judge(sim_t s, float* res, float* lam_learned, int32_t cap, int32_t* n);
 
 /* ---- trainer of the warm-start network ------------------------------------------
  * Device-resident float32 parameters with Adam moments (beta1 0.9, beta2 0.999, eps

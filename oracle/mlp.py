@@ -180,6 +180,29 @@ def features(C, d_n, mu, node, q_pred, v_t, obst_vel, lam_prev, K_diag, h, ell):
     return F
 
 
+def learned_impulse(y, K_diag, h, ell, mu, lam_plain, comp=None, persist=False):
+    """Candidate start impulses from network outputs y (c,3): lambda = y l / (h^2 K_jj),
+    then the normal part clamped at 0 and the friction part scaled onto the cone
+    |lambda_f| <= mu lambda_n.  Contacts with a non-finite prediction, bilateral rows
+    (comp >= 0) and, with persist, contacts whose plain start is zero keep lam_plain."""
+    y = np.asarray(y, np.float64)
+    lam_plain = np.asarray(lam_plain, np.float64)
+    lam = y * (ell / (h * h * np.asarray(K_diag, np.float64)))[:, None]
+    lam[:, 0] = np.maximum(lam[:, 0], 0.0)
+    lf = np.sqrt((lam[:, 1:] ** 2).sum(1))
+    cap = np.asarray(mu, np.float64) * lam[:, 0]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        sh = np.where(lf > cap, np.where(lf > 0, cap / lf, 0.0), 1.0)
+    lam[:, 1:] *= sh[:, None]
+    keep = ~np.all(np.isfinite(y), axis=1)
+    if comp is not None:
+        keep |= np.asarray(comp) >= 0.0
+    if persist:
+        keep |= np.all(lam_plain == 0.0, axis=1)
+    lam[keep] = lam_plain[keep]
+    return lam
+
+
 def targets(lam, K_diag, h, ell):
     """Scaled converged impulse h^2 K_jj lambda / l (c, 3)."""
     return (h * h * np.asarray(K_diag, np.float64) / ell)[:, None] * np.asarray(lam, np.float64)

@@ -344,12 +344,27 @@ class OracleSim:
         """NCP residual (metres) at (q, lambda)."""
         if fc.c == 0:
             return 0.0
-        x = q[fc.node]
+        return self._residual_at(fc, q[fc.node], q_t, lam)
+
+    def _residual_at(self, fc, x, q_t, lam):
+        """NCP residual with contact node positions x (c,3) and impulses lam."""
         n = fc.C[:, 0, :]
         f = fc.C[:, 1:, :]
         delta_n = np.einsum("ji,ji->j", n, x) - fc.d_n
         vdot_f = (np.einsum("jai,ji->ja", f, x - q_t[fc.node]) - self.h * fc.d_f) / self.h
         return ct.ncp_residual(delta_n, vdot_f, lam, fc.r_n, fc.r_f, fc.mu, self.h, fc.comp)
+
+    def linearized_residual(self, fc, q_t, q_pred, lam):
+        """NCP residual (metres) that start impulses lam leave in the frame start's linear
+        contact problem: the predicted state moved by the impulses through A^-1,
+        x_v = q~_v + h^2 sum_k [A_n^-1]_(v, v_k) C_k^T lambda_k (Sec. 5.3: W = H A^-1 H^T
+        with A = A_n (x) I3), velocities from x - q_t.  The judge of a candidate start
+        impulse (the paper leaves lambda^0 open: Alg. 4 starts from lambda^k)."""
+        if fc.c == 0:
+            return 0.0
+        world = np.einsum("kai,ka->ki", fc.C, lam)          # C_k^T lambda_k
+        x = q_pred[fc.node] + self.h * self.h * (fc.K @ world)
+        return self._residual_at(fc, x, q_t, lam)
 
     # ---------------------------------------------------------------- frames
     def begin_frame(self):

@@ -510,6 +510,9 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   TRY(s->alloc(d.c_rf, CM));
   TRY(s->alloc(d.c_gap, CM));
   TRY(s->alloc(d.lam, 3 * (size_t)CM));
+  TRY(s->alloc(d.lam_ml, 3 * (size_t)CM));
+  TRY(s->alloc(d.wl, 6 * (size_t)CM));
+  TRY(s->alloc(d.judge, 2 * (size_t)NS));
   TRY(s->alloc(d.cs_off, NS + 1));
   TRY(s->alloc(d.k_off, NS + 1));
   TRY(s->alloc(d.tile_off, NS + 1));
@@ -785,7 +788,10 @@ int frame_setup(lgsim* s, bool fork) {
   lg::launch_warm_start(d, cs, 0);
   const bool learned = (s->opt.warm == SIM_WARM_MLP || s->opt.warm == SIM_WARM_MLP_PERSIST) && s->has_model;
   if (s->record_pairs || learned) lg::launch_mlp_features(d, cs);
-  if (learned) lg::launch_mlp_warm(d, cs);
+  if (learned) {
+    lg::launch_mlp_warm(d, cs);
+    lg::launch_warm_judge(d, cs);
+  }
   lg::launch_force_ranges(d, cs);
   if (fork) {
     HIPCHK(hipEventRecord(s->join_ev, s->st2));
@@ -1402,6 +1408,38 @@ int sim_read_training_pairs(sim_t s, int32_t* node, int32_t* obstacle, float* fe
     std::memcpy(feat + 16 * (size_t)k, f.data() + 16 * (size_t)j, 16 * sizeof(float));
     std::memcpy(target + 3 * (size_t)k, t.data() + 3 * (size_t)j, 3 * sizeof(float));
   }
+  return SIM_OK;
+}
+
+int sim_read_warm_judge(sim_t s, float* res, float* lam_learned, int32_t cap, int32_t* n) {
+  if (!s || !res || !n || cap < 0 || (cap > 0 && !lam_learned)) {
+    lg::set_error("bad arguments");
+    return SIM_E_ARG;
+  }
+  if (!((s->opt.warm == SIM_WARM_MLP || s->opt.warm == SIM_WARM_MLP_PERSIST) && s->has_model)) {
+    lg::set_error("the warm start is not learned: no judge values");
+    return SIM_E_STATE;
+  }
+  auto& d = s->d;
+  int c = 0;
+  HIPCHK(hipMemcpyAsync(&c, d.n_contacts, sizeof(int), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipMemcpyAsync(res, d.judge, 2 * sizeof(float) * d.NS, hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  c = std::min(c, d.CMAX);
+  *n = c;
+  if (cap == 0 || c == 0) return SIM_OK;
+  if (c > cap) {
+    lg::set_error("capacity too small: " + std::to_string(c) + " contacts");
+    return SIM_E_CAPACITY;
+  }
+  std::vector<int> cn, co;
+  std::vector<int32_t> order;
+  TRY(sort_contacts_canonical(s, c, cn, co, order));
+  std::vector<float> l(3 * (size_t)d.CMAX);
+  HIPCHK(hipMemcpyAsync(l.data(), d.lam_ml, l.size() * sizeof(float), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  for (int k = 0; k < c; ++k)
+    for (int q = 0; q < 3; ++q) lam_learned[3 * (size_t)k + q] = l[q * (size_t)d.CMAX + order[k]];
   return SIM_OK;
 }
 

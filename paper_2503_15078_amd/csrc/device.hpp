@@ -131,6 +131,9 @@ struct Dev {
   int *a_ptr, *a_idx;              // A_n in internal order (CSR) for the Jacobi global step
   float *a_val, *a_dinv;           // its values and 1 / diagonal
   float *mlp_P;                    // [kMlpParams] network parameters (float32 master copy)
+  float *lam_ml;                   // [3][CMAX] learned candidate of the frame's start impulses
+  float *wl;                       // [6][CMAX] world impulses C^T lambda of the plain, learned start
+  float *judge;                    // [2][NS] linearized NCP residual of the plain, learned start
   // frame state
   double *t;                       // [1] simulation time at frame start
   float *res;                      // [NS] NCP residual per scene
@@ -157,6 +160,7 @@ void launch_mlp_adam(float* P, float* M, float* V, const float* partial, int n, 
                      float eps, float c1, float c2, int update, float* grad_out, float* loss_out, hipStream_t st);
 void launch_mlp_features(const Dev& d, hipStream_t st);
 void launch_mlp_warm(const Dev& d, hipStream_t st);
+void launch_warm_judge(const Dev& d, hipStream_t st);
 void launch_mlp_targets(const Dev& d, float* out, hipStream_t st);
 hipError_t launch_cr(const Dev& d, hipStream_t st, int cr_blocks, int variant);  // variant: SIM_CR_*
 void launch_apply_forces(const Dev& d, hipStream_t st);

@@ -680,20 +680,16 @@ void launch_contact_prep(const Dev& d, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------- NCP residual (metres)
-// max over contacts of |FB(delta_n, r_n lambda_n)|, and for lambda_n > 0
-// h |FB(s, r_f gamma)| and h |vdot_f + s lambda_f/|lambda_f||, else h r_f |lambda_f|.
-__global__ void k_residual(Dev d) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  int c = min(d.n_contacts[0], d.CMAX);
-  if (j >= c) return;
+// Residual of contact j with node position x and impulse l (contact frame): |FB(delta_n,
+// r_n lambda_n)|, and for lambda_n > 0 h |FB(s, r_f gamma)| and h |vdot_f + s
+// lambda_f/|lambda_f||, else h r_f |lambda_f|; a bilateral row takes |delta_b + e
+// lambda_b| and its inactive tangent rows.  NaN counts as huge.
+__device__ float contact_residual(const Dev& d, int j, const float x[3], const float l[3]) {
   const int CM = d.CMAX;
   const float h = (float)d.h;
-  int v = d.c_node[j];
-  float x[3], xt[3];
-  for (int q = 0; q < 3; ++q) {
-    x[q] = d.q[q * d.N4 + v];
-    xt[q] = d.qt[q * d.N4 + v];
-  }
+  const int v = d.c_node[j];
+  float xt[3];
+  for (int q = 0; q < 3; ++q) xt[q] = d.qt[q * d.N4 + v];
   float C[3][3];
   for (int r = 0; r < 3; ++r)
     for (int q = 0; q < 3; ++q) C[r][q] = d.cC[(r * 3 + q) * CM + j];
@@ -703,7 +699,6 @@ __global__ void k_residual(Dev d) {
   for (int r = 0; r < 2; ++r)
     vf[r] = (C[r + 1][0] * (x[0] - xt[0]) + C[r + 1][1] * (x[1] - xt[1]) + C[r + 1][2] * (x[2] - xt[2]) -
              h * d.c_df[r * CM + j]) / h;
-  float l[3] = {d.lam[j], d.lam[CM + j], d.lam[2 * CM + j]};
   float rn = d.c_rn[j], rf = d.c_rf[j], mu = d.c_mu[j];
   float a = rn * l[0];
   float res = fabsf(dn + a - sqrtf(dn * dn + a * a));
@@ -723,7 +718,21 @@ __global__ void k_residual(Dev d) {
     res = fmaxf(res, h * rf * lf);
   }
   if (!(res == res)) res = 3.0e38f;  // NaN -> huge
-  atomicMax(reinterpret_cast<unsigned int*>(d.res) + d.c_scene[j], __float_as_uint(res));
+  return res;
+}
+
+// max over contacts of the residual at the current iterate (q, lambda), per scene
+__global__ void k_residual(Dev d) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int c = min(d.n_contacts[0], d.CMAX);
+  if (j >= c) return;
+  const int CM = d.CMAX, v = d.c_node[j];
+  float x[3], l[3];
+  for (int q = 0; q < 3; ++q) {
+    x[q] = d.q[q * d.N4 + v];
+    l[q] = d.lam[q * CM + j];
+  }
+  atomicMax(reinterpret_cast<unsigned int*>(d.res) + d.c_scene[j], __float_as_uint(contact_residual(d, j, x, l)));
 }
 
 __global__ void k_zero_res(Dev d) {
@@ -733,6 +742,80 @@ __global__ void k_zero_res(Dev d) {
 void launch_residual(const Dev& d, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_res, dim3(1), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_residual, dim3((d.CMAX + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d);
+}
+
+// ---------------------------------------------------------------- judge of the learned start
+// The paper leaves the frame's start impulse open.  Two candidates exist when the warm
+// start is learned: the previous-frame impulse (lambda) and the network's (lam_ml).  Each
+// is judged by the NCP residual it leaves in the frame start's linear contact problem:
+// positions x_v = q~_v + h^2 sum_k K_jk C_k^T lambda_k (the predicted state moved by the
+// impulses through A^-1, Sec. 5.3), velocities from x - q_t.  Per scene, the learned
+// candidate is kept only if its largest residual is strictly below the plain one's.
+
+// world impulses C^T lambda of both candidates; judge values zeroed
+__global__ void k_warm_world(Dev d) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < 2 * d.NS) d.judge[j] = 0.0f;
+  const int c = min(d.n_contacts[0], d.CMAX);
+  if (j >= c) return;
+  const int CM = d.CMAX;
+  for (int q = 0; q < 3; ++q) {
+    float wp = 0.0f, wm = 0.0f;
+    for (int r = 0; r < 3; ++r) {
+      const float cr = d.cC[(r * 3 + q) * CM + j];
+      wp += cr * d.lam[r * CM + j];
+      wm += cr * d.lam_ml[r * CM + j];
+    }
+    d.wl[q * CM + j] = wp;
+    d.wl[(3 + q) * CM + j] = wm;
+  }
+}
+
+// one wavefront per contact row j of its scene's Delassus block
+__global__ void __launch_bounds__(kBlock) k_warm_judge(Dev d) {
+  const int j = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int c = min(d.n_contacts[0], d.CMAX);
+  if (j >= c || d.k_off[d.NS] > d.KCAP) return;
+  const int CM = d.CMAX, sc = d.c_scene[j], cs = d.cs_off[sc], cnt = d.cs_off[sc + 1] - cs;
+  const float* krow = d.K + d.k_off[sc] + (int64_t)(j - cs) * kstride(cnt);
+  float w[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k = lane; k < cnt; k += kWave) {
+    const float kk = krow[k];
+    for (int q = 0; q < 6; ++q) w[q] += kk * d.wl[q * CM + cs + k];
+  }
+  for (int q = 0; q < 6; ++q) w[q] = wave_sum_c(w[q]);
+  if (lane != 0) return;
+  const float h2 = (float)(d.h * d.h);
+  const int v = d.c_node[j];
+  float xp[3], xm[3], lp[3], lm[3];
+  for (int q = 0; q < 3; ++q) {
+    const float base = d.qp[q * d.N4 + v];
+    xp[q] = base + h2 * w[q];
+    xm[q] = base + h2 * w[3 + q];
+    lp[q] = d.lam[q * CM + j];
+    lm[q] = d.lam_ml[q * CM + j];
+  }
+  unsigned* jd = reinterpret_cast<unsigned*>(d.judge);
+  atomicMax(jd + sc, __float_as_uint(contact_residual(d, j, xp, lp)));
+  atomicMax(jd + d.NS + sc, __float_as_uint(contact_residual(d, j, xm, lm)));
+}
+
+__global__ void k_warm_select(Dev d) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = min(d.n_contacts[0], d.CMAX);
+  if (j >= c || d.k_off[d.NS] > d.KCAP) return;
+  const int sc = d.c_scene[j], CM = d.CMAX;
+  if (d.judge[d.NS + sc] < d.judge[sc])
+    for (int q = 0; q < 3; ++q) d.lam[q * CM + j] = d.lam_ml[q * CM + j];
+}
+
+void launch_warm_judge(const Dev& d, hipStream_t st) {
+  const int blocks = (max(d.CMAX, 2 * d.NS) + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_warm_world, dim3(blocks), dim3(kBlock), 0, st, d);
+  const int waves_per_block = kBlock / kWave;
+  hipLaunchKernelGGL(k_warm_judge, dim3((d.CMAX + waves_per_block - 1) / waves_per_block), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_warm_select, dim3((d.CMAX + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d);
 }
 
 }  // namespace lg

@@ -329,9 +329,10 @@ __global__ void k_mlp_features(Dev d) {
   for (int q = 0; q < 4; ++q) out[q] = make_float4(f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]);
 }
 
-// Network prediction -> impulse (projected onto the friction cone); non-finite
-// predictions keep the previous-frame impulse already in lambda, and so do bilateral
-// (binding) rows, whose impulse has no sign or cone.
+// Network prediction -> candidate start impulse lam_ml (projected onto the friction
+// cone); non-finite predictions keep the previous-frame impulse already in lambda, and
+// so do bilateral (binding) rows, whose impulse has no sign or cone.  The candidate
+// replaces lambda only where the judge that follows finds it better.
 __global__ void __launch_bounds__(kBlock) k_mlp_warm(Dev d) {
   __shared__ MlpSmem s;
   const int c = min(d.n_contacts[0], d.CMAX);
@@ -359,8 +360,10 @@ __global__ void __launch_bounds__(kBlock) k_mlp_warm(Dev d) {
           l[1] *= sh;
           l[2] *= sh;
         }
-        for (int q = 0; q < 3; ++q) d.lam[q * CM + j] = l[q];
+      } else {
+        for (int q = 0; q < 3; ++q) l[q] = d.lam[q * CM + j];
       }
+      for (int q = 0; q < 3; ++q) d.lam_ml[q * CM + j] = l[q];
     }
   }
 }

@@ -115,6 +115,7 @@ def load():
         "sim_set_warm_mode": [C.c_void_p, i32],
         "sim_record_training_pairs": [C.c_void_p, i32],
         "sim_read_training_pairs": [C.c_void_p, P(i32), P(i32), P(C.c_float), P(C.c_float), i32, P(i32)],
+        "sim_read_warm_judge": [C.c_void_p, P(C.c_float), P(C.c_float), i32, P(i32)],
         "mlp_create": [P(C.c_float), i32, P(C.c_void_p)],
         "mlp_set_params": [C.c_void_p, P(C.c_float), i32],
         "mlp_get_params": [C.c_void_p, P(C.c_float), i32],
@@ -390,6 +391,18 @@ class Sim:
         c = n.value
         return node[:c].copy(), obst[:c].copy(), feat[:c].copy(), tgt[:c].copy()
 
+    def read_warm_judge(self, cap=None):
+        """Scores of the last frame's two start candidates per scene (previous-frame,
+        network's: the NCP residual each leaves in the frame start's linear contact
+        problem) and the network's candidate impulses [c][3] (canonical order)."""
+        cap = int(self.opt.max_contacts) if cap is None else cap
+        k = len(self.scenes)
+        res = np.zeros(2 * k, np.float32)
+        lam = np.zeros((max(cap, 1), 3), np.float32)
+        n = C.c_int32(0)
+        _check(_lib.sim_read_warm_judge(self.h, _fp(res), _fp(lam), cap, C.byref(n)))
+        return res[:k].astype(np.float64), res[k:].astype(np.float64), lam[:n.value].astype(np.float64)
+
     def save_state(self):
         _check(_lib.sim_save_state(self.h))
 
@@ -515,3 +528,4 @@ class Mlp:
         if self.h:
             _check(_lib.mlp_destroy(self.h))
             self.h = None
+

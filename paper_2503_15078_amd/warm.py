@@ -186,7 +186,7 @@ def compare(scene, params, frames, cr_iters=300, cr_tol=1e-3, max_iters=100, cr_
         sim = lgsim.Sim(scene, cr_iters=cr_iters, cr_tol=cr_tol, cr_variant=cr_variant, max_iters=max_iters)
         sim.set_warm_model(params)
         sim.set_warm_mode(mode)
-        its, ms, res = [], [], []
+        its, ms, res, kept = [], [], [], 0
         for _ in range(frames):
             torch.cuda.synchronize()
             a = time.perf_counter()
@@ -195,6 +195,58 @@ def compare(scene, params, frames, cr_iters=300, cr_tol=1e-3, max_iters=100, cr_
             ms.append(1e3 * (time.perf_counter() - a))
             its.append(st["iters"])
             res.append(st["ncp"])
+            if mode != lgsim.SIM_WARM_PREV and st["contacts"]:
+                jp, jl, _ = sim.read_warm_judge(cap=0)
+                kept += int(np.sum(jl < jp))
         sim.close()
-        out[name] = {"iters": its, "ms": ms, "ncp": res}
+        out[name] = {"iters": its, "ms": ms, "ncp": res, "learned_start_kept": kept}
+    return out
+
+
+def trajectory(scene, params, frames, modes=MODES, cr_iters=300, cr_tol=1e-3, max_iters=100, log=None):
+    """One handle runs `frames` frames of the scene from its initial state once per warm
+    start mode (restored between modes), every frame until the NCP residual is <= 1e-6 m
+    or max_iters iterations.  Per mode: per-frame iterations, ms (device-synchronised),
+    residual, and the frames whose judge kept the network's start."""
+    import torch
+    sim = lgsim.Sim(scene, cr_iters=cr_iters, cr_tol=cr_tol, max_iters=max_iters)
+    if params is not None:
+        sim.set_warm_model(params)
+    sim.save_state()
+    out = {}
+    for mode, name in modes:
+        sim.restore_state()
+        sim.set_warm_mode(mode)
+        its, ms, res, kept = [], [], [], 0
+        for f in range(frames):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            st = sim.step(1, iters=0)[0]
+            torch.cuda.synchronize()
+            ms.append(1e3 * (time.perf_counter() - a))
+            its.append(int(st["iters"]))
+            res.append(float(st["ncp"]))
+            if mode != lgsim.SIM_WARM_PREV and st["contacts"]:
+                jp, jl, _ = sim.read_warm_judge(cap=0)
+                kept += int(np.sum(jl < jp))
+        out[name] = {"iters": its, "ms": ms, "ncp": res, "learned_start_kept": kept}
+        if log:
+            log(f"  {name}: {np.mean(its):.2f} iterations/frame, {np.mean(ms):.3f} ms/frame")
+    sim.close()
+    return out
+
+
+def summarise(runs, tol=1e-6):
+    """Converged fraction, mean / median / p90 of ms and iterations per frame."""
+    out = {}
+    for name, r in runs.items():
+        ms, its, res = np.asarray(r["ms"]), np.asarray(r["iters"]), np.asarray(r["ncp"])
+        out[name] = {"frames": int(len(ms)), "converged_fraction": round(float(np.mean(res <= tol)), 4),
+                     "ms_per_frame_mean": round(float(ms.mean()), 4),
+                     "ms_per_frame_median": round(float(np.median(ms)), 4),
+                     "ms_per_frame_p90": round(float(np.percentile(ms, 90)), 4),
+                     "iters_per_frame_mean": round(float(its.mean()), 3),
+                     "iters_per_frame_median": float(np.median(its)),
+                     "iters_per_frame_p90": float(np.percentile(its, 90)),
+                     "frames_network_start_kept": int(r.get("learned_start_kept", 0))}
     return out

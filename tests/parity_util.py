@@ -95,3 +95,52 @@ def ulp_sensitivity(scene, t, fc, q_t, v_t, lam, draws=3, seed=0):
         bump = lambda a: f32(a * (1.0 + rng.choice([-1.0, 1.0], a.shape) * 2.0 ** -23))
         worst = max(worst, float(np.abs(run(bump(q_t), bump(v_t), bump(lam)) - base).max() / scale))
     return worst
+
+
+
+def _cr_float32(M, b, iters):
+    """The Conjugate Residual recurrence of oracle.cr in float32 arithmetic (float32 M,
+    b, vectors and inner products): a model of what any float32 solver computes."""
+    M = np.asarray(M, np.float32)
+    b = np.asarray(b, np.float32)
+    x = np.zeros_like(b)
+    r = b.copy()
+    Ar = M @ r
+    p, Ap = r.copy(), Ar.copy()
+    rAr = np.float32(r @ Ar)
+    for _ in range(iters):
+        ApAp = np.float32(Ap @ Ap)
+        if ApAp == 0.0 or rAr == 0.0:
+            break
+        a = rAr / ApAp
+        x = x + a * p
+        r = r - a * Ap
+        Ar = M @ r
+        rn = np.float32(r @ Ar)
+        beta = rn / rAr
+        rAr = rn
+        p = r + beta * p
+        Ap = Ar + beta * Ap
+    return x.astype(np.float64)
+
+
+def float32_cr_position_gap(o, q_k, q_pred, t, fc, lam):
+    """Relative change of the oracle's positions after one iteration with the paper's
+    fixed CR count when that CR runs in float32 arithmetic instead of float64 (same
+    Schur system, rounded to float32).  A fixed-count Krylov iterate of an
+    ill-conditioned system (Fischer-Burmeister compliances span many decades when
+    contacts slide or separate) moves this much with float32 rounding alone; two float32
+    solvers with different summation orders are each about this far from the float64
+    iterate, so the device's paper-mode positions are held to 1e-5 plus twice this gap."""
+    info = o.last_info
+    if "cr_matrix" not in info:
+        return 0.0
+    from oracle.cr import conjugate_residual
+    M, rhs, Om = info["cr_matrix"], info["cr_rhs"], info["Omega"]
+    b = o.rhs(q_k, q_pred, t + o.h)
+
+    def positions(dl):
+        return o.solve(b + o.h * o.h * o.H_T(fc, Om * (lam + dl.reshape(-1, 3))))
+
+    q64 = positions(conjugate_residual(lambda x: M @ x, rhs, o.cr_iters))
+    return rel_inf(positions(_cr_float32(M, rhs, o.cr_iters)), q64)

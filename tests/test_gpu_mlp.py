@@ -8,7 +8,7 @@ h2, |W3| (u |h2| + |gelu'(z2)| (|W2| u |h1|)) with u = 2^-8 (two roundings, doub
 bounds the gap to the exact network (the oracle's own pin checks the same bound).
 Gradients are compared with the oracle's form that takes the same bf16 rounding points
 (oracle.mlp.grad_bf16); what remains is float32 summation order and the odd bf16
-rounding that falls the other way, bounded per parameter block by 1e-2 of the block's
+rounding that falls the other way, bounded per parameter block by 1e-3 of the block's
 largest entry."""
 import os
 
@@ -87,7 +87,7 @@ def test_gradient_matches_oracle(n):
         err = np.abs(gd[k] - ref[k]).max() / scale
         print(f"n={n} {k}: rel gap to bf16-point oracle {err:.2e}, "
               f"to exact {np.abs(gd[k] - exact[k]).max() / (np.abs(exact[k]).max() + 1e-30):.2e}")
-        assert err <= 1e-2, (k, err)
+        assert err <= 1e-3, (k, err)
 
 
 def test_adam_step_matches_oracle():
@@ -217,7 +217,7 @@ def test_persisting_mode_leaves_new_contacts_at_the_plain_start():
     """On persisting contacts only, the network predicts nothing for a contact that has no
     previous impulse: a frame whose contacts are all new (the teaser's first contact) runs
     exactly as with the previous-frame warm start, whatever the network; a frame after it,
-    whose contacts persist, does not."""
+    whose contacts persist, takes the network's start where the judge keeps it."""
     sc = scenes.teaser_scene(0)
     runs = []
     for mode in (lgsim.SIM_WARM_PREV, lgsim.SIM_WARM_MLP_PERSIST):
@@ -227,13 +227,21 @@ def test_persisting_mode_leaves_new_contacts_at_the_plain_start():
         st0 = sim.step(1, iters=0)[0]
         first = sim.read_state()
         st1 = sim.step(1, iters=0)[0]
-        runs.append((st0, first, st1, sim.read_state()))
+        judge = sim.read_warm_judge(cap=0) if mode == lgsim.SIM_WARM_MLP_PERSIST else None
+        runs.append((st0, first, st1, sim.read_state(), judge))
         sim.close()
     assert runs[0][0]["contacts"] > 0
     assert runs[0][0]["iters"] == runs[1][0]["iters"]
     np.testing.assert_array_equal(runs[0][1][0], runs[1][1][0])
     np.testing.assert_array_equal(runs[0][1][2]["lam"], runs[1][1][2]["lam"])
-    assert not np.array_equal(runs[0][3][2]["lam"], runs[1][3][2]["lam"])
+    # the second frame's contacts persist: the network's start is used unless the judge
+    # finds it worse than the previous-frame start, and then the frame is the plain one
+    res_p, res_l, _ = runs[1][4]
+    print(f"second frame: judge scores previous-frame {res_p[0]:.3e}, network {res_l[0]:.3e}")
+    if res_l[0] < res_p[0]:
+        assert not np.array_equal(runs[0][3][2]["lam"], runs[1][3][2]["lam"])
+    else:
+        np.testing.assert_array_equal(runs[0][3][2]["lam"], runs[1][3][2]["lam"])
 
 
 def test_learned_start_keeps_previous_impulse_of_bindings():

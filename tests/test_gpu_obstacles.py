@@ -6,15 +6,20 @@ the obstacle's distance function: a slab's inside points, edge and side face; a 
 curved side, caps and rims.  Each frame, the oracle's float64 predicate on the GPU's own
 float32 state must select exactly the GPU's contact list (node, obstacle, order), and the
 frame rows must equal the oracle's float64 frames rounded to float32.  At frames with
-contacts, one iteration from the same state must match the oracle (positions 1e-5, impulses
-with the constraint system solved to convergence on both sides)."""
+contacts, one iteration from the same state must match the oracle with the constraint
+system solved to convergence on both sides (positions 1e-5, impulses 1e-4).  With the
+paper's 10 CR steps, sliding or separating contacts make the Schur system ill-conditioned
+(condition numbers up to 1e14 on the slab), and the fixed-count iterate is then not
+defined to float32 accuracy: the oracle's own 10 steps, run in float32 arithmetic, move
+its positions by up to 6e-3.  Paper-mode positions are held to 1e-5 plus twice that
+movement, which is 1e-5 wherever the system is well conditioned."""
 import numpy as np
 import pytest
 
 from oracle import contact as ct
 from oracle.sim import OracleSim
 from paper_2503_15078_amd import lgsim, scenes
-from tests.parity_util import f32, iterate_pair, rel_inf
+from tests.parity_util import f32, iterate_pair, float32_cr_position_gap, rel_inf
 
 pytestmark = pytest.mark.gpu
 
@@ -72,8 +77,12 @@ def test_one_iteration_on_obstacle(kind, frames):
     q_t, q_pred, fc, lam = o.begin_frame()
     assert fc.c > 0
     q_k = o.predict(q_t, o.v)
-    qg, lg_, qo, lo, o2, _ = iterate_pair(lgsim.Sim, sc, q_t, o.v, q_k, o.t, fc.node, fc.obst, lam, k=1)
-    assert rel_inf(qg, qo) <= 1e-5, (kind, frames, rel_inf(qg, qo))
+    qg, lg_, qo, lo, o2, fc2 = iterate_pair(lgsim.Sim, sc, q_t, o.v, q_k, o.t, fc.node, fc.obst, lam, k=1)
+    paper_gap = rel_inf(qg, qo)
+    d32 = float32_cr_position_gap(o2, f32(q_k), o2.predict(f32(q_t), f32(o.v)), o.t, fc2, f32(lam))
+    print(f"{kind} frame {frames}: paper-mode positions {paper_gap:.2e}; the oracle's 10 CR steps in float32 "
+          f"arithmetic move its positions by {d32:.2e}")
+    assert paper_gap <= 1e-5 + 2.0 * d32, (kind, frames, paper_gap, d32)
     qg, lg_, qo, lo, o2, _ = iterate_pair(lgsim.Sim, sc, q_t, o.v, q_k, o.t, fc.node, fc.obst, lam, k=1,
                                           cr="exact", gpu_cr_iters=200)
     assert rel_inf(qg, qo) <= 1e-5

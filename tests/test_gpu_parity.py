@@ -1,10 +1,10 @@
 """GPU parity of the HIP solver against the FP64 oracle, through the C-ABI.
 
 Tolerances (per iteration, same float32-representable input state on both sides):
-positions ||dq||_inf / ||q_oracle||_inf <= 1e-5; impulses
-||dl||_inf / max(||l_oracle||_inf, 1e-3 m_total |g|) <= max(1e-4, B), where B is the
-first-order float32 rounding bound of the constraint right-hand side propagated through
-the constraint system (tests.parity_util.impulse_rounding_bound).  Contact lists are
+positions ||dq||_inf / ||q_oracle||_inf <= 1e-5; impulses, with the constraint system
+solved to convergence on both sides, ||dl||_inf / max(||l_oracle||_inf, 1e-3 m_total |g|)
+<= 1e-4 (the first-order float32 rounding bound of the constraint right-hand side,
+tests.parity_util.impulse_rounding_bound, is printed beside each gap).  Contact lists are
 compared bit for bit (the oracle evaluates the contact predicate in float64 on the
 GPU's own float32 state)."""
 import numpy as np
@@ -152,8 +152,9 @@ def test_teaser_iteration_with_delassus_rows_from_global_memory():
                                           gpu_cr_iters=1000)
     assert rel_inf(qg, qo) <= 1e-5
     lam_scale = max(np.abs(lo).max(), 1e-3 * o2.mass.sum() * 9.81)
-    bound = max(1e-4, impulse_rounding_bound(o2, lam_scale))
-    assert rel_inf(lg_, lo, lam_scale) <= bound, (rel_inf(lg_, lo, lam_scale), bound)
+    print(f"converged impulse gap {rel_inf(lg_, lo, lam_scale):.2e} (float32 right-hand-side rounding bound "
+          f"{impulse_rounding_bound(o2, lam_scale):.2e})")
+    assert rel_inf(lg_, lo, lam_scale) <= 1e-4, rel_inf(lg_, lo, lam_scale)
 
 
 def test_smallest_mesh_iteration_and_contact_list():
@@ -161,24 +162,29 @@ def test_smallest_mesh_iteration_and_contact_list():
     four bottom contacts fill a quarter of one Delassus tile.  One iteration against the
     oracle's exact solve, and the contact list over 30 frames of the drop bit for bit.
 
-    The cube rests on the plane here, where the iteration map amplifies rounding of the
-    contact state strongly: the oracle's own impulses move by ulp_sensitivity (a few 1e-5)
-    when its float32 inputs move by one ulp.  The device rounds that state to float32
-    several times before the Fischer-Burmeister evaluation (prediction, the S and S^T
-    passes, the path sums, the frame products), so the impulse bound allows 16 such
-    roundings on top of the right-hand-side bound; positions keep 1e-5."""
+    The cube rests on the plane on four sticking contacts.  How the friction is shared
+    among them is nearly indeterminate: the oracle's own per-contact friction impulses
+    move by 2e-5 to 4e-5 of the largest impulse when its float32 inputs move by one ulp,
+    while each normal impulse and the net contact force move by under 1e-5.  So what the
+    state determines is compared (normal impulses per contact and the net impulse in the
+    world frame, 1e-4; positions 1e-5), and the gap of the per-contact friction impulses is
+    printed."""
     sc = scenes.cube_drop(4, nodes=2)
     o, q_t, v_t, t, fc, lam = oracle_state_after(sc, 12)
     assert fc.c == 4
     q_k = o.predict(q_t, v_t)
-    qg, lg_, qo, lo, o2, _ = iterate_pair(make_sim, sc, q_t, v_t, q_k, t, fc.node, fc.obst, lam, k=1,
-                                          cr="exact", gpu_cr_iters=100)
+    qg, lg_, qo, lo, o2, fc2 = iterate_pair(make_sim, sc, q_t, v_t, q_k, t, fc.node, fc.obst, lam, k=1,
+                                            cr="exact", gpu_cr_iters=100)
     assert rel_inf(qg, qo) <= 1e-5
     lam_scale = max(np.abs(lo).max(), 1e-3 * o2.mass.sum() * 9.81)
-    sens = ulp_sensitivity(sc, t, fc, q_t, v_t, lam)
-    bound = max(1e-4, impulse_rounding_bound(o2, lam_scale), 16.0 * sens)
-    print(f"impulse gap {rel_inf(lg_, lo, lam_scale):.2e}, one-ulp sensitivity {sens:.2e}, bound {bound:.2e}")
-    assert rel_inf(lg_, lo, lam_scale) <= bound, (rel_inf(lg_, lo, lam_scale), bound)
+    net = lambda L: np.einsum("kai,ka->i", fc2.C, L)
+    gap_n = rel_inf(lg_[:, 0], lo[:, 0], lam_scale)
+    gap_net = rel_inf(net(lg_), net(lo), lam_scale)
+    gap_f = rel_inf(lg_[:, 1:], lo[:, 1:], lam_scale)
+    print(f"normal impulses {gap_n:.2e}, net impulse {gap_net:.2e}, per-contact friction {gap_f:.2e} "
+          f"(one-ulp sensitivity of the oracle's {ulp_sensitivity(sc, t, fc, q_t, v_t, lam):.2e})")
+    assert gap_n <= 1e-4 and gap_net <= 1e-4, (gap_n, gap_net)
+    assert np.all(lg_[:, 0] > 0.0)
     sim = make_sim(sc)
     od = OracleSim(sc)
     seen = 0
@@ -198,7 +204,11 @@ def test_smallest_mesh_iteration_and_contact_list():
 def test_one_iteration_with_contacts(frames):
     """Positions with the paper's 10 CR iterations on both sides; impulses with the
     constraint system solved to convergence on both sides (a 10-iteration Krylov
-    iterate amplifies float32 rounding; its gap is printed, not bounded)."""
+    iterate amplifies float32 rounding; its gap is printed, not bounded).  Impulses are
+    held to 1e-4, except at frame 12, the first impact: there the two terms of the
+    constraint right-hand side (h - Omega H u) / h^2 cancel 16-fold, the measured gap is
+    1.1e-4, and the bound is the first-order effect of their float32 rounding through
+    |M^-1| (impulse_rounding_bound, 4.5e-4)."""
     sc = scenes.cube_drop(0)
     o, q_t, v_t, t, fc, lam = oracle_state_after(sc, frames)
     assert fc.c > 0
@@ -211,7 +221,9 @@ def test_one_iteration_with_contacts(frames):
                                             cr="exact", gpu_cr_iters=100)
     assert rel_inf(qg, qo) <= 1e-5
     lam_scale = max(np.abs(lo).max(), 1e-3 * o2.mass.sum() * 9.81)
-    bound = max(1e-4, impulse_rounding_bound(o2, lam_scale))
+    print(f"converged impulse gap {rel_inf(lg_, lo, lam_scale):.2e} (float32 right-hand-side rounding bound "
+          f"{impulse_rounding_bound(o2, lam_scale):.2e})")
+    bound = impulse_rounding_bound(o2, lam_scale) if frames == 12 else 1e-4
     assert rel_inf(lg_, lo, lam_scale) <= bound, (rel_inf(lg_, lo, lam_scale), bound)
 
 
@@ -303,8 +315,9 @@ def test_teaser_contacts_and_iteration():
                                             cr="exact", gpu_cr_iters=1000)
     assert rel_inf(qg, qo) <= 1e-5
     lam_scale = max(np.abs(lo).max(), 1e-3 * o2.mass.sum() * 9.81)
-    bound = max(1e-4, impulse_rounding_bound(o2, lam_scale))
-    assert rel_inf(lg_, lo, lam_scale) <= bound, (rel_inf(lg_, lo, lam_scale), bound)
+    print(f"converged impulse gap {rel_inf(lg_, lo, lam_scale):.2e} (float32 right-hand-side rounding bound "
+          f"{impulse_rounding_bound(o2, lam_scale):.2e})")
+    assert rel_inf(lg_, lo, lam_scale) <= 1e-4, rel_inf(lg_, lo, lam_scale)
 
 
 @pytest.mark.parametrize("variant", [0, 1])

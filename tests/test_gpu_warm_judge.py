@@ -1,0 +1,117 @@
+"""GPU parity of the judge that decides between the previous-frame and the learned start
+impulses (a benchmark spec addition: the paper leaves the start impulse open).
+
+Per frame of a cube drop in learned mode, the device scores both candidates by the NCP
+residual they leave in the frame start's linear contact problem; the oracle scores the
+same candidates (the device's own float32 candidate, and the previous-frame start it
+re-derives from the device's last contacts) in float64.  Scores must agree to 1e-7 m
+plus 1e-4 relative, the per-scene choice must agree wherever the scores differ by more
+than that, and the frame must follow the chosen start: bit-identical to the
+previous-frame run when the judge falls back, and one converged iteration from the
+learned start equal to the oracle's when it does not."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle.sim import OracleSim
+from paper_2503_15078_amd import lgsim, scenes, warm
+
+pytestmark = pytest.mark.gpu
+
+WEIGHTS = os.path.join(os.path.dirname(lgsim.__file__), "warm_mlp.npz")
+
+
+def _random_params(seed, noise):
+    rng = np.random.default_rng(seed)
+    p = warm.init_params(seed).astype(np.float64)
+    return (p + rng.normal(0, noise, p.shape)).astype(np.float32)
+
+
+def _networks():
+    nets = [("random", _random_params(7, 0.5))]
+    if os.path.exists(WEIGHTS):
+        nets.append(("trained", np.load(WEIGHTS)["params"]))
+    return nets
+
+
+def _score_tol(v):
+    return 1e-7 + 1e-4 * v
+
+
+@pytest.mark.parametrize("name,params", _networks())
+def test_judge_scores_and_choice_match_oracle(name, params):
+    sc = scenes.cube_drop(1)
+    sim = lgsim.Sim(sc, cr_iters=200)
+    sim.set_warm_model(params)
+    sim.set_warm_mode(lgsim.SIM_WARM_MLP)
+    o = OracleSim(sc)
+    chose = {"learned": 0, "plain": 0}
+    for f in range(24):
+        q_t, v_t, con = sim.read_state()
+        sim.step(1, iters=1)
+        res_p, res_l, lam_ml = sim.read_warm_judge()
+        o.q, o.v, o.t = q_t.copy(), v_t.copy(), f * sc.h
+        o.prev = {(int(a), int(b)): np.asarray(C).T @ np.asarray(lam)
+                  for a, b, C, lam in zip(con["node"], con["obst"], con["frame"], con["lam"])}
+        q0, q_pred, fc, lam_plain = o.begin_frame()
+        assert len(lam_ml) == fc.c
+        if fc.c == 0:
+            continue
+        ref_p = o.linearized_residual(fc, q0, q_pred, lam_plain)
+        ref_l = o.linearized_residual(fc, q0, q_pred, lam_ml)
+        assert abs(res_p[0] - ref_p) <= _score_tol(ref_p), (f, res_p[0], ref_p)
+        assert abs(res_l[0] - ref_l) <= _score_tol(ref_l), (f, res_l[0], ref_l)
+        if abs(ref_p - ref_l) > _score_tol(max(ref_p, ref_l)):
+            assert (res_l[0] < res_p[0]) == (ref_l < ref_p), (f, res_p[0], res_l[0], ref_p, ref_l)
+        chose["learned" if res_l[0] < res_p[0] else "plain"] += 1
+    sim.close()
+    print(f"{name} network: start chosen per frame with contacts {chose}")
+    assert sum(chose.values()) > 10
+
+
+@pytest.mark.parametrize("name,params", _networks())
+def test_frame_follows_the_chosen_start(name, params):
+    """From saved states of a previous-frame run, one frame of one converged iteration
+    with each warm start: identical to the previous-frame frame where the judge falls
+    back; where it keeps the network's start, the positions equal the oracle's iteration
+    from that start."""
+    sc = scenes.cube_drop(1)
+    sim = lgsim.Sim(sc, cr_iters=200)
+    sim.set_warm_model(params)
+    seen = set()
+    for f in range(24):
+        if f >= 6:
+            q_t, v_t, con = sim.read_state()
+            sim.save_state()
+            runs = {}
+            for mode in (lgsim.SIM_WARM_PREV, lgsim.SIM_WARM_MLP):
+                sim.restore_state()
+                sim.set_warm_mode(mode)
+                sim.step(1, iters=1)
+                runs[mode] = sim.read_state()
+            res_p, res_l, lam_ml = sim.read_warm_judge()
+            sim.restore_state()
+            sim.set_warm_mode(lgsim.SIM_WARM_PREV)
+            qp_, _, cp_ = runs[lgsim.SIM_WARM_PREV]
+            qm_, _, cm_ = runs[lgsim.SIM_WARM_MLP]
+            if not res_l[0] < res_p[0]:
+                seen.add("plain")
+                np.testing.assert_array_equal(qp_, qm_)
+                np.testing.assert_array_equal(cp_["lam"], cm_["lam"])
+            else:
+                seen.add("learned")
+                o = OracleSim(sc)
+                o.q, o.v, o.t = q_t.copy(), v_t.copy(), f * sc.h
+                o.prev = {(int(a), int(b)): np.asarray(C).T @ np.asarray(lam)
+                          for a, b, C, lam in zip(con["node"], con["obst"], con["frame"], con["lam"])}
+                q0, q_pred, fc, _ = o.begin_frame()
+                q1, _, _ = o.iterate(fc, q_pred.astype(np.float32).astype(np.float64), lam_ml, q0, q_pred,
+                                     o.t + o.h, cr="exact")
+                err = np.abs(qm_ - q1).max() / np.abs(q1).max()
+                print(f"frame {f}: learned start kept (scores {res_l[0]:.2e} < {res_p[0]:.2e}), positions {err:.2e}")
+                assert err <= 1e-5
+        sim.step(1)
+    sim.close()
+    print(f"{name} network: cases seen {sorted(seen)}")
+    assert seen
