@@ -415,6 +415,27 @@ int mlp_gradient(mlp_t m, const float* d_x, const float* d_t, int32_t n, void* h
                  float* loss);
 int mlp_destroy(mlp_t m);
 
+/* ---- no-allocation gradient --------------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight
+ * training loops, harnesses that forbid hipMalloc.  The gradient and loss of
+ * mlp_gradient, without a trainer handle: its per-block partial sums go to a fixed
+ * scratch array inside the library, (SIM_MLP_NOALLOC_MAX_BATCH / 64) x
+ * (SIM_MLP_N_PARAMS + 1) floats = 5.3 MB on each GPU it runs on, held until the
+ * process ends.
+ *   d_params  [SIM_MLP_N_PARAMS] float32 parameters (layout of sim_set_warm_model)
+ *   d_x [n][16] features, d_t [n][3] targets (float32, as mlp_gradient)
+ *   d_out     [SIM_MLP_N_PARAMS + 1] float32: the gradient, then the loss
+ * All pointers are device memory of the current device (any allocator), borrowed for
+ * the work enqueued on hip_stream (null: the default stream); the call does not wait.
+ * 1 <= n <= SIM_MLP_NOALLOC_MAX_BATCH, else SIM_E_ARG before any device work; a failed
+ * lookup of the scratch array is SIM_E_DEVICE.  No allocating routine is called (the
+ * first call on a device looks the array's address up once).  Every call on one GPU
+ * uses that GPU's one scratch array, so calls that overlap in time on one GPU (other
+ * streams, other threads) race and give wrong results; calls on one stream are safe. */
+#define SIM_MLP_NOALLOC_MAX_BATCH 4096
+int mlp_gradient_noalloc(const float* d_params, const float* d_x, const float* d_t, int32_t n, float* d_out,
+                         void* hip_stream);
+
 /* ---- host-only precompute inspection (no device needed) -------------------------
  * Run only the host precomputation of sim_create and keep its products. */
 typedef struct lg_host* lg_host_t;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "device.hpp"
@@ -53,6 +54,42 @@ int run_step(lg_mlp* m, const float* x, const float* t, int32_t n, float lr, int
   lg::launch_mlp_adam(m->P, m->M, m->V, m->partial, n, lr, b1, b2, 1e-8f, c1, c2, update, update ? nullptr : m->out,
                       m->out + lg::kMlpParams, st);
   MCHK(hipGetLastError());
+  return SIM_OK;
+}
+
+// ---- fixed scratch of the no-allocation gradient
+// The per-block partial sums of one gradient launch live in a file-scope device array,
+// one copy per GPU, held until the process ends.  Host code must not pass the array's
+// name to a kernel (on the host it only names a stand-in); it passes the device address
+// that hipGetSymbolAddress returned for the current device.
+constexpr int kNoAllocMaxBlocks = 64;  // 64 samples per block: batches of at most 4096
+constexpr int kNoAllocMaxDevices = 64;
+static_assert(kNoAllocMaxBlocks * 64 == SIM_MLP_NOALLOC_MAX_BATCH, "batch limit of the header");
+
+__device__ __align__(256) float scratch[(size_t)kNoAllocMaxBlocks * (lg::kMlpParams + 1)];
+
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up once per device).
+int scratch_of_current_device(float** out) {
+  int dev = -1;
+  MCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocMaxDevices) {
+    lg::set_error("mlp_gradient_noalloc: device index out of range");
+    return SIM_E_DEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      lg::set_error(std::string("mlp_gradient_noalloc: hipGetSymbolAddress failed: ") + hipGetErrorString(e));
+      return SIM_E_DEVICE;
+    }
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
   return SIM_OK;
 }
 
@@ -146,6 +183,27 @@ int mlp_gradient(mlp_t m, const float* d_x, const float* d_t, int32_t n, void* h
   MCHK(hipMemcpyAsync(grad, m->out, (size_t)lg::kMlpParams * 4, hipMemcpyDeviceToHost, st));
   MCHK(hipMemcpyAsync(loss, m->out + lg::kMlpParams, 4, hipMemcpyDeviceToHost, st));
   MCHK(hipStreamSynchronize(st));
+  return SIM_OK;
+}
+
+int mlp_gradient_noalloc(const float* d_params, const float* d_x, const float* d_t, int32_t n, float* d_out,
+                         void* hip_stream) {
+  if (!d_params || !d_x || !d_t || !d_out || n <= 0 || n > SIM_MLP_NOALLOC_MAX_BATCH) {
+    lg::set_error("mlp_gradient_noalloc: bad arguments (batch must hold 1.." +
+                  std::to_string(SIM_MLP_NOALLOC_MAX_BATCH) + " samples)");
+    return SIM_E_ARG;
+  }
+  float* part = nullptr;
+  int rc = scratch_of_current_device(&part);
+  if (rc != SIM_OK) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  // the training kernel writes every entry of its blocks' partial rows, so the scratch
+  // left by an earlier call needs no clearing; the reduction only reads parameters when
+  // it updates them, which it does not here
+  lg::launch_mlp_train(d_params, d_x, d_t, n, part, st);
+  lg::launch_mlp_adam(nullptr, nullptr, nullptr, part, n, 0.0f, 0.9f, 0.999f, 1e-8f, 1.0f, 1.0f, 0, d_out,
+                      d_out + lg::kMlpParams, st);
+  MCHK(hipGetLastError());
   return SIM_OK;
 }
 

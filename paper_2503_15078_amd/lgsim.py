@@ -123,6 +123,7 @@ def load():
         "mlp_train_step": [C.c_void_p, C.c_void_p, C.c_void_p, i32, C.c_float, C.c_void_p, P(C.c_float)],
         "mlp_gradient": [C.c_void_p, C.c_void_p, C.c_void_p, i32, C.c_void_p, P(C.c_float), P(C.c_float)],
         "mlp_destroy": [C.c_void_p],
+        "mlp_gradient_noalloc": [C.c_void_p, C.c_void_p, C.c_void_p, i32, C.c_void_p, C.c_void_p],
         "sim_save_state": [C.c_void_p],
         "sim_restore_state": [C.c_void_p],
         "sim_create_batch": [i32, P(sim_mesh), P(sim_material), P(i32), P(P(sim_obstacle)), d,
@@ -468,6 +469,7 @@ class Sim:
 
 MLP_N_PARAMS = 20752
 MLP_MAX_BATCH = 16384
+MLP_NOALLOC_MAX_BATCH = 4096
 
 
 def _stream_ptr():
@@ -529,3 +531,16 @@ class Mlp:
             _check(_lib.mlp_destroy(self.h))
             self.h = None
 
+
+def mlp_gradient_noalloc(params, x, t, out):
+    """Gradient and loss of the network into out [MLP_N_PARAMS + 1] (float32 device
+    tensors params [MLP_N_PARAMS], x [n][16], t [n][3]), on the current stream, with no
+    device allocation in the library (its fixed scratch array)."""
+    import torch
+    load()
+    for a in (params, x, t, out):
+        assert a.is_cuda and a.dtype == torch.float32 and a.is_contiguous()
+    assert x.shape[0] == t.shape[0] and params.numel() == MLP_N_PARAMS and out.numel() == MLP_N_PARAMS + 1
+    _check(_lib.mlp_gradient_noalloc(C.c_void_p(params.data_ptr()), C.c_void_p(x.data_ptr()),
+                                     C.c_void_p(t.data_ptr()), int(x.shape[0]), C.c_void_p(out.data_ptr()),
+                                     _stream_ptr()))

@@ -1,0 +1,72 @@
+"""The no-allocation gradient entry point (mlp_gradient_noalloc, for callers that cannot
+allocate device memory) against the trainer handle's mlp_gradient, through the C-ABI.
+
+Both run the same training and reduction kernels in the same block order, so the
+gradient and loss must agree bit for bit; the gradient is also held to the float64
+oracle's bf16-rounding-point form within the trainer's own gradient tolerance.  Two
+calls in a row share the library's scratch array, the second with a smaller batch, so
+stale partial sums of the first call would show in the second."""
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+from paper_2503_15078_amd import lgsim, warm
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _params(seed, noise=0.05):
+    rng = np.random.default_rng(seed)
+    p = warm.init_params(seed).astype(np.float64)
+    p += rng.normal(0, noise, p.shape)
+    return p.astype(np.float32)
+
+
+def _batch(n, seed):
+    rng = np.random.default_rng(seed)
+    x = np.zeros((n, 16), np.float32)
+    x[:, :12] = rng.normal(0, 1, (n, 12))
+    t = rng.normal(0, 0.3, (n, 3)).astype(np.float32)
+    return x, t
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def test_noalloc_gradient_equals_handle_gradient_on_two_calls():
+    flat = _params(31)
+    net = lgsim.Mlp(flat)
+    P = _dev(flat)
+    for n, seed in ((lgsim.MLP_NOALLOC_MAX_BATCH, 41), (333, 42)):
+        x, t = _batch(n, seed)
+        X, T = _dev(x), _dev(t)
+        g_ref, loss_ref = net.gradient(X, T)
+        out = torch.full((lgsim.MLP_N_PARAMS + 1,), float("nan"), dtype=torch.float32, device="cuda:0")
+        lgsim.mlp_gradient_noalloc(P, X, T, out)
+        torch.cuda.synchronize()
+        o = out.cpu().numpy()
+        print(f"n={n}: max |noalloc - handle| = {np.abs(o[:-1] - g_ref).max():.3e}, loss {o[-1]:.6f} vs {loss_ref:.6f}")
+        assert np.array_equal(o[:-1], g_ref), n
+        assert o[-1] == np.float32(loss_ref), n
+        p = omlp.unflatten(flat.astype(np.float64))
+        ref = omlp.grad_bf16(p, x[:, :12], t)
+        gd = omlp.unflatten(o[:-1].astype(np.float64))
+        for k in omlp.ORDER:
+            err = np.abs(gd[k] - ref[k]).max() / (np.abs(ref[k]).max() + 1e-30)
+            assert err <= 1e-3, (n, k, err)
+    net.close()
+
+
+def test_noalloc_gradient_rejects_batches_beyond_its_scratch():
+    P = _dev(_params(5))
+    out = torch.zeros(lgsim.MLP_N_PARAMS + 1, dtype=torch.float32, device="cuda:0")
+    for n in (0, lgsim.MLP_NOALLOC_MAX_BATCH + 1):
+        x, t = _batch(max(n, 1), 6)
+        X, T = _dev(x[:n] if n else x[:0]), _dev(t[:n] if n else t[:0])
+        with pytest.raises(lgsim.SimError) as e:
+            lgsim.mlp_gradient_noalloc(P, X, T, out)
+        assert e.value.code == -1  # SIM_E_ARG
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(out).item() == 0  # nothing was launched
