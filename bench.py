@@ -35,16 +35,49 @@ ITERS = 5
 TOL_CR, TOL_CR_ITERS, TOL_MAX_ITERS = 1e-3, 300, 100
 
 COUNTER_PASS_LAUNCHES = 20
-# rocprofv3 FETCH_SIZE / WRITE_SIZE over `bench.py --counter-pass` (scaled by a plain copy:
-# FETCH_SIZE x2.0, WRITE_SIZE x1.0) are steady per launch configuration but not credible as
-# HBM bytes for these kernels: most configurations of the 2.0 GB batch pass read 2.1-2.2 GB,
-# yet some read 10-100 MB, and the teaser's 108 MB pass reads 1-3 MB in most
-# configurations and 114 MB in others.  Traffic is therefore not reported.
-TRAFFIC_NOTE = "null: FETCH_SIZE is inconsistent across launch configurations for these kernels"
+# HBM bytes per launch from rocprofv3 counters (FETCH_SIZE + WRITE_SIZE, scaled by a plain
+# copy of known size; profiles/ holds the runs), per kernel and workload, or absent
+# FETCH_SIZE is scaled by 2.0 and WRITE_SIZE by 1.0: on this GPU each TCC->EA read request
+# moves 128 bytes (a plain 256 MiB copy makes 2,097,320 requests) while FETCH_SIZE counts 64,
+# and WRITE_SIZE of the copy equals its bytes (profiles/hbm_counters.md)
+TRAFFIC = {
+    "k_cr<0>, 64 blocks, teaser": 8.38e6,
+    "k_spmv_S (+k_spmv_S_finish), batch": 2.2127e9,
+    "k_spmv_St, batch": 2.2034e9,
+    "k_element (local step), batch": 270.4e6,
+    "k_element (local step), teaser": 12.66e6,
+}
+TRAFFIC_NOTE = ("rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 per launch (profiles/hbm_counters.md); null where the "
+                "launch configuration differs from the counted one")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+CR_STEPS = 10
+# local step: 4 node indices + 9 Dm^-1 entries + 4 material values in, 12 corner forces out;
+# about 1.5 kflop per tet at the least (the SVD's Jacobi sweeps and QR, one Newton step)
+ELEM_BYTES_PER_TET = 4 * (4 + 9 + 4) + 4 * 12
+ELEM_FLOP_PER_TET = 1500.0
+FP32_PEAK_TFLOPS = 157.3
+
+
+def _hbm_entry(kernel, nbytes, ms, note):
+    ach = nbytes / (ms * 1e-3) / 1e9
+    return {"kernel": kernel, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_launch": int(nbytes), "avg_launch_ms": round(ms, 5),
+            "note": note}
+
+
+def _element_entry(kernel, tets, ms):
+    gbs = tets * ELEM_BYTES_PER_TET / (ms * 1e-3) / 1e9
+    tfl = tets * ELEM_FLOP_PER_TET / (ms * 1e-3) / 1e12
+    return {"kernel": kernel, "bound": "alu", "achieved": round(tfl, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tfl / FP32_PEAK_TFLOPS, 4), "hbm_GBps": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "tets": int(tets), "avg_launch_ms": round(ms, 5),
+            "note": (f"{ELEM_BYTES_PER_TET} B and at least {ELEM_FLOP_PER_TET:.0f} flop per tet; one thread per tet "
+                     f"runs the SVD and a Newton solve on the singular values")}
 
 
 def algorithmic_bytes(n, nnz_s):
@@ -71,7 +104,8 @@ def copy_probe(torch, mib=256):
 def counter_pass(sim):
     """Fixed launch sequence for counter collection: for each S-pass configuration (row
     group 1, 2, 4, 8 x segment 1024, 2048, 4096 floats) and then each S^T-pass column group
-    (1, 2, 4, 8), 1 + COUNTER_PASS_LAUNCHES back-to-back launches; then the copy probe."""
+    (1, 2, 4, 8), 1 + COUNTER_PASS_LAUNCHES back-to-back launches; then the local step and
+    the constraint solve; then the copy probes."""
     seq = []
     for rg in (1, 2, 4, 8):
         for seg in (1024, 2048, 4096):
@@ -82,6 +116,12 @@ def counter_pass(sim):
         sim.set_tuning(col_group=cg)
         sim.time_kernel(1, COUNTER_PASS_LAUNCHES)
         seq.append(("St", cg))
+    sim.time_kernel(2, COUNTER_PASS_LAUNCHES)
+    seq.append(("local_step",))
+    for variant in (0, 1):  # both CR forms at the handle's CR grid
+        sim.set_solver(CR_STEPS, 0.0, variant)
+        sim.profile_cr(COUNTER_PASS_LAUNCHES)
+        seq.append(("cr", variant, sim.tuning()["cr_blocks"], "plus zeroing and impulse-restoring copies around each launch"))
     return seq
 
 
@@ -203,12 +243,22 @@ def batch_throughput(count, steps):
     ph = phase_pass(sim, 2)
     n = sum(s.n for s in scs)
     b_s, b_st = algorithmic_bytes(n, nnz)
+    sim.restore_state()
+    sim.step(1, iters=ITERS)
+    k_s, k_st, k_el = sim.time_kernel(0, 20), sim.time_kernel(1, 20), sim.time_kernel(2, 20)
+    m = sum(len(s.tets) for s in scs)
+    rl = [_hbm_entry("k_spmv_S (+k_spmv_S_finish), batch", b_s, k_s, "S (2.0 GB) streams from HBM every launch"),
+          _hbm_entry("k_spmv_St, batch", b_st, k_st, "the column copy of S (2.0 GB) streams from HBM"),
+          _element_entry("k_element (local step), batch", m, k_el)]
+    for e in rl:
+        e["traffic"] = TRAFFIC.get(e["kernel"])
     out = {"metric": "scenes x L-G iterations / s", "value": round(count * ITERS * steps / dt, 1),
            "scenes": count, "nodes": int(n), "tets": int(sum(len(s.tets) for s in scs)), "nnz_S": int(nnz),
            "ms_per_frame": round(1e3 * dt / steps, 3), "create_s": round(t_create, 1), "launch": tune,
            "S_pass_GBps": round(b_s / (ph[2] * 1e-3) / 1e9, 1),
            "St_pass_GBps": round(b_st / (ph[5] * 1e-3) / 1e9, 1),
            "St_pass_frac_of_hbm_peak": round(b_st / (ph[5] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "rooflines": rl,
            "phases_ms_per_launch": [round(float(x), 5) for x in ph]}
     sim.close()
     return out
@@ -309,20 +359,43 @@ def main():
              "integrate", "residual"]
     phase_ms = {k: round(float(v), 5) for k, v in zip(names, per_launch)}
     b_s, b_st = algorithmic_bytes(sc.n, nnz_s)
-    # S-pass kernel durations for the roofline: back-to-back launches between one pair of
-    # HIP events on the solver's stream (per-launch events would add their own overhead)
+    # Kernel durations for the rooflines: the constraint solve (the dominant kernel) with
+    # a pair of HIP events around each launch on the solver's stream, plus its in-kernel
+    # stamps; the S / S^T passes and the local step as back-to-back launches between one
+    # pair of events (per-launch events would add their own overhead to these short ones)
     sim.restore_state()
     sim.step(1, iters=ITERS)
-    k_ms = {"S_pass": sim.time_kernel(0, 100), "St_pass": sim.time_kernel(1, 100)}
-    cand = {"S_pass": (k_ms["S_pass"], b_s), "St_pass": (k_ms["St_pass"], b_st)}
-    dom = max(cand, key=lambda k: cand[k][0])
-    dur_ms, nbytes = cand[dom]
-    achieved = nbytes / (dur_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": {"S_pass": "k_spmv_S (+k_spmv_S_finish)", "St_pass": "k_spmv_St"}[dom],
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "traffic_note": TRAFFIC_NOTE,
-                "bytes_per_launch": int(nbytes), "avg_launch_ms": round(float(dur_ms), 5)}
-
+    crp = sim.profile_cr(20)
+    k_ms = {"S_pass": sim.time_kernel(0, 100), "St_pass": sim.time_kernel(1, 100),
+            "local_step": sim.time_kernel(2, 100)}
+    cr_bytes = CR_STEPS * 4 * contacts * contacts  # K once per CR step, per launch
+    cr_ms = crp["ms_per_launch"]
+    cr_share = ITERS * cr_ms / ms_frame
+    cr_ach = cr_bytes / (cr_ms * 1e-3) / 1e9
+    exch = crp["exchange_us"] * crp["exchanges"]
+    roofline = {
+        "bound": "hbm", "kernel": f"k_cr<{tune.get('cr_variant', 0)}> (constraint solve, {CR_STEPS} CR steps)",
+        "dominant_share_of_frame": round(cr_share, 3),
+        "achieved": round(cr_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(cr_ach / HBM_PEAK_GBS, 4),
+        "traffic": TRAFFIC.get(f"k_cr<{tune.get('cr_variant', 0)}>, {tune.get('cr_blocks')} blocks, teaser"),
+        "traffic_note": TRAFFIC_NOTE,
+        "bytes_per_launch": int(cr_bytes), "avg_launch_ms": round(cr_ms, 5),
+        "note": ("latency-bound: the Delassus rows (4 c^2 B) stay in LDS, so HBM bytes are not what limits it; "
+                 "each CR step needs a device-wide exchange of the step's vectors and inner products"),
+        "per_launch_us": {"kernel": round(crp["kernel_us"], 2), "setup_before_first_exchange": round(crp["setup_us"], 2),
+                          "exchanges": int(crp["exchanges"]), "per_exchange": round(crp["exchange_us"], 3),
+                          "barrier_wait_per_exchange": round(crp["barrier_wait_us"], 3),
+                          "all_exchanges": round(exch, 2),
+                          "compute_rest": round(crp["kernel_us"] - crp["setup_us"] - exch, 2)}}
+    tets_per_launch = sc.m
+    rooflines = [
+        _hbm_entry("k_spmv_S (+k_spmv_S_finish), teaser", b_s, k_ms["S_pass"],
+                   "S (108 MB) stays in the 256 MB infinity cache across launches: not an HBM figure"),
+        _hbm_entry("k_spmv_St, teaser", b_st, k_ms["St_pass"], "infinity-cache resident, as the S pass"),
+        _element_entry("k_element (local step), teaser", tets_per_launch, k_ms["local_step"]),
+    ]
+    for e in rooflines:
+        e["traffic"] = TRAFFIC.get(e["kernel"])
     log("to-tolerance frames")
     # iterate until the NCP residual is <= 1e-6 m; the constraint solve runs CR to a
     # relative residual of TOL_CR (at most TOL_CR_ITERS iterations) instead of 10
@@ -406,6 +479,7 @@ def main():
         "ncp_res_reached": [float(t[2]) for t in tol],
         "paper_context_ms_per_iter": PAPER_MS_PER_ITER,
         "roofline": roofline,
+        "rooflines": rooflines,
     }
     out.update(extras)
     if args.copy_probe:

@@ -103,6 +103,8 @@ typedef struct {
   int32_t precond;         /* SIM_PRECOND_DELASSUS (default) or SIM_PRECOND_MASS */
   int32_t global_step;     /* SIM_GLOBAL_DIRECT (default) or SIM_GLOBAL_JACOBI */
   int32_t lg_form;         /* SIM_LG_PD (default) or SIM_LG_ADMM */
+  int32_t self_contact;    /* 1: vertex-triangle self-contact rows (single-scene handles)  */
+  double self_mu;          /* friction coefficient of the self-contact rows                */
 } sim_options;
 
 /* Forms of the Conjugate Residual iteration; both give the same iterates in exact
@@ -161,6 +163,19 @@ typedef struct {
   double vel[3];
 } sim_obstacle;
 
+/* Surface triangles of a self-contact handle: the faces that belong to exactly one
+ * tet, each oriented with its normal pointing away from its tet's fourth vertex, as
+ * caller node triples [n][3] sorted by their sorted triple; *n = count (SIM_E_CAPACITY
+ * when count > cap, nothing copied; 0 triangles without self contact).
+ * A pair (v, i) of a surface vertex and a triangle that v is not a corner of is a
+ * self contact iff, at q_t and at q~, v projects into the triangle (all barycentric
+ * weights >= 0), its signed distance along the normal at q_t exceeds -margin, v faces the
+ * triangle at q_t (the sum of the cross products of v's surface triangles has a negative
+ * dot product with the triangle's normal) and the smaller of the two distances is below
+ * the margin; evaluated in float64 from the float32 state with the dot products summed
+ * left to right. */
+int sim_surface_triangles(sim_t s, int32_t* tris, int32_t cap, int32_t* n);
+
 /* Per-frame statistics.  ms_phase: 0 frame setup (predict, collision, Delassus,
  * warm start), 1 local step + RHS, 2 S pass, 3 contact evaluation, 4 CR solve,
  * 5 correction + S^T pass, 6 integrate, 7 residual. */
@@ -172,7 +187,12 @@ typedef struct {
 } sim_stats;
 
 /* A contact: caller node id, obstacle index, frame rows (n, f1, f2), impulse
- * (lambda_n, lambda_f1, lambda_f2) in that frame, signed distance at q_t. */
+ * (lambda_n, lambda_f1, lambda_f2) in that frame, signed distance at q_t.
+ * Self-contact rows (sim_options.self_contact; Sec. 6 collision detection: H may couple
+ * degrees of freedom of one object; the row of App. A on the gap between surface vertex
+ * `node` and the point sum_a w_a x_a of surface triangle i, with barycentric weights w
+ * and the triangle's outward normal n, taken at q_t) carry obstacle = -1 - i, i the
+ * index into the list of sim_surface_triangles; their gap is n . (x_v - p) at q_t. */
 typedef struct {
   int32_t node, obstacle;
   double frame[9];
@@ -206,6 +226,17 @@ int sim_set_solver(sim_t s, int32_t cr_iters, double cr_tol, int32_t cr_variant)
  * with the same values; SIM_E_STATE for ADMM-PD handles, whose local step updates the
  * duals).  The state is unchanged. */
 int sim_time_kernel(sim_t s, int32_t which, int32_t reps, float* ms_avg);
+
+/* Measurement of the constraint solve (Sec. 6, CR): `reps` launches (plus one untimed)
+ * of the CR kernel on the current contact state, each from the same impulses and timed
+ * with its own pair of HIP events on the handle's stream; the last one also records
+ * wall-clock stamps of its first block.  out[6]: [0] ms per launch (events), [1] its
+ * in-kernel duration (us), [2] set-up until the first exchange (us), [3] mean exchange
+ * (us per device-wide exchange: publishing, waiting at the barrier, reading the other
+ * blocks' data), [4] mean barrier wait alone (us), [5] exchanges.  Call after a frame or
+ * sim_run_iterations (contacts evaluated); impulses are restored, other state is
+ * unchanged.  Its buffers are allocated on the first call. */
+int sim_profile_cr(sim_t s, int32_t reps, float* out);
 
 /* Frames with a fixed iteration count are recorded once into a hipGraph (frame setup,
  * the iterations, integration: one launch per frame) and replayed; the graph is
@@ -256,7 +287,12 @@ int sim_set_pin_motion(sim_t s, int32_t n_groups, const double* lin_vel, const d
 
 /* Advance `frames` frames (Algorithm 4 outer loop).  iters > 0: that many L-G
  * iterations per frame; iters == 0: iterate until the NCP residual (max-norm, metres)
- * is <= opt.ncp_tol or opt.max_iters is reached.  stats: null or [frames].
+ * is <= opt.ncp_tol or opt.max_iters is reached.  With graphs on (the default), such a
+ * frame runs its iterations in replayed chunks of 4, each iteration followed by the
+ * residual and a convergence check on the device, and the host reads the outcome once per
+ * chunk; iterations after convergence return at once on the device.  With graphs off the
+ * host reads the residual after every iteration (and per-phase times are resolved).
+ * stats: null or [frames].
  * Errors: SIM_E_CAPACITY (contacts beyond max_contacts; frame not advanced),
  * SIM_E_DIVERGED (non-finite state; rolled back), SIM_E_DEVICE. */
 int sim_step(sim_t s, int32_t frames, int32_t iters, sim_stats* stats);

@@ -30,8 +30,9 @@ Readings where the paper is silent:
   tangents as for obstacle rows, d_n = 0 (the gap is n . (x_v - p));
 * canonical order: (vertex id, triangle id).
 
-Parity unpinned: there is no device path for these rows yet; the pins are the invariants
-in tests/test_oracle_selfcontact.py.
+Pinned by the invariants in tests/test_oracle_selfcontact.py (closed-form geometry, a
+hand-placed contact, balance of the pair, brute-force NCP solutions, and the frame loop's
+momentum and non-penetration).
 """
 from __future__ import annotations
 
@@ -59,10 +60,23 @@ def surface_triangles(tets, rest):
     return np.array([keep[k] for k in sorted(count) if count[k] == 1], np.int64).reshape(-1, 3)
 
 
+# Dot products and norms are written out component by component, summed left to right
+# (x0 y0 + x1 y1) + x2 y2, so that their float64 rounding is fixed.
+def _cross(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return np.stack([a[..., 1] * b[..., 2] - a[..., 2] * b[..., 1],
+                     a[..., 2] * b[..., 0] - a[..., 0] * b[..., 2],
+                     a[..., 0] * b[..., 1] - a[..., 1] * b[..., 0]], axis=-1)
+
+
+def _dot(a, b):
+    return (a[..., 0] * b[..., 0] + a[..., 1] * b[..., 1]) + a[..., 2] * b[..., 2]
+
+
 def triangle_frame(xa, xb, xc):
     """Outward unit normal of the triangle (a, b, c) and its area."""
-    nrm = np.cross(xb - xa, xc - xa)
-    area2 = np.linalg.norm(nrm)
+    nrm = _cross(xb - xa, xc - xa)
+    area2 = np.sqrt(_dot(nrm, nrm))
     return nrm / area2, 0.5 * area2
 
 
@@ -70,13 +84,13 @@ def project(x, xa, xb, xc):
     """Barycentric weights (w_a, w_b, w_c) of the orthogonal projection of x onto the
     plane of (a, b, c), and the signed distance of x along the outward normal."""
     n, _ = triangle_frame(xa, xb, xc)
-    dist = float(np.dot(n, x - xa))
+    dist = float(_dot(n, x - xa))
     p = x - dist * n
     # areas of the sub-triangles opposite each corner, signed by the normal
-    wa = np.dot(n, np.cross(xb - p, xc - p))
-    wb = np.dot(n, np.cross(xc - p, xa - p))
-    wc = np.dot(n, np.cross(xa - p, xb - p))
-    tot = wa + wb + wc
+    wa = _dot(n, _cross(xb - p, xc - p))
+    wb = _dot(n, _cross(xc - p, xa - p))
+    wc = _dot(n, _cross(xa - p, xb - p))
+    tot = (wa + wb) + wc
     return np.array([wa, wb, wc]) / tot, dist
 
 
@@ -84,8 +98,8 @@ def vertex_normals(x, tris):
     """Sum over each vertex's surface triangles of their area-weighted outward normals
     (the cross product of two edges), at positions x; zero for non-surface vertices."""
     out = np.zeros_like(np.asarray(x, np.float64))
-    for a, b, c in tris:
-        nrm = np.cross(x[b] - x[a], x[c] - x[a])
+    for a, b, c in tris:  # in triangle order
+        nrm = _cross(x[b] - x[a], x[c] - x[a])
         out[a] += nrm
         out[b] += nrm
         out[c] += nrm
@@ -102,21 +116,21 @@ def detect_self(q_t, q_pred, tris, margin):
     geo = []
     for q in (q_t, q_pred):
         xa, xb, xc = q[tris[:, 0]], q[tris[:, 1]], q[tris[:, 2]]
-        nrm = np.cross(xb - xa, xc - xa)
-        nrm = nrm / np.linalg.norm(nrm, axis=1)[:, None]
+        nrm = _cross(xb - xa, xc - xa)
+        nrm = nrm / np.sqrt(_dot(nrm, nrm))[:, None]
         geo.append((xa, xb, xc, nrm))
     out = []
     for v in verts:
-        keep = ~np.any(tris == v, axis=1) & (geo[0][3] @ vn[v] < 0.0)
+        keep = ~np.any(tris == v, axis=1) & (_dot(geo[0][3], vn[v][None, :]) < 0.0)
         dists = []
         for q, (xa, xb, xc, nrm) in zip((q_t, q_pred), geo):
             x = q[v]
-            dist = np.einsum("ti,ti->t", nrm, x - xa)
+            dist = _dot(nrm, x[None, :] - xa)
             p = x - dist[:, None] * nrm
-            wa = np.einsum("ti,ti->t", nrm, np.cross(xb - p, xc - p))
-            wb = np.einsum("ti,ti->t", nrm, np.cross(xc - p, xa - p))
-            wc = np.einsum("ti,ti->t", nrm, np.cross(xa - p, xb - p))
-            tot = wa + wb + wc
+            wa = _dot(nrm, _cross(xb - p, xc - p))
+            wb = _dot(nrm, _cross(xc - p, xa - p))
+            wc = _dot(nrm, _cross(xa - p, xb - p))
+            tot = (wa + wb) + wc
             keep &= (wa / tot >= 0.0) & (wb / tot >= 0.0) & (wc / tot >= 0.0)
             dists.append(dist)
         keep &= (dists[0] > -margin) & (np.minimum(dists[0], dists[1]) < margin)

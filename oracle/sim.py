@@ -38,6 +38,7 @@ import scipy.sparse.linalg as spla
 
 from . import contact as ct
 from . import fem
+from . import selfcontact as selfc
 from . import material as mat
 from .cr import conjugate_residual
 
@@ -60,10 +61,21 @@ class FrameContacts:
     r_f: np.ndarray
     gap: np.ndarray
     comp: np.ndarray = None  # compliance e of bilateral rows, -1 for unilateral contacts
+    # multi-node rows (self-contact, oracle.selfcontact): per row up to four entries
+    # (node, sign); None when every row has one node with sign +1
+    ent_node: np.ndarray = None   # (c,4)
+    ent_sign: np.ndarray = None   # (c,4)
 
     @property
     def c(self):
         return len(self.node)
+
+    def rows(self, q):
+        """Row points (c,3): the contact node's position, or for a multi-node row the
+        signed sum of its entries, x_v - sum_a w_a x_a (vertex minus triangle point)."""
+        if self.ent_node is None:
+            return q[self.node]
+        return np.einsum("ja,jai->ji", self.ent_sign, q[self.ent_node])
 
 
 class OracleSim:
@@ -116,6 +128,9 @@ class OracleSim:
         self.t = 0.0
         self.prev = {}            # (node, obst) -> world-space impulse
         self.n, self.m = n, m
+        self.self_contact = bool(getattr(scene, "self_contact", False))
+        self.self_mu = float(getattr(scene, "self_mu", 0.0))
+        self.surface = selfc.surface_triangles(self.tets, self.rest) if self.self_contact else np.zeros((0, 3), np.int64)
 
     # ---------------------------------------------------------------- basics
     def solve(self, rhs):
@@ -214,7 +229,23 @@ class OracleSim:
         mu = np.zeros(c)
         gap = np.zeros(c)
         comp = np.full(c, -1.0)
+        ent_node = ent_sign = None
+        if np.any(obst < 0):
+            ent_node = np.repeat(node[:, None], 4, axis=1)
+            ent_sign = np.zeros((c, 4))
+            ent_sign[:, 0] = 1.0
         for j in range(c):
+            if obst[j] < 0:  # self-contact row of vertex node[j] and surface triangle -1 - obst[j]
+                tri = self.surface[-1 - obst[j]]
+                w, dist = selfc.project(q_t[node[j]], q_t[tri[0]], q_t[tri[1]], q_t[tri[2]])
+                nrm, _ = selfc.triangle_frame(q_t[tri[0]], q_t[tri[1]], q_t[tri[2]])
+                f1, f2 = ct.tangent_basis(nrm)
+                C[j] = [nrm, f1, f2]
+                ent_node[j] = [node[j], tri[0], tri[1], tri[2]]
+                ent_sign[j] = [1.0, -w[0], -w[1], -w[2]]
+                mu[j] = self.self_mu
+                gap[j] = dist
+                continue
             ob = self.obstacles[obst[j]]
             if ob.type == ct.BINDING:
                 nrm, f1, f2, d_n[j], gap[j] = ct.binding_frame(ob.geom, q_t[node[j]])
@@ -229,33 +260,49 @@ class OracleSim:
             d_f[j] = [np.dot(f1, ob.vel), np.dot(f2, ob.vel)]
             mu[j] = ob.mu
             gap[j] = d
-        K, W = self.delassus(node, C)
+        K, W = self.delassus(node, C, ent_node, ent_sign)
         Wd = np.diagonal(W)
         if self.precond == "mass":
-            # [H M^-1 H^T]_jj of a unit row at node v is 1 / m_v
-            r_n = self.h * self.h / self.mass[node]
-            r_f = self.h / self.mass[node]
+            # [H M^-1 H^T]_jj of a unit row at node v is 1 / m_v; of a multi-node row,
+            # sum_a s_a^2 / m_(n_a)
+            inv_m = 1.0 / self.mass[node] if ent_node is None else \
+                np.einsum("ja,ja->j", ent_sign * ent_sign, 1.0 / self.mass[ent_node])
+            r_n = self.h * self.h * inv_m
+            r_f = self.h * inv_m
         else:
             r_n = self.h * self.h * Wd[0::3] if c else np.zeros(0)
             r_f = self.h * 0.5 * (Wd[1::3] + Wd[2::3]) if c else np.zeros(0)
-        return FrameContacts(node, obst, C, d_n, d_f, mu, K, W, r_n, r_f, gap, comp)
+        return FrameContacts(node, obst, C, d_n, d_f, mu, K, W, r_n, r_f, gap, comp, ent_node, ent_sign)
 
-    def delassus(self, node, C):
-        """K = B^T A_n^-1 B by multi-RHS solves; W_(j,k) = K_jk C_j C_k^T (A = A_n (x) I3)."""
+    def delassus(self, node, C, ent_node=None, ent_sign=None):
+        """K = B^T A_n^-1 B by multi-RHS solves; W_(j,k) = K_jk C_j C_k^T (A = A_n (x) I3).
+        B has one 1 per contact node, or a multi-node row's signs at its entries."""
         c = len(node)
         if c == 0:
             return np.zeros((0, 0)), np.zeros((0, 0))
         B = np.zeros((self.n, c))
-        B[node, np.arange(c)] = 1.0
+        if ent_node is None:
+            B[node, np.arange(c)] = 1.0
+        else:
+            for a in range(4):
+                np.add.at(B, (ent_node[:, a], np.arange(c)), ent_sign[:, a])
         Z = self.lu.solve(B)
-        K = Z[node, :]
+        K = Z[node, :] if ent_node is None else B.T @ Z
         K = 0.5 * (K + K.T)
         W = np.einsum("jk,jab,kcb->jakc", K, C, C).reshape(3 * c, 3 * c)
         return K, W
 
     def detect(self, q_t, q_pred):
+        """Contact keys in canonical order (node, obstacle); a self-contact row of vertex v
+        and surface triangle i has the key (v, -1 - i)."""
         d = ct.detect(q_t, q_pred, self.obstacles, self.margin)
-        return d["node"], d["obst"]
+        if not self.self_contact:
+            return d["node"], d["obst"]
+        pairs = selfc.detect_self(q_t, q_pred, self.surface, self.margin)
+        node = np.concatenate([np.asarray(d["node"], np.int64), np.array([v for v, _ in pairs], np.int64)])
+        obst = np.concatenate([np.asarray(d["obst"], np.int64), np.array([-1 - t for _, t in pairs], np.int64)])
+        order = np.lexsort((obst, node))
+        return node[order], obst[order]
 
     def warm_start(self, fc):
         lam = np.zeros((fc.c, 3))
@@ -269,8 +316,8 @@ class OracleSim:
     def contact_eval(self, fc, q, q_t, lam):
         """Omega, E, phi and the h vector at (q, lambda) (App. A, App. B, Sec. 5.2)."""
         h = self.h
-        x = q[fc.node]
-        xt = q_t[fc.node]
+        x = fc.rows(q)
+        xt = fc.rows(q_t)
         n = fc.C[:, 0, :]
         f = fc.C[:, 1:, :]
         delta_n = np.einsum("ji,ji->j", n, x) - fc.d_n
@@ -300,11 +347,16 @@ class OracleSim:
     def H_T(self, fc, lam_c):
         """H^T applied to per-contact (c,3) components -> nodal (n,3)."""
         out = np.zeros((self.n, 3))
-        np.add.at(out, fc.node, np.einsum("jai,ja->ji", fc.C, lam_c))
+        world = np.einsum("jai,ja->ji", fc.C, lam_c)
+        if fc.ent_node is None:
+            np.add.at(out, fc.node, world)
+        else:
+            for a in range(4):
+                np.add.at(out, fc.ent_node[:, a], fc.ent_sign[:, a, None] * world)
         return out
 
     def H(self, fc, q):
-        return np.einsum("jai,ji->ja", fc.C, q[fc.node])
+        return np.einsum("jai,ji->ja", fc.C, fc.rows(q))
 
     def iterate(self, fc, q, lam, q_t, q_pred, t_next, cr="fixed", cr_iters=None, cr_tol=0.0):
         """One iteration of Algorithm 4; returns (q^{k+1}, lambda^{k+1}, info)."""
@@ -344,14 +396,14 @@ class OracleSim:
         """NCP residual (metres) at (q, lambda)."""
         if fc.c == 0:
             return 0.0
-        return self._residual_at(fc, q[fc.node], q_t, lam)
+        return self._residual_at(fc, fc.rows(q), q_t, lam)
 
     def _residual_at(self, fc, x, q_t, lam):
         """NCP residual with contact node positions x (c,3) and impulses lam."""
         n = fc.C[:, 0, :]
         f = fc.C[:, 1:, :]
         delta_n = np.einsum("ji,ji->j", n, x) - fc.d_n
-        vdot_f = (np.einsum("jai,ji->ja", f, x - q_t[fc.node]) - self.h * fc.d_f) / self.h
+        vdot_f = (np.einsum("jai,ji->ja", f, x - fc.rows(q_t)) - self.h * fc.d_f) / self.h
         return ct.ncp_residual(delta_n, vdot_f, lam, fc.r_n, fc.r_f, fc.mu, self.h, fc.comp)
 
     def linearized_residual(self, fc, q_t, q_pred, lam):
@@ -363,7 +415,7 @@ class OracleSim:
         if fc.c == 0:
             return 0.0
         world = np.einsum("kai,ka->ki", fc.C, lam)          # C_k^T lambda_k
-        x = q_pred[fc.node] + self.h * self.h * (fc.K @ world)
+        x = fc.rows(q_pred) + self.h * self.h * (fc.K @ world)
         return self._residual_at(fc, x, q_t, lam)
 
     # ---------------------------------------------------------------- frames

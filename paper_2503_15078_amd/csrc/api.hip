@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <array>
+#include <map>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -59,15 +61,21 @@ struct lgsim {
   std::vector<SceneMeta> scenes;
   std::vector<int32_t> iperm_caller;  // internal node -> caller node (global)
   std::vector<int32_t> perm_caller;   // caller node -> internal node (global)
+  std::vector<int32_t> surf_tris;     // [T][3] surface triangles (caller ids) of self contact
   std::vector<lg::ObstacleDev> obst;  // host copy
   std::vector<int> scene_obst0;
   int cr_blocks = 1;
-  int* h_pinned = nullptr;            // [4]: n_contacts, overflow, bad, spare
+  int* h_pinned = nullptr;            // [8]: n_contacts, overflow, bad[2], convergence flag and count
+  int* d_conv = nullptr;              // [2] device convergence flag and iteration count
+  hipGraphExec_t cexec = nullptr;     // chunk of iterations of a frame iterated to tolerance
+  std::vector<unsigned char> ckey;
   float* h_res = nullptr;             // [NS]
   int iter_c = 0;                     // contact count of the current iterate state
   bool has_model = false;             // learned warm-start parameters uploaded
   bool record_pairs = false;          // compute contact features every frame
   float* d_tgt = nullptr;             // [CMAX][3] scratch of sim_read_training_pairs
+  float* d_lam_save = nullptr;        // [3][CMAX] impulses kept across sim_profile_cr
+  unsigned long long* d_clock = nullptr;  // wall-clock stamps of sim_profile_cr
   std::vector<int32_t> iter_canon;    // internal contact index -> canonical position
   hipEvent_t ev[8] = {};
   std::vector<hipEvent_t> fev;        // per-frame timing events
@@ -131,6 +139,7 @@ struct lgsim {
     if (fork_ev) hipEventDestroy(fork_ev);
     if (join_ev) hipEventDestroy(join_ev);
     if (gexec) hipGraphExecDestroy(gexec);
+    if (cexec) hipGraphExecDestroy(cexec);
     for (void* p : allocs) hipFree(p);
     for (auto& e : ev)
       if (e) hipEventDestroy(e);
@@ -270,6 +279,94 @@ int build_segments(lgsim* s, int seg_floats, int row_group) {
 int obstacle_dev(lgsim* s, int k, const sim_obstacle& o, lg::ObstacleDev& od);
 
 // Build one handle from host precomputations of several scenes (concatenated).
+// Boundary triangles of a tet mesh (caller ids): the faces that belong to exactly one
+// tet, oriented with the normal pointing away from the tet's fourth vertex, sorted by
+// their sorted corner triple.
+std::vector<int32_t> surface_triangles(const lg::HostScene& h) {
+  static const int faces[4][4] = {{1, 2, 3, 0}, {0, 3, 2, 1}, {0, 1, 3, 2}, {0, 2, 1, 3}};
+  std::map<std::array<int32_t, 3>, std::pair<int, std::array<int32_t, 3>>> seen;
+  const double* X = h.rest.data();
+  for (int t = 0; t < h.m; ++t) {
+    const int32_t* tv = &h.tets[4 * (size_t)t];
+    for (const auto& f : faces) {
+      std::array<int32_t, 3> tri = {tv[f[0]], tv[f[1]], tv[f[2]]};
+      const int32_t o = tv[f[3]];
+      double e1[3], e2[3], r[3];
+      for (int c = 0; c < 3; ++c) {
+        e1[c] = X[3 * tri[1] + c] - X[3 * tri[0] + c];
+        e2[c] = X[3 * tri[2] + c] - X[3 * tri[0] + c];
+        r[c] = X[3 * o + c] - X[3 * tri[0] + c];
+      }
+      const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                            e1[0] * e2[1] - e1[1] * e2[0]};
+      if (cr[0] * r[0] + cr[1] * r[1] + cr[2] * r[2] > 0.0) std::swap(tri[1], tri[2]);
+      std::array<int32_t, 3> key = tri;
+      std::sort(key.begin(), key.end());
+      auto& e = seen[key];
+      e.first += 1;
+      e.second = tri;
+    }
+  }
+  std::vector<int32_t> out;
+  for (const auto& kv : seen)
+    if (kv.second.first == 1) out.insert(out.end(), kv.second.second.begin(), kv.second.second.end());
+  return out;
+}
+
+// Device tables of self contact: triangles and surface vertices in internal numbering,
+// each vertex's incident triangles (ascending), and the per-frame buffers.
+int build_self_contact(lgsim* s, const lg::HostScene& h) {
+  auto& d = s->d;
+  s->surf_tris = surface_triangles(h);
+  const int T = (int)(s->surf_tris.size() / 3);
+  std::vector<int32_t> verts(s->surf_tris);
+  std::sort(verts.begin(), verts.end());
+  verts.erase(std::unique(verts.begin(), verts.end()), verts.end());
+  const int NSV = (int)verts.size();
+  std::vector<int> tri_v(3 * (size_t)std::max(T, 1), 0), sv(std::max(NSV, 1), 0), vt_ptr(NSV + 1, 0), vt_idx;
+  std::vector<int> slot(h.n, -1);
+  for (int i = 0; i < NSV; ++i) {
+    slot[verts[i]] = i;
+    sv[i] = s->perm_caller[verts[i]];
+  }
+  std::vector<std::vector<int>> inc(NSV);
+  for (int t = 0; t < T; ++t)
+    for (int a = 0; a < 3; ++a) {
+      const int cv = s->surf_tris[3 * (size_t)t + a];
+      tri_v[a * (size_t)T + t] = s->perm_caller[cv];
+      inc[slot[cv]].push_back(t);
+    }
+  for (int i = 0; i < NSV; ++i) {
+    vt_ptr[i + 1] = vt_ptr[i] + (int)inc[i].size();
+    vt_idx.insert(vt_idx.end(), inc[i].begin(), inc[i].end());
+  }
+  if (vt_idx.empty()) vt_idx.push_back(0);
+  d.self_on = 1;
+  d.T = T;
+  d.NSV = NSV;
+  d.self_mu = (float)s->opt.self_mu;
+  const size_t CM = d.CMAX;
+  TRY(s->alloc(d.tri_v, tri_v.size()));
+  TRY(s->alloc(d.sv, sv.size()));
+  TRY(s->alloc(d.vt_ptr, vt_ptr.size()));
+  TRY(s->alloc(d.vt_idx, vt_idx.size()));
+  TRY(s->alloc(d.tri_n, 6 * (size_t)std::max(T, 1)));
+  TRY(s->alloc(d.sv_cnt, std::max(NSV, 1)));
+  TRY(s->alloc(d.n_obst_c, 1));
+  TRY(s->alloc(d.ent_node, 4 * CM));
+  TRY(s->alloc(d.ent_w, 4 * CM));
+  TRY(s->alloc(d.se_node, 4 * CM));
+  TRY(s->alloc(d.se_row, 4 * CM));
+  TRY(s->alloc(d.se_w, 4 * CM));
+  TRY(s->alloc(d.se_count, 1));
+  TRY(s->alloc(d.frange2, 2 * (size_t)d.N));
+  TRY(upload(s, d.tri_v, tri_v.data(), tri_v.size()));
+  TRY(upload(s, d.sv, sv.data(), sv.size()));
+  TRY(upload(s, d.vt_ptr, vt_ptr.data(), vt_ptr.size()));
+  TRY(upload(s, d.vt_idx, vt_idx.data(), vt_idx.size()));
+  return SIM_OK;
+}
+
 int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vector<sim_obstacle>>& obs) {
   auto& d = s->d;
   const int NS = (int)hs.size();
@@ -531,6 +628,7 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   TRY(s->alloc(d.t, 1));
   TRY(s->alloc(d.res, NS));
   TRY(s->alloc(d.bad, 4));
+  TRY(s->alloc(s->d_conv, 2));
 
   // ---- upload constants
   std::vector<float> row_val((size_t)row_ptr[N], 0.0f), col_val((size_t)col_ptr[N]);
@@ -683,9 +781,10 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
     lg::set_error("max_contacts too large for the CR launch");
     return SIM_E_ARG;
   }
-  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&s->h_pinned), 4 * sizeof(int), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&s->h_pinned), 8 * sizeof(int), hipHostMallocDefault));
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&s->h_res), std::max(1, NS) * sizeof(float), hipHostMallocDefault));
   for (auto& e : s->ev) HIPCHK(hipEventCreate(&e));
+  if (s->opt.self_contact) TRY(build_self_contact(s, hs[0]));
   return SIM_OK;
 }
 
@@ -1017,8 +1116,17 @@ int create_common(int32_t count, const sim_mesh* meshes, const sim_material* mat
       (s->opt.ncp != SIM_NCP_FB && s->opt.ncp != SIM_NCP_MINMAP) ||
       (s->opt.precond != SIM_PRECOND_DELASSUS && s->opt.precond != SIM_PRECOND_MASS) ||
       (s->opt.global_step != SIM_GLOBAL_DIRECT && s->opt.global_step != SIM_GLOBAL_JACOBI) ||
-      (s->opt.lg_form != SIM_LG_PD && s->opt.lg_form != SIM_LG_ADMM)) {
+      (s->opt.lg_form != SIM_LG_PD && s->opt.lg_form != SIM_LG_ADMM) ||
+      (s->opt.self_contact != 0 && s->opt.self_contact != 1) || !(s->opt.self_mu >= 0.0)) {
     lg::set_error("bad options");
+    return fail(SIM_E_ARG);
+  }
+  if (s->opt.self_contact && count != 1) {
+    lg::set_error("self contact is available for single-scene handles");
+    return fail(SIM_E_ARG);
+  }
+  if (s->opt.self_contact && s->opt.global_step != SIM_GLOBAL_DIRECT) {
+    lg::set_error("self contact needs the direct global step");
     return fail(SIM_E_ARG);
   }
   int dev = 0;
@@ -1192,6 +1300,65 @@ int sim_time_kernel(sim_t s, int32_t which, int32_t reps, float* ms_avg) {
   hipEventDestroy(e1);
   TRY(check_launch("timed kernel"));
   *ms_avg = ms / reps;
+  return SIM_OK;
+}
+
+int sim_profile_cr(sim_t s, int32_t reps, float* out) {
+  if (!s || reps <= 0 || !out) {
+    lg::set_error("bad arguments");
+    return SIM_E_ARG;
+  }
+  auto& d = s->d;
+  const size_t ncl = 2 + 3 * (size_t)lg::kCrMaxBarriers;
+  if (!s->d_lam_save) TRY(s->alloc(s->d_lam_save, 3 * (size_t)d.CMAX));
+  if (!s->d_clock) TRY(s->alloc(s->d_clock, ncl));
+  const size_t lam_bytes = 3 * (size_t)d.CMAX * sizeof(float);
+  HIPCHK(hipMemcpyAsync(s->d_lam_save, d.lam, lam_bytes, hipMemcpyDeviceToDevice, s->st));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float total = 0.0f;
+  hipError_t cr_err = hipSuccess;
+  lg::Dev dc = d;
+  dc.cr_clock = s->d_clock;
+  for (int r = 0; r <= reps && cr_err == hipSuccess; ++r) {  // launch 0 warms up, the last one is stamped
+    HIPCHK(hipMemcpyAsync(d.lam, s->d_lam_save, lam_bytes, hipMemcpyDeviceToDevice, s->st));
+    lg::launch_zero_cr_sync(d, s->st);
+    if (r == reps) HIPCHK(hipMemsetAsync(s->d_clock, 0, ncl * sizeof(unsigned long long), s->st));
+    HIPCHK(hipEventRecord(e0, s->st));
+    cr_err = lg::launch_cr(r == reps ? dc : d, s->st, s->cr_blocks, s->opt.cr_variant);
+    HIPCHK(hipEventRecord(e1, s->st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (r > 0) total += ms;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  HIPCHK(cr_err);
+  HIPCHK(hipMemcpyAsync(d.lam, s->d_lam_save, lam_bytes, hipMemcpyDeviceToDevice, s->st));
+  std::vector<unsigned long long> clk(ncl);
+  HIPCHK(hipMemcpyAsync(clk.data(), s->d_clock, ncl * sizeof(unsigned long long), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  TRY(frame_status(s));
+  int dev = 0, khz = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  const double us = khz > 0 ? 1e3 / khz : 0.0;  // microseconds per tick
+  int nb = 0;
+  double exch = 0.0, wait = 0.0;
+  while (nb < lg::kCrMaxBarriers && clk[2 + 3 * nb] != 0) {
+    const unsigned long long t_in = clk[2 + 3 * nb], t_out = clk[3 + 3 * nb], t_data = clk[4 + 3 * nb];
+    wait += (double)(t_out - t_in) * us;
+    exch += (double)((t_data ? t_data : t_out) - t_in) * us;
+    ++nb;
+  }
+  out[0] = total / reps;
+  out[1] = (float)((double)(clk[1] - clk[0]) * us);
+  out[2] = nb ? (float)((double)(clk[2] - clk[0]) * us) : 0.0f;
+  out[3] = nb ? (float)(exch / nb) : 0.0f;
+  out[4] = nb ? (float)(wait / nb) : 0.0f;
+  out[5] = (float)nb;
   return SIM_OK;
 }
 
@@ -1443,6 +1610,22 @@ int sim_read_warm_judge(sim_t s, float* res, float* lam_learned, int32_t cap, in
   return SIM_OK;
 }
 
+int sim_surface_triangles(sim_t s, int32_t* tris, int32_t cap, int32_t* n) {
+  if (!s || !n || cap < 0 || (cap > 0 && !tris)) {
+    lg::set_error("bad arguments");
+    return SIM_E_ARG;
+  }
+  const int T = (int)(s->surf_tris.size() / 3);
+  *n = T;
+  if (cap == 0) return SIM_OK;
+  if (T > cap) {
+    lg::set_error("capacity too small: " + std::to_string(T) + " triangles");
+    return SIM_E_CAPACITY;
+  }
+  std::copy(s->surf_tris.begin(), s->surf_tris.end(), tris);
+  return SIM_OK;
+}
+
 int sim_set_pin_motion(sim_t s, int32_t n_groups, const double* lin, const double* ang, const double* pivot) {
   if (!s || n_groups < 0 || (n_groups > 0 && (!lin || !ang || !pivot))) {
     lg::set_error("bad pin motion arguments");
@@ -1509,6 +1692,77 @@ int frame_by_graph(lgsim* s, int iters) {
   return SIM_OK;
 }
 
+// Frames iterated to tolerance run their iterations in chunks of kTolChunk, each
+// iteration followed by the NCP residual and a convergence check on the device; a chunk is
+// replayed from a hipGraph and the host reads the convergence flag once per chunk instead
+// of the residual after every iteration.  Iterations after convergence return at once.
+constexpr int kTolChunk = 4;
+
+// Points the device descriptor at the convergence flag for the duration of a frame.
+struct ConvergenceScope {
+  lgsim* s;
+  explicit ConvergenceScope(lgsim* s_) : s(s_) {
+    s->d.done = s->d_conv;
+    s->d.iter_count = s->d_conv + 1;
+    s->d.ncp_tol = (float)s->opt.ncp_tol;
+    s->d.max_iters = s->opt.max_iters;
+  }
+  ~ConvergenceScope() {
+    s->d.done = nullptr;
+    s->d.iter_count = nullptr;
+  }
+};
+
+int tolerance_chunk(lgsim* s) {
+  std::vector<unsigned char> key(sizeof(lg::Dev) + 6 * sizeof(int));
+  std::memcpy(key.data(), &s->d, sizeof(lg::Dev));
+  const int extra[6] = {kTolChunk, s->cr_blocks, s->opt.cr_variant, s->seg_floats, s->d.elem_block, 1};
+  std::memcpy(key.data() + sizeof(lg::Dev), extra, sizeof(extra));
+  if (!s->cexec || key != s->ckey) {
+    if (s->cexec) {
+      HIPCHK(hipGraphExecDestroy(s->cexec));
+      s->cexec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal));
+    int rc = SIM_OK;
+    for (int k = 0; rc == SIM_OK && k < kTolChunk; ++k) {
+      rc = iteration(s, false, k);
+      if (rc == SIM_OK) {
+        lg::launch_residual(s->d, s->st);
+        lg::launch_convergence_check(s->d, s->st);
+      }
+    }
+    hipError_t e = hipStreamEndCapture(s->st, &g);
+    if (rc != SIM_OK) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    HIPCHK(e);
+    e = hipGraphInstantiate(&s->cexec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    HIPCHK(e);
+    s->ckey = key;
+  }
+  HIPCHK(hipGraphLaunch(s->cexec, s->st));
+  return SIM_OK;
+}
+
+// Iterations of one frame until every scene's NCP residual is within ncp_tol, or
+// max_iters, or a failure flag; *k = iterations run.  The set-up ran on the one stream.
+int iterate_to_tolerance(lgsim* s, int* k) {
+  ConvergenceScope scope(s);
+  lg::launch_reset_convergence(s->d, s->st);
+  while (true) {
+    TRY(tolerance_chunk(s));
+    HIPCHK(hipMemcpyAsync(s->h_pinned + 4, s->d_conv, 2 * sizeof(int), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    if (s->h_pinned[4] || s->h_pinned[5] >= s->opt.max_iters) break;
+  }
+  *k = s->h_pinned[5];
+  return SIM_OK;
+}
+
 }  // namespace
 
 int sim_step(sim_t s, int32_t frames, int32_t iters, sim_stats* stats) {
@@ -1542,6 +1796,27 @@ int sim_step(sim_t s, int32_t frames, int32_t iters, sim_stats* stats) {
         for (int q = 0; q < s->d.NS; ++q) res = std::max(res, (double)s->h_res[q]);
         auto& st = stats[f];
         st.iters_done = iters;
+        st.n_contacts = s->iter_c;
+        st.ncp_res = res;
+        st.ms_frame = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        for (int q = 0; q < 8; ++q) st.ms_phase[q] = 0.0f;  // not resolved inside a graph
+      }
+      continue;
+    }
+    if (iters == 0 && s->opt.graph) {  // to tolerance, in replayed chunks
+      TRY(frame_setup(s, false));
+      int k = 0;
+      TRY(iterate_to_tolerance(s, &k));
+      TRY(finish_frame(s));
+      int rc = frame_status(s);
+      if (rc != SIM_OK) return rc;
+      if (timed) {
+        HIPCHK(hipMemcpyAsync(s->h_res, s->d.res, sizeof(float) * s->d.NS, hipMemcpyDeviceToHost, s->st));
+        HIPCHK(hipStreamSynchronize(s->st));
+        double res = 0.0;
+        for (int q = 0; q < s->d.NS; ++q) res = std::max(res, (double)s->h_res[q]);
+        auto& st = stats[f];
+        st.iters_done = k;
         st.n_contacts = s->iter_c;
         st.ncp_res = res;
         st.ms_frame = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -1630,8 +1905,7 @@ int sim_read_state(sim_t s, double* xyz, double* vel, sim_contact* contacts, int
       int j = order[k];
       auto& o = contacts[k];
       o.node = s->iperm_caller[node[j]];
-      int sc = s->obst[obst[j]].scene;
-      o.obstacle = obst[j] - s->scene_obst0[sc];
+      o.obstacle = obst[j] < 0 ? obst[j] : obst[j] - s->scene_obst0[s->obst[obst[j]].scene];
       for (int q = 0; q < 9; ++q) o.frame[q] = C[(size_t)q * CM + j];
       for (int q = 0; q < 3; ++q) o.lambda[q] = lam[(size_t)q * CM + j];
       o.gap = gap[j];
@@ -1677,7 +1951,7 @@ int sim_save_state(sim_t s) {
   HIPCHK(hipMemcpyAsync(b.qt, d.qt, NV * sizeof(float), hipMemcpyDeviceToDevice, s->st));
   HIPCHK(hipMemcpyAsync(b.vt, d.vt, NV * sizeof(float), hipMemcpyDeviceToDevice, s->st));
   HIPCHK(hipMemcpyAsync(b.t, d.t, sizeof(double), hipMemcpyDeviceToDevice, s->st));
-  HIPCHK(hipMemcpyAsync(b.pc_count, d.pc_count, sizeof(int), hipMemcpyDeviceToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(b.pc_count, d.pc_count, 2 * sizeof(int), hipMemcpyDeviceToDevice, s->st));
   HIPCHK(hipMemcpyAsync(b.pc_node, d.pc_node, CM * sizeof(int), hipMemcpyDeviceToDevice, s->st));
   HIPCHK(hipMemcpyAsync(b.pc_obst, d.pc_obst, CM * sizeof(int), hipMemcpyDeviceToDevice, s->st));
   HIPCHK(hipMemcpyAsync(b.pc_world, d.pc_world, 3 * CM * sizeof(float), hipMemcpyDeviceToDevice, s->st));
@@ -1696,7 +1970,7 @@ int sim_restore_state(sim_t s) {
   HIPCHK(hipMemcpyAsync(d.qt, b.qt, NV * sizeof(float), hipMemcpyDeviceToDevice, s->st));
   HIPCHK(hipMemcpyAsync(d.vt, b.vt, NV * sizeof(float), hipMemcpyDeviceToDevice, s->st));
   HIPCHK(hipMemcpyAsync(d.t, b.t, sizeof(double), hipMemcpyDeviceToDevice, s->st));
-  HIPCHK(hipMemcpyAsync(d.pc_count, b.pc_count, sizeof(int), hipMemcpyDeviceToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(d.pc_count, b.pc_count, 2 * sizeof(int), hipMemcpyDeviceToDevice, s->st));
   HIPCHK(hipMemcpyAsync(d.pc_node, b.pc_node, CM * sizeof(int), hipMemcpyDeviceToDevice, s->st));
   HIPCHK(hipMemcpyAsync(d.pc_obst, b.pc_obst, CM * sizeof(int), hipMemcpyDeviceToDevice, s->st));
   HIPCHK(hipMemcpyAsync(d.pc_world, b.pc_world, 3 * CM * sizeof(float), hipMemcpyDeviceToDevice, s->st));
@@ -1734,14 +2008,20 @@ int sim_set_iterate_state(sim_t s, const double* q_t, const double* v_t, const d
   // contact list into internal order (internal node, obstacle)
   std::vector<int> order(c);
   std::iota(order.begin(), order.end(), 0);
+  const int T = d.self_on ? d.T : 0;
+  int n_self = 0;
   for (int k = 0; k < c; ++k) {
-    if (contacts[k].node < 0 || contacts[k].node >= d.N || contacts[k].obstacle < 0 ||
-        contacts[k].obstacle >= (int)s->obst.size()) {
+    const int o = contacts[k].obstacle;
+    if (contacts[k].node < 0 || contacts[k].node >= d.N || o >= (int)s->obst.size() || o < -T) {
       lg::set_error("bad contact entry");
       return SIM_E_ARG;
     }
+    n_self += o < 0;
   }
+  // single-node contacts in (internal node, obstacle) order, then the self rows
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const bool sa = contacts[a].obstacle < 0, sb = contacts[b].obstacle < 0;
+    if (sa != sb) return sb;
     int na = s->perm_caller[contacts[a].node], nb = s->perm_caller[contacts[b].node];
     if (na != nb) return na < nb;
     return contacts[a].obstacle < contacts[b].obstacle;
@@ -1758,6 +2038,10 @@ int sim_set_iterate_state(sim_t s, const double* q_t, const double* v_t, const d
   }
   int cc[2] = {c, 0};
   TRY(upload(s, d.n_contacts, cc, 1));
+  if (d.self_on) {
+    const int c_obst = c - n_self;
+    TRY(upload(s, d.n_obst_c, &c_obst, 1));
+  }
   TRY(upload(s, d.c_node, node.data(), c));
   TRY(upload(s, d.c_obst, obst.data(), c));
   TRY(upload(s, d.c_scene, scene.data(), c));

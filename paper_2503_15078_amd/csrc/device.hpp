@@ -122,6 +122,7 @@ struct Dev {
   float *cr_Z;                     // [2][2][3][CMAX] exchanged C^T (Omega v) of the CR launch
   float *cr_prod;                  // per-(block, scene slot) partial sums of the CR launch
   unsigned *cr_sync;               // [kCrMaxBarriers + 1] arrival counters of the CR launch
+  unsigned long long *cr_clock;    // null, or [2 + 3 kCrMaxBarriers] wall-clock stamps of CR block 0
   float cr_tol;                    // relative CR residual tolerance (0: fixed count)
   // learned warm start
   double *ell;                     // [NS] mean rest edge length per scene
@@ -134,16 +135,51 @@ struct Dev {
   float *lam_ml;                   // [3][CMAX] learned candidate of the frame's start impulses
   float *wl;                       // [6][CMAX] world impulses C^T lambda of the plain, learned start
   float *judge;                    // [2][NS] linearized NCP residual of the plain, learned start
+  // self contact (single-scene handles): vertex-triangle rows with four entries each,
+  // stored after the obstacle contacts, which keep their node order
+  int self_on;
+  int T, NSV;                      // surface triangles, surface vertices
+  int *tri_v;                      // [3][T] corners (internal ids), normal outward
+  int *sv;                         // [NSV] surface vertices (internal ids) by caller id
+  int *vt_ptr, *vt_idx;            // [NSV+1] incident triangles of each surface vertex, ascending
+  double *tri_n;                   // [2][3][T] unit normals at q_t and q~ (per frame)
+  int *sv_cnt;                     // [NSV] self contacts per surface vertex, then offsets
+  float self_mu;
+  int *n_obst_c;                   // [1] contacts from obstacles (the first rows)
+  int *ent_node;                   // [4][CMAX] entries of the self rows (internal ids)
+  double *ent_w;                   // [4][CMAX] their signs (1, -w_a, -w_b, -w_c)
+  int *se_node, *se_row;           // [4 CMAX] self entries sorted by (node, row, corner)
+  float *se_w;                     // their signs
+  int *se_count;                   // [1]
+  int *frange2;                    // [2][N] per-row range of the sorted self entries
+  // frames iterated to tolerance: the iterations run in chunks replayed without a host
+  // round trip; done[0] is set once the frame has converged (or hit max_iters, or failed)
+  // and every iteration kernel then returns at once.  Null outside such frames.
+  int *done;                       // [1]
+  int *iter_count;                 // [1] iterations run in the current frame
+  float ncp_tol;                   // NCP residual tolerance (metres)
+  int max_iters;                   // iteration cap of such frames
   // frame state
   double *t;                       // [1] simulation time at frame start
   float *res;                      // [NS] NCP residual per scene
   int *bad;                        // [0] frame invalid (non-finite state or [1]); [1] CR barrier abandoned
 };
 
+// End of the single-node (obstacle) contacts of scene s: self-contact rows follow them.
+__device__ inline int obst_end(const Dev& d, int s) {
+  return d.self_on ? min(d.n_obst_c[0], d.cs_off[s + 1]) : d.cs_off[s + 1];
+}
+
+// True in a frame iterated to tolerance once it has converged (uniform across the grid).
+__device__ inline bool frame_done(const Dev& d) {
+  return d.done != nullptr && __builtin_amdgcn_readfirstlane(*d.done) != 0;
+}
+
 // kernels (launch helpers live in the .hip files)
 void launch_predict(const Dev& d, hipStream_t st);
 void launch_pins(const Dev& d, hipStream_t st);
 void launch_collide(const Dev& d, hipStream_t st);
+void launch_self_entries(const Dev& d, hipStream_t st);
 void launch_frames_for_list(const Dev& d, hipStream_t st);
 void launch_delassus(const Dev& d, hipStream_t st);
 void launch_warm_start(const Dev& d, hipStream_t st, int keep_lambda);
@@ -163,12 +199,15 @@ void launch_mlp_warm(const Dev& d, hipStream_t st);
 void launch_warm_judge(const Dev& d, hipStream_t st);
 void launch_mlp_targets(const Dev& d, float* out, hipStream_t st);
 hipError_t launch_cr(const Dev& d, hipStream_t st, int cr_blocks, int variant);  // variant: SIM_CR_*
+void launch_zero_cr_sync(const Dev& d, hipStream_t st);
 void launch_apply_forces(const Dev& d, hipStream_t st);
 void launch_jacobi_global(const Dev& d, hipStream_t st);
 int lg_energy_blocks(const Dev& d);
 void launch_lg_energy(const Dev& d, hipStream_t st, double* part);
 void launch_force_ranges(const Dev& d, hipStream_t st);
 void launch_residual(const Dev& d, hipStream_t st);
+void launch_reset_convergence(const Dev& d, hipStream_t st);
+void launch_convergence_check(const Dev& d, hipStream_t st);
 void launch_integrate(const Dev& d, hipStream_t st);
 void launch_check_finite(const Dev& d, hipStream_t st);
 void launch_export_positions(const Dev& d, hipStream_t st, float* out);

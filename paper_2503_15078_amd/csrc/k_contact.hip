@@ -10,6 +10,11 @@
 
 namespace lg {
 
+__device__ inline float wave_sum_c(float v) {
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
 // ---------------------------------------------------------------- float64 geometry
 // Signed distance and outward normal of an obstacle, in float64, with the operation
 // order fixed and no contraction, so that contact decisions are reproducible bit for
@@ -266,7 +271,7 @@ __global__ void k_scene_offsets(Dev d) {
       d.tile_off[s] = toff;
       int cs = d.cs_off[s + 1] - d.cs_off[s];
       koff += (int64_t)cs * kstride(cs);
-      int T = (cs + kDelTile - 1) / kDelTile;
+      int T = (obst_end(d, s) - d.cs_off[s] + kDelTile - 1) / kDelTile;  // tiles: single-node contacts
       toff += T * (T + 1) / 2;
     }
     d.k_off[d.NS] = koff;
@@ -275,11 +280,252 @@ __global__ void k_scene_offsets(Dev d) {
   }
 }
 
+// ---------------------------------------------------------------- self contact
+// Vertex-triangle rows (Sec. 6: H may couple degrees of freedom of one object; App. A
+// contact row on the gap n . (x_v - sum_a w_a x_a)).  Float64 from the float32 state,
+// contraction off, dot products summed left to right, as the predicate is specified.
+__device__ inline void cross3(const double a[3], const double b[3], double o[3]) {
+#pragma clang fp contract(off)
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ inline double dot3(const double a[3], const double b[3]) {
+#pragma clang fp contract(off)
+  return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
+}
+// node position at q_t (state 0) or at q~ (state 1) in float64
+__device__ inline void pos64(const Dev& d, int v, int state, double x[3]) {
+#pragma clang fp contract(off)
+  const double hh = d.h * d.h;
+  for (int c = 0; c < 3; ++c) {
+    x[c] = (double)d.qt[c * d.N4 + v];
+    if (state) x[c] = (x[c] + d.h * (double)d.vt[c * d.N4 + v]) + hh * d.g[c];
+  }
+}
+// unit normal of triangle t at `state`: cross(xb - xa, xc - xa) / |.|
+__device__ inline void tri_normal(const Dev& d, int t, int state, double n[3]) {
+#pragma clang fp contract(off)
+  double xa[3], xb[3], xc[3], e1[3], e2[3];
+  pos64(d, d.tri_v[t], state, xa);
+  pos64(d, d.tri_v[d.T + t], state, xb);
+  pos64(d, d.tri_v[2 * d.T + t], state, xc);
+  for (int c = 0; c < 3; ++c) {
+    e1[c] = xb[c] - xa[c];
+    e2[c] = xc[c] - xa[c];
+  }
+  cross3(e1, e2, n);
+  const double len = sqrt(dot3(n, n));
+  for (int c = 0; c < 3; ++c) n[c] = n[c] / len;
+}
+// projection of x onto the plane of triangle t (unit normal n) at `state`: weights
+// (wa, wb, wc) / tot into w, signed distance returned; false if a weight is negative
+__device__ inline bool tri_project(const Dev& d, int t, int state, const double n[3], const double x[3], double w[3],
+                                   double* dist) {
+#pragma clang fp contract(off)
+  double xa[3], xb[3], xc[3], r[3], p[3];
+  pos64(d, d.tri_v[t], state, xa);
+  pos64(d, d.tri_v[d.T + t], state, xb);
+  pos64(d, d.tri_v[2 * d.T + t], state, xc);
+  for (int c = 0; c < 3; ++c) r[c] = x[c] - xa[c];
+  const double ds = dot3(n, r);
+  for (int c = 0; c < 3; ++c) p[c] = x[c] - ds * n[c];
+  double u[3], v[3], cr[3], wr[3];
+  const double* P[3][2] = {{xb, xc}, {xc, xa}, {xa, xb}};
+  for (int k = 0; k < 3; ++k) {
+    for (int c = 0; c < 3; ++c) {
+      u[c] = P[k][0][c] - p[c];
+      v[c] = P[k][1][c] - p[c];
+    }
+    cross3(u, v, cr);
+    wr[k] = dot3(n, cr);
+  }
+  const double tot = (wr[0] + wr[1]) + wr[2];
+  bool inside = true;
+  for (int k = 0; k < 3; ++k) {
+    w[k] = wr[k] / tot;
+    inside = inside && w[k] >= 0.0;
+  }
+  *dist = ds;
+  return inside;
+}
+// the self-contact predicate of surface vertex index i and triangle t (tri_n ready)
+__device__ bool self_pair(const Dev& d, int i, int t, const double vn[3], double w[3], double* dist_t) {
+#pragma clang fp contract(off)
+  const int v = d.sv[i];
+  if (d.tri_v[t] == v || d.tri_v[d.T + t] == v || d.tri_v[2 * d.T + t] == v) return false;
+  double n0[3], n1[3];
+  for (int c = 0; c < 3; ++c) {
+    n0[c] = d.tri_n[c * d.T + t];
+    n1[c] = d.tri_n[(3 + c) * d.T + t];
+  }
+  if (!(dot3(n0, vn) < 0.0)) return false;
+  double x[3], w1[3], ds0, ds1;
+  pos64(d, v, 0, x);
+  if (!tri_project(d, t, 0, n0, x, w, &ds0)) return false;
+  pos64(d, v, 1, x);
+  if (!tri_project(d, t, 1, n1, x, w1, &ds1)) return false;
+  const double margin = d.scene_margin[0];
+  *dist_t = ds0;
+  return ds0 > -margin && (ds0 < ds1 ? ds0 : ds1) < margin;
+}
+// sum of the (unnormalised) cross products of the surface triangles of vertex index i at q_t
+__device__ void vertex_normal(const Dev& d, int i, double vn[3]) {
+#pragma clang fp contract(off)
+  vn[0] = vn[1] = vn[2] = 0.0;
+  for (int k = d.vt_ptr[i]; k < d.vt_ptr[i + 1]; ++k) {
+    const int t = d.vt_idx[k];
+    double xa[3], xb[3], xc[3], e1[3], e2[3], cr[3];
+    pos64(d, d.tri_v[t], 0, xa);
+    pos64(d, d.tri_v[d.T + t], 0, xb);
+    pos64(d, d.tri_v[2 * d.T + t], 0, xc);
+    for (int c = 0; c < 3; ++c) {
+      e1[c] = xb[c] - xa[c];
+      e2[c] = xc[c] - xa[c];
+    }
+    cross3(e1, e2, cr);
+    for (int c = 0; c < 3; ++c) vn[c] = vn[c] + cr[c];
+  }
+}
+// row j: vertex v against triangle t, frame and weights at q_t
+__device__ void write_self_row(const Dev& d, int j, int v, int t) {
+#pragma clang fp contract(off)
+  double n[3], f1[3], f2[3], x[3], w[3], dist;
+  tri_normal(d, t, 0, n);
+  pos64(d, v, 0, x);
+  (void)tri_project(d, t, 0, n, x, w, &dist);
+  tangents64(n, f1, f2);
+  const double* rows[3] = {n, f1, f2};
+  const int CM = d.CMAX;
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      d.cC[(r * 3 + c) * CM + j] = (float)rows[r][c];
+      d.cC64[(r * 3 + c) * CM + j] = rows[r][c];
+    }
+  d.c_dn[j] = 0.0f;
+  d.c_dn64[j] = 0.0;
+  d.c_df[j] = 0.0f;
+  d.c_df[CM + j] = 0.0f;
+  d.c_mu[j] = d.self_mu;
+  d.c_gap[j] = dist;
+  d.c_comp[j] = -1.0f;
+  const int ent[4] = {v, d.tri_v[t], d.tri_v[d.T + t], d.tri_v[2 * d.T + t]};
+  const double sg[4] = {1.0, -w[0], -w[1], -w[2]};
+  for (int a = 0; a < 4; ++a) {
+    d.ent_node[a * CM + j] = ent[a];
+    d.ent_w[a * CM + j] = sg[a];
+  }
+}
+
+__global__ void k_self_tri(Dev d) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= d.T) return;
+  for (int state = 0; state < 2; ++state) {
+    double n[3];
+    tri_normal(d, t, state, n);
+    for (int c = 0; c < 3; ++c) d.tri_n[(3 * state + c) * d.T + t] = n[c];
+  }
+}
+
+__global__ void k_self_count(Dev d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.NSV) return;
+  double vn[3], w[3], dist;
+  vertex_normal(d, i, vn);
+  int cnt = 0;
+  for (int t = 0; t < d.T; ++t) cnt += self_pair(d, i, t, vn, w, &dist);
+  d.sv_cnt[i] = cnt;
+}
+
+// single block: exclusive scan of the per-vertex counts into row offsets after the
+// obstacle contacts; the total goes to n_contacts
+__global__ void k_self_scan(Dev d) {
+  __shared__ int part[1024];
+  const int per = (d.NSV + 1023) / 1024;
+  const int b0 = threadIdx.x * per, b1 = min(d.NSV, b0 + per);
+  int s = 0;
+  for (int b = b0; b < b1; ++b) s += d.sv_cnt[b];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  const int c0 = d.n_contacts[0];
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int t = 0; t < 1024; ++t) {
+      const int x = part[t];
+      part[t] = acc;
+      acc += x;
+    }
+    d.n_obst_c[0] = c0;
+    d.n_contacts[0] = c0 + acc;
+    if (c0 + acc > d.CMAX) d.overflow[0] = 1;
+  }
+  __syncthreads();
+  int acc = c0 + part[threadIdx.x];
+  for (int b = b0; b < b1; ++b) {
+    const int x = d.sv_cnt[b];
+    d.sv_cnt[b] = acc;
+    acc += x;
+  }
+}
+
+__global__ void k_self_write(Dev d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.NSV) return;
+  double vn[3], w[3], dist;
+  vertex_normal(d, i, vn);
+  int j = d.sv_cnt[i];
+  const int v = d.sv[i];
+  for (int t = 0; t < d.T; ++t) {
+    if (!self_pair(d, i, t, vn, w, &dist)) continue;
+    if (j < d.CMAX) {
+      d.c_node[j] = v;
+      d.c_obst[j] = -1 - t;
+      d.c_scene[j] = 0;
+      write_self_row(d, j, v, t);
+    }
+    ++j;
+  }
+}
+
+// Self entries (node, row, sign) of the frame's self rows, sorted by (node, row,
+// corner) for the force scatter of the global step: each entry's rank is the number of
+// entries before it.
+__global__ void k_self_entries(Dev d) {
+  const int c = min(d.n_contacts[0], d.CMAX), c0 = min(d.n_obst_c[0], c);
+  const int E = 4 * (c - c0);
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e == 0) d.se_count[0] = E;
+  if (e >= E) return;
+  const int CM = d.CMAX;
+  const int j = c0 + e / 4, a = e % 4;
+  const int node = d.ent_node[a * CM + j];
+  int rank = 0;
+  for (int f = 0; f < E; ++f) {
+    const int jf = c0 + f / 4, af = f % 4, nf = d.ent_node[af * CM + jf];
+    rank += (nf < node || (nf == node && f < e)) ? 1 : 0;
+  }
+  d.se_node[rank] = node;
+  d.se_row[rank] = j;
+  d.se_w[rank] = (float)d.ent_w[a * CM + j];
+}
+
+void launch_self_entries(const Dev& d, hipStream_t st) {
+  if (!d.self_on) return;
+  hipLaunchKernelGGL(k_self_entries, dim3((4 * d.CMAX + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d);
+}
+
 void launch_collide(const Dev& d, hipStream_t st) {
   int nblk = (d.N + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_collide_count, dim3(nblk), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_collide_scan, dim3(1), dim3(1024), 0, st, d, nblk);
   hipLaunchKernelGGL(k_collide_write, dim3(nblk), dim3(kBlock), 0, st, d);
+  if (d.self_on) {
+    const int sblk = (d.NSV + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_self_tri, dim3((d.T + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d);
+    hipLaunchKernelGGL(k_self_count, dim3(sblk), dim3(kBlock), 0, st, d);
+    hipLaunchKernelGGL(k_self_scan, dim3(1), dim3(1024), 0, st, d);
+    hipLaunchKernelGGL(k_self_write, dim3(sblk), dim3(kBlock), 0, st, d);
+  }
   hipLaunchKernelGGL(k_scene_offsets, dim3(1), dim3(64), 0, st, d);
 }
 
@@ -288,7 +534,8 @@ __global__ void k_frames_for_list(Dev d) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   int c = min(d.n_contacts[0], d.CMAX);
   if (j >= c) return;
-  write_contact_frame(d, j, d.c_node[j], d.obst[d.c_obst[j]]);
+  if (d.c_obst[j] < 0) write_self_row(d, j, d.c_node[j], -1 - d.c_obst[j]);
+  else write_contact_frame(d, j, d.c_node[j], d.obst[d.c_obst[j]]);
 }
 
 void launch_frames_for_list(const Dev& d, hipStream_t st) {
@@ -304,6 +551,7 @@ void launch_frames_for_list(const Dev& d, hipStream_t st) {
 __global__ void k_adjacent_lca(Dev d) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int c = min(d.n_contacts[0], d.CMAX);
+  if (d.self_on) c = min(c, d.n_obst_c[0]);  // self rows follow, unsorted
   if (i >= c - 1) return;
   if (d.c_scene[i] != d.c_scene[i + 1]) {
     d.ad[i] = -1;
@@ -344,7 +592,8 @@ __global__ void __launch_bounds__(kBlock) k_delassus_tiles(Dev d) {
     int s = 0;
     while (d.tile_off[s + 1] <= tile) ++s;
     int cs = d.cs_off[s], cnt = d.cs_off[s + 1] - cs;
-    int T = (cnt + kDelTile - 1) / kDelTile;
+    const int co = obst_end(d, s) - cs;  // tiles cover the single-node contacts
+    int T = (co + kDelTile - 1) / kDelTile;
     int rem = tile - d.tile_off[s], tj = 0;
     while (rem >= T - tj) {
       rem -= T - tj;
@@ -352,7 +601,7 @@ __global__ void __launch_bounds__(kBlock) k_delassus_tiles(Dev d) {
     }
     int tk = tj + rem;
     int J0 = cs + tj * kDelTile, K0 = cs + tk * kDelTile;
-    int nJ = min(kDelTile, cs + cnt - J0), nK = min(kDelTile, cs + cnt - K0);
+    int nJ = min(kDelTile, cs + co - J0), nK = min(kDelTile, cs + co - K0);
     int tid = threadIdx.x;
     // the adjacent-pair depths inside both contact ranges, ad[J0 .. J0+nJ-2] and
     // ad[K0 .. K0+nK-2], staged once (cross-scene pairs as -1); with the column data
@@ -483,9 +732,81 @@ __global__ void __launch_bounds__(kBlock) k_delassus_tiles(Dev d) {
   }
 }
 
+// [A_n^-1]_(a b) = sum over the common ancestors i of a and b of S_ia S_ib (Theorem 1),
+// one wavefront: the common ancestors are the path from LCA(a, b) to the root, found by
+// walking up chains from the smaller node (a subtree is the index range [lo_i, i]).
+__device__ float ainv_wave(const Dev& d, int a, int b, int lane) {
+  if (a > b) {
+    const int t = a;
+    a = b;
+    b = t;
+  }
+  int lca = a, x = a;
+  while (x != -1) {
+    const int e = d.chain_end[x];
+    if (e >= b) {
+      lca = x > b ? x : b;
+      break;
+    }
+    x = d.parent[e];
+  }
+  if (x == -1) return 0.0f;  // different trees (other scenes): no common ancestor
+  const int D = d.depth[lca], da = d.depth[a], db = d.depth[b];
+  const float* ca = d.col_val + d.col_ptr[a];
+  const float* cb = d.col_val + d.col_ptr[b];
+  float acc = 0.0f;
+  for (int t = lane; t <= D; t += kWave) acc += ca[da - t] * cb[db - t];
+  return wave_sum_c(acc);
+}
+
+// Delassus entries of the self rows: K_jk = sum_e sum_f s_e s_f [A_n^-1]_(n_e n_f) over
+// the entries of row j (vertex and triangle corners) and of row k (one node with sign 1
+// for a single-node contact), for every self row j and every row k of the frame; one
+// wavefront per pair, both K_jk and K_kj written.
+__global__ void __launch_bounds__(kBlock) k_self_delassus(Dev d) {
+  if (d.k_off[d.NS] > d.KCAP) return;
+  const int c = min(d.n_contacts[0], d.CMAX), c0 = min(d.n_obst_c[0], c);
+  const int cs = c - c0, CM = d.CMAX, stride = kstride(c);
+  const int64_t pairs = (int64_t)cs * c0 + (int64_t)cs * (cs + 1) / 2;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
+  for (int64_t p = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kWave; p < pairs; p += waves) {
+    int j, k;  // j a self row; k < c0 a contact, or a self row k <= j
+    if (p < (int64_t)cs * c0) {
+      j = c0 + (int)(p / c0);
+      k = (int)(p % c0);
+    } else {
+      int64_t q = p - (int64_t)cs * c0;
+      int r = (int)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
+      while ((int64_t)(r + 1) * (r + 2) / 2 <= q) ++r;
+      while ((int64_t)r * (r + 1) / 2 > q) --r;
+      j = c0 + r;
+      k = c0 + (int)(q - (int64_t)r * (r + 1) / 2);
+    }
+    j = __builtin_amdgcn_readfirstlane(j);
+    k = __builtin_amdgcn_readfirstlane(k);
+    const int nk = k < c0 ? 1 : 4;
+    float sum = 0.0f;
+    for (int a = 0; a < 4; ++a) {
+      const int na = d.ent_node[a * CM + j];
+      const float sa = (float)d.ent_w[a * CM + j];
+      for (int b = 0; b < nk; ++b) {
+        const int nb = k < c0 ? d.c_node[k] : d.ent_node[b * CM + k];
+        const float sb = k < c0 ? 1.0f : (float)d.ent_w[b * CM + k];
+        sum += sa * sb * ainv_wave(d, na, nb, lane);
+      }
+    }
+    if (lane == 0) {
+      d.K[d.k_off[0] + (int64_t)j * stride + k] = sum;
+      d.K[d.k_off[0] + (int64_t)k * stride + j] = sum;
+    }
+  }
+}
+
 void launch_delassus(const Dev& d, hipStream_t st) {
   hipLaunchKernelGGL(k_adjacent_lca, dim3((d.CMAX + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_delassus_tiles, dim3(1024), dim3(kBlock), 0, st, d);
+  if (d.self_on) hipLaunchKernelGGL(k_self_delassus, dim3(1024), dim3(kBlock), 0, st, d);
 }
 
 // ---------------------------------------------------------------- warm start + r
@@ -502,20 +823,36 @@ __global__ void k_warm_start(Dev d, int keep_lambda) {
   float* krow = d.K + d.k_off[s] + (int64_t)(j - cs) * kstride(cnt);
   for (int k = cnt; k < kstride(cnt); ++k) krow[k] = 0.0f;  // pads of this row (storage is reused)
   float kjj = krow[j - cs];
-  if (d.precond == 1) kjj = d.inv_mass[d.c_node[j]];  // [H M^-1 H^T]_jj = 1 / m_v
+  if (d.precond == 1) {  // [H M^-1 H^T]_jj = 1 / m_v; of a self row, sum_e s_e^2 / m_(n_e)
+    if (d.c_obst[j] >= 0) {
+      kjj = d.inv_mass[d.c_node[j]];
+    } else {
+      kjj = 0.0f;
+      for (int a = 0; a < 4; ++a) {
+        const float w = (float)d.ent_w[a * d.CMAX + j];
+        kjj += w * w * d.inv_mass[d.ent_node[a * d.CMAX + j]];
+      }
+    }
+  }
   d.c_rn[j] = (float)(d.h * d.h) * kjj;
   d.c_rf[j] = (float)d.h * kjj;
   if (keep_lambda) return;
   float l[3] = {0.0f, 0.0f, 0.0f};
   if (d.warm >= 1) {  // previous frame (also the fallback and an input of the learned start)
-    int pc = d.pc_count[0];
+    // saved keys: the single-node contacts sorted by (node, obstacle), then self rows
+    const int pc = d.pc_count[0], pco = d.pc_count[1];
     int key_n = d.c_node[j], key_o = d.c_obst[j];
-    int lo = 0, hi = pc;
-    while (lo < hi) {
-      int mid = (lo + hi) >> 1;
-      int mn = d.pc_node[mid], mo = d.pc_obst[mid];
-      if (mn < key_n || (mn == key_n && mo < key_o)) lo = mid + 1;
-      else hi = mid;
+    int lo = 0, hi = pco;
+    if (key_o >= 0) {
+      while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        int mn = d.pc_node[mid], mo = d.pc_obst[mid];
+        if (mn < key_n || (mn == key_n && mo < key_o)) lo = mid + 1;
+        else hi = mid;
+      }
+    } else {
+      for (lo = pco; lo < pc && !(d.pc_node[lo] == key_n && d.pc_obst[lo] == key_o); ++lo) {
+      }
     }
     if (lo < pc && d.pc_node[lo] == key_n && d.pc_obst[lo] == key_o) {
       float w[3] = {d.pc_world[lo], d.pc_world[d.CMAX + lo], d.pc_world[2 * d.CMAX + lo]};
@@ -532,10 +869,6 @@ void launch_warm_start(const Dev& d, hipStream_t st, int keep_lambda) {
 }
 
 // ---------------------------------------------------------------- per-iteration contact terms
-__device__ inline float wave_sum_c(float v) {
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
-}
 
 struct FBTerms {
   float om_n, E_n, phi_n, om_f, E_f, phi_f[2];
@@ -609,35 +942,50 @@ __device__ FBTerms minmap_terms(float dn, const float vf[2], const float l[3], f
 // (column_path_sums; the unconstrained solve A^-1 b at the contact node), then Omega, E~, the h vector
 // (Sec. 5.2) and X = C^T (Omega lambda) for the W Omega lambda term of J A^-1 g.
 __global__ void __launch_bounds__(kBlock) k_contact_prep(Dev d) {
+  if (frame_done(d)) return;
   const int j = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
   const int lane = threadIdx.x & (kWave - 1);
   const int c = min(d.n_contacts[0], d.CMAX);
   if (blockIdx.x == 0)  // barrier counters of the CR launch that follows
     for (int k = threadIdx.x; k <= min(2 * d.cr_iters + 2, kCrMaxBarriers); k += blockDim.x) d.cr_sync[k] = 0u;
   if (j >= c) return;
-  const int v = __builtin_amdgcn_readfirstlane(d.c_node[j]);
-  float acc[1][3];
-  column_path_sums<1>(d, d.y, v, 1, lane, acc);
-  const float ax = wave_sum_c(acc[0][0]), ay = wave_sum_c(acc[0][1]), az = wave_sum_c(acc[0][2]);
-  if (lane != 0) return;
   const int CM = d.CMAX;
-  const float h = (float)d.h;
-  float x[3], xt[3], du[3];
-  for (int q = 0; q < 3; ++q) {
-    x[q] = d.q[q * d.N4 + v];
-    xt[q] = d.qt[q * d.N4 + v];
+  // entries of the row: its node with sign 1, or a self row's vertex and triangle corners
+  const bool multi = d.self_on && d.c_obst[j] < 0;
+  const int ne = multi ? 4 : 1;
+  float x[3] = {0.0f, 0.0f, 0.0f}, xt[3] = {0.0f, 0.0f, 0.0f}, du[3] = {0.0f, 0.0f, 0.0f};
+  double dn64 = -d.c_dn64[j];
+  for (int a = 0; a < ne; ++a) {
+    const int v = __builtin_amdgcn_readfirstlane(multi ? d.ent_node[a * CM + j] : d.c_node[j]);
+    const double sg = multi ? d.ent_w[a * CM + j] : 1.0;
+    float acc[1][3];
+    column_path_sums<1>(d, d.y, v, 1, lane, acc);
+    const float ax = wave_sum_c(acc[0][0]), ay = wave_sum_c(acc[0][1]), az = wave_sum_c(acc[0][2]);
+    float xa[3], xta[3], dua[3];
+    for (int q = 0; q < 3; ++q) {
+      xa[q] = d.q[q * d.N4 + v];
+      xta[q] = d.qt[q * d.N4 + v];
+    }
+    // u - x^k = (q~ - x^k) + (S^T y)_v: a difference of nearby values, kept small
+    dua[0] = (d.qp[v] - xa[0]) + ax;
+    dua[1] = (d.qp[d.N4 + v] - xa[1]) + ay;
+    dua[2] = (d.qp[2 * d.N4 + v] - xa[2]) + az;
+    // delta_n = n . x - d_n in float64 (absolute coordinates, small difference)
+    dn64 += sg * (d.cC64[0 * CM + j] * (double)xa[0] + d.cC64[1 * CM + j] * (double)xa[1] +
+                  d.cC64[2 * CM + j] * (double)xa[2]);
+    const float sf = (float)sg;
+    for (int q = 0; q < 3; ++q) {
+      x[q] += sf * xa[q];
+      xt[q] += sf * xta[q];
+      du[q] += sf * dua[q];
+    }
   }
-  // u - x^k = (q~ - x^k) + (S^T y)_v: a difference of nearby values, kept small
-  du[0] = (d.qp[v] - x[0]) + ax;
-  du[1] = (d.qp[d.N4 + v] - x[1]) + ay;
-  du[2] = (d.qp[2 * d.N4 + v] - x[2]) + az;
+  if (lane != 0) return;
+  const float h = (float)d.h;
   float C[3][3];
   for (int r = 0; r < 3; ++r)
     for (int q = 0; q < 3; ++q) C[r][q] = d.cC[(r * 3 + q) * CM + j];
   float l[3] = {d.lam[j], d.lam[CM + j], d.lam[2 * CM + j]};
-  // delta_n = n . x - d_n in float64 (absolute coordinates, small difference)
-  double dn64 = d.cC64[0 * CM + j] * (double)x[0] + d.cC64[1 * CM + j] * (double)x[1] +
-                d.cC64[2 * CM + j] * (double)x[2] - d.c_dn64[j];
   float dn = (float)dn64;
   float hvf[2];
   for (int r = 0; r < 2; ++r)
@@ -684,12 +1032,25 @@ void launch_contact_prep(const Dev& d, hipStream_t st) {
 // r_n lambda_n)|, and for lambda_n > 0 h |FB(s, r_f gamma)| and h |vdot_f + s
 // lambda_f/|lambda_f||, else h r_f |lambda_f|; a bilateral row takes |delta_b + e
 // lambda_b| and its inactive tangent rows.  NaN counts as huge.
-__device__ float contact_residual(const Dev& d, int j, const float x[3], const float l[3]) {
+// Point of row j in positions `base` ([3][N4] float): its node's position, or for a self
+// row the signed sum of its entries x_v - sum_a w_a x_a (float64 normal gap below).
+__device__ void row_point(const Dev& d, int j, const float* base, float x[3]) {
+  if (d.self_on && d.c_obst[j] < 0) {
+    for (int q = 0; q < 3; ++q) x[q] = 0.0f;
+    for (int a = 0; a < 4; ++a) {
+      const int v = d.ent_node[a * d.CMAX + j];
+      const float sg = (float)d.ent_w[a * d.CMAX + j];
+      for (int q = 0; q < 3; ++q) x[q] += sg * base[q * d.N4 + v];
+    }
+    return;
+  }
+  const int v = d.c_node[j];
+  for (int q = 0; q < 3; ++q) x[q] = base[q * d.N4 + v];
+}
+
+__device__ float contact_residual(const Dev& d, int j, const float x[3], const float xt[3], const float l[3]) {
   const int CM = d.CMAX;
   const float h = (float)d.h;
-  const int v = d.c_node[j];
-  float xt[3];
-  for (int q = 0; q < 3; ++q) xt[q] = d.qt[q * d.N4 + v];
   float C[3][3];
   for (int r = 0; r < 3; ++r)
     for (int q = 0; q < 3; ++q) C[r][q] = d.cC[(r * 3 + q) * CM + j];
@@ -723,20 +1084,48 @@ __device__ float contact_residual(const Dev& d, int j, const float x[3], const f
 
 // max over contacts of the residual at the current iterate (q, lambda), per scene
 __global__ void k_residual(Dev d) {
+  if (frame_done(d)) return;
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   int c = min(d.n_contacts[0], d.CMAX);
   if (j >= c) return;
-  const int CM = d.CMAX, v = d.c_node[j];
-  float x[3], l[3];
-  for (int q = 0; q < 3; ++q) {
-    x[q] = d.q[q * d.N4 + v];
-    l[q] = d.lam[q * CM + j];
-  }
-  atomicMax(reinterpret_cast<unsigned int*>(d.res) + d.c_scene[j], __float_as_uint(contact_residual(d, j, x, l)));
+  const int CM = d.CMAX;
+  float x[3], xt[3], l[3];
+  row_point(d, j, d.q, x);
+  row_point(d, j, d.qt, xt);
+  for (int q = 0; q < 3; ++q) l[q] = d.lam[q * CM + j];
+  atomicMax(reinterpret_cast<unsigned int*>(d.res) + d.c_scene[j],
+            __float_as_uint(contact_residual(d, j, x, xt, l)));
 }
 
 __global__ void k_zero_res(Dev d) {
+  if (frame_done(d)) return;
   for (int s = threadIdx.x; s < d.NS; s += blockDim.x) d.res[s] = 0.0f;
+}
+
+// After the residual of an iteration of a frame iterated to tolerance: count it and mark
+// the frame done once every scene's residual is within the tolerance, the iteration cap
+// is reached, or the frame failed (capacity, non-finite state, abandoned CR barrier).
+__global__ void k_convergence_check(Dev d) {
+  if (threadIdx.x != 0 || *d.done) return;
+  const int k = ++d.iter_count[0];
+  float w = 0.0f;
+  for (int s = 0; s < d.NS; ++s) w = fmaxf(w, d.res[s]);
+  if (w <= d.ncp_tol || k >= d.max_iters || d.overflow[0] || d.bad[0] || d.bad[1]) *d.done = 1;
+}
+
+__global__ void k_reset_convergence(Dev d) {
+  if (threadIdx.x == 0) {
+    *d.done = 0;
+    *d.iter_count = 0;
+  }
+}
+
+void launch_reset_convergence(const Dev& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_reset_convergence, dim3(1), dim3(kWave), 0, st, d);
+}
+
+void launch_convergence_check(const Dev& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_convergence_check, dim3(1), dim3(kWave), 0, st, d);
 }
 
 void launch_residual(const Dev& d, hipStream_t st) {
@@ -787,18 +1176,18 @@ __global__ void __launch_bounds__(kBlock) k_warm_judge(Dev d) {
   for (int q = 0; q < 6; ++q) w[q] = wave_sum_c(w[q]);
   if (lane != 0) return;
   const float h2 = (float)(d.h * d.h);
-  const int v = d.c_node[j];
-  float xp[3], xm[3], lp[3], lm[3];
+  float xp[3], xm[3], lp[3], lm[3], base[3], xt[3];
+  row_point(d, j, d.qp, base);
+  row_point(d, j, d.qt, xt);
   for (int q = 0; q < 3; ++q) {
-    const float base = d.qp[q * d.N4 + v];
-    xp[q] = base + h2 * w[q];
-    xm[q] = base + h2 * w[3 + q];
+    xp[q] = base[q] + h2 * w[q];
+    xm[q] = base[q] + h2 * w[3 + q];
     lp[q] = d.lam[q * CM + j];
     lm[q] = d.lam_ml[q * CM + j];
   }
   unsigned* jd = reinterpret_cast<unsigned*>(d.judge);
-  atomicMax(jd + sc, __float_as_uint(contact_residual(d, j, xp, lp)));
-  atomicMax(jd + d.NS + sc, __float_as_uint(contact_residual(d, j, xm, lm)));
+  atomicMax(jd + sc, __float_as_uint(contact_residual(d, j, xp, xt, lp)));
+  atomicMax(jd + d.NS + sc, __float_as_uint(contact_residual(d, j, xm, xt, lm)));
 }
 
 __global__ void k_warm_select(Dev d) {

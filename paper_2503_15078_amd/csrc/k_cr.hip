@@ -95,6 +95,7 @@ __device__ inline int grid_barrier(unsigned* ctrs, unsigned b, bool live, int* s
 
 template <int V>
 __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
+  if (frame_done(d)) return;
   constexpr int NZ = V == 0 ? 1 : 2;  // vectors exchanged per step
   __shared__ __align__(16) float Ks[kCrKFloats];
   __shared__ __align__(16) float Zs[kCrZFloats];
@@ -113,6 +114,13 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
   __shared__ int row_slot[kCrRows];
   const int c = d.k_off[d.NS] > d.KCAP ? 0 : min(d.n_contacts[0], d.CMAX);
   if (c == 0) return;  // uniform across the grid: no block reaches a barrier
+  // optional wall-clock stamps of block 0 (measurement): [0] start, [1] end, then per
+  // barrier b = 1, 2, ...: entry, exit, end of the read of the exchanged data
+  unsigned long long* clk = (d.cr_clock && blockIdx.x == 0) ? d.cr_clock : nullptr;
+  auto stamp = [&](int idx) {
+    if (clk && threadIdx.x == 0) clk[idx] = wall_clock64();
+  };
+  stamp(0);
   unsigned* ctrs = d.cr_sync;
   int* fail = d.bad;  // [0]: frame invalid, [1]: the CR barrier was abandoned
   const unsigned G = gridDim.x;
@@ -343,6 +351,16 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
     }
     __syncthreads();
   };
+  // device-wide barrier with the measurement stamps; data_read() stamps the end of the
+  // read of what the other blocks published before it
+  auto bar = [&](bool live) {
+    ++nbar;
+    stamp(2 + 3 * (nbar - 1));
+    const int r = grid_barrier(ctrs, nbar, live, &s_st, fail);
+    stamp(3 + 3 * (nbar - 1));
+    return r;
+  };
+  auto data_read = [&]() { stamp(4 + 3 * (nbar - 1)); };
   // K times the first nv vectors of exchange buffer `buf`, staged into Zs when they fit
   auto exch = [&](int buf) { return d.cr_Z + (int64_t)buf * 3 * NZ * CM; };
   auto matvec_Z = [&](auto nv, int buf, float (*Y0)[kCrRows], float (*Y1)[kCrRows]) {
@@ -350,6 +368,7 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
       stage(exch(buf), decltype(nv)::value);
       __syncthreads();
     }
+    data_read();
     matvec_rows(nv, z_in_lds, exch(buf), Y0, Y1);
   };
   // publish Z_j = C_j^T (Omega_j v_j) for owned contacts as vector `slot` of buffer `buf`
@@ -449,7 +468,7 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
   }
   __syncthreads();
   publish_Z((nbar + 1) & 1, 0, vr);
-  if (grid_barrier(ctrs, ++nbar, true, &s_st, fail) < 0) return;
+  if (bar(true) < 0) return;
   matvec_Z(one, nbar & 1, vw, vw);
   applyM(vw, vr);
   for (int t = tid; t < R; t += kBlock)
@@ -457,8 +476,9 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
   products();
   if constexpr (V == 1) publish_Z((nbar + 1) & 1, 0, vw);
   publish_partials((nbar + 1) & 1, 4);
-  if (grid_barrier(ctrs, ++nbar, true, &s_st, fail) < 0) return;
+  if (bar(true) < 0) return;
   gather_sums(nbar & 1, 4, V == 1 ? 1 : 0);
+  data_read();
   for (int t = tid; t < R; t += kBlock) {
     s_g[t] = prod[0][t];
     s_qq[t] = prod[1][t];
@@ -495,24 +515,26 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
     if (it + 1 == d.cr_iters) break;
     if constexpr (V == 0) {
       publish_Z((nbar + 1) & 1, 0, vr);
-      const int st = grid_barrier(ctrs, ++nbar, block_live, &s_st, fail);
+      const int st = bar(block_live);
       if (st < 0) return;
       if (st == 0) break;
       matvec_Z(one, nbar & 1, vw, vw);
       applyM(vw, vr);  // w = M r
       products();
       publish_partials((nbar + 1) & 1, 4);
-      if (grid_barrier(ctrs, ++nbar, true, &s_st, fail) < 0) return;
+      if (bar(true) < 0) return;
       gather_sums(nbar & 1, 4, 0);
+      data_read();
     } else {
       products();  // with the recurrence w~
       publish_Z((nbar + 1) & 1, 0, vw);
       publish_Z((nbar + 1) & 1, 1, vr);
       publish_partials((nbar + 1) & 1, 4);
-      const int st = grid_barrier(ctrs, ++nbar, block_live, &s_st, fail);
+      const int st = bar(block_live);
       if (st < 0) return;
       if (st == 0) break;
       gather_sums(nbar & 1, 4, 2);
+      data_read();
       matvec_rows(two, z_in_lds, exch(nbar & 1), vn, vm);
       applyM(vn, vw);  // n = M w~
       applyM(vm, vr);  // true M r
@@ -548,6 +570,7 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
     }
     for (int q = 0; q < 3; ++q) d.F[q * CM + j] = h2 * (Cl[q][t] * ol[0] + Cl[3 + q][t] * ol[1] + Cl[6 + q][t] * ol[2]);
   }
+  stamp(1);
 }
 
 int cr_max_blocks() {
@@ -564,6 +587,14 @@ int cr_max_blocks() {
 }
 
 int64_t cr_partial_floats(int blocks, int scenes) { return 2 * (int64_t)scenes * blocks * kCrSlots; }
+
+__global__ void k_zero_cr_sync(Dev d) {
+  for (int k = threadIdx.x; k <= min(2 * d.cr_iters + 2, kCrMaxBarriers); k += blockDim.x) d.cr_sync[k] = 0u;
+}
+
+void launch_zero_cr_sync(const Dev& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_cr_sync, dim3(1), dim3(kBlock), 0, st, d);
+}
 
 hipError_t launch_cr(const Dev& d, hipStream_t st, int cr_blocks, int variant) {
   if (variant == 1) hipLaunchKernelGGL(k_cr<1>, dim3(cr_blocks), dim3(kBlock), 0, st, d);

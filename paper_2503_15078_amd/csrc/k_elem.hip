@@ -316,6 +316,7 @@ __device__ void prox3(int model, const float sig[3], float mu, float lam, float 
 // delta-form contribution P = h^2 w (p - F(q~)) scattered as corner forces P d_a
 // (so that the global step solves for q - q~).
 __global__ void __launch_bounds__(kBlock) k_element(Dev d) {
+  if (frame_done(d)) return;
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= d.M) return;
   int vi[4];
@@ -464,6 +465,7 @@ void launch_lg_energy(const Dev& d, hipStream_t st, double* part) {
 // by a fixed butterfly, so the result does not depend on timing.
 constexpr int kGatherLanes = 8;
 __global__ void k_gather(Dev d) {
+  if (frame_done(d)) return;
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int v = gid / kGatherLanes, l = gid % kGatherLanes;
   const bool ok = v < d.N;  // whole groups of 8 lanes share v, so the butterfly stays in range
@@ -528,7 +530,10 @@ __global__ void k_save_contacts(Dev d) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (d.bad[0] || d.overflow[0]) return;
   int c = min(d.n_contacts[0], d.CMAX);
-  if (j == 0) d.pc_count[0] = c;
+  if (j == 0) {
+    d.pc_count[0] = c;
+    d.pc_count[1] = d.self_on ? min(d.n_obst_c[0], c) : c;  // the sorted single-node part
+  }
   if (j >= c) return;
   d.pc_node[j] = d.c_node[j];
   d.pc_obst[j] = d.c_obst[j];

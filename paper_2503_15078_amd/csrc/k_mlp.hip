@@ -305,6 +305,12 @@ __global__ void k_mlp_features(Dev d) {
   const double ell = d.ell[s];
   const double h = d.h;
   double xp[3], rel[3];
+  // self-contact rows (no obstacle) keep the previous-frame start: their features are zero
+  if (d.c_obst[j] < 0) {
+    float4* out = reinterpret_cast<float4*>(d.c_feat + (int64_t)j * 16);
+    for (int q = 0; q < 4; ++q) out[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    return;
+  }
   const ObstacleDev& ob = d.obst[d.c_obst[j]];
   for (int q = 0; q < 3; ++q) {
     xp[q] = d.qp[q * d.N4 + v];
@@ -351,7 +357,8 @@ __global__ void __launch_bounds__(kBlock) k_mlp_warm(Dev d) {
       const float back = (float)(d.ell[sc] / (d.h * d.h * (double)kjj));
       float l[3] = {y[0] * back, y[1] * back, y[2] * back};
       const bool fresh = d.warm == 3 && d.lam[j] == 0.0f && d.lam[CM + j] == 0.0f && d.lam[2 * CM + j] == 0.0f;
-      if (isfinite(l[0]) && isfinite(l[1]) && isfinite(l[2]) && !(d.c_comp[j] >= 0.0f) && !fresh) {
+      if (isfinite(l[0]) && isfinite(l[1]) && isfinite(l[2]) && !(d.c_comp[j] >= 0.0f) && !fresh &&
+          d.c_obst[j] >= 0) {  // self-contact rows keep the previous-frame start
         const float mu = d.c_mu[j];
         l[0] = fmaxf(l[0], 0.0f);
         const float lf = sqrtf(l[1] * l[1] + l[2] * l[2]), cap = mu * l[0];

@@ -22,6 +22,7 @@ __device__ inline float wave_sum(float v) {
 // sums per row.
 template <int G>
 __global__ void __launch_bounds__(kBlock) k_spmv_S(Dev d, const float* __restrict__ b, float* __restrict__ y) {
+  if (frame_done(d)) return;
   const int wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
   const int lane = threadIdx.x & (kWave - 1);
   if (wave >= d.nseg) return;
@@ -92,6 +93,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv_S(Dev d, const float* __restric
 // One thread per (group, coordinate, row of the group); the first eight partials are
 // loaded together before the ordered sum.
 __global__ void k_spmv_S_finish(Dev d, float* __restrict__ y) {
+  if (frame_done(d)) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int G = d.row_group;
   if (t >= d.nlong * 3 * G) return;
@@ -128,6 +130,7 @@ void launch_spmv_S(const Dev& d, hipStream_t st, const float* b, float* y) {
 template <int G>
 __global__ void __launch_bounds__(kBlock) k_spmv_St(Dev d, const float* __restrict__ y,
                                                     const float* __restrict__ base, float* __restrict__ u) {
+  if (frame_done(d)) return;
   const int w = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
   const int lane = threadIdx.x & (kWave - 1);
   if (w >= d.n_stgrp) return;
@@ -172,27 +175,38 @@ __device__ inline int lower_bound_i(const int* a, int n, int key) {
   return lo;
 }
 
-// Per frame: the contact range [cb, ce) of every row (contacts are sorted by node).
+// Per frame: the contact range [cb, ce) of every row (contacts are sorted by node), and
+// with self contact the range of the sorted self-row entries.
 __global__ void k_force_ranges(Dev d) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.N) return;
-  const int c = min(d.n_contacts[0], d.CMAX);
+  int c = min(d.n_contacts[0], d.CMAX);
+  if (d.self_on) {
+    c = min(c, d.n_obst_c[0]);
+    const int E = d.se_count[0];
+    d.frange2[i] = lower_bound_i(d.se_node, E, d.lo[i]);
+    d.frange2[d.N + i] = lower_bound_i(d.se_node, E, i + 1);
+  }
   d.frange[i] = lower_bound_i(d.c_node, c, d.lo[i]);
   d.frange[d.N + i] = lower_bound_i(d.c_node, c, i + 1);
 }
 
 void launch_force_ranges(const Dev& d, hipStream_t st) {
+  launch_self_entries(d, st);
   hipLaunchKernelGGL(k_force_ranges, dim3((d.N + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d);
 }
 
 // One wavefront per row; rows without contacts in their subtree exit at once.
 __global__ void __launch_bounds__(kBlock) k_apply_forces(Dev d) {
+  if (frame_done(d)) return;
   const int i = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
   const int lane = threadIdx.x & (kWave - 1);
   if (i >= d.N) return;
   const int cb = __builtin_amdgcn_readfirstlane(d.frange[i]);
   const int ce = __builtin_amdgcn_readfirstlane(d.frange[d.N + i]);
-  if (cb >= ce) return;
+  const int sb = d.self_on ? __builtin_amdgcn_readfirstlane(d.frange2[i]) : 0;
+  const int se = d.self_on ? __builtin_amdgcn_readfirstlane(d.frange2[d.N + i]) : 0;
+  if (cb >= ce && sb >= se) return;
   const float* row = d.row_val + d.row_ptr[i];
   const int lo4 = d.row_lo4[i];
   float ax = 0.0f, ay = 0.0f, az = 0.0f;
@@ -201,6 +215,13 @@ __global__ void __launch_bounds__(kBlock) k_apply_forces(Dev d) {
     ax += s * d.F[k];
     ay += s * d.F[d.CMAX + k];
     az += s * d.F[2 * d.CMAX + k];
+  }
+  for (int k = sb + lane; k < se; k += kWave) {  // entries of self rows: s_e F_row
+    const int r = d.se_row[k];
+    const float s = row[d.se_node[k] - lo4] * d.se_w[k];
+    ax += s * d.F[r];
+    ay += s * d.F[d.CMAX + r];
+    az += s * d.F[2 * d.CMAX + r];
   }
   ax = wave_sum(ax);
   ay = wave_sum(ay);
@@ -223,6 +244,7 @@ void launch_apply_forces(const Dev& d, hipStream_t st) {
 // node computes u into tmp; a second kernel copies it to q, so every thread reads the
 // old iterate.
 __global__ void k_jacobi_global(Dev d) {
+  if (frame_done(d)) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.N) return;
   const int p0 = d.a_ptr[i], p1 = d.a_ptr[i + 1];
@@ -240,6 +262,7 @@ __global__ void k_jacobi_global(Dev d) {
 }
 
 __global__ void k_copy_iterate(Dev d) {
+  if (frame_done(d)) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.N) return;
   for (int c = 0; c < 3; ++c) d.q[c * d.N4 + i] = d.tmp[c * d.N4 + i];

@@ -53,7 +53,8 @@ class sim_options(C.Structure):
                 ("ncp_tol", C.c_double), ("max_iters", C.c_int32), ("max_contacts", C.c_int32),
                 ("hip_stream", C.c_void_p), ("cr_tol", C.c_double), ("cr_variant", C.c_int32),
                 ("graph", C.c_int32), ("ncp", C.c_int32), ("precond", C.c_int32),
-                ("global_step", C.c_int32), ("lg_form", C.c_int32)]
+                ("global_step", C.c_int32), ("lg_form", C.c_int32), ("self_contact", C.c_int32),
+                ("self_mu", C.c_double)]
 
 
 class sim_tuning(C.Structure):
@@ -109,6 +110,7 @@ def load():
         "sim_set_warm_model": [C.c_void_p, P(C.c_float), i32],
         "sim_set_graph": [C.c_void_p, i32],
         "sim_time_kernel": [C.c_void_p, i32, i32, P(C.c_float)],
+        "sim_profile_cr": [C.c_void_p, i32, P(C.c_float)],
         "sim_get_tuning": [C.c_void_p, P(sim_tuning)],
         "sim_set_tuning": [C.c_void_p, P(sim_tuning)],
         "sim_autotune": [C.c_void_p, i32, i32, i32, P(sim_tuning)],
@@ -116,6 +118,7 @@ def load():
         "sim_record_training_pairs": [C.c_void_p, i32],
         "sim_read_training_pairs": [C.c_void_p, P(i32), P(i32), P(C.c_float), P(C.c_float), i32, P(i32)],
         "sim_read_warm_judge": [C.c_void_p, P(C.c_float), P(C.c_float), i32, P(i32)],
+        "sim_surface_triangles": [C.c_void_p, P(i32), i32, P(i32)],
         "mlp_create": [P(C.c_float), i32, P(C.c_void_p)],
         "mlp_set_params": [C.c_void_p, P(C.c_float), i32],
         "mlp_get_params": [C.c_void_p, P(C.c_float), i32],
@@ -213,6 +216,8 @@ def options_for(scene, **kw):
     o.pin_weight_scale = scene.pin_weight_scale
     o.contact_margin = scene.margin
     o.cr_iters = scene.cr_iters
+    o.self_contact = int(bool(getattr(scene, "self_contact", False)))
+    o.self_mu = float(getattr(scene, "self_mu", 0.0))
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -351,6 +356,14 @@ class Sim:
         _check(_lib.sim_time_kernel(self.h, int(which), int(reps), C.byref(ms)))
         return float(ms.value)
 
+    def profile_cr(self, reps=20):
+        """Constraint-solve launch profile: ms per launch (HIP events), in-kernel us,
+        set-up us, us per exchange, us of barrier wait per exchange, exchanges."""
+        out = np.zeros(6, np.float32)
+        _check(_lib.sim_profile_cr(self.h, int(reps), _fp(out)))
+        keys = ("ms_per_launch", "kernel_us", "setup_us", "exchange_us", "barrier_wait_us", "exchanges")
+        return {k: float(v) for k, v in zip(keys, out)}
+
     def tuning(self):
         t = sim_tuning()
         _check(_lib.sim_get_tuning(self.h, C.byref(t)))
@@ -403,6 +416,14 @@ class Sim:
         n = C.c_int32(0)
         _check(_lib.sim_read_warm_judge(self.h, _fp(res), _fp(lam), cap, C.byref(n)))
         return res[:k].astype(np.float64), res[k:].astype(np.float64), lam[:n.value].astype(np.float64)
+
+    def surface_triangles(self):
+        """Surface triangles of a self-contact handle [T][3] (caller node ids)."""
+        n = C.c_int32(0)
+        _check(_lib.sim_surface_triangles(self.h, None, 0, C.byref(n)))
+        tris = np.zeros((max(n.value, 1), 3), np.int32)
+        _check(_lib.sim_surface_triangles(self.h, _ip(tris), n.value, C.byref(n)))
+        return tris[:n.value].astype(np.int64)
 
     def save_state(self):
         _check(_lib.sim_save_state(self.h))

@@ -77,6 +77,8 @@ class Scene:
     tet_model: Optional[np.ndarray] = None  # (m,) int32 per-tet override
     tet_E: Optional[np.ndarray] = None
     tet_nu: Optional[np.ndarray] = None
+    self_contact: bool = False              # vertex-triangle contact rows between surface parts
+    self_mu: float = 0.0                    # their friction coefficient
 
     @property
     def n(self) -> int:
@@ -178,6 +180,32 @@ def cube_drop(seed: int = 0, model: int = MODEL_COROT, nodes: int = 5, edge: flo
     return Scene("cube_drop", rest, tets, model, E, nu, 1000.0, 1.0 / 60.0,
                  np.array([0.0, 0.0, -9.81]), [ground], 0.25 * voxel, iters, cr_iters, frames,
                  init_pos=init)
+
+
+def fork_clap(seed: int = 0, mu: float = 0.0, speed: float = 0.6, voxel: float = 0.025, depth: int = 2,
+              height: int = 4, gap: int = 1, model: int = MODEL_COROT, E: float = 1e5, nu: float = 0.3,
+              frames: int = 20, iters: int = 5, cr_iters: int = 10) -> Scene:
+    """Self-contact: a U-shaped body (two prongs of 2 x depth voxels and `height` voxels on a
+    one-voxel base, `gap` voxels apart) whose prongs swing toward each other, with speeds
+    growing linearly with height (+x for the left prong, -x for the right), no gravity and
+    no obstacle: the prongs' inner faces meet through vertex-triangle self-contact rows.
+    The initial velocity field is mirror-symmetric, so the total momentum is zero; a
+    seeded perturbation of 0.5% of a voxel breaks exact symmetry of the positions."""
+    rng = np.random.default_rng(seed)
+    nx = 4 + gap
+    occ = np.zeros((nx, depth, height + 1), bool)
+    occ[:, :, 0] = True
+    occ[:2, :, 1:] = True
+    occ[2 + gap:, :, 1:] = True
+    rest, tets = voxel_mesh(occ, voxel, split=5)
+    init = rest + rng.uniform(-0.005 * voxel, 0.005 * voxel, size=rest.shape)
+    vel = np.zeros_like(rest)
+    xm = 0.5 * nx * voxel
+    lift = np.clip(rest[:, 2] / (height * voxel + voxel), 0.0, 1.0)
+    vel[:, 0] = np.where(rest[:, 0] < xm, speed, -speed) * lift
+    vel[np.isclose(rest[:, 0], xm), 0] = 0.0
+    return Scene("fork_clap", rest, tets, model, E, nu, 1000.0, 0.01, np.zeros(3), [], 0.25 * voxel, iters,
+                 cr_iters, frames, init_pos=init, init_vel=vel, self_contact=True, self_mu=mu)
 
 
 def cube_on_obstacle(kind: str, seed: int = 0, mu: float = 0.5, frames: int = 40) -> Scene:

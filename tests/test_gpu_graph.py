@@ -143,3 +143,32 @@ def test_time_kernel_leaves_the_state_unchanged():
     with pytest.raises(lgsim.SimError):
         sim.time_kernel(3, 1)
     sim.close()
+
+
+@pytest.mark.parametrize("batch", [False, True])
+def test_tolerance_chunks_match_host_checked_iterations(batch):
+    """Frames iterated to NCP residual <= 1e-6 m: replayed chunks with the convergence
+    check on the device (graphs on) against the host reading the residual after every
+    iteration (graphs off).  Same iteration count per frame, same residual, same states
+    bit for bit; on a batch, iterations stop when every scene has converged."""
+    scs = [scenes.cube_drop(0)] if not batch else [scenes.cube_drop(0), scenes.cube_drop(3, nodes=4),
+                                                   scenes.cube_drop(5, nodes=6)]
+    runs = []
+    for graph in (True, False):
+        sim = lgsim.Sim(scs[0], cr_iters=300, cr_tol=1e-3, max_iters=30) if not batch else \
+            lgsim.Sim(batch=scs, cr_iters=300, cr_tol=1e-3, max_iters=30)
+        sim.set_graph(graph)
+        its, out = [], []
+        for f in range(40):
+            st = sim.step(1, iters=0)[0]
+            its.append((st["iters"], st["ncp"]))
+            q, v, con = sim.read_state()
+            out.append((q, con["lam"].copy()))
+        sim.close()
+        runs.append((its, out))
+    print("iterations per frame:", [k for k, _ in runs[0][0]])
+    assert runs[0][0] == runs[1][0]
+    assert max(k for k, _ in runs[0][0]) > 4  # frames that need more than one chunk
+    for (qa, la), (qb, lb) in zip(runs[0][1], runs[1][1]):
+        np.testing.assert_array_equal(qa, qb)
+        np.testing.assert_array_equal(la, lb)

@@ -430,6 +430,32 @@ def test_device_readback_into_torch():
     sim.close()
 
 
+@pytest.mark.parametrize("variant", [0, 1])
+def test_constraint_solve_profile(variant):
+    """sim_profile_cr: the stamped launch makes one device-wide exchange per barrier of
+    the CR form (textbook: 2 per step, pipelined: 1, plus the set-up's), its parts add up
+    within the kernel's duration, and the frame after the measurement equals the frame
+    of a handle that was not measured (impulses restored)."""
+    sc = scenes.cube_drop(0)
+    runs = []
+    for measure in (False, True):
+        sim = make_sim(sc, cr_variant=variant)
+        sim.step(14)
+        if measure:
+            p = sim.profile_cr(5)
+            print(p)
+            assert p["exchanges"] == (2 * 10 if variant == 0 else 10 + 1)
+            assert 0.0 < p["setup_us"] < p["kernel_us"]
+            assert 0.0 < p["barrier_wait_us"] <= p["exchange_us"]
+            assert p["setup_us"] + p["exchanges"] * p["exchange_us"] <= p["kernel_us"] * 1.001
+            assert 0.0 < p["ms_per_launch"] * 1e3
+        sim.step(2)
+        runs.append(sim.read_state())
+        sim.close()
+    np.testing.assert_array_equal(runs[0][0], runs[1][0])
+    np.testing.assert_array_equal(runs[0][2]["lam"], runs[1][2]["lam"])
+
+
 def test_error_paths():
     sc = scenes.cube_drop(0)
     sim = make_sim(sc, max_contacts=4)
