@@ -218,6 +218,45 @@ def warm_drops(params, seeds=(1001, 1002, 1003), frames=60):
     return out
 
 
+def stiffness_sweep(frames):
+    """The stiffness and model sweep: the 40x10x10-node bar (stable Neo-Hookean and
+    Mooney-Rivlin with c10 = c01, E 1e4..1e8, nu 0.4) whose ends turn by +-360 degrees over 400
+    frames while pressed 20% of its height into the plane, mu 0 / 0.2 / 0.8, 10 L-G
+    iterations per frame: ms per frame over `frames` frames, the most contacts at the frames
+    sampled every 50 (and the last), the NCP residual of the last frame, and whether every
+    frame stayed finite."""
+    import numpy as np
+    import torch
+    from paper_2503_15078_amd import lgsim, scenes
+    rows = []
+    for model, mname in ((scenes.MODEL_SNH, "stable_nh"), (scenes.MODEL_MR, "mooney_rivlin")):
+        for E in (1e4, 1e5, 1e6, 1e7, 1e8):
+            for mu in (0.0, 0.2, 0.8):
+                sc = scenes.twist_bar(0, model=model, E=E, nu=0.4, mu=mu)
+                sim = lgsim.Sim(sc)
+                most, ok = 0, True
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                try:
+                    for f in range(frames):
+                        st = sim.step(1, iters=10, stats=(f % 50 == 49 or f == frames - 1))
+                        if st:
+                            most = max(most, int(st[0]["contacts"]))
+                            res = float(st[0]["ncp"])
+                except lgsim.SimError as e:
+                    ok, res = False, str(e)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - a
+                q, v, _ = sim.read_state()
+                sim.close()
+                rows.append({"model": mname, "E": E, "mu": mu, "ms_per_frame": round(1e3 * dt / frames, 3),
+                             "contacts_max": most, "ncp_res_last": res, "finite": ok and bool(np.isfinite(q).all()),
+                             "speed_max": round(float(np.abs(v).max()), 4)})
+    return {"workload": (f"bar 40x10x10 nodes (4000 nodes, 15795 tets), ends turned +-360 deg over 400 frames and "
+                         f"pressed 20% into the plane, 10 L-G iterations/frame, {frames} frames per configuration"),
+            "rows": rows}
+
+
 def batch_throughput(count, steps):
     """A batch of `count` blobs on tilted planes in one handle: scenes x iterations / s, and the
     S-pass bandwidth at a size that does not fit the infinity cache."""
@@ -280,6 +319,8 @@ def main():
     ap.add_argument("--traj-frames", type=int, default=100,
                     help="frames of each to-tolerance trajectory (held-out teaser seeds; 0: none)")
     ap.add_argument("--traj-seeds", type=int, default=1, help="held-out teaser seeds 1000, 1001, ...")
+    ap.add_argument("--sweep-frames", type=int, default=400,
+                    help="frames of each stiffness/model sweep configuration (0: none)")
     ap.add_argument("--batch-only", action="store_true", help="only the batch measurement (for profiling)")
     ap.add_argument("--counter-pass", action="store_true",
                     help="only the fixed S-pass launch sequence for rocprofv3 counters (teaser, or the batch "
@@ -448,6 +489,9 @@ def main():
             **{k: {"precision": r["precision"], "precision_moves": r["precision_moves"],
                    "slide_fraction_by_offset": {str(x["offset"]): round(x["slide_fraction"], 4) for x in r["rows"]}}
                for k, r in ((k, stick_slide.scan(k)) for k in stick_slide.CONFIGS)}}
+    if not args.no_extras and args.sweep_frames > 0:
+        log(f"stiffness and model sweep ({args.sweep_frames} frames each)")
+        extras["stiffness_sweep"] = stiffness_sweep(args.sweep_frames)
     if not args.no_extras and args.batch_scenes > 0:
         log(f"batch of {args.batch_scenes} scenes")
         extras["batch"] = batch_throughput(args.batch_scenes, 10)
