@@ -40,6 +40,7 @@
 
 namespace lg {
 
+constexpr int kCrBlock = 512;         // threads per block: eight wavefronts share a CU's LDS
 constexpr int kCrKFloats = 20480;     // 80 KB of (padded) K rows per block
 constexpr int kCrZFloats = 3 * 2048;  // gathered (padded) Z of the touched scenes
 constexpr int kCrRows = 256;          // max contacts per block
@@ -94,7 +95,7 @@ __device__ inline int grid_barrier(unsigned* ctrs, unsigned b, bool live, int* s
 }
 
 template <int V>
-__global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
+__global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
   if (frame_done(d)) return;
   constexpr int NZ = V == 0 ? 1 : 2;  // vectors exchanged per step
   __shared__ __align__(16) float Ks[kCrKFloats];
@@ -137,13 +138,13 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
   const int nsl = R > 0 ? d.c_scene[j1 - 1] - sfirst + 1 : 0;
 
   // ---- stage per-contact data, slot tables and K rows
-  for (int sl = tid; sl < nsl; sl += kBlock) {
+  for (int sl = tid; sl < nsl; sl += kCrBlock) {
     const int s = sfirst + sl;
     sl_cs[sl] = d.cs_off[s];
     sl_ce[sl] = d.cs_off[s + 1];
     sl_koff[sl] = d.k_off[s];
   }
-  for (int t = tid; t < R; t += kBlock) {
+  for (int t = tid; t < R; t += kCrBlock) {
     int j = j0 + t;
     row_slot[t] = d.c_scene[j] - sfirst;
     for (int q = 0; q < 9; ++q) Cl[q][t] = d.cC[q * CM + j];
@@ -194,11 +195,11 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
     // float4 with eight loads in flight per thread
     const int total4 = sl_kb[nsl] / 4;
     float4* dst = reinterpret_cast<float4*>(Ks);
-    for (int base = 0; base < total4; base += 8 * kBlock) {
+    for (int base = 0; base < total4; base += 8 * kCrBlock) {
       float4 v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int e4 = base + tid + u * kBlock;
+        const int e4 = base + tid + u * kCrBlock;
         if (e4 < total4) {
           const int sl = nsl == 1 ? 0 : slot_of(sl_kb, nsl, 4 * e4);
           const int cs = sl_cs[sl], pc = pad4(sl_ce[sl] - cs);
@@ -208,7 +209,7 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        if (base + tid + u * kBlock < total4) dst[base + tid + u * kBlock] = v[u];
+        if (base + tid + u * kCrBlock < total4) dst[base + tid + u * kCrBlock] = v[u];
     }
   }
 
@@ -218,18 +219,18 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
   auto stage = [&](const float* Vg, int nv) {
     if (nsl == 1) {  // one scene: all loads of a round issued before the stores
       const int cs = sl_cs[0], cnt = sl_ce[0] - cs;
-      for (int base = 0; base < zpad; base += 4 * kBlock) {
+      for (int base = 0; base < zpad; base += 4 * kCrBlock) {
         float v[4][6];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int e = base + tid + u * kBlock;
+          const int e = base + tid + u * kCrBlock;
 #pragma unroll
           for (int q = 0; q < 6; ++q)
             if (q < 3 * nv) v[u][q] = e < cnt ? Vg[q * CM + cs + e] : 0.0f;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int e = base + tid + u * kBlock;
+          const int e = base + tid + u * kCrBlock;
           if (e < zpad)
 #pragma unroll
             for (int q = 0; q < 6; ++q)
@@ -239,11 +240,11 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
       return;
     }
     // several scenes: four elements per thread, all loads of a round issued before the stores
-    for (int base = 0; base < zpad; base += 4 * kBlock) {
+    for (int base = 0; base < zpad; base += 4 * kCrBlock) {
       float v[4][6];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int e = base + tid + u * kBlock;
+        const int e = base + tid + u * kCrBlock;
         const int sl = e < zpad ? slot_of(sl_zb, nsl, e) : 0;
         const int k = e - sl_zb[sl] + sl_cs[sl];
         const bool ok = e < zpad && k < sl_ce[sl];
@@ -252,7 +253,7 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int e = base + tid + u * kBlock;
+        const int e = base + tid + u * kCrBlock;
         if (e < zpad)
 #pragma unroll
           for (int q = 0; q < 6; ++q)
@@ -267,7 +268,7 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
     constexpr int NV = decltype(nv)::value;
     if (k_in_lds && staged) {
       const int grp = tid >> 4, gl = tid & 15;
-      for (int t = grp; t < R; t += kBlock / 16) {
+      for (int t = grp; t < R; t += kCrBlock / 16) {
         const int sl = row_slot[t], cs = sl_cs[sl], pc = pad4(sl_ce[sl] - cs);
         const int rrow = j0 + t - max(cs, j0);
         const float4* K4 = reinterpret_cast<const float4*>(Ks + sl_kb[sl] + rrow * pc);
@@ -299,7 +300,7 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
     // K rows from global memory (or unstaged V): 16 lanes per row, 16 rows in flight;
     // rows are padded to 4 with zero pads and 16-byte aligned in both places
     const int grp = tid >> 4, gl = tid & 15;
-    for (int t = grp; t < R; t += kBlock / 16) {
+    for (int t = grp; t < R; t += kCrBlock / 16) {
       const int sl = row_slot[t], cs = sl_cs[sl], cnt = sl_ce[sl] - cs, pc = pad4(cnt);
       const int rrow = j0 + t - max(cs, j0);
       const float4* K4 = reinterpret_cast<const float4*>(k_in_lds ? Ks + sl_kb[sl] + rrow * pc
@@ -374,14 +375,14 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
   // publish Z_j = C_j^T (Omega_j v_j) for owned contacts as vector `slot` of buffer `buf`
   auto publish_Z = [&](int buf, int slot, float (*v)[kCrRows]) {
     float* Zg = exch(buf) + 3 * slot * CM;
-    for (int t = tid; t < R; t += kBlock) {
+    for (int t = tid; t < R; t += kCrBlock) {
       float ov[3] = {Oml[0][t] * v[0][t], Oml[1][t] * v[1][t], Oml[2][t] * v[2][t]};
       for (int q = 0; q < 3; ++q) Zg[q * CM + j0 + t] = Cl[q][t] * ov[0] + Cl[3 + q][t] * ov[1] + Cl[6 + q][t] * ov[2];
     }
   };
   // out = Omega (C Y) + E~ v (row t), in place into Y
   auto applyM = [&](float (*Y)[kCrRows], float (*v)[kCrRows]) {
-    for (int t = tid; t < R; t += kBlock) {
+    for (int t = tid; t < R; t += kCrBlock) {
       float y[3] = {Y[0][t], Y[1][t], Y[2][t]};
       for (int rr = 0; rr < 3; ++rr) {
         float cy = Cl[3 * rr][t] * y[0] + Cl[3 * rr + 1][t] * y[1] + Cl[3 * rr + 2][t] * y[2];
@@ -391,9 +392,10 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
     __syncthreads();
   };
   // per-scene partial sums of prod[0..nt) over owned contacts -> buffer `buf`
-  auto publish_partials = [&](int buf, int nt) {
+  auto publish_partials = [&](int buf) {
+    constexpr int nt = kCrSlots;
     float* part = d.cr_prod + buf * part_half;
-    for (int sl = wave; sl < nsl; sl += kBlock / kWave) {
+    for (int sl = wave; sl < nsl; sl += kCrBlock / kWave) {
       int t0 = max(sl_cs[sl], j0) - j0, t1 = min(sl_ce[sl], j1) - j0;
       float a[kCrSlots] = {0.0f, 0.0f, 0.0f, 0.0f};
       for (int t = t0 + lane; t < t1; t += kWave)
@@ -408,9 +410,10 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
   // of all blocks holding it, added in block order.  With stage_nv > 0, also stage that
   // many vectors of exchange buffer `buf` into Zs, its loads issued together with the
   // first round of partial-sum loads.
-  auto gather_sums = [&](int buf, int nt, int stage_nv) {
+  auto gather_sums = [&](int buf, int stage_nv) {
+    constexpr int nt = kCrSlots;
     const float* part = d.cr_prod + buf * part_half;
-    for (int sl = wave, round = 0; sl < nsl || round == 0; sl += kBlock / kWave, ++round) {
+    for (int sl = wave, round = 0; sl < nsl || round == 0; sl += kCrBlock / kWave, ++round) {
       const bool mine = sl < nsl;
       int b0 = 0, b1 = -1;
       if (mine) {
@@ -434,7 +437,7 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
   };
   // inner products of one step into prod: (r, w), (w, w), (w, q), (r, r)
   auto products = [&]() {
-    for (int t = tid; t < R; t += kBlock) {
+    for (int t = tid; t < R; t += kCrBlock) {
       float a = 0.0f, b = 0.0f, e = 0.0f, f = 0.0f;
       for (int rr = 0; rr < 3; ++rr) {
         a += vr[rr][t] * vw[rr][t];
@@ -457,7 +460,7 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
   if (z_in_lds) stage(d.X, 1);
   __syncthreads();
   matvec_rows(one, z_in_lds, d.X, vn, vn);
-  for (int t = tid; t < R; t += kBlock) {
+  for (int t = tid; t < R; t += kCrBlock) {
     int j = j0 + t;
     float y[3] = {vn[0][t], vn[1][t], vn[2][t]};
     for (int rr = 0; rr < 3; ++rr) {
@@ -471,15 +474,15 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
   if (bar(true) < 0) return;
   matvec_Z(one, nbar & 1, vw, vw);
   applyM(vw, vr);
-  for (int t = tid; t < R; t += kBlock)
+  for (int t = tid; t < R; t += kCrBlock)
     for (int rr = 0; rr < 3; ++rr) vq[rr][t] = vw[rr][t];  // (w, q) is not used here
   products();
   if constexpr (V == 1) publish_Z((nbar + 1) & 1, 0, vw);
-  publish_partials((nbar + 1) & 1, 4);
+  publish_partials((nbar + 1) & 1);
   if (bar(true) < 0) return;
-  gather_sums(nbar & 1, 4, V == 1 ? 1 : 0);
+  gather_sums(nbar & 1, V == 1 ? 1 : 0);
   data_read();
-  for (int t = tid; t < R; t += kBlock) {
+  for (int t = tid; t < R; t += kCrBlock) {
     s_g[t] = prod[0][t];
     s_qq[t] = prod[1][t];
     s_rr[t] = prod[3][t];
@@ -497,7 +500,7 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
   for (int it = 0; it < d.cr_iters; ++it) {
     // a scene is finished after exact breakdown or once |r| <= tol |r_0|
     int mine = 0;
-    for (int t = tid; t < R; t += kBlock) {
+    for (int t = tid; t < R; t += kCrBlock) {
       float g = s_g[t], qq = s_qq[t];
       bool live = qq != 0.0f && g != 0.0f && !(tol2 > 0.0f && s_rr[t] <= tol2 * s_rr0[t]);
       s_live[t] = live;
@@ -521,25 +524,25 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
       matvec_Z(one, nbar & 1, vw, vw);
       applyM(vw, vr);  // w = M r
       products();
-      publish_partials((nbar + 1) & 1, 4);
+      publish_partials((nbar + 1) & 1);
       if (bar(true) < 0) return;
-      gather_sums(nbar & 1, 4, 0);
+      gather_sums(nbar & 1, 0);
       data_read();
     } else {
       products();  // with the recurrence w~
       publish_Z((nbar + 1) & 1, 0, vw);
       publish_Z((nbar + 1) & 1, 1, vr);
-      publish_partials((nbar + 1) & 1, 4);
+      publish_partials((nbar + 1) & 1);
       const int st = bar(block_live);
       if (st < 0) return;
       if (st == 0) break;
-      gather_sums(nbar & 1, 4, 2);
+      gather_sums(nbar & 1, 2);
       data_read();
       matvec_rows(two, z_in_lds, exch(nbar & 1), vn, vm);
       applyM(vn, vw);  // n = M w~
       applyM(vm, vr);  // true M r
     }
-    for (int t = tid; t < R; t += kBlock) {
+    for (int t = tid; t < R; t += kCrBlock) {
       if (s_live[t]) {
         float g = s_g[t], qq = s_qq[t];
         float g_new = prod[0][t], ww = prod[1][t], wq = prod[2][t];
@@ -560,7 +563,7 @@ __global__ void __launch_bounds__(kBlock) k_cr(Dev d) {
     __syncthreads();
   }
   // lambda += dlambda; F = h^2 C^T (Omega lambda)
-  for (int t = tid; t < R; t += kBlock) {
+  for (int t = tid; t < R; t += kCrBlock) {
     int j = j0 + t;
     float ol[3];
     for (int rr = 0; rr < 3; ++rr) {
@@ -577,9 +580,9 @@ int cr_max_blocks() {
   int dev = 0, cus = 0, per = 0, per1 = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 1;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(k_cr<0>), kBlock, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(k_cr<0>), kCrBlock, 0) !=
           hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per1, reinterpret_cast<const void*>(k_cr<1>), kBlock, 0) !=
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per1, reinterpret_cast<const void*>(k_cr<1>), kCrBlock, 0) !=
           hipSuccess)
     return 1;
   // at most one block per CU is resident (LDS), so the grid must not exceed the CU count
@@ -597,8 +600,8 @@ void launch_zero_cr_sync(const Dev& d, hipStream_t st) {
 }
 
 hipError_t launch_cr(const Dev& d, hipStream_t st, int cr_blocks, int variant) {
-  if (variant == 1) hipLaunchKernelGGL(k_cr<1>, dim3(cr_blocks), dim3(kBlock), 0, st, d);
-  else hipLaunchKernelGGL(k_cr<0>, dim3(cr_blocks), dim3(kBlock), 0, st, d);
+  if (variant == 1) hipLaunchKernelGGL(k_cr<1>, dim3(cr_blocks), dim3(kCrBlock), 0, st, d);
+  else hipLaunchKernelGGL(k_cr<0>, dim3(cr_blocks), dim3(kCrBlock), 0, st, d);
   return hipGetLastError();
 }
 
