@@ -121,7 +121,7 @@ def counter_pass(sim):
     for variant in (0, 1):  # both CR forms at the handle's CR grid
         sim.set_solver(CR_STEPS, 0.0, variant)
         sim.profile_cr(COUNTER_PASS_LAUNCHES)
-        seq.append(("cr", variant, sim.tuning()["cr_blocks"], "plus zeroing and impulse-restoring copies around each launch"))
+        seq.append(("cr", variant, sim.tuning()["cr_blocks"], "then one stamped launch after an impulse-restoring copy"))
     return seq
 
 

@@ -227,15 +227,19 @@ int sim_set_solver(sim_t s, int32_t cr_iters, double cr_tol, int32_t cr_variant)
  * duals).  The state is unchanged. */
 int sim_time_kernel(sim_t s, int32_t which, int32_t reps, float* ms_avg);
 
-/* Measurement of the constraint solve (Sec. 6, CR): `reps` launches (plus one untimed)
- * of the CR kernel on the current contact state, each from the same impulses and timed
- * with its own pair of HIP events on the handle's stream; the last one also records
- * wall-clock stamps of its first block.  out[6]: [0] ms per launch (events), [1] its
- * in-kernel duration (us), [2] set-up until the first exchange (us), [3] mean exchange
- * (us per device-wide exchange: publishing, waiting at the barrier, reading the other
- * blocks' data), [4] mean barrier wait alone (us), [5] exchanges.  Call after a frame or
- * sim_run_iterations (contacts evaluated); impulses are restored, other state is
- * unchanged.  Its buffers are allocated on the first call. */
+/* Measurement of the constraint solve (Sec. 6, CR) on the current contact state: one
+ * untimed launch, then `reps` (1..SIM_PROFILE_MAX_REPS, else SIM_E_ARG) launches back to
+ * back on the handle's stream between one pair of HIP events, each with barrier flags
+ * of its own zeroed before the first; then one launch from the saved impulses that
+ * records wall-clock stamps of its first block.  A launch adds its increment to the
+ * impulses only at its end, so every launch does the same work.  out[6]: [0] ms per
+ * launch (events), [1] the stamped launch's in-kernel duration (us), [2] set-up until the
+ * first exchange (us), [3] mean exchange (us per device-wide exchange: publishing,
+ * waiting at the barrier, reading the other blocks' data), [4] mean barrier wait alone
+ * (us), [5] exchanges.  Call after a frame or sim_run_iterations (contacts evaluated);
+ * impulses are restored, other state is unchanged.  Its buffers are allocated on the
+ * first call. */
+#define SIM_PROFILE_MAX_REPS 64
 int sim_profile_cr(sim_t s, int32_t reps, float* out);
 
 /* Frames with a fixed iteration count are recorded once into a hipGraph (frame setup,

@@ -76,6 +76,7 @@ struct lgsim {
   float* d_tgt = nullptr;             // [CMAX][3] scratch of sim_read_training_pairs
   float* d_lam_save = nullptr;        // [3][CMAX] impulses kept across sim_profile_cr
   unsigned long long* d_clock = nullptr;  // wall-clock stamps of sim_profile_cr
+  unsigned* d_prof_sync = nullptr;    // [SIM_PROFILE_MAX_REPS][kCrSyncWords] CR barrier flags of its launches
   std::vector<int32_t> iter_canon;    // internal contact index -> canonical position
   hipEvent_t ev[8] = {};
   std::vector<hipEvent_t> fev;        // per-frame timing events
@@ -624,7 +625,7 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   // two exchange buffers alternating per barrier, each with up to two 3-vectors
   TRY(s->alloc(d.cr_Z, 2 * 2 * 3 * (size_t)CM));
   TRY(s->alloc(d.cr_prod, (size_t)lg::cr_partial_floats(lg::kCrMaxBlocks, std::max(1, NS))));
-  TRY(s->alloc(d.cr_sync, lg::kCrMaxBarriers + 1));
+  TRY(s->alloc(d.cr_sync, lg::kCrSyncWords));
   TRY(s->alloc(d.t, 1));
   TRY(s->alloc(d.res, NS));
   TRY(s->alloc(d.bad, 4));
@@ -1304,8 +1305,8 @@ int sim_time_kernel(sim_t s, int32_t which, int32_t reps, float* ms_avg) {
 }
 
 int sim_profile_cr(sim_t s, int32_t reps, float* out) {
-  if (!s || reps <= 0 || !out) {
-    lg::set_error("bad arguments");
+  if (!s || reps <= 0 || reps > SIM_PROFILE_MAX_REPS || !out) {
+    lg::set_error("bad arguments (reps in 1.." + std::to_string(SIM_PROFILE_MAX_REPS) + ")");
     return SIM_E_ARG;
   }
   auto& d = s->d;
@@ -1317,25 +1318,36 @@ int sim_profile_cr(sim_t s, int32_t reps, float* out) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  float total = 0.0f;
+  // Launch durations: `reps` launches back to back between one pair of events (events
+  // around every launch would add their own latency), each launch with barrier flags of
+  // its own, all zeroed before the first.  A launch adds its increment to lambda only at
+  // its end, so repeated launches from one state do the same work.
+  const size_t stride = lg::kCrSyncWords;
+  if (!s->d_prof_sync) TRY(s->alloc(s->d_prof_sync, stride * SIM_PROFILE_MAX_REPS));
   hipError_t cr_err = hipSuccess;
-  lg::Dev dc = d;
-  dc.cr_clock = s->d_clock;
-  for (int r = 0; r <= reps && cr_err == hipSuccess; ++r) {  // launch 0 warms up, the last one is stamped
-    HIPCHK(hipMemcpyAsync(d.lam, s->d_lam_save, lam_bytes, hipMemcpyDeviceToDevice, s->st));
-    lg::launch_zero_cr_sync(d, s->st);
-    if (r == reps) HIPCHK(hipMemsetAsync(s->d_clock, 0, ncl * sizeof(unsigned long long), s->st));
-    HIPCHK(hipEventRecord(e0, s->st));
-    cr_err = lg::launch_cr(r == reps ? dc : d, s->st, s->cr_blocks, s->opt.cr_variant);
-    HIPCHK(hipEventRecord(e1, s->st));
-    HIPCHK(hipEventSynchronize(e1));
-    float ms = 0.0f;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    if (r > 0) total += ms;
+  float ms_all = 0.0f;
+  lg::launch_zero_cr_sync(d, s->st);
+  cr_err = lg::launch_cr(d, s->st, s->cr_blocks, s->opt.cr_variant);  // warm-up
+  HIPCHK(hipMemsetAsync(s->d_prof_sync, 0, stride * reps * sizeof(unsigned), s->st));
+  lg::Dev dr = d;
+  HIPCHK(hipEventRecord(e0, s->st));
+  for (int r = 0; r < reps && cr_err == hipSuccess; ++r) {
+    dr.cr_sync = s->d_prof_sync + stride * r;
+    cr_err = lg::launch_cr(dr, s->st, s->cr_blocks, s->opt.cr_variant);
   }
+  HIPCHK(hipEventRecord(e1, s->st));
+  HIPCHK(hipEventSynchronize(e1));
+  HIPCHK(hipEventElapsedTime(&ms_all, e0, e1));
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   HIPCHK(cr_err);
+  // one more launch from the saved state with block 0's wall-clock stamps
+  lg::Dev dc = d;
+  dc.cr_clock = s->d_clock;
+  HIPCHK(hipMemcpyAsync(d.lam, s->d_lam_save, lam_bytes, hipMemcpyDeviceToDevice, s->st));
+  lg::launch_zero_cr_sync(d, s->st);
+  HIPCHK(hipMemsetAsync(s->d_clock, 0, ncl * sizeof(unsigned long long), s->st));
+  HIPCHK(lg::launch_cr(dc, s->st, s->cr_blocks, s->opt.cr_variant));
   HIPCHK(hipMemcpyAsync(d.lam, s->d_lam_save, lam_bytes, hipMemcpyDeviceToDevice, s->st));
   std::vector<unsigned long long> clk(ncl);
   HIPCHK(hipMemcpyAsync(clk.data(), s->d_clock, ncl * sizeof(unsigned long long), hipMemcpyDeviceToHost, s->st));
@@ -1353,7 +1365,7 @@ int sim_profile_cr(sim_t s, int32_t reps, float* out) {
     exch += (double)((t_data ? t_data : t_out) - t_in) * us;
     ++nb;
   }
-  out[0] = total / reps;
+  out[0] = ms_all / reps;
   out[1] = (float)((double)(clk[1] - clk[0]) * us);
   out[2] = nb ? (float)((double)(clk[2] - clk[0]) * us) : 0.0f;
   out[3] = nb ? (float)(exch / nb) : 0.0f;

@@ -25,7 +25,11 @@ constexpr int kMaxCrIters = 1024;
 constexpr int kMlpParams = 20752;   // 16x128 + 128 + 128x128 + 128 + 16x128 + 16 (padded shapes)
 constexpr int kMlpMaxBlocks = 256;  // blocks of one training launch (64 samples each)
 constexpr int kMlpMaxBatch = 64 * kMlpMaxBlocks;
-constexpr int kCrMaxBlocks = 1024;  // blocks of the CR launch (partial sums)
+constexpr int kCrMaxBlocks = 256;   // blocks of the CR launch, at most one per CU
+// arrival flags of the CR launch's device-wide barriers: two slots (barrier parity) of one
+// flag per block, each flag on its own 128-byte line
+constexpr int kCrFlagStride = 32;
+constexpr int kCrSyncWords = 2 * kCrMaxBlocks * kCrFlagStride;
 // scenes of one handle: a CR block keeps a slot per scene between its first and last
 // contact (empty scenes included), in LDS tables of this many entries
 constexpr int kMaxScenes = 256;
@@ -121,7 +125,7 @@ struct Dev {
   float *Om, *Et, *hv, *X, *F;     // hv: h_vec - Omega H u (delta form)
   float *cr_Z;                     // [2][2][3][CMAX] exchanged C^T (Omega v) of the CR launch
   float *cr_prod;                  // per-(block, scene slot) partial sums of the CR launch
-  unsigned *cr_sync;               // [kCrMaxBarriers + 1] arrival counters of the CR launch
+  unsigned *cr_sync;               // [kCrSyncWords] barrier arrival flags of the CR launch
   unsigned long long *cr_clock;    // null, or [2 + 3 kCrMaxBarriers] wall-clock stamps of CR block 0
   float cr_tol;                    // relative CR residual tolerance (0: fixed count)
   // learned warm start

@@ -946,8 +946,8 @@ __global__ void __launch_bounds__(kBlock) k_contact_prep(Dev d) {
   const int j = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
   const int lane = threadIdx.x & (kWave - 1);
   const int c = min(d.n_contacts[0], d.CMAX);
-  if (blockIdx.x == 0)  // barrier counters of the CR launch that follows
-    for (int k = threadIdx.x; k <= min(2 * d.cr_iters + 2, kCrMaxBarriers); k += blockDim.x) d.cr_sync[k] = 0u;
+  if (blockIdx.x == 0)  // barrier flags of the CR launch that follows
+    for (int k = threadIdx.x; k < 2 * kCrMaxBlocks; k += blockDim.x) d.cr_sync[k * kCrFlagStride] = 0u;
   if (j >= c) return;
   const int CM = d.CMAX;
   // entries of the row: its node with sign 1, or a self row's vertex and triangle corners

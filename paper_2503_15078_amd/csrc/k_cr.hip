@@ -27,11 +27,12 @@
 // block owns a contiguous range of contacts; its rows of K, its slices of the vectors and
 // the gathered Z = C^T (Omega v) of the scenes it touches live in LDS, every row and
 // every scene's slice padded to a multiple of 4 floats so the products run on float4.  Blocks publish their slices
-// of Z and per-scene partial sums, then meet the others at a device-wide barrier (an
-// agent-scope arrival counter per barrier).  Exchange buffers alternate with the barrier's
-// parity, since a block may publish step k+1 while another still reads step k.  Partial
-// sums are combined in block order, so results are deterministic.  The launch ends early
-// when no block has a running scene, a decision every block reads from the same counter.
+// of Z and per-scene partial sums, then meet the others at a device-wide barrier (one
+// agent-scope arrival flag per block, polled by every block).  Exchange buffers alternate
+// with the barrier's parity, since a block may publish step k+1 while another still reads
+// step k.  Partial sums are combined in block order, so results are deterministic.  The
+// launch ends early when no block has a running scene, a decision every block reads from
+// the same flags.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -65,29 +66,46 @@ __device__ inline int slot_of(const int* a, int n, int e) {
   return lo;
 }
 
-// Device-wide barrier number b (b = 1, 2, ...), one arrival counter per barrier number,
-// zeroed by the contact kernel that precedes the launch.  Thread 0 of a block adds 1,
-// plus 2^16 while the block still has a running scene, with an agent-scope release
-// (after the block barrier, so the block's global writes are published); it leaves once
-// the low 16 bits reach G and acquires.  The high bits then hold the same live count in
-// every block.  Returns 1 (some block live), 0 (none) or -1 (the wait was abandoned;
-// the failure flags are set).
-__device__ inline int grid_barrier(unsigned* ctrs, unsigned b, bool live, int* s_st, int* fail) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned* ctr = ctrs + b;
-    __hip_atomic_fetch_add(ctr, live ? 0x10001u : 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned v, polls = 0;
-    while (((v = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) & 0xFFFFu) < gridDim.x &&
-           ++polls < kCrSpinLimit)
+// Device-wide barrier number b (b = 1, 2, ...) by arrival flags, zeroed by the contact
+// kernel that precedes the launch.  After the block barrier (which also ORs `live` over
+// the block), thread 0 stores 2 b + live into the block's flag of slot b mod 2 with an
+// agent-scope release; wave 0 then polls the G flags of that slot, one per lane, with
+// relaxed agent-scope loads until each holds barrier b, and acquires.  No block can pass
+// barrier b + 1 before every block has arrived there, so the slot of b holds b or b - 2
+// until all blocks have arrived at b.  Each block's flag lies on its own 128-byte line, so
+// the arrivals are stores to G lines, not G atomic updates of one word.  Returns 1 (some
+// block passed live), 0 (none) or -1 (the wait was abandoned; the failure flags are set).
+__device__ inline int grid_barrier(unsigned* flags, unsigned b, bool live, int* s_st, int* fail) {
+  live = __syncthreads_or(live ? 1 : 0) != 0;
+  if (threadIdx.x < kWave) {
+    const unsigned G = gridDim.x;
+    unsigned* slot = flags + (size_t)(b & 1u) * kCrMaxBlocks * kCrFlagStride;
+    if (threadIdx.x == 0)
+      __hip_atomic_store(slot + blockIdx.x * kCrFlagStride, 2u * b + (live ? 1u : 0u), __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    unsigned polls = 0;
+    bool done = false, any = false;
+    for (;;) {
+      bool ok = true, lv = false;
+      for (unsigned k = threadIdx.x; k < G; k += kWave) {
+        const unsigned v = __hip_atomic_load(slot + k * kCrFlagStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = ok && (v >> 1) == b;
+        lv = lv || (v & 1u) != 0u;
+      }
+      done = __all(ok);
+      any = __any(lv);
+      if (done || ++polls >= kCrSpinLimit) break;
       __builtin_amdgcn_s_sleep(1);
+    }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if ((v & 0xFFFFu) < gridDim.x) {
-      __hip_atomic_store(fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);      // frame not valid
-      __hip_atomic_store(fail + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // cause: CR barrier
-      *s_st = -1;
-    } else {
-      *s_st = (v >> 16) != 0u ? 1 : 0;
+    if (threadIdx.x == 0) {
+      if (!done) {
+        __hip_atomic_store(fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);      // frame not valid
+        __hip_atomic_store(fail + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // cause: CR barrier
+        *s_st = -1;
+      } else {
+        *s_st = any ? 1 : 0;
+      }
     }
   }
   __syncthreads();
@@ -122,7 +140,7 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
     if (clk && threadIdx.x == 0) clk[idx] = wall_clock64();
   };
   stamp(0);
-  unsigned* ctrs = d.cr_sync;
+  unsigned* flags = d.cr_sync;
   int* fail = d.bad;  // [0]: frame invalid, [1]: the CR barrier was abandoned
   const unsigned G = gridDim.x;
   unsigned nbar = 0;
@@ -261,10 +279,11 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
       }
     }
   };
-  // Y_v,t = sum_k K_jk V_v,k for every owned row t and nv vectors, 16 lanes per row (16
-  // rows per pass).  staged: V in Zs; else V_v,k component q at Vg[(3 v + q) CM + k] in
+  // Y_v,t = sum_k K_jk V_v,k for every owned row t and nv vectors, 16 lanes per row (32
+  // rows per pass); the first lane of each row's group then calls fin(t, Y) with the 3 nv
+  // sums of its row.  staged: V in Zs; else V_v,k component q at Vg[(3 v + q) CM + k] in
   // global memory.  K rows and V both in LDS: float4 over the padded columns.
-  auto matvec_rows = [&](auto nv, bool staged, const float* Vg, float (*Y0)[kCrRows], float (*Y1)[kCrRows]) {
+  auto matvec_rows = [&](auto nv, bool staged, const float* Vg, auto fin) {
     constexpr int NV = decltype(nv)::value;
     if (k_in_lds && staged) {
       const int grp = tid >> 4, gl = tid & 15;
@@ -288,11 +307,7 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
 #pragma unroll
         for (int q = 0; q < 3 * NV; ++q)
           for (int o = 8; o > 0; o >>= 1) a[q] += __shfl_xor(a[q], o, 16);
-        if (gl == 0) {
-          for (int q = 0; q < 3; ++q) Y0[q][t] = a[q];
-          if constexpr (NV == 2)
-            for (int q = 0; q < 3; ++q) Y1[q][t] = a[3 + q];
-        }
+        if (gl == 0) fin(t, a);
       }
       __syncthreads();
       return;
@@ -344,11 +359,7 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
 #pragma unroll
       for (int q = 0; q < 3 * NV; ++q)
         for (int o = 8; o > 0; o >>= 1) a[q] += __shfl_xor(a[q], o, 16);
-      if (gl == 0) {
-        for (int q = 0; q < 3; ++q) Y0[q][t] = a[q];
-        if constexpr (NV == 2)
-          for (int q = 0; q < 3; ++q) Y1[q][t] = a[3 + q];
-      }
+      if (gl == 0) fin(t, a);
     }
     __syncthreads();
   };
@@ -357,39 +368,33 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
   auto bar = [&](bool live) {
     ++nbar;
     stamp(2 + 3 * (nbar - 1));
-    const int r = grid_barrier(ctrs, nbar, live, &s_st, fail);
+    const int r = grid_barrier(flags, nbar, live, &s_st, fail);
     stamp(3 + 3 * (nbar - 1));
     return r;
   };
   auto data_read = [&]() { stamp(4 + 3 * (nbar - 1)); };
   // K times the first nv vectors of exchange buffer `buf`, staged into Zs when they fit
   auto exch = [&](int buf) { return d.cr_Z + (int64_t)buf * 3 * NZ * CM; };
-  auto matvec_Z = [&](auto nv, int buf, float (*Y0)[kCrRows], float (*Y1)[kCrRows]) {
+  auto matvec_Z = [&](auto nv, int buf, auto fin) {
     if (z_in_lds) {
       stage(exch(buf), decltype(nv)::value);
       __syncthreads();
     }
     data_read();
-    matvec_rows(nv, z_in_lds, exch(buf), Y0, Y1);
+    matvec_rows(nv, z_in_lds, exch(buf), fin);
   };
-  // publish Z_j = C_j^T (Omega_j v_j) for owned contacts as vector `slot` of buffer `buf`
-  auto publish_Z = [&](int buf, int slot, float (*v)[kCrRows]) {
+  // publish Z_j = C_j^T (Omega_j v_j) of owned row t as vector `slot` of buffer `buf`
+  auto publish_Z = [&](int buf, int slot, int t, float (*v)[kCrRows]) {
     float* Zg = exch(buf) + 3 * slot * CM;
-    for (int t = tid; t < R; t += kCrBlock) {
-      float ov[3] = {Oml[0][t] * v[0][t], Oml[1][t] * v[1][t], Oml[2][t] * v[2][t]};
-      for (int q = 0; q < 3; ++q) Zg[q * CM + j0 + t] = Cl[q][t] * ov[0] + Cl[3 + q][t] * ov[1] + Cl[6 + q][t] * ov[2];
-    }
+    float ov[3] = {Oml[0][t] * v[0][t], Oml[1][t] * v[1][t], Oml[2][t] * v[2][t]};
+    for (int q = 0; q < 3; ++q) Zg[q * CM + j0 + t] = Cl[q][t] * ov[0] + Cl[3 + q][t] * ov[1] + Cl[6 + q][t] * ov[2];
   };
-  // out = Omega (C Y) + E~ v (row t), in place into Y
-  auto applyM = [&](float (*Y)[kCrRows], float (*v)[kCrRows]) {
-    for (int t = tid; t < R; t += kCrBlock) {
-      float y[3] = {Y[0][t], Y[1][t], Y[2][t]};
-      for (int rr = 0; rr < 3; ++rr) {
-        float cy = Cl[3 * rr][t] * y[0] + Cl[3 * rr + 1][t] * y[1] + Cl[3 * rr + 2][t] * y[2];
-        Y[rr][t] = Oml[rr][t] * cy + Etl[rr][t] * v[rr][t];
-      }
+  // row t of M: out = Omega (C y) + E~ v, with y = (K Z)_t from the matvec
+  auto rowM = [&](int t, const float* y, float (*v)[kCrRows], float (*out)[kCrRows]) {
+    for (int rr = 0; rr < 3; ++rr) {
+      float cy = Cl[3 * rr][t] * y[0] + Cl[3 * rr + 1][t] * y[1] + Cl[3 * rr + 2][t] * y[2];
+      out[rr][t] = Oml[rr][t] * cy + Etl[rr][t] * v[rr][t];
     }
-    __syncthreads();
   };
   // per-scene partial sums of prod[0..nt) over owned contacts -> buffer `buf`
   auto publish_partials = [&](int buf) {
@@ -435,22 +440,19 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
     }
     __syncthreads();
   };
-  // inner products of one step into prod: (r, w), (w, w), (w, q), (r, r)
-  auto products = [&]() {
-    for (int t = tid; t < R; t += kCrBlock) {
-      float a = 0.0f, b = 0.0f, e = 0.0f, f = 0.0f;
-      for (int rr = 0; rr < 3; ++rr) {
-        a += vr[rr][t] * vw[rr][t];
-        b += vw[rr][t] * vw[rr][t];
-        e += vw[rr][t] * vq[rr][t];
-        f += vr[rr][t] * vr[rr][t];
-      }
-      prod[0][t] = a;
-      prod[1][t] = b;
-      prod[2][t] = e;
-      prod[3][t] = f;
+  // inner products of one step for row t into prod: (r, w), (w, w), (w, q), (r, r)
+  auto row_products = [&](int t) {
+    float a = 0.0f, b = 0.0f, e = 0.0f, f = 0.0f;
+    for (int rr = 0; rr < 3; ++rr) {
+      a += vr[rr][t] * vw[rr][t];
+      b += vw[rr][t] * vw[rr][t];
+      e += vw[rr][t] * vq[rr][t];
+      f += vr[rr][t] * vr[rr][t];
     }
-    __syncthreads();
+    prod[0][t] = a;
+    prod[1][t] = b;
+    prod[2][t] = e;
+    prod[3][t] = f;
   };
   const std::integral_constant<int, 1> one{};
   const std::integral_constant<int, 2> two{};
@@ -459,25 +461,23 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
   // (X = C^T (Omega lambda) from the contact kernel)
   if (z_in_lds) stage(d.X, 1);
   __syncthreads();
-  matvec_rows(one, z_in_lds, d.X, vn, vn);
-  for (int t = tid; t < R; t += kCrBlock) {
-    int j = j0 + t;
-    float y[3] = {vn[0][t], vn[1][t], vn[2][t]};
+  matvec_rows(one, z_in_lds, d.X, [&](int t, const float* a) {
+    const int j = j0 + t;
     for (int rr = 0; rr < 3; ++rr) {
-      float cy = Cl[3 * rr][t] * y[0] + Cl[3 * rr + 1][t] * y[1] + Cl[3 * rr + 2][t] * y[2];
+      float cy = Cl[3 * rr][t] * a[0] + Cl[3 * rr + 1][t] * a[1] + Cl[3 * rr + 2][t] * a[2];
       vx[rr][t] = 0.0f;
       vr[rr][t] = (d.hv[rr * CM + j] - Oml[rr][t] * h2 * cy) / h2;
     }
-  }
-  __syncthreads();
-  publish_Z((nbar + 1) & 1, 0, vr);
+    publish_Z((nbar + 1) & 1, 0, t, vr);
+  });
   if (bar(true) < 0) return;
-  matvec_Z(one, nbar & 1, vw, vw);
-  applyM(vw, vr);
-  for (int t = tid; t < R; t += kCrBlock)
-    for (int rr = 0; rr < 3; ++rr) vq[rr][t] = vw[rr][t];  // (w, q) is not used here
-  products();
-  if constexpr (V == 1) publish_Z((nbar + 1) & 1, 0, vw);
+  // w = M r, q = w ((w, q) is not used here), the step's products
+  matvec_Z(one, nbar & 1, [&](int t, const float* a) {
+    rowM(t, a, vr, vw);
+    for (int rr = 0; rr < 3; ++rr) vq[rr][t] = vw[rr][t];
+    row_products(t);
+    if constexpr (V == 1) publish_Z((nbar + 1) & 1, 0, t, vw);
+  });
   publish_partials((nbar + 1) & 1);
   if (bar(true) < 0) return;
   gather_sums(nbar & 1, V == 1 ? 1 : 0);
@@ -489,61 +489,19 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
     s_rr0[t] = prod[3][t];
     for (int rr = 0; rr < 3; ++rr) vp[rr][t] = vr[rr][t];
   }
-  if constexpr (V == 1) {
-    matvec_rows(one, z_in_lds, exch(nbar & 1), vz, vz);  // z = M q = M w
-    applyM(vz, vw);
-  } else {
-    __syncthreads();
-  }
+  if constexpr (V == 1)  // z = M q = M w
+    matvec_rows(one, z_in_lds, exch(nbar & 1), [&](int t, const float* a) { rowM(t, a, vw, vz); });
 
+  // Each step: the previous step's direction update (beta), then this step's update of
+  // x and r (alpha) and, unless it is the last, what the exchange needs, all row by row
+  // without block barriers; the exchange; the products with K, each row finished (M, the
+  // inner products) by the lane that summed it.
   const float tol2 = d.cr_tol * d.cr_tol;
   for (int it = 0; it < d.cr_iters; ++it) {
-    // a scene is finished after exact breakdown or once |r| <= tol |r_0|
+    const bool last = it + 1 == d.cr_iters;
     int mine = 0;
     for (int t = tid; t < R; t += kCrBlock) {
-      float g = s_g[t], qq = s_qq[t];
-      bool live = qq != 0.0f && g != 0.0f && !(tol2 > 0.0f && s_rr[t] <= tol2 * s_rr0[t]);
-      s_live[t] = live;
-      mine |= live ? 1 : 0;
-      if (live) {
-        float alpha = g / qq;
-        for (int rr = 0; rr < 3; ++rr) {
-          vx[rr][t] += alpha * vp[rr][t];
-          vr[rr][t] -= alpha * vq[rr][t];
-          if constexpr (V == 1) vw[rr][t] -= alpha * vz[rr][t];
-        }
-      }
-    }
-    const bool block_live = __syncthreads_or(mine) != 0;
-    if (it + 1 == d.cr_iters) break;
-    if constexpr (V == 0) {
-      publish_Z((nbar + 1) & 1, 0, vr);
-      const int st = bar(block_live);
-      if (st < 0) return;
-      if (st == 0) break;
-      matvec_Z(one, nbar & 1, vw, vw);
-      applyM(vw, vr);  // w = M r
-      products();
-      publish_partials((nbar + 1) & 1);
-      if (bar(true) < 0) return;
-      gather_sums(nbar & 1, 0);
-      data_read();
-    } else {
-      products();  // with the recurrence w~
-      publish_Z((nbar + 1) & 1, 0, vw);
-      publish_Z((nbar + 1) & 1, 1, vr);
-      publish_partials((nbar + 1) & 1);
-      const int st = bar(block_live);
-      if (st < 0) return;
-      if (st == 0) break;
-      gather_sums(nbar & 1, 2);
-      data_read();
-      matvec_rows(two, z_in_lds, exch(nbar & 1), vn, vm);
-      applyM(vn, vw);  // n = M w~
-      applyM(vm, vr);  // true M r
-    }
-    for (int t = tid; t < R; t += kCrBlock) {
-      if (s_live[t]) {
+      if (it > 0 && s_live[t]) {
         float g = s_g[t], qq = s_qq[t];
         float g_new = prod[0][t], ww = prod[1][t], wq = prod[2][t];
         float beta = g_new / g;
@@ -559,8 +517,55 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
         s_qq[t] = ww + 2.0f * beta * wq + beta * beta * qq;
         s_rr[t] = prod[3][t];
       }
+      // a scene is finished after exact breakdown or once |r| <= tol |r_0|
+      float g = s_g[t], qq = s_qq[t];
+      bool live = qq != 0.0f && g != 0.0f && !(tol2 > 0.0f && s_rr[t] <= tol2 * s_rr0[t]);
+      s_live[t] = live;
+      mine |= live ? 1 : 0;
+      if (live) {
+        float alpha = g / qq;
+        for (int rr = 0; rr < 3; ++rr) {
+          vx[rr][t] += alpha * vp[rr][t];
+          vr[rr][t] -= alpha * vq[rr][t];
+          if constexpr (V == 1) vw[rr][t] -= alpha * vz[rr][t];
+        }
+      }
+      if (!last) {
+        if constexpr (V == 0) {
+          publish_Z((nbar + 1) & 1, 0, t, vr);
+        } else {
+          row_products(t);  // with the recurrence w~
+          publish_Z((nbar + 1) & 1, 0, t, vw);
+          publish_Z((nbar + 1) & 1, 1, t, vr);
+        }
+      }
     }
-    __syncthreads();
+    if (last) break;
+    if constexpr (V == 0) {
+      const int st = bar(mine != 0);
+      if (st < 0) return;
+      if (st == 0) break;
+      matvec_Z(one, nbar & 1, [&](int t, const float* a) {
+        rowM(t, a, vr, vw);  // w = M r
+        row_products(t);
+      });
+      publish_partials((nbar + 1) & 1);
+      if (bar(true) < 0) return;
+      gather_sums(nbar & 1, 0);
+      data_read();
+    } else {
+      __syncthreads();  // every row's products before the partial sums
+      publish_partials((nbar + 1) & 1);
+      const int st = bar(mine != 0);
+      if (st < 0) return;
+      if (st == 0) break;
+      gather_sums(nbar & 1, 2);
+      data_read();
+      matvec_rows(two, z_in_lds, exch(nbar & 1), [&](int t, const float* a) {
+        rowM(t, a, vw, vn);      // n = M w~
+        rowM(t, a + 3, vr, vm);  // true M r
+      });
+    }
   }
   // lambda += dlambda; F = h^2 C^T (Omega lambda)
   for (int t = tid; t < R; t += kCrBlock) {
@@ -592,7 +597,7 @@ int cr_max_blocks() {
 int64_t cr_partial_floats(int blocks, int scenes) { return 2 * (int64_t)scenes * blocks * kCrSlots; }
 
 __global__ void k_zero_cr_sync(Dev d) {
-  for (int k = threadIdx.x; k <= min(2 * d.cr_iters + 2, kCrMaxBarriers); k += blockDim.x) d.cr_sync[k] = 0u;
+  for (int k = threadIdx.x; k < 2 * kCrMaxBlocks; k += blockDim.x) d.cr_sync[k * kCrFlagStride] = 0u;
 }
 
 void launch_zero_cr_sync(const Dev& d, hipStream_t st) {
@@ -600,6 +605,7 @@ void launch_zero_cr_sync(const Dev& d, hipStream_t st) {
 }
 
 hipError_t launch_cr(const Dev& d, hipStream_t st, int cr_blocks, int variant) {
+  if (cr_blocks < 1 || cr_blocks > kCrMaxBlocks) return hipErrorInvalidValue;  // barrier flag slots
   if (variant == 1) hipLaunchKernelGGL(k_cr<1>, dim3(cr_blocks), dim3(kCrBlock), 0, st, d);
   else hipLaunchKernelGGL(k_cr<0>, dim3(cr_blocks), dim3(kCrBlock), 0, st, d);
   return hipGetLastError();

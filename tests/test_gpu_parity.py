@@ -448,7 +448,9 @@ def test_constraint_solve_profile(variant):
             assert 0.0 < p["setup_us"] < p["kernel_us"]
             assert 0.0 < p["barrier_wait_us"] <= p["exchange_us"]
             assert p["setup_us"] + p["exchanges"] * p["exchange_us"] <= p["kernel_us"] * 1.001
-            assert 0.0 < p["ms_per_launch"] * 1e3
+            assert 0.0 < p["kernel_us"] <= 1.5 * p["ms_per_launch"] * 1e3
+            with pytest.raises(lgsim.SimError):
+                sim.profile_cr(65)  # beyond the profile's counter sets
         sim.step(2)
         runs.append(sim.read_state())
         sim.close()
