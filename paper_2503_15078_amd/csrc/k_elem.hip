@@ -158,23 +158,35 @@ __device__ void svd3(const float F[3][3], float U[3][3], float s[3], float V[3][
 // SNH    psi = mu/2 (Ic-3) + lam/2 (J-alpha)^2 - mu/2 log(Ic+1), alpha = 1 + 3mu/(4lam)
 // MR     psi = c (J^-2/3 I1 - 3) + c (J^-4/3 I2 - 3) + kap/2 (J-1)^2, c = mu/4,
 //        kap = lam + 2mu/3, J clamped below at 1e-4 in the isochoric factors
-__device__ float psi(int model, const float s[3], float mu, float lam) {
+// psi, and in mag the sum of the magnitudes of its terms: the scale of its float32
+// rounding error, which cancellation between the terms can leave far above |psi|
+__device__ float psi_m(int model, const float s[3], float mu, float lam, float& mag) {
   float J = s[0] * s[1] * s[2];
   float I1 = s[0] * s[0] + s[1] * s[1] + s[2] * s[2];
   if (model == 1) {
     float a = s[0] - 1.0f, b = s[1] - 1.0f, c = s[2] - 1.0f;
-    return mu * (a * a + b * b + c * c) + 0.5f * lam * (J - 1.0f) * (J - 1.0f);
+    float v = mu * (a * a + b * b + c * c) + 0.5f * lam * (J - 1.0f) * (J - 1.0f);
+    mag = v;
+    return v;
   }
   if (model == 2) {
     float alpha = 1.0f + 0.75f * mu * rcp1(lam);
-    return 0.5f * mu * (I1 - 3.0f) + 0.5f * lam * (J - alpha) * (J - alpha) - 0.5f * mu * __logf(I1 + 1.0f);
+    float vol = 0.5f * lam * (J - alpha) * (J - alpha), lg = 0.5f * mu * __logf(I1 + 1.0f);
+    mag = 0.5f * mu * (I1 + 3.0f) + vol + fabsf(lg);
+    return 0.5f * mu * (I1 - 3.0f) + vol - lg;
   }
   float q0 = s[0] * s[0], q1 = s[1] * s[1], q2 = s[2] * s[2];
   float I2 = q0 * q1 + q0 * q2 + q1 * q2;
   float Jh = fmaxf(J, 1e-4f);
   float jm23 = 1.0f / (cbrtf(Jh) * cbrtf(Jh));
   float c10 = 0.25f * mu, kap = lam + 2.0f * mu / 3.0f;
-  return c10 * (jm23 * I1 - 3.0f) + c10 * (jm23 * jm23 * I2 - 3.0f) + 0.5f * kap * (J - 1.0f) * (J - 1.0f);
+  float vol = 0.5f * kap * (J - 1.0f) * (J - 1.0f);
+  mag = c10 * (jm23 * I1 + 3.0f) + c10 * (jm23 * jm23 * I2 + 3.0f) + vol;
+  return c10 * (jm23 * I1 - 3.0f) + c10 * (jm23 * jm23 * I2 - 3.0f) + vol;
+}
+__device__ inline float psi(int model, const float s[3], float mu, float lam) {
+  float mag;
+  return psi_m(model, s, mu, lam, mag);
 }
 
 __device__ void psi_grad_hess(int model, const float s[3], float mu, float lam, float g[3], float H[3][3]) {
@@ -255,7 +267,12 @@ __device__ inline bool chol3_solve(const float K[3][3], float tau, const float r
 }
 
 // s* = argmin k/2 |s - sigma|^2 + psi(s): Newton from sigma with the shifted-Hessian
-// rule (tau = 0, 1e-2 k, 1e-1 k, ...) and Armijo halving, at most 8 iterations.
+// rule (tau = 0, 1e-2 k, 1e-1 k, ...) and Armijo halving, at most 8 iterations.  The
+// objective is evaluated in float32, so a decrease below its rounding error cannot be
+// tested: the Armijo test allows 8 ulp of the magnitude of the objective's terms.
+// Without that allowance, steps near the minimiser are rejected on rounding noise: the
+// line search halves the step to nothing and Newton stops early or runs to its cap
+// farther from the minimiser, while every lane of the wavefront waits.
 __device__ void prox3(int model, const float sig[3], float mu, float lam, float k, float s[3]) {
   s[0] = sig[0];
   s[1] = sig[1];
@@ -264,8 +281,9 @@ __device__ void prox3(int model, const float sig[3], float mu, float lam, float 
     s[0] = s[1] = s[2] = 1.0f;
     return;
   }
+  constexpr float kRound = 8.0f * 1.1920929e-7f;  // 8 ulp (float32 epsilon 2^-23)
   float scale = fmaxf(1.0f, fmaxf(fabsf(sig[0]), fmaxf(fabsf(sig[1]), fabsf(sig[2]))));
-  float f0 = 0.0f;  // objective at s
+  float f0 = 0.0f, m0 = 0.0f;  // objective at s and the magnitude of its terms
   bool have_f0 = false;
   for (int it = 0; it < 8; ++it) {
     float g[3], H[3][3];
@@ -288,7 +306,9 @@ __device__ void prox3(int model, const float sig[3], float mu, float lam, float 
     float slope = g[0] * dx[0] + g[1] * dx[1] + g[2] * dx[2];
     if (!have_f0) {  // later iterations start from the accepted line-search value
       float a = s[0] - sig[0], b = s[1] - sig[1], c = s[2] - sig[2];
-      f0 = psi(model, s, mu, lam) + 0.5f * k * (a * a + b * b + c * c);
+      const float prox = 0.5f * k * (a * a + b * b + c * c);
+      f0 = psi_m(model, s, mu, lam, m0) + prox;
+      m0 += prox;
       have_f0 = true;
     }
     float t = 1.0f;
@@ -296,12 +316,15 @@ __device__ void prox3(int model, const float sig[3], float mu, float lam, float 
     for (int ls = 0; ls < 10; ++ls) {
       float tr[3] = {s[0] + t * dx[0], s[1] + t * dx[1], s[2] + t * dx[2]};
       float a = tr[0] - sig[0], b = tr[1] - sig[1], c = tr[2] - sig[2];
-      float f1 = psi(model, tr, mu, lam) + 0.5f * k * (a * a + b * b + c * c);
-      if (f1 <= f0 + 1e-4f * t * slope) {
+      const float prox = 0.5f * k * (a * a + b * b + c * c);
+      float m1;
+      float f1 = psi_m(model, tr, mu, lam, m1) + prox;
+      if (f1 <= f0 + 1e-4f * t * slope + kRound * m0) {
         s[0] = tr[0];
         s[1] = tr[1];
         s[2] = tr[2];
         f0 = f1;
+        m0 = m1 + prox;
         acc = true;
         break;
       }
