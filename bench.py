@@ -41,11 +41,14 @@ COUNTER_PASS_LAUNCHES = 20
 # moves 128 bytes (a plain 256 MiB copy makes 2,097,320 requests) while FETCH_SIZE counts 64,
 # and WRITE_SIZE of the copy equals its bytes (profiles/hbm_counters.md)
 TRAFFIC = {
-    "k_cr<0>, 64 blocks, teaser": 8.38e6,
-    "k_spmv_S (+k_spmv_S_finish), batch": 2.2127e9,
+    "k_cr<0>, 32 blocks, teaser": 9.2e6,
+    "k_cr<0>, 64 blocks, teaser": 11.0e6,
+    "k_cr<1>, 32 blocks, teaser": 9.9e6,
+    "k_cr<1>, 64 blocks, teaser": 11.4e6,
+    "k_spmv_S (+k_spmv_S_finish), batch": 2.2124e9,
     "k_spmv_St, batch": 2.2034e9,
-    "k_element (local step), batch": 270.4e6,
-    "k_element (local step), teaser": 12.66e6,
+    "k_element (local step), batch": 269.5e6,
+    "k_element (local step), teaser": 12.7e6,
 }
 TRAFFIC_NOTE = ("rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 per launch (profiles/hbm_counters.md); null where the "
                 "launch configuration differs from the counted one")
@@ -57,9 +60,11 @@ def log(msg):
 
 CR_STEPS = 10
 # local step: 4 node indices + 9 Dm^-1 entries + 4 material values in, 12 corner forces out;
-# about 1.5 kflop per tet at the least (the SVD's Jacobi sweeps and QR, one Newton step)
+# about 1.2 kflop per tet: the SVD's Jacobi sweeps and QR about 650, two Newton steps on the
+# singular values about 330, deformation gradients, P = U s V^T and the corner forces about
+# 200 (counters on the batch: 64 x SQ_INSTS_VALU_FLOPS_FP32 x lane utilisation / tets = 1181)
 ELEM_BYTES_PER_TET = 4 * (4 + 9 + 4) + 4 * 12
-ELEM_FLOP_PER_TET = 1500.0
+ELEM_FLOP_PER_TET = 1200.0
 FP32_PEAK_TFLOPS = 157.3
 
 
@@ -76,8 +81,20 @@ def _element_entry(kernel, tets, ms):
     return {"kernel": kernel, "bound": "alu", "achieved": round(tfl, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(tfl / FP32_PEAK_TFLOPS, 4), "hbm_GBps": round(gbs, 1),
             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "tets": int(tets), "avg_launch_ms": round(ms, 5),
-            "note": (f"{ELEM_BYTES_PER_TET} B and at least {ELEM_FLOP_PER_TET:.0f} flop per tet; one thread per tet "
-                     f"runs the SVD and a Newton solve on the singular values")}
+            "note": (f"{ELEM_BYTES_PER_TET} B and about {ELEM_FLOP_PER_TET:.0f} flop per tet; one thread per tet "
+                     f"runs the SVD and a Newton solve on the singular values; VALU counters (profiles/"
+                     f"element_valu_counters.md): VALU busy 0.69, lane utilisation 0.77")}
+
+
+def _with_traffic(entry):
+    """The counter-measured HBM bytes per launch of the entry's kernel and workload, and the
+    rate they give at the entry's launch time (null where not counted)."""
+    t = TRAFFIC.get(entry["kernel"])
+    entry["traffic"] = t
+    if t:
+        entry["traffic_GBps"] = round(t / (entry["avg_launch_ms"] * 1e-3) / 1e9, 1)
+        entry["traffic_frac"] = round(entry["traffic_GBps"] / HBM_PEAK_GBS, 4)
+    return entry
 
 
 def algorithmic_bytes(n, nnz_s):
@@ -106,6 +123,7 @@ def counter_pass(sim):
     group 1, 2, 4, 8 x segment 1024, 2048, 4096 floats) and then each S^T-pass column group
     (1, 2, 4, 8), 1 + COUNTER_PASS_LAUNCHES back-to-back launches; then the local step and
     the constraint solve; then the copy probes."""
+    from paper_2503_15078_amd import lgsim
     seq = []
     for rg in (1, 2, 4, 8):
         for seg in (1024, 2048, 4096):
@@ -118,10 +136,16 @@ def counter_pass(sim):
         seq.append(("St", cg))
     sim.time_kernel(2, COUNTER_PASS_LAUNCHES)
     seq.append(("local_step",))
-    for variant in (0, 1):  # both CR forms at the handle's CR grid
+    grids = sorted({sim.tuning()["cr_blocks"], 32, 64})
+    for variant in (0, 1):  # both CR forms at the handle's grid and at 32 and 64 blocks
         sim.set_solver(CR_STEPS, 0.0, variant)
-        sim.profile_cr(COUNTER_PASS_LAUNCHES)
-        seq.append(("cr", variant, sim.tuning()["cr_blocks"], "then one stamped launch after an impulse-restoring copy"))
+        for blocks in grids:
+            try:
+                sim.set_tuning(cr_blocks=blocks, cr_variant=variant)
+            except lgsim.SimError:  # fewer blocks than the contact capacity needs
+                continue
+            sim.profile_cr(COUNTER_PASS_LAUNCHES)
+            seq.append(("cr", variant, blocks, "then one stamped launch after an impulse-restoring copy"))
     return seq
 
 
@@ -289,8 +313,7 @@ def batch_throughput(count, steps):
     rl = [_hbm_entry("k_spmv_S (+k_spmv_S_finish), batch", b_s, k_s, "S (2.0 GB) streams from HBM every launch"),
           _hbm_entry("k_spmv_St, batch", b_st, k_st, "the column copy of S (2.0 GB) streams from HBM"),
           _element_entry("k_element (local step), batch", m, k_el)]
-    for e in rl:
-        e["traffic"] = TRAFFIC.get(e["kernel"])
+    rl = [_with_traffic(e) for e in rl]
     out = {"metric": "scenes x L-G iterations / s", "value": round(count * ITERS * steps / dt, 1),
            "scenes": count, "nodes": int(n), "tets": int(sum(len(s.tets) for s in scs)), "nnz_S": int(nnz),
            "ms_per_frame": round(1e3 * dt / steps, 3), "create_s": round(t_create, 1), "launch": tune,
@@ -435,8 +458,7 @@ def main():
         _hbm_entry("k_spmv_St, teaser", b_st, k_ms["St_pass"], "infinity-cache resident, as the S pass"),
         _element_entry("k_element (local step), teaser", tets_per_launch, k_ms["local_step"]),
     ]
-    for e in rooflines:
-        e["traffic"] = TRAFFIC.get(e["kernel"])
+    rooflines = [_with_traffic(e) for e in rooflines]
     log("to-tolerance frames")
     # iterate until the NCP residual is <= 1e-6 m; the constraint solve runs CR to a
     # relative residual of TOL_CR (at most TOL_CR_ITERS iterations) instead of 10

@@ -242,6 +242,14 @@ int sim_time_kernel(sim_t s, int32_t which, int32_t reps, float* ms_avg);
 #define SIM_PROFILE_MAX_REPS 64
 int sim_profile_cr(sim_t s, int32_t reps, float* out);
 
+/* Measurement: the wall-clock stamps (ticks at hipDeviceAttributeWallClockRate kHz) of
+ * the last sim_profile_cr's stamped launch, taken by the first block: [0] start, [1] end,
+ * then for each device-wide barrier b = 1, 2, ...: entry, exit, end of the read of the
+ * data the other blocks published before it, end of the products with the Delassus rows
+ * that follow (0 where none follow).  Copies min(cap, count) values; *n receives the
+ * count (0 before the first sim_profile_cr). */
+int sim_read_cr_stamps(sim_t s, uint64_t* out, int32_t cap, int32_t* n);
+
 /* Frames with a fixed iteration count are recorded once into a hipGraph (frame setup,
  * the iterations, integration: one launch per frame) and replayed; the graph is
  * re-recorded when a setting or the device state layout changes.  on = 0 launches the

@@ -76,6 +76,7 @@ struct lgsim {
   float* d_tgt = nullptr;             // [CMAX][3] scratch of sim_read_training_pairs
   float* d_lam_save = nullptr;        // [3][CMAX] impulses kept across sim_profile_cr
   unsigned long long* d_clock = nullptr;  // wall-clock stamps of sim_profile_cr
+  std::vector<unsigned long long> cr_stamps;  // the last stamped launch's stamps, as read back
   unsigned* d_prof_sync = nullptr;    // [SIM_PROFILE_MAX_REPS][kCrSyncWords] CR barrier flags of its launches
   std::vector<int32_t> iter_canon;    // internal contact index -> canonical position
   hipEvent_t ev[8] = {};
@@ -1310,7 +1311,7 @@ int sim_profile_cr(sim_t s, int32_t reps, float* out) {
     return SIM_E_ARG;
   }
   auto& d = s->d;
-  const size_t ncl = 2 + 3 * (size_t)lg::kCrMaxBarriers;
+  const size_t ncl = 2 + 4 * (size_t)lg::kCrMaxBarriers;
   if (!s->d_lam_save) TRY(s->alloc(s->d_lam_save, 3 * (size_t)d.CMAX));
   if (!s->d_clock) TRY(s->alloc(s->d_clock, ncl));
   const size_t lam_bytes = 3 * (size_t)d.CMAX * sizeof(float);
@@ -1359,18 +1360,30 @@ int sim_profile_cr(sim_t s, int32_t reps, float* out) {
   const double us = khz > 0 ? 1e3 / khz : 0.0;  // microseconds per tick
   int nb = 0;
   double exch = 0.0, wait = 0.0;
-  while (nb < lg::kCrMaxBarriers && clk[2 + 3 * nb] != 0) {
-    const unsigned long long t_in = clk[2 + 3 * nb], t_out = clk[3 + 3 * nb], t_data = clk[4 + 3 * nb];
+  while (nb < lg::kCrMaxBarriers && clk[2 + 4 * nb] != 0) {
+    const unsigned long long t_in = clk[2 + 4 * nb], t_out = clk[3 + 4 * nb], t_data = clk[4 + 4 * nb];
     wait += (double)(t_out - t_in) * us;
     exch += (double)((t_data ? t_data : t_out) - t_in) * us;
     ++nb;
   }
+  s->cr_stamps.assign(clk.begin(), clk.begin() + 2 + 4 * (size_t)nb);
   out[0] = ms_all / reps;
   out[1] = (float)((double)(clk[1] - clk[0]) * us);
   out[2] = nb ? (float)((double)(clk[2] - clk[0]) * us) : 0.0f;
   out[3] = nb ? (float)(exch / nb) : 0.0f;
   out[4] = nb ? (float)(wait / nb) : 0.0f;
   out[5] = (float)nb;
+  return SIM_OK;
+}
+
+int sim_read_cr_stamps(sim_t s, uint64_t* out, int32_t cap, int32_t* n) {
+  if (!s || !n || cap < 0 || (cap > 0 && !out)) {
+    lg::set_error("bad arguments");
+    return SIM_E_ARG;
+  }
+  const size_t m = std::min(s->cr_stamps.size(), (size_t)cap);
+  for (size_t i = 0; i < m; ++i) out[i] = s->cr_stamps[i];
+  *n = (int32_t)s->cr_stamps.size();
   return SIM_OK;
 }
 

@@ -126,7 +126,7 @@ struct Dev {
   float *cr_Z;                     // [2][2][3][CMAX] exchanged C^T (Omega v) of the CR launch
   float *cr_prod;                  // per-(block, scene slot) partial sums of the CR launch
   unsigned *cr_sync;               // [kCrSyncWords] barrier arrival flags of the CR launch
-  unsigned long long *cr_clock;    // null, or [2 + 3 kCrMaxBarriers] wall-clock stamps of CR block 0
+  unsigned long long *cr_clock;    // null, or [2 + 4 kCrMaxBarriers] wall-clock stamps of CR block 0
   float cr_tol;                    // relative CR residual tolerance (0: fixed count)
   // learned warm start
   double *ell;                     // [NS] mean rest edge length per scene

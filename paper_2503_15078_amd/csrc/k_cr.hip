@@ -50,9 +50,43 @@ constexpr unsigned kCrSpinLimit = 1u << 21;  // polls before a barrier wait is a
 // a block's scene slots span at most every scene of the handle
 static_assert(kMaxScenes <= kCrRows, "scene slot tables of a CR block");
 
-__device__ inline float wave_sum_cr(float v) {
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+// Cross-lane sums by DPP row operations and lane reads (a few cycles each) instead of
+// LDS-routed shuffles (an LDS round trip each).  All 16 lanes of a row must be active.
+template <int Ctrl>
+__device__ inline float dpp_mov(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), Ctrl, 0xF, 0xF, true));
+}
+// sum over each row of 16 lanes, in every lane of the row
+__device__ inline float row16_sum(float v) {
+  v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]: pairs
+  v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]: quads
+  v += dpp_mov<0x141>(v);  // row_half_mirror: the other quad of each 8
+  v += dpp_mov<0x140>(v);  // row_mirror: the other 8 of the row
   return v;
+}
+__device__ inline float lane_value(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+// sum over the 64 lanes (all active), the same value in every lane
+__device__ inline float wave_sum_cr(float v) {
+  v = row16_sum(v);
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+// v of the same lane in the other half (rows 0-1 <-> 2-3) and in the other row of the
+// half (0 <-> 1, 2 <-> 3), added to u: gfx950's lane-swap instructions
+__device__ inline float swap32_add(float keep_lo, float keep_hi) {
+  // lanes 0..31 keep keep_lo and receive keep_lo of lane + 32; lanes 32..63 keep keep_hi
+  // and receive keep_hi of lane - 32
+  const auto p = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(int, keep_lo), __builtin_bit_cast(int, keep_hi),
+                                                  false, false);
+  return __builtin_bit_cast(float, (int)p[0]) + __builtin_bit_cast(float, (int)p[1]);
+}
+__device__ inline float swap16_add(float keep_even, float keep_odd) {
+  // even rows keep keep_even and receive keep_even of the odd row beside them; odd rows
+  // keep keep_odd and receive keep_odd of the even row
+  const auto p = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(int, keep_even), __builtin_bit_cast(int, keep_odd),
+                                                  false, false);
+  return __builtin_bit_cast(float, (int)p[0]) + __builtin_bit_cast(float, (int)p[1]);
 }
 __device__ inline int pad4(int n) { return (n + 3) & ~3; }
 // largest i in [0, n) with a[i] <= e (a ascending, a[0] <= e)
@@ -134,7 +168,8 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
   const int c = d.k_off[d.NS] > d.KCAP ? 0 : min(d.n_contacts[0], d.CMAX);
   if (c == 0) return;  // uniform across the grid: no block reaches a barrier
   // optional wall-clock stamps of block 0 (measurement): [0] start, [1] end, then per
-  // barrier b = 1, 2, ...: entry, exit, end of the read of the exchanged data
+  // barrier b = 1, 2, ...: entry, exit, end of the read of the exchanged data, end of the
+  // products with K that follow it
   unsigned long long* clk = (d.cr_clock && blockIdx.x == 0) ? d.cr_clock : nullptr;
   auto stamp = [&](int idx) {
     if (clk && threadIdx.x == 0) clk[idx] = wall_clock64();
@@ -286,8 +321,56 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
   auto matvec_rows = [&](auto nv, bool staged, const float* Vg, auto fin) {
     constexpr int NV = decltype(nv)::value;
     if (k_in_lds && staged) {
+      // Per pass each wavefront takes 4 consecutive rows.  When they belong to one scene
+      // (always, for a single scene) the wavefront runs them together: each lane loads a
+      // column quad of V once for all 4 rows, and the 4 x 3 NV sums are reduced across the
+      // 64 lanes by halving exchanges (each step trades half of a lane's sums with its
+      // partner), so lane 16 r ends with row r's sums.  Otherwise each 16-lane group takes
+      // one of the rows, with its own slice of V.
       const int grp = tid >> 4, gl = tid & 15;
-      for (int t = grp; t < R; t += kCrBlock / 16) {
+      for (int base = 0; base < R; base += kCrBlock / 16) {
+        const int tw = base + 4 * wave, nr = min(4, R - tw);
+        if (nr <= 0) continue;
+        const int sl0 = row_slot[tw];
+        if (row_slot[tw + nr - 1] == sl0) {  // rows are in contact order, so scenes are contiguous
+          constexpr int NQ = 3 * NV;
+          const int cs = sl_cs[sl0], pc = pad4(sl_ce[sl0] - cs);
+          const float* kb = Ks + sl_kb[sl0] + (j0 + tw - max(cs, j0)) * pc;
+          const float* zb = Zs + sl_zb[sl0];
+          float a[4][NQ];
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) a[r][q] = 0.0f;
+          for (int k4 = lane; k4 < pc / 4; k4 += kWave) {
+            float4 z[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) z[q] = reinterpret_cast<const float4*>(zb + q * zpad)[k4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              if (r < nr) {
+                const float4 kv = reinterpret_cast<const float4*>(kb + r * pc)[k4];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) a[r][q] += kv.x * z[q].x + kv.y * z[q].y + kv.z * z[q].z + kv.w * z[q].w;
+              }
+            }
+          }
+          // rows (0, 1) stay in lanes 0..31 and rows (2, 3) in lanes 32..63, then the
+          // first row of each pair in the even 16-lane rows; the rest within each row
+          float w[2][NQ];
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) w[i][q] = swap32_add(a[i][q], a[2 + i][q]);
+          float u[NQ];
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) u[q] = row16_sum(swap16_add(w[0][q], w[1][q]));
+          const int r = lane >> 4;
+          if ((lane & 15) == 0 && r < nr) fin(tw + r, u);
+          continue;
+        }
+        const int t = base + grp;
+        if (t >= R) continue;
         const int sl = row_slot[t], cs = sl_cs[sl], pc = pad4(sl_ce[sl] - cs);
         const int rrow = j0 + t - max(cs, j0);
         const float4* K4 = reinterpret_cast<const float4*>(Ks + sl_kb[sl] + rrow * pc);
@@ -305,8 +388,7 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
           }
         }
 #pragma unroll
-        for (int q = 0; q < 3 * NV; ++q)
-          for (int o = 8; o > 0; o >>= 1) a[q] += __shfl_xor(a[q], o, 16);
+        for (int q = 0; q < 3 * NV; ++q) a[q] = row16_sum(a[q]);
         if (gl == 0) fin(t, a);
       }
       __syncthreads();
@@ -357,8 +439,7 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
         }
       }
 #pragma unroll
-      for (int q = 0; q < 3 * NV; ++q)
-        for (int o = 8; o > 0; o >>= 1) a[q] += __shfl_xor(a[q], o, 16);
+      for (int q = 0; q < 3 * NV; ++q) a[q] = row16_sum(a[q]);
       if (gl == 0) fin(t, a);
     }
     __syncthreads();
@@ -367,12 +448,13 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
   // read of what the other blocks published before it
   auto bar = [&](bool live) {
     ++nbar;
-    stamp(2 + 3 * (nbar - 1));
+    stamp(2 + 4 * (nbar - 1));
     const int r = grid_barrier(flags, nbar, live, &s_st, fail);
-    stamp(3 + 3 * (nbar - 1));
+    stamp(3 + 4 * (nbar - 1));
     return r;
   };
-  auto data_read = [&]() { stamp(4 + 3 * (nbar - 1)); };
+  auto data_read = [&]() { stamp(4 + 4 * (nbar - 1)); };
+  auto products_done = [&]() { stamp(5 + 4 * (nbar - 1)); };
   // K times the first nv vectors of exchange buffer `buf`, staged into Zs when they fit
   auto exch = [&](int buf) { return d.cr_Z + (int64_t)buf * 3 * NZ * CM; };
   auto matvec_Z = [&](auto nv, int buf, auto fin) {
@@ -478,6 +560,7 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
     row_products(t);
     if constexpr (V == 1) publish_Z((nbar + 1) & 1, 0, t, vw);
   });
+  products_done();
   publish_partials((nbar + 1) & 1);
   if (bar(true) < 0) return;
   gather_sums(nbar & 1, V == 1 ? 1 : 0);
@@ -549,6 +632,7 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
         rowM(t, a, vr, vw);  // w = M r
         row_products(t);
       });
+      products_done();
       publish_partials((nbar + 1) & 1);
       if (bar(true) < 0) return;
       gather_sums(nbar & 1, 0);
@@ -565,6 +649,7 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
         rowM(t, a, vw, vn);      // n = M w~
         rowM(t, a + 3, vr, vm);  // true M r
       });
+      products_done();
     }
   }
   // lambda += dlambda; F = h^2 C^T (Omega lambda)

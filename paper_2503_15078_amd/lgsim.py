@@ -111,6 +111,7 @@ def load():
         "sim_set_graph": [C.c_void_p, i32],
         "sim_time_kernel": [C.c_void_p, i32, i32, P(C.c_float)],
         "sim_profile_cr": [C.c_void_p, i32, P(C.c_float)],
+        "sim_read_cr_stamps": [C.c_void_p, P(C.c_uint64), i32, P(i32)],
         "sim_get_tuning": [C.c_void_p, P(sim_tuning)],
         "sim_set_tuning": [C.c_void_p, P(sim_tuning)],
         "sim_autotune": [C.c_void_p, i32, i32, i32, P(sim_tuning)],
@@ -363,6 +364,16 @@ class Sim:
         _check(_lib.sim_profile_cr(self.h, int(reps), _fp(out)))
         keys = ("ms_per_launch", "kernel_us", "setup_us", "exchange_us", "barrier_wait_us", "exchanges")
         return {k: float(v) for k, v in zip(keys, out)}
+
+    def cr_stamps(self):
+        """Wall-clock stamps (ticks) of the last profile_cr's stamped launch: start, end,
+        then per barrier (entry, exit, data read, products done; 0 where none)."""
+        n = C.c_int32(0)
+        _check(_lib.sim_read_cr_stamps(self.h, None, 0, C.byref(n)))
+        out = np.zeros(n.value, np.uint64)
+        if n.value:
+            _check(_lib.sim_read_cr_stamps(self.h, out.ctypes.data_as(C.POINTER(C.c_uint64)), n.value, C.byref(n)))
+        return out
 
     def tuning(self):
         t = sim_tuning()

@@ -449,6 +449,12 @@ def test_constraint_solve_profile(variant):
             assert 0.0 < p["barrier_wait_us"] <= p["exchange_us"]
             assert p["setup_us"] + p["exchanges"] * p["exchange_us"] <= p["kernel_us"] * 1.001
             assert 0.0 < p["kernel_us"] <= 1.5 * p["ms_per_launch"] * 1e3
+            st = sim.cr_stamps()
+            assert len(st) == 2 + 4 * int(p["exchanges"])
+            bars = st[2:].reshape(-1, 4).astype(np.int64)
+            assert (st[0] <= bars[0, 0]) and (bars[-1, 1] <= st[1])
+            assert np.all(bars[:, 1] >= bars[:, 0]) and np.all(bars[:, 2] >= bars[:, 1])
+            assert np.all(bars[1:, 0] >= np.maximum(bars[:-1, 2], bars[:-1, 3]))
             with pytest.raises(lgsim.SimError):
                 sim.profile_cr(65)  # beyond the profile's counter sets
         sim.step(2)
