@@ -6,14 +6,11 @@
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
+#include "lanes.hpp"
 #include "path_sums.hpp"
 
 namespace lg {
 
-__device__ inline float wave_sum_c(float v) {
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
-}
 
 // ---------------------------------------------------------------- float64 geometry
 // Signed distance and outward normal of an obstacle, in float64, with the operation
@@ -756,7 +753,7 @@ __device__ float ainv_wave(const Dev& d, int a, int b, int lane) {
   const float* cb = d.col_val + d.col_ptr[b];
   float acc = 0.0f;
   for (int t = lane; t <= D; t += kWave) acc += ca[da - t] * cb[db - t];
-  return wave_sum_c(acc);
+  return wave_sum(acc);
 }
 
 // Delassus entries of the self rows: K_jk = sum_e sum_f s_e s_f [A_n^-1]_(n_e n_f) over
@@ -960,7 +957,7 @@ __global__ void __launch_bounds__(kBlock) k_contact_prep(Dev d) {
     const double sg = multi ? d.ent_w[a * CM + j] : 1.0;
     float acc[1][3];
     column_path_sums<1>(d, d.y, v, 1, lane, acc);
-    const float ax = wave_sum_c(acc[0][0]), ay = wave_sum_c(acc[0][1]), az = wave_sum_c(acc[0][2]);
+    const float ax = wave_sum(acc[0][0]), ay = wave_sum(acc[0][1]), az = wave_sum(acc[0][2]);
     float xa[3], xta[3], dua[3];
     for (int q = 0; q < 3; ++q) {
       xa[q] = d.q[q * d.N4 + v];
@@ -1173,7 +1170,7 @@ __global__ void __launch_bounds__(kBlock) k_warm_judge(Dev d) {
     const float kk = krow[k];
     for (int q = 0; q < 6; ++q) w[q] += kk * d.wl[q * CM + cs + k];
   }
-  for (int q = 0; q < 6; ++q) w[q] = wave_sum_c(w[q]);
+  for (int q = 0; q < 6; ++q) w[q] = wave_sum(w[q]);
   if (lane != 0) return;
   const float h2 = (float)(d.h * d.h);
   float xp[3], xm[3], lp[3], lm[3], base[3], xt[3];

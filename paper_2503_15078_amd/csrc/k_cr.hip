@@ -38,6 +38,7 @@
 #include <type_traits>
 
 #include "device.hpp"
+#include "lanes.hpp"
 
 namespace lg {
 
@@ -50,44 +51,6 @@ constexpr unsigned kCrSpinLimit = 1u << 21;  // polls before a barrier wait is a
 // a block's scene slots span at most every scene of the handle
 static_assert(kMaxScenes <= kCrRows, "scene slot tables of a CR block");
 
-// Cross-lane sums by DPP row operations and lane reads (a few cycles each) instead of
-// LDS-routed shuffles (an LDS round trip each).  All 16 lanes of a row must be active.
-template <int Ctrl>
-__device__ inline float dpp_mov(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), Ctrl, 0xF, 0xF, true));
-}
-// sum over each row of 16 lanes, in every lane of the row
-__device__ inline float row16_sum(float v) {
-  v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]: pairs
-  v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]: quads
-  v += dpp_mov<0x141>(v);  // row_half_mirror: the other quad of each 8
-  v += dpp_mov<0x140>(v);  // row_mirror: the other 8 of the row
-  return v;
-}
-__device__ inline float lane_value(float v, int l) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
-}
-// sum over the 64 lanes (all active), the same value in every lane
-__device__ inline float wave_sum_cr(float v) {
-  v = row16_sum(v);
-  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
-}
-// v of the same lane in the other half (rows 0-1 <-> 2-3) and in the other row of the
-// half (0 <-> 1, 2 <-> 3), added to u: gfx950's lane-swap instructions
-__device__ inline float swap32_add(float keep_lo, float keep_hi) {
-  // lanes 0..31 keep keep_lo and receive keep_lo of lane + 32; lanes 32..63 keep keep_hi
-  // and receive keep_hi of lane - 32
-  const auto p = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(int, keep_lo), __builtin_bit_cast(int, keep_hi),
-                                                  false, false);
-  return __builtin_bit_cast(float, (int)p[0]) + __builtin_bit_cast(float, (int)p[1]);
-}
-__device__ inline float swap16_add(float keep_even, float keep_odd) {
-  // even rows keep keep_even and receive keep_even of the odd row beside them; odd rows
-  // keep keep_odd and receive keep_odd of the even row
-  const auto p = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(int, keep_even), __builtin_bit_cast(int, keep_odd),
-                                                  false, false);
-  return __builtin_bit_cast(float, (int)p[0]) + __builtin_bit_cast(float, (int)p[1]);
-}
 __device__ inline int pad4(int n) { return (n + 3) & ~3; }
 // largest i in [0, n) with a[i] <= e (a ascending, a[0] <= e)
 __device__ inline int slot_of(const int* a, int n, int e) {
@@ -488,7 +451,7 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
       for (int t = t0 + lane; t < t1; t += kWave)
         for (int q = 0; q < nt; ++q) a[q] += prod[q][t];
       for (int q = 0; q < nt; ++q) {
-        float v = wave_sum_cr(a[q]);
+        float v = wave_sum(a[q]);
         if (lane == 0) part[((int64_t)(sfirst + sl) * G + blockIdx.x) * kCrSlots + q] = v;
       }
     }
@@ -516,7 +479,7 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
       if (!mine) continue;
       const int t0 = max(sl_cs[sl], j0) - j0, t1 = min(sl_ce[sl], j1) - j0;
       for (int q = 0; q < nt; ++q) {
-        const float v = wave_sum_cr(a[q]);
+        const float v = wave_sum(a[q]);
         for (int t = t0 + lane; t < t1; t += kWave) prod[q][t] = v;
       }
     }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
+#include "lanes.hpp"
 
 namespace lg {
 
@@ -501,8 +502,8 @@ __global__ void k_gather(Dev d) {
       for (int c = 0; c < 3; ++c) acc[c] += d.fc[(corner * 3 + c) * d.M + tet];
     }
   }
-  for (int o = kGatherLanes / 2; o > 0; o >>= 1)
-    for (int c = 0; c < 3; ++c) acc[c] += __shfl_xor(acc[c], o, kGatherLanes);
+  static_assert(kGatherLanes == 8, "one node per half row of 8 lanes");
+  for (int c = 0; c < 3; ++c) acc[c] = sum8(acc[c]);
   if (!ok || l != 0) return;
   float w = d.pin_w[v];
   if (w != 0.0f)

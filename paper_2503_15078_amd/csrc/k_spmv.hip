@@ -5,14 +5,10 @@
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
+#include "lanes.hpp"
 #include "path_sums.hpp"
 
 namespace lg {
-
-__device__ inline float wave_sum(float v) {
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
-}
 
 // One wavefront per segment of a row group.  Row i is stored over columns
 // [lo4_i, hi4_i) in 16-byte groups; the rows of a group share lo4, so one float4 of
