@@ -47,6 +47,8 @@ constexpr int kCrKFloats = 20480;     // 80 KB of (padded) K rows per block
 constexpr int kCrZFloats = 3 * 2048;  // gathered (padded) Z of the touched scenes
 constexpr int kCrRows = 256;          // max contacts per block
 constexpr int kCrSlots = 4;           // partial sums per (block, scene slot)
+// blocks of at most this many rows keep each row's state in the registers of one lane
+constexpr int kCrRegRows = kCrBlock / 16;
 constexpr unsigned kCrSpinLimit = 1u << 21;  // polls before a barrier wait is abandoned
 // a block's scene slots span at most every scene of the handle
 static_assert(kMaxScenes <= kCrRows, "scene slot tables of a CR block");
@@ -163,10 +165,12 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
   for (int t = tid; t < R; t += kCrBlock) {
     int j = j0 + t;
     row_slot[t] = d.c_scene[j] - sfirst;
-    for (int q = 0; q < 9; ++q) Cl[q][t] = d.cC[q * CM + j];
-    for (int q = 0; q < 3; ++q) {
-      Oml[q][t] = d.Om[q * CM + j];
-      Etl[q][t] = d.Et[q * CM + j];
+    if (per > kCrRegRows) {  // else the rows' frames live in registers
+      for (int q = 0; q < 9; ++q) Cl[q][t] = d.cC[q * CM + j];
+      for (int q = 0; q < 3; ++q) {
+        Oml[q][t] = d.Om[q * CM + j];
+        Etl[q][t] = d.Et[q * CM + j];
+      }
     }
   }
   __syncthreads();
@@ -501,6 +505,181 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
   };
   const std::integral_constant<int, 1> one{};
   const std::integral_constant<int, 2> two{};
+  const float tol2 = d.cr_tol * d.cr_tol;
+
+  if (per <= kCrRegRows) {
+    // ---- every block owns at most 32 rows (uniform over the grid): row t = 4 w + i is
+    // owned by lane 16 i of wavefront w, the lane that finishes its products with K, and
+    // its state (frame, Omega, E~, the CR vectors and scalars) stays in that lane's
+    // registers.  Same arithmetic, exchanges and barriers as the form below.
+    const int t = 4 * wave + (lane >> 4);
+    const bool own = (lane & 15) == 0 && t < R;
+    const int j = j0 + t;
+    float C[9], Om[3], Et[3], x[3], r[3], p[3], q[3], w[3];
+    float z[3], n[3], m[3];  // pipelined form only
+    float g = 0.0f, qq = 0.0f, rr = 0.0f, rr0 = 0.0f;
+    bool live = false;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) x[k] = r[k] = p[k] = q[k] = w[k] = z[k] = n[k] = m[k] = Om[k] = Et[k] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) C[k] = 0.0f;
+    if (own) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) C[k] = d.cC[k * CM + j];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        Om[k] = d.Om[k * CM + j];
+        Et[k] = d.Et[k * CM + j];
+      }
+    }
+    // out = Omega (C y) + E~ v
+    auto rowM_r = [&](const float* y, const float* v, float* out) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float cy = C[3 * k] * y[0] + C[3 * k + 1] * y[1] + C[3 * k + 2] * y[2];
+        out[k] = Om[k] * cy + Et[k] * v[k];
+      }
+    };
+    auto publish_r = [&](int buf, int slot, const float* v) {
+      float* Zg = exch(buf) + 3 * slot * CM;
+      const float ov[3] = {Om[0] * v[0], Om[1] * v[1], Om[2] * v[2]};
+#pragma unroll
+      for (int k = 0; k < 3; ++k) Zg[k * CM + j] = C[k] * ov[0] + C[3 + k] * ov[1] + C[6 + k] * ov[2];
+    };
+    auto products_r = [&]() {  // (r, w), (w, w), (w, q), (r, r)
+      float a = 0.0f, b = 0.0f, e = 0.0f, f = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        a += r[k] * w[k];
+        b += w[k] * w[k];
+        e += w[k] * q[k];
+        f += r[k] * r[k];
+      }
+      prod[0][t] = a;
+      prod[1][t] = b;
+      prod[2][t] = e;
+      prod[3][t] = f;
+    };
+
+    // setup: r = (g - Omega h^2 W Omega lambda) / h^2, x = 0, w = M r, p = r, q = w
+    if (z_in_lds) stage(d.X, 1);
+    __syncthreads();
+    matvec_rows(one, z_in_lds, d.X, [&](int, const float* a) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float cy = C[3 * k] * a[0] + C[3 * k + 1] * a[1] + C[3 * k + 2] * a[2];
+        r[k] = (d.hv[k * CM + j] - Om[k] * h2 * cy) / h2;
+      }
+      publish_r((nbar + 1) & 1, 0, r);
+    });
+    if (bar(true) < 0) return;
+    matvec_Z(one, nbar & 1, [&](int, const float* a) {
+      rowM_r(a, r, w);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) q[k] = w[k];
+      products_r();
+      if constexpr (V == 1) publish_r((nbar + 1) & 1, 0, w);
+    });
+    products_done();
+    publish_partials((nbar + 1) & 1);
+    if (bar(true) < 0) return;
+    gather_sums(nbar & 1, V == 1 ? 1 : 0);
+    data_read();
+    if (own) {
+      g = prod[0][t];
+      qq = prod[1][t];
+      rr = rr0 = prod[3][t];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) p[k] = r[k];
+    }
+    if constexpr (V == 1)  // z = M q = M w
+      matvec_rows(one, z_in_lds, exch(nbar & 1), [&](int, const float* a) { rowM_r(a, w, z); });
+
+    for (int it = 0; it < d.cr_iters; ++it) {
+      const bool last = it + 1 == d.cr_iters;
+      int mine = 0;
+      if (own) {
+        if (it > 0 && live) {
+          const float g_new = prod[0][t], ww = prod[1][t], wq = prod[2][t];
+          const float beta = g_new / g;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            p[k] = r[k] + beta * p[k];
+            q[k] = w[k] + beta * q[k];
+            if constexpr (V == 1) {
+              z[k] = n[k] + beta * z[k];
+              w[k] = m[k];
+            }
+          }
+          qq = ww + 2.0f * beta * wq + beta * beta * qq;
+          g = g_new;
+          rr = prod[3][t];
+        }
+        live = qq != 0.0f && g != 0.0f && !(tol2 > 0.0f && rr <= tol2 * rr0);
+        mine = live ? 1 : 0;
+        if (live) {
+          const float alpha = g / qq;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            x[k] += alpha * p[k];
+            r[k] -= alpha * q[k];
+            if constexpr (V == 1) w[k] -= alpha * z[k];
+          }
+        }
+        if (!last) {
+          if constexpr (V == 0) {
+            publish_r((nbar + 1) & 1, 0, r);
+          } else {
+            products_r();  // with the recurrence w~
+            publish_r((nbar + 1) & 1, 0, w);
+            publish_r((nbar + 1) & 1, 1, r);
+          }
+        }
+      }
+      if (last) break;
+      if constexpr (V == 0) {
+        const int st = bar(mine != 0);
+        if (st < 0) return;
+        if (st == 0) break;
+        matvec_Z(one, nbar & 1, [&](int, const float* a) {
+          rowM_r(a, r, w);  // w = M r
+          products_r();
+        });
+        products_done();
+        publish_partials((nbar + 1) & 1);
+        if (bar(true) < 0) return;
+        gather_sums(nbar & 1, 0);
+        data_read();
+      } else {
+        __syncthreads();  // every row's products before the partial sums
+        publish_partials((nbar + 1) & 1);
+        const int st = bar(mine != 0);
+        if (st < 0) return;
+        if (st == 0) break;
+        gather_sums(nbar & 1, 2);
+        data_read();
+        matvec_rows(two, z_in_lds, exch(nbar & 1), [&](int, const float* a) {
+          rowM_r(a, w, n);      // n = M w~
+          rowM_r(a + 3, r, m);  // true M r
+        });
+        products_done();
+      }
+    }
+    // lambda += dlambda; F = h^2 C^T (Omega lambda)
+    if (own) {
+      float ol[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float l = d.lam[k * CM + j] + x[k];
+        d.lam[k * CM + j] = l;
+        ol[k] = Om[k] * l;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) d.F[k * CM + j] = h2 * (C[k] * ol[0] + C[3 + k] * ol[1] + C[6 + k] * ol[2]);
+    }
+    stamp(1);
+    return;
+  }
 
   // ---- setup: r = (g - Omega h^2 W Omega lambda) / h^2, x = 0, w = M r, p = r, q = w
   // (X = C^T (Omega lambda) from the contact kernel)
@@ -542,7 +721,6 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
   // x and r (alpha) and, unless it is the last, what the exchange needs, all row by row
   // without block barriers; the exchange; the products with K, each row finished (M, the
   // inner products) by the lane that summed it.
-  const float tol2 = d.cr_tol * d.cr_tol;
   for (int it = 0; it < d.cr_iters; ++it) {
     const bool last = it + 1 == d.cr_iters;
     int mine = 0;
