@@ -339,6 +339,9 @@ __device__ void prox3(int model, const float sig[3], float mu, float lam, float 
 // Per tet: F = sum_{a=1..3} (x_a - x_0) d_a^T at q^k and at q~, p = prox(F), and the
 // delta-form contribution P = h^2 w (p - F(q~)) scattered as corner forces P d_a
 // (so that the global step solves for q - q~).
+// FORM: 0 projective dynamics, 1 ADMM-PD (one instantiation each, so that the PD form
+// carries no dual registers)
+template <int FORM>
 __global__ void __launch_bounds__(kBlock) k_element(Dev d) {
   if (frame_done(d)) return;
   int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -364,7 +367,7 @@ __global__ void __launch_bounds__(kBlock) k_element(Dev d) {
     }
   // ADMM-PD: project F + u (u the tet's dual), then u += F - p and the global step takes
   // p - u; PD projects F itself
-  const bool admm = d.lg_form == 1;
+  constexpr bool admm = FORM == 1;
   float Fz[3][3], du[3][3];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
@@ -415,7 +418,8 @@ void launch_zero_dual(const Dev& d, hipStream_t st) {
 
 void launch_element(const Dev& d, hipStream_t st) {
   const int bs = d.elem_block > 0 ? d.elem_block : kBlock;
-  hipLaunchKernelGGL(k_element, dim3((d.M + bs - 1) / bs), dim3(bs), 0, st, d);
+  if (d.lg_form == 1) hipLaunchKernelGGL(k_element<1>, dim3((d.M + bs - 1) / bs), dim3(bs), 0, st, d);
+  else hipLaunchKernelGGL(k_element<0>, dim3((d.M + bs - 1) / bs), dim3(bs), 0, st, d);
 }
 
 // ---------------------------------------------------------------- L-G objective
