@@ -309,18 +309,23 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
           for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int q = 0; q < NQ; ++q) a[r][q] = 0.0f;
-          for (int k4 = lane; k4 < pc / 4; k4 += kWave) {
-            float4 z[NQ];
+          // every row's load issued before any product (a row past the block's last
+          // repeats that row; its sums are never used)
+          const float4* kr[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) kr[r] = reinterpret_cast<const float4*>(kb + min(r, nr - 1) * pc);
+          const int n4 = pc / 4;
+          for (int k4 = lane; k4 < n4; k4 += kWave) {
+            float4 z[NQ], kv[4];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) z[q] = reinterpret_cast<const float4*>(zb + q * zpad)[k4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              if (r < nr) {
-                const float4 kv = reinterpret_cast<const float4*>(kb + r * pc)[k4];
+            for (int r = 0; r < 4; ++r) kv[r] = kr[r][k4];
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) a[r][q] += kv.x * z[q].x + kv.y * z[q].y + kv.z * z[q].z + kv.w * z[q].w;
-              }
-            }
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+              for (int q = 0; q < NQ; ++q)
+                a[r][q] += kv[r].x * z[q].x + kv[r].y * z[q].y + kv[r].z * z[q].z + kv[r].w * z[q].w;
           }
           // rows (0, 1) stay in lanes 0..31 and rows (2, 3) in lanes 32..63, then the
           // first row of each pair in the even 16-lane rows; the rest within each row
