@@ -45,8 +45,8 @@ TRAFFIC = {
     "k_cr<0>, 64 blocks, teaser": 11.0e6,
     "k_cr<1>, 32 blocks, teaser": 9.9e6,
     "k_cr<1>, 64 blocks, teaser": 11.4e6,
-    "k_spmv_S (+k_spmv_S_finish), batch": 2.2124e9,
-    "k_spmv_St, batch": 2.2034e9,
+    "k_spmv_S (+k_spmv_S_finish), batch": 2.2152e9,
+    "k_spmv_St, batch": 2.2281e9,
     "k_element (local step), batch": 269.5e6,
     "k_element (local step), teaser": 12.7e6,
 }
