@@ -636,13 +636,11 @@ __global__ void __launch_bounds__(kBlock) k_delassus_tiles(Dev d) {
     int gm = 1 << 30;
     if (tj != tk)
       for (int q = J0 + nJ - 1 + tid; q < K0; q += kBlock) gm = min(gm, d.ad[q] < 0 ? -1 : d.ad[q]);
-    red[tid] = gm;
+    gm = wave_min_i(gm);
+    if ((tid & (kWave - 1)) == 0) red[tid / kWave] = gm;
     __syncthreads();
-    for (int o = kBlock / 2; o > 0; o >>= 1) {
-      if (tid < o) red[tid] = min(red[tid], red[tid + o]);
-      __syncthreads();
-    }
     int gap_min = red[0];
+    for (int w = 1; w < kBlock / kWave; ++w) gap_min = min(gap_min, red[w]);
     int lmax = 0;
     for (int p = tid; p < kDelTile * kDelTile; p += kBlock) {
       int a = p / kDelTile, b = p % kDelTile;
@@ -666,14 +664,15 @@ __global__ void __launch_bounds__(kBlock) k_delassus_tiles(Dev d) {
       LJK[a][b] = L;
       lmax = max(lmax, L);
     }
+    lmax = wave_max_i(lmax);
+    __syncthreads();  // every read of red[] above is done
+    if ((tid & (kWave - 1)) == 0) red[tid / kWave] = lmax;
     __syncthreads();
-    red[tid] = lmax;
-    __syncthreads();
-    for (int o = kBlock / 2; o > 0; o >>= 1) {
-      if (tid < o) red[tid] = max(red[tid], red[tid + o]);
-      __syncthreads();
+    if (tid == 0) {
+      int m = red[0];
+      for (int w = 1; w < kBlock / kWave; ++w) m = max(m, red[w]);
+      maxL = m;
     }
-    if (tid == 0) maxL = red[0];
     __syncthreads();
     // each thread: kPP pairs (a, b0 + r) of the tile
     constexpr int kPP = kDelTile * kDelTile / kBlock;
@@ -681,10 +680,11 @@ __global__ void __launch_bounds__(kBlock) k_delassus_tiles(Dev d) {
     const int a = tid / kCols, b0 = (tid % kCols) * kPP;
     float acc[kPP];
     for (int r = 0; r < kPP; ++r) acc[r] = 0.0f;
-    for (int base = 0; base < maxL; base += kDelChunk) {
-      // all loads of the chunk issued before the LDS stores (one memory round trip)
-      constexpr int kPer = kDelTile * kDelChunk / kBlock;
-      float vj[kPer], vk[kPer];
+    // chunks of kDelChunk depths, double-buffered: the next chunk's loads are in flight
+    // (all issued before any of its stores) while the current one is summed from LDS
+    constexpr int kPer = kDelTile * kDelChunk / kBlock;
+    float vj[kPer], vk[kPer];
+    auto load_chunk = [&](int base) {
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {
         const int p = tid + u * kBlock, r = p / kDelChunk, q = p % kDelChunk;
@@ -692,13 +692,23 @@ __global__ void __launch_bounds__(kBlock) k_delassus_tiles(Dev d) {
         vj[u] = (r < nJ && depthidx <= dJ[r]) ? d.col_val[cJ[r] + (dJ[r] - depthidx)] : 0.0f;
         vk[u] = (r < nK && depthidx <= dK[r]) ? d.col_val[cK[r] + (dK[r] - depthidx)] : 0.0f;
       }
+    };
+    auto store_chunk = [&]() {
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {
         const int p = tid + u * kBlock, r = p / kDelChunk, q = p % kDelChunk;
         PJ[r][q] = vj[u];
         PK[r][q] = vk[u];
       }
-      __syncthreads();
+    };
+    if (maxL > 0) {
+      load_chunk(0);
+      store_chunk();
+    }
+    __syncthreads();
+    for (int base = 0; base < maxL; base += kDelChunk) {
+      const bool more = base + kDelChunk < maxL;
+      if (more) load_chunk(base + kDelChunk);
       for (int r = 0; r < kPP; ++r) {
         const int L = LJK[a][b0 + r] - base;
         const int lim = min(L, kDelChunk), lim4 = max(lim, 0) >> 2;
@@ -712,6 +722,8 @@ __global__ void __launch_bounds__(kBlock) k_delassus_tiles(Dev d) {
         for (int q = 4 * lim4; q < lim; ++q) sacc += PJ[a][q] * PK[b0 + r][q];
         acc[r] += sacc;
       }
+      __syncthreads();
+      if (more) store_chunk();
       __syncthreads();
     }
     const int64_t ko = d.k_off[s];

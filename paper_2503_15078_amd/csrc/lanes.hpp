@@ -35,6 +35,27 @@ __device__ inline float wave_sum(float v) {
   v = row16_sum(v);
   return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
+// minimum / maximum over the 64 lanes (all active), the same value in every lane
+template <int Ctrl>
+__device__ inline int dpp_mov_i(int v) {
+  return __builtin_amdgcn_mov_dpp(v, Ctrl, 0xF, 0xF, true);
+}
+__device__ inline int wave_min_i(int v) {
+  v = min(v, dpp_mov_i<0xB1>(v));
+  v = min(v, dpp_mov_i<0x4E>(v));
+  v = min(v, dpp_mov_i<0x141>(v));
+  v = min(v, dpp_mov_i<0x140>(v));
+  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+__device__ inline int wave_max_i(int v) {
+  v = max(v, dpp_mov_i<0xB1>(v));
+  v = max(v, dpp_mov_i<0x4E>(v));
+  v = max(v, dpp_mov_i<0x141>(v));
+  v = max(v, dpp_mov_i<0x140>(v));
+  return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
 // v of the same lane in the other half (rows 0-1 <-> 2-3) and in the other row of the
 // half (0 <-> 1, 2 <-> 3), added to u: gfx950's lane-swap instructions
 __device__ inline float swap32_add(float keep_lo, float keep_hi) {
