@@ -56,6 +56,18 @@ __device__ inline int wave_max_i(int v) {
   return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
              max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
+// inclusive prefix sum over the 64 lanes (all active): within each row of 16 by shifts of
+// 1, 2, 4 and 8 lanes, then row 0's total into row 1 and row 2's into row 3 (row_bcast:15),
+// then row 1's total into rows 2 and 3 (row_bcast:31)
+__device__ inline int wave_incl_scan_i(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15, rows 1 and 3
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31, rows 2 and 3
+  return v;
+}
 // v of the same lane in the other half (rows 0-1 <-> 2-3) and in the other row of the
 // half (0 <-> 1, 2 <-> 3), added to u: gfx950's lane-swap instructions
 __device__ inline float swap32_add(float keep_lo, float keep_hi) {

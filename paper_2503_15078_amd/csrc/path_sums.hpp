@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
+#include "lanes.hpp"
 
 namespace lg {
 
@@ -19,8 +20,10 @@ __device__ inline float dot4(const float4& s, const float4& x) {
 // zero-padded to whole 4-node groups), so S values and the three y coordinates are
 // 16-byte loads, and one float4 of each y coordinate serves every column of the group.
 // The runs are flattened: up to 64 runs are held one per lane with their storage offsets
-// (a prefix sum), and each lane finds the run of its storage quad by a binary search
-// over the lanes, so every lane loads on every pass however short the runs are.  The
+// (a prefix sum), and each lane takes the storage quad t = c + lane of every pass c; the
+// runs that meet a pass's 64 quads are consecutive lanes, found by two ballots, and each
+// lane finds the run of its quad by reading their offsets (v_readlane), so every lane
+// loads on every pass however short the runs are, without LDS round trips.  The
 // caller reduces acc over the wavefront.
 template <int G>
 __device__ inline void column_path_sums(const Dev& d, const float* __restrict__ y, int j0, int ng, int lane,
@@ -49,23 +52,22 @@ __device__ inline void column_path_sums(const Dev& d, const float* __restrict__ 
       my_a4 = d.run_a[rb + c0 + lane] >> 2;
       my_n4 = (d.run_e[rb + c0 + lane] >> 2) + 1 - my_a4;
     }
-    int incl = my_n4;
-    for (int o = 1; o < kWave; o <<= 1) {
-      const int v = __shfl_up(incl, o, kWave);
-      if (lane >= o) incl += v;
-    }
-    const int my_t0 = incl - my_n4;  // storage offset of this lane's run within the batch
-    const int T = __shfl(incl, kWave - 1, kWave);
+    const int incl = wave_incl_scan_i(my_n4);
+    const int my_t0 = incl - my_n4;     // storage offset of this lane's run within the batch
+    const int my_off = my_a4 - my_t0;   // y quad of storage quad t in this run: t + my_off
+    const int T = __builtin_amdgcn_readlane(incl, kWave - 1);
 #pragma unroll 2
     for (int c = 0; c < T; c += kWave) {
       const int t = c + lane;
-      int r = 0;  // the last run whose storage offset is <= t
-      for (int step = kWave / 2; step > 0; step >>= 1) {
-        const int cand = r + step;
-        const int t0c = __shfl(my_t0, cand, kWave);
-        if (cand < nrb && t0c <= t) r = cand;
-      }
-      const int yq = __shfl(my_a4, r, kWave) + (t - __shfl(my_t0, r, kWave));
+      // runs r0 .. r1 meet quads [c, c + 64): r0 the last starting at or before c (run 0
+      // starts at 0), r1 the last starting before c + 64
+      const unsigned long long le = __ballot(lane < nrb && my_t0 <= c);
+      const unsigned long long lt = __ballot(lane < nrb && my_t0 < c + kWave);
+      const int r0 = 63 - __clzll(le), r1 = 63 - __clzll(lt);
+      int off = __builtin_amdgcn_readlane(my_off, r0);
+      for (int k = r0 + 1; k <= r1; ++k)
+        if (t >= __builtin_amdgcn_readlane(my_t0, k)) off = __builtin_amdgcn_readlane(my_off, k);
+      const int yq = t + off;
       if (t < T) {
         const float4 x = y0[yq], yy = y1[yq], z = y2[yq];
 #pragma unroll
