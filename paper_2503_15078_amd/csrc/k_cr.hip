@@ -185,20 +185,13 @@ __global__ void __launch_bounds__(kCrBlock) k_cr(Dev d) {
         nk = rows * pad4(cnt);
         nz = pad4(cnt);
       }
-      int vk = nk, vz2 = nz;
-      for (int o = 1; o < kWave; o <<= 1) {
-        int uk = __shfl_up(vk, o, kWave), uz = __shfl_up(vz2, o, kWave);
-        if (lane >= o) {
-          vk += uk;
-          vz2 += uz;
-        }
-      }
+      const int vk = wave_incl_scan_i(nk), vz2 = wave_incl_scan_i(nz);
       if (sl < nsl) {
         sl_kb[sl] = ck + vk - nk;
         sl_zb[sl] = cz + vz2 - nz;
       }
-      ck += __shfl(vk, kWave - 1, kWave);
-      cz += __shfl(vz2, kWave - 1, kWave);
+      ck += __builtin_amdgcn_readlane(vk, kWave - 1);
+      cz += __builtin_amdgcn_readlane(vz2, kWave - 1);
     }
     if (lane == 0) {
       sl_kb[nsl] = ck;

@@ -206,11 +206,34 @@ __global__ void __launch_bounds__(kBlock) k_apply_forces(Dev d) {
   const float* row = d.row_val + d.row_ptr[i];
   const int lo4 = d.row_lo4[i];
   float ax = 0.0f, ay = 0.0f, az = 0.0f;
-  for (int k = cb + lane; k < ce; k += kWave) {
-    float s = row[d.c_node[k] - lo4];
-    ax += s * d.F[k];
-    ay += s * d.F[d.CMAX + k];
-    az += s * d.F[2 * d.CMAX + k];
+  // four contacts per lane in flight (a row high in the tree holds every contact below it);
+  // each lane still adds its contacts in index order
+  constexpr int U = 4;
+  for (int k0 = cb + lane; k0 < ce; k0 += U * kWave) {
+    int node[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * kWave;
+      node[u] = k < ce ? d.c_node[k] : lo4;
+    }
+    float s[U], f[U][3];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * kWave;
+      const bool in = k < ce;
+      s[u] = in ? row[node[u] - lo4] : 0.0f;
+      f[u][0] = in ? d.F[k] : 0.0f;
+      f[u][1] = in ? d.F[d.CMAX + k] : 0.0f;
+      f[u][2] = in ? d.F[2 * d.CMAX + k] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (k0 + u * kWave < ce) {
+        ax += s[u] * f[u][0];
+        ay += s[u] * f[u][1];
+        az += s[u] * f[u][2];
+      }
+    }
   }
   for (int k = sb + lane; k < se; k += kWave) {  // entries of self rows: s_e F_row
     const int r = d.se_row[k];
