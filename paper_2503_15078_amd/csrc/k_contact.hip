@@ -169,8 +169,25 @@ __device__ void write_contact_frame(const Dev& d, int j, int v, const ObstacleDe
 }
 
 // ---------------------------------------------------------------- detection + compaction
+// exclusive prefix of v over a block of 32 * 64 threads at most (wavefront scans by DPP,
+// then the wavefront totals), and the block total in *total
+__device__ inline int block_excl_scan_i(int v, int* wsum, int* total) {
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  const int incl = wave_incl_scan_i(v);
+  if (lane == kWave - 1) wsum[w] = incl;
+  __syncthreads();
+  int before = 0, all = 0;
+  for (int k = 0; k < nw; ++k) {
+    const int x = wsum[k];
+    if (k < w) before += x;
+    all += x;
+  }
+  *total = all;
+  return before + incl - v;
+}
+
 __global__ void k_collide_count(Dev d) {
-  __shared__ int red[kBlock];
+  __shared__ int wsum[kBlock / kWave];
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   int cnt = 0;
   if (v < d.N) {
@@ -179,36 +196,24 @@ __global__ void k_collide_count(Dev d) {
     for (int o = d.scene_obst0[s]; o < d.scene_obst0[s + 1]; ++o) cnt += in_contact(d, d.obst[o], v, margin);
     d.cnt[v] = cnt;
   }
-  red[threadIdx.x] = cnt;
-  __syncthreads();
-  for (int o = kBlock / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) d.blk[blockIdx.x] = red[0];
+  int total = 0;
+  block_excl_scan_i(cnt, wsum, &total);
+  if (threadIdx.x == 0) d.blk[blockIdx.x] = total;
 }
 
 // single block: exclusive scan of the per-block counts; total -> n_contacts
 __global__ void k_collide_scan(Dev d, int nblk) {
-  __shared__ int part[1024];
+  __shared__ int wsum[1024 / kWave];
   int per = (nblk + 1023) / 1024;
   int b0 = threadIdx.x * per, b1 = min(nblk, b0 + per);
   int s = 0;
   for (int b = b0; b < b1; ++b) s += d.blk[b];
-  part[threadIdx.x] = s;
-  __syncthreads();
+  int total = 0;
+  int acc = block_excl_scan_i(s, wsum, &total);
   if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int t = 0; t < 1024; ++t) {
-      int x = part[t];
-      part[t] = acc;
-      acc += x;
-    }
-    d.n_contacts[0] = acc;
-    if (acc > d.CMAX) d.overflow[0] = 1;
+    d.n_contacts[0] = total;
+    if (total > d.CMAX) d.overflow[0] = 1;
   }
-  __syncthreads();
-  int acc = part[threadIdx.x];
   for (int b = b0; b < b1; ++b) {
     int x = d.blk[b];
     d.blk[b] = acc;
@@ -217,19 +222,13 @@ __global__ void k_collide_scan(Dev d, int nblk) {
 }
 
 __global__ void k_collide_write(Dev d) {
-  __shared__ int sc[kBlock];
+  __shared__ int wsum[kBlock / kWave];
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   int cnt = v < d.N ? d.cnt[v] : 0;
-  sc[threadIdx.x] = cnt;
-  __syncthreads();
-  for (int o = 1; o < kBlock; o <<= 1) {
-    int x = threadIdx.x >= o ? sc[threadIdx.x - o] : 0;
-    __syncthreads();
-    sc[threadIdx.x] += x;
-    __syncthreads();
-  }
+  int total = 0;
+  const int excl = block_excl_scan_i(cnt, wsum, &total);
   if (v >= d.N || cnt == 0) return;
-  int j = d.blk[blockIdx.x] + sc[threadIdx.x] - cnt;
+  int j = d.blk[blockIdx.x] + excl;
   int s = d.node_scene[v];
   double margin = d.scene_margin[s];
   for (int o = d.scene_obst0[s]; o < d.scene_obst0[s + 1]; ++o) {
@@ -680,11 +679,12 @@ __global__ void __launch_bounds__(kBlock) k_delassus_tiles(Dev d) {
     const int a = tid / kCols, b0 = (tid % kCols) * kPP;
     float acc[kPP];
     for (int r = 0; r < kPP; ++r) acc[r] = 0.0f;
-    // chunks of kDelChunk depths, double-buffered: the next chunk's loads are in flight
-    // (all issued before any of its stores) while the current one is summed from LDS
-    constexpr int kPer = kDelTile * kDelChunk / kBlock;
-    float vj[kPer], vk[kPer];
-    auto load_chunk = [&](int base) {
+    for (int base = 0; base < maxL; base += kDelChunk) {
+      // all loads of the chunk issued before the LDS stores (one memory round trip); the
+      // chunk is not prefetched during the previous one's sums, which would keep the rows'
+      // path offsets in registers and cost a wavefront per SIMD on large batches
+      constexpr int kPer = kDelTile * kDelChunk / kBlock;
+      float vj[kPer], vk[kPer];
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {
         const int p = tid + u * kBlock, r = p / kDelChunk, q = p % kDelChunk;
@@ -692,23 +692,13 @@ __global__ void __launch_bounds__(kBlock) k_delassus_tiles(Dev d) {
         vj[u] = (r < nJ && depthidx <= dJ[r]) ? d.col_val[cJ[r] + (dJ[r] - depthidx)] : 0.0f;
         vk[u] = (r < nK && depthidx <= dK[r]) ? d.col_val[cK[r] + (dK[r] - depthidx)] : 0.0f;
       }
-    };
-    auto store_chunk = [&]() {
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {
         const int p = tid + u * kBlock, r = p / kDelChunk, q = p % kDelChunk;
         PJ[r][q] = vj[u];
         PK[r][q] = vk[u];
       }
-    };
-    if (maxL > 0) {
-      load_chunk(0);
-      store_chunk();
-    }
-    __syncthreads();
-    for (int base = 0; base < maxL; base += kDelChunk) {
-      const bool more = base + kDelChunk < maxL;
-      if (more) load_chunk(base + kDelChunk);
+      __syncthreads();
       for (int r = 0; r < kPP; ++r) {
         const int L = LJK[a][b0 + r] - base;
         const int lim = min(L, kDelChunk), lim4 = max(lim, 0) >> 2;
@@ -722,8 +712,6 @@ __global__ void __launch_bounds__(kBlock) k_delassus_tiles(Dev d) {
         for (int q = 4 * lim4; q < lim; ++q) sacc += PJ[a][q] * PK[b0 + r][q];
         acc[r] += sacc;
       }
-      __syncthreads();
-      if (more) store_chunk();
       __syncthreads();
     }
     const int64_t ko = d.k_off[s];
