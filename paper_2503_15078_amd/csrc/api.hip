@@ -486,7 +486,7 @@ int build(lgsim* s, std::vector<lg::HostScene>& hs, const std::vector<std::vecto
   {
     std::vector<int> fill(g_ptr.begin(), g_ptr.end() - 1);
     for (int t = 0; t < M; ++t)
-      for (int a = 0; a < 4; ++a) g_slot[fill[tidx[a * (size_t)M + t]]++] = a * M + t;
+      for (int a = 0; a < 4; ++a) g_slot[fill[tidx[a * (size_t)M + t]]++] = 3 * a * M + t;  // fc offset of corner a
   }
   // S: row storage re-padded on global 4-aligned columns, column storage concatenated
   std::vector<int64_t> row_ptr(N + 1, 0), col_ptr(N + 1, 0);

@@ -62,7 +62,7 @@ struct Dev {
   float *qt, *vt, *qp, *q, *b, *y, *tgt, *pin_w, *tmp;
   int *node_scene;
   int *iperm_caller;               // internal node -> caller node
-  int *g_ptr, *g_slot;             // node -> (corner*M + tet) gather lists
+  int *g_ptr, *g_slot;             // node -> corner-force offsets (3 corner M + tet) gather lists
   // pins
   int *pin_node, *pin_group;
   double *pin_x0;                  // [3][P]

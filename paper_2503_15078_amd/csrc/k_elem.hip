@@ -499,11 +499,22 @@ __global__ void k_gather(Dev d) {
   const bool ok = v < d.N;  // whole groups of 8 lanes share v, so the butterfly stays in range
   float acc[3] = {0.0f, 0.0f, 0.0f};
   if (ok) {
+    // the node's corner forces, three per lane in flight, added in list order per lane
     const int e = d.g_ptr[v + 1];
-    for (int p = d.g_ptr[v] + l; p < e; p += kGatherLanes) {
-      int slot = d.g_slot[p];
-      int corner = slot / d.M, tet = slot - corner * d.M;
-      for (int c = 0; c < 3; ++c) acc[c] += d.fc[(corner * 3 + c) * d.M + tet];
+    constexpr int U = 3;
+    for (int p0 = d.g_ptr[v] + l; p0 < e; p0 += U * kGatherLanes) {
+      int base[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) base[u] = p0 + u * kGatherLanes < e ? d.g_slot[p0 + u * kGatherLanes] : -1;
+      float f[U][3];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) f[u][c] = base[u] >= 0 ? d.fc[base[u] + c * d.M] : 0.0f;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (base[u] >= 0)
+          for (int c = 0; c < 3; ++c) acc[c] += f[u][c];
     }
   }
   static_assert(kGatherLanes == 8, "one node per half row of 8 lanes");
@@ -539,6 +550,7 @@ void launch_check_finite(const Dev& d, hipStream_t st) {
 __global__ void k_integrate(Dev d) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (d.bad[0] || d.overflow[0]) return;
+  if (v == 0) d.t[0] += d.h;  // no thread of this kernel reads the time
   if (v < d.N) {
     const float ih = (float)(1.0 / d.h);
     for (int c = 0; c < 3; ++c) {
@@ -547,10 +559,6 @@ __global__ void k_integrate(Dev d) {
       d.qt[c * d.N4 + v] = x;
     }
   }
-}
-
-__global__ void k_advance_time(Dev d) {
-  if (threadIdx.x == 0 && blockIdx.x == 0 && !d.bad[0] && !d.overflow[0]) d.t[0] += d.h;
 }
 
 // Save the frame's contacts (key and world-space impulse) for the next warm start.
@@ -574,7 +582,6 @@ __global__ void k_save_contacts(Dev d) {
 void launch_integrate(const Dev& d, hipStream_t st) {
   hipLaunchKernelGGL(k_save_contacts, dim3((d.CMAX + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_integrate, dim3((d.N + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d);
-  hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(64), 0, st, d);
 }
 
 // positions (q_t) in caller order, float32 [3][N]
