@@ -326,6 +326,40 @@ def batch_throughput(count, steps):
     return out
 
 
+def mlp_throughput(steps=50):
+    """Warm-start network on random features: Adam training steps (forward, backward, the
+    gradient reduction and the update over the whole batch) and forward passes, per call
+    and in samples/s, timed with events on the stream the calls run on."""
+    import numpy as np
+    import torch
+    from paper_2503_15078_amd import lgsim, warm
+    rng = np.random.default_rng(0)
+    out = []
+    for n in (8192, lgsim.MLP_MAX_BATCH):
+        x = np.zeros((n, 16), np.float32)
+        x[:, :12] = rng.normal(0, 1, (n, 12))
+        X = torch.from_numpy(x).cuda()
+        T = torch.from_numpy(rng.normal(0, 0.3, (n, 3)).astype(np.float32)).cuda()
+        net = lgsim.Mlp(warm.init_params(0))
+        res = {"batch": n}
+        for name, call in (("train_step", lambda: net.train_step(X, T, 1e-3)), ("forward", lambda: net.forward(X))):
+            for _ in range(5):
+                call()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(steps):
+                call()
+            e1.record()
+            torch.cuda.synchronize()
+            us = 1e3 * e0.elapsed_time(e1) / steps
+            res[f"{name}_us"] = round(us, 1)
+            res[f"{name}_Msamples_per_s"] = round(n / us, 2)
+        net.close()
+        out.append(res)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -345,6 +379,8 @@ def main():
     ap.add_argument("--sweep-frames", type=int, default=400,
                     help="frames of each stiffness/model sweep configuration (0: none)")
     ap.add_argument("--batch-only", action="store_true", help="only the batch measurement (for profiling)")
+    ap.add_argument("--mlp-only", action="store_true", help="only the warm-start network's training and "
+                                                             "inference throughput")
     ap.add_argument("--counter-pass", action="store_true",
                     help="only the fixed S-pass launch sequence for rocprofv3 counters (teaser, or the batch "
                          "with --batch-only), then copy probes of 256 MiB and 4 GiB")
@@ -374,6 +410,9 @@ def main():
         return
     if args.batch_only:
         print(json.dumps({"batch": batch_throughput(args.batch_scenes, 10)}))
+        return
+    if args.mlp_only:
+        print(json.dumps({"warm_mlp_throughput": mlp_throughput()}))
         return
     log("building scene")
     sc = scenes.teaser_scene(0)
@@ -479,6 +518,8 @@ def main():
         params = np.load(weights)["params"]
         extras["warm_start_benchmark_state"] = warm_compare(sim, params)
         extras["warm_start_held_out_drops"] = warm_drops(params)
+    if not args.no_extras:
+        extras["warm_mlp_throughput"] = mlp_throughput()
     sim.close()
     if not args.no_extras and args.traj_frames > 0:
         seeds = [1000 + k for k in range(args.traj_seeds)]

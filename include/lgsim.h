@@ -442,7 +442,7 @@ int sim_read_warm_judge(sim_t s, float* res, float* lam_learned, int32_t cap, in
 /* ---- trainer of the warm-start network ------------------------------------------
  * Device-resident float32 parameters with Adam moments (beta1 0.9, beta2 0.999, eps
  * 1e-8, bias-corrected; Kingma and Ba 2015).  Batches are device pointers: d_x [n][16]
- * float32 features, d_t [n][3] float32 targets, loss = mean over n x 3 of (y - t)^2;
+ * float32 features (16-byte aligned, else SIM_E_ARG), d_t [n][3] float32 targets, loss = mean over n x 3 of (y - t)^2;
  * a training or gradient batch holds at most SIM_MLP_MAX_BATCH samples.
  * Work is enqueued on hip_stream (null: the default stream).  The gradient is a sum of
  * per-block partial sums added in block order, so results are deterministic. */
@@ -470,12 +470,14 @@ int mlp_destroy(mlp_t m);
  * scratch array inside the library, (SIM_MLP_NOALLOC_MAX_BATCH / 64) x
  * (SIM_MLP_N_PARAMS + 1) floats = 5.3 MB on each GPU it runs on, held until the
  * process ends.
- *   d_params  [SIM_MLP_N_PARAMS] float32 parameters (layout of sim_set_warm_model)
- *   d_x [n][16] features, d_t [n][3] targets (float32, as mlp_gradient)
+ *   d_params  [SIM_MLP_N_PARAMS] float32 parameters (layout of sim_set_warm_model),
+ *             16-byte aligned
+ *   d_x [n][16] features (16-byte aligned), d_t [n][3] targets (float32, as mlp_gradient)
  *   d_out     [SIM_MLP_N_PARAMS + 1] float32: the gradient, then the loss
  * All pointers are device memory of the current device (any allocator), borrowed for
  * the work enqueued on hip_stream (null: the default stream); the call does not wait.
- * 1 <= n <= SIM_MLP_NOALLOC_MAX_BATCH, else SIM_E_ARG before any device work; a failed
+ * 1 <= n <= SIM_MLP_NOALLOC_MAX_BATCH and the alignments hold, else SIM_E_ARG before
+ * any device work; a failed
  * lookup of the scratch array is SIM_E_DEVICE.  No allocating routine is called (the
  * first call on a device looks the array's address up once).  Every call on one GPU
  * uses that GPU's one scratch array, so calls that overlap in time on one GPU (other

@@ -4,12 +4,20 @@
 // cores with float32 accumulation, float32 master weights and Adam for training.
 //
 // Every layer is computed transposed, Z^T = W H^T, with the 16 samples of a wavefront
-// as the N dimension of v_mfma_f32_16x16x16_bf16.  In that form the float32 output tile
-// of one layer (lane l: rows 4 (l / 16) + i, column l % 16) is, after bias, GELU and
-// bf16 rounding, exactly the B operand of the next layer, so activations stay in
-// registers through the forward and backward passes.  Weight gradients contract over
-// samples; for them the block's 64 samples of each activation are written to LDS with
-// samples contiguous and each wavefront accumulates 20 of the 80 gradient tiles.
+// as the N dimension of the 16x16 matrix-core tiles.  In that form the float32 output
+// tile of one layer (lane l: rows 4 (l / 16) + i, column l % 16) is, after bias, GELU
+// and bf16 rounding, a B operand of the next layer, so activations stay in registers
+// through the forward and backward passes.  Contractions over 128 features use
+// v_mfma_f32_16x16x32_bf16, whose B operand is two such output tiles side by side; the
+// 16-wide ones (the input layer, the output gradient) use v_mfma_f32_16x16x16_bf16.
+// Weight gradients contract over samples; for them the block's 64 samples of each
+// activation are written to LDS with samples contiguous and each wavefront accumulates
+// 20 of the 80 gradient tiles.
+//
+// LDS rows are padded by 16 bytes so that the 16 rows one operand load touches start
+// on different banks.  The 128-wide weight rows are stored with their columns permuted
+// within each block of 32 (kperm), so that one 16-byte load gives a lane the eight
+// weights that meet its two output-tile halves.
 //
 // Features (per contact, frame start), with l the mean rest edge length of the scene:
 //   f0 (n . x~ - d_n) / l, f1..3 n, f4..6 h C (v_t - u_obstacle) / l,
@@ -24,6 +32,8 @@
 namespace lg {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // bf16 by round to nearest even on the bit pattern (NaN kept quiet)
@@ -34,40 +44,123 @@ __device__ inline short f2bf(float f) {
   return (short)(u >> 16);
 }
 __device__ inline float bf2f(short b) { return __uint_as_float(((unsigned)(unsigned short)b) << 16); }
-__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
-__device__ inline float gelu_grad(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
+// GELU h = z Phi(z) and its derivative Phi(z) + z phi(z), from one erf
+__device__ inline float gelu(float z, float& grad) {
+  const float Phi = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
+  grad = Phi + z * 0.39894228040143268f * __expf(-0.5f * z * z);
+  return z * Phi;
 }
 __device__ inline f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
+// K = 32: slot s of lane group g carries one contraction index for both operands alike,
+// so the sum is the same for any assignment of the 32 indices to (g, s)
+__device__ inline f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), c,
+                                                 0, 0, 0);
+}
 __device__ inline bf16x4 ld4(const short* p) { return *reinterpret_cast<const bf16x4*>(p); }
+__device__ inline bf16x8 ld8(const short* p) { return *reinterpret_cast<const bf16x8*>(p); }
+__device__ inline bf16x8 cat(bf16x4 a, bf16x4 b) { return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7); }
+
+// Row strides in LDS (shorts): 128-wide weight rows and 64-sample activation rows, each
+// padded by 8.
+constexpr int kW = 136, kS = 72;
+// Position of column c of a 128-wide weight row: within each block of 32 columns, lane
+// group g reads positions 8 g .. 8 g + 7, which hold columns 4 g .. 4 g + 3 (the first
+// output tile's rows for that group) and 16 + 4 g .. 16 + 4 g + 3 (the second tile's).
+__host__ __device__ constexpr int kperm(int c) { return (c & ~31) + 8 * ((c & 15) >> 2) + 4 * ((c & 31) >> 4) + (c & 3); }
 
 constexpr int kOW1 = 0, kOB1 = 2048, kOW2 = 2176, kOB2 = 18560, kOW3 = 18688, kOB3 = 20736;
 static_assert(kOB3 + 16 == kMlpParams, "parameter layout");
+static_assert(kOB1 % 4 == 0 && kOW2 % 4 == 0 && kOB2 % 4 == 0 && kOW3 % 4 == 0 && kOB3 % 4 == 0, "float4 staging");
 
-// weights of the forward pass in LDS (bf16, row-major [out][in]) and biases (float32)
-struct MlpSmem {
-  short W1[128 * 16], W2[128 * 128], W3[16 * 128];
+// weights of the forward pass in LDS (bf16, row-major [out][in], W2 and W3 rows padded
+// to kW with columns at kperm) and biases (float32)
+struct __attribute__((aligned(16))) MlpSmem {
+  short W1[128 * 16], W2[128 * kW], W3[16 * kW];
   float b1[128], b2[128], b3[16];
 };
 
-__device__ inline void load_forward_weights(MlpSmem& s, const float* P) {
-  for (int i = threadIdx.x; i < 128 * 16; i += blockDim.x) s.W1[i] = f2bf(P[kOW1 + i]);
-  for (int i = threadIdx.x; i < 128 * 128; i += blockDim.x) s.W2[i] = f2bf(P[kOW2 + i]);
-  for (int i = threadIdx.x; i < 16 * 128; i += blockDim.x) s.W3[i] = f2bf(P[kOW3 + i]);
-  for (int i = threadIdx.x; i < 128; i += blockDim.x) {
-    s.b1[i] = P[kOB1 + i];
-    s.b2[i] = P[kOB2 + i];
+__device__ inline bf16x4 f2bf4(float4 v) {
+  bf16x4 b;
+  b[0] = f2bf(v.x);
+  b[1] = f2bf(v.y);
+  b[2] = f2bf(v.z);
+  b[3] = f2bf(v.w);
+  return b;
+}
+
+// Reads N floats at src (16-byte aligned; the block's kBlock threads) as float4, up to
+// eight loads in flight per thread, and hands each to put(index of its first float, v).
+template <int N, class F>
+__device__ inline void stage(const float* src, F put) {
+  static_assert(N % 4 == 0, "whole float4");
+  constexpr int n4 = N / 4;
+  const float4* s4 = reinterpret_cast<const float4*>(src);
+  for (int i0 = threadIdx.x; i0 < n4; i0 += 8 * kBlock) {
+    float4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i0 + u * kBlock < n4) v[u] = s4[i0 + u * kBlock];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i0 + u * kBlock < n4) put(4 * (i0 + u * kBlock), v[u]);
   }
-  for (int i = threadIdx.x; i < 16; i += blockDim.x) s.b3[i] = P[kOB3 + i];
+}
+
+// Transposed bf16 copy of an R x 128 block of float32 parameters at src (row-major,
+// 16-byte aligned): entry (o, c) goes to dst[c * ld + col(o)], where col keeps every run
+// of four rows o = 4 k .. 4 k + 3 consecutive.  Each thread moves 4 x 4 sub-blocks, so
+// its stores are 8 bytes wide and the 32 lanes that share a row of dst fill it.
+template <int R, class Col>
+__device__ inline void stage_transposed(short* dst, int ld, const float* src, Col col) {
+  constexpr int nb = (R / 4) * 32;
+  for (int b0 = threadIdx.x; b0 < nb; b0 += 4 * kBlock) {
+    f32x4 v[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int b = b0 + u * kBlock, o = 4 * (b % (R / 4)), c = 4 * (b / (R / 4));
+      if (b < nb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[u][q] = *reinterpret_cast<const f32x4*>(src + (o + q) * 128 + c);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int b = b0 + u * kBlock, o = 4 * (b % (R / 4)), c = 4 * (b / (R / 4));
+      if (b < nb)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          bf16x4 t;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) t[q] = f2bf(v[u][q][k]);
+          *reinterpret_cast<bf16x4*>(dst + (c + k) * ld + col(o)) = t;
+        }
+    }
+  }
+}
+
+// P: the float32 parameters, 16-byte aligned; the block has kBlock threads
+__device__ inline void load_forward_weights(MlpSmem& s, const float* P) {
+  stage<128 * 16>(P + kOW1, [&](int e, float4 v) { *reinterpret_cast<bf16x4*>(s.W1 + e) = f2bf4(v); });
+  // four consecutive columns of a 128-wide row stay consecutive under kperm
+  stage<128 * 128>(P + kOW2, [&](int e, float4 v) {
+    *reinterpret_cast<bf16x4*>(s.W2 + (e >> 7) * kW + kperm(e & 127)) = f2bf4(v);
+  });
+  stage<16 * 128>(P + kOW3, [&](int e, float4 v) {
+    *reinterpret_cast<bf16x4*>(s.W3 + (e >> 7) * kW + kperm(e & 127)) = f2bf4(v);
+  });
+  stage<128>(P + kOB1, [&](int e, float4 v) { *reinterpret_cast<float4*>(s.b1 + e) = v; });
+  stage<128>(P + kOB2, [&](int e, float4 v) { *reinterpret_cast<float4*>(s.b2 + e) = v; });
+  stage<16>(P + kOB3, [&](int e, float4 v) { *reinterpret_cast<float4*>(s.b3 + e) = v; });
 }
 
 // Forward pass of one wavefront's 16 samples.  xb: B operand of the input (lane l:
 // sample l % 16, features 4 (l / 16) .. +3).  Returns y (lane l < 16: outputs 0..3 of
-// sample l); z1, z2 (pre-activations) and h1b, h2b (bf16 activations) in the output
-// tile layout (lane l: features 16 m + 4 (l / 16) + i of sample l % 16).
-__device__ inline f32x4 forward_tile(const MlpSmem& s, bf16x4 xb, f32x4 z1[8], bf16x4 h1b[8], f32x4 z2[8],
+// sample l); g1, g2 (GELU derivatives at the pre-activations, for the backward pass)
+// and h1b, h2b (bf16 activations) in the output tile layout (lane l: features
+// 16 m + 4 (l / 16) + i of sample l % 16).
+__device__ inline f32x4 forward_tile(const MlpSmem& s, bf16x4 xb, f32x4 g1[8], bf16x4 h1b[8], f32x4 g2[8],
                                      bf16x4 h2b[8]) {
   const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
   const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -75,31 +168,36 @@ __device__ inline f32x4 forward_tile(const MlpSmem& s, bf16x4 xb, f32x4 z1[8], b
   for (int m = 0; m < 8; ++m) {
     f32x4 z = mfma(ld4(s.W1 + (16 * m + r) * 16 + 4 * g), xb, zero);
     bf16x4 hb;
+    f32x4 gr;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      z[i] += s.b1[16 * m + 4 * g + i];
-      hb[i] = f2bf(gelu(z[i]));
+      float d;
+      hb[i] = f2bf(gelu(z[i] + s.b1[16 * m + 4 * g + i], d));
+      gr[i] = d;
     }
-    z1[m] = z;
+    g1[m] = gr;
     h1b[m] = hb;
   }
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
     f32x4 z = zero;
 #pragma unroll
-    for (int kc = 0; kc < 8; ++kc) z = mfma(ld4(s.W2 + (16 * m + r) * 128 + 16 * kc + 4 * g), h1b[kc], z);
+    for (int kc = 0; kc < 4; ++kc)
+      z = mfma32(ld8(s.W2 + (16 * m + r) * kW + 32 * kc + 8 * g), cat(h1b[2 * kc], h1b[2 * kc + 1]), z);
     bf16x4 hb;
+    f32x4 gr;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      z[i] += s.b2[16 * m + 4 * g + i];
-      hb[i] = f2bf(gelu(z[i]));
+      float d;
+      hb[i] = f2bf(gelu(z[i] + s.b2[16 * m + 4 * g + i], d));
+      gr[i] = d;
     }
-    z2[m] = z;
+    g2[m] = gr;
     h2b[m] = hb;
   }
   f32x4 y = zero;
 #pragma unroll
-  for (int kc = 0; kc < 8; ++kc) y = mfma(ld4(s.W3 + r * 128 + 16 * kc + 4 * g), h2b[kc], y);
+  for (int kc = 0; kc < 4; ++kc) y = mfma32(ld8(s.W3 + r * kW + 32 * kc + 8 * g), cat(h2b[2 * kc], h2b[2 * kc + 1]), y);
 #pragma unroll
   for (int i = 0; i < 4; ++i) y[i] += s.b3[4 * g + i];
   return y;
@@ -127,22 +225,22 @@ __global__ void __launch_bounds__(kBlock) k_mlp_forward(const float* P, const fl
   load_forward_weights(s, P);
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  f32x4 z1[8], z2[8];
+  f32x4 g1[8], g2[8];
   bf16x4 h1b[8], h2b[8];
   for (int base = (blockIdx.x * 4 + wave) * 16; base < n; base += gridDim.x * 64) {
     const int row = base + (lane & 15);
-    const f32x4 y = forward_tile(s, load_x(X, row, n), z1, h1b, z2, h2b);
+    const f32x4 y = forward_tile(s, load_x(X, row, n), g1, h1b, g2, h2b);
     if (lane < 16 && row < n)
       for (int i = 0; i < 3; ++i) Y[(int64_t)row * 3 + i] = y[i];
   }
 }
 
 // ---------------------------------------------------------------- training
-struct MlpTrainSmem {
+struct __attribute__((aligned(16))) MlpTrainSmem {
   MlpSmem f;
-  short W2T[128 * 128], W3T[128 * 16];  // transposes for the backward products
-  // the block's 64 samples of each activation, [feature][sample]
-  short XT[16 * 64], H1T[128 * 64], H2T[128 * 64], D1T[128 * 64], D2T[128 * 64], DYT[16 * 64];
+  short W2T[128 * kW], W3T[128 * 16];  // transposes for the backward products
+  // the block's 64 samples of each activation, [feature][sample], rows padded to kS
+  short XT[16 * kS], H1T[128 * kS], H2T[128 * kS], D1T[128 * kS], D2T[128 * kS], DYT[16 * kS];
   float red[kBlock / 64];
 };
 
@@ -154,8 +252,8 @@ __global__ void __launch_bounds__(kBlock) k_mlp_train(const float* P, const floa
                                                       float* partial) {
   __shared__ MlpTrainSmem s;
   load_forward_weights(s.f, P);
-  for (int i = threadIdx.x; i < 128 * 128; i += kBlock) s.W2T[(i % 128) * 128 + i / 128] = f2bf(P[kOW2 + i]);
-  for (int i = threadIdx.x; i < 16 * 128; i += kBlock) s.W3T[(i % 128) * 16 + i / 128] = f2bf(P[kOW3 + i]);
+  stage_transposed<128>(s.W2T, kW, P + kOW2, [](int o) { return kperm(o); });
+  stage_transposed<16>(s.W3T, 16, P + kOW3, [](int o) { return o; });
   __syncthreads();
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, r = lane & 15, g = lane >> 4;
   const float inv3n = 1.0f / (3.0f * (float)n);
@@ -163,14 +261,14 @@ __global__ void __launch_bounds__(kBlock) k_mlp_train(const float* P, const floa
   f32x4 acc[20];
   float db = 0.0f, db3 = 0.0f, loss = 0.0f;
   const int s0 = blockIdx.x * 64, s1 = min(n, s0 + 64);
-  f32x4 z1[8], z2[8];
+  f32x4 g1[8], g2[8];
   bf16x4 h1b[8], h2b[8];
   {
     const int base = s0;
     const int row = base + 16 * wave + r, col = 16 * wave + r;
     const bool valid = row < s1;
     const bf16x4 xb = load_x(X, valid ? row : n, n);
-    const f32x4 y = forward_tile(s.f, xb, z1, h1b, z2, h2b);
+    const f32x4 y = forward_tile(s.f, xb, g1, h1b, g2, h2b);
     // dL/dy for outputs 0..2 of valid samples (lanes 0..15 hold outputs 0..3)
     bf16x4 dyb;
 #pragma unroll
@@ -189,27 +287,28 @@ __global__ void __launch_bounds__(kBlock) k_mlp_train(const float* P, const floa
     for (int m = 0; m < 8; ++m) {
       f32x4 dh = mfma(ld4(s.W3T + (16 * m + r) * 16 + 4 * g), dyb, zero);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) d2b[m][i] = f2bf(dh[i] * gelu_grad(z2[m][i]));
+      for (int i = 0; i < 4; ++i) d2b[m][i] = f2bf(dh[i] * g2[m][i]);
     }
     // dZ1 = (W2^T dZ2^T) * gelu'(z1); activations to LDS, samples contiguous
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       f32x4 dh = zero;
 #pragma unroll
-      for (int kc = 0; kc < 8; ++kc) dh = mfma(ld4(s.W2T + (16 * m + r) * 128 + 16 * kc + 4 * g), d2b[kc], dh);
+      for (int kc = 0; kc < 4; ++kc)
+        dh = mfma32(ld8(s.W2T + (16 * m + r) * kW + 32 * kc + 8 * g), cat(d2b[2 * kc], d2b[2 * kc + 1]), dh);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int f = 16 * m + 4 * g + i;
-        s.D1T[f * 64 + col] = f2bf(dh[i] * gelu_grad(z1[m][i]));
-        s.D2T[f * 64 + col] = d2b[m][i];
-        s.H1T[f * 64 + col] = h1b[m][i];
-        s.H2T[f * 64 + col] = h2b[m][i];
+        s.D1T[f * kS + col] = f2bf(dh[i] * g1[m][i]);
+        s.D2T[f * kS + col] = d2b[m][i];
+        s.H1T[f * kS + col] = h1b[m][i];
+        s.H2T[f * kS + col] = h2b[m][i];
       }
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      s.XT[(4 * g + i) * 64 + col] = xb[i];
-      s.DYT[(4 * g + i) * 64 + col] = dyb[i];
+      s.XT[(4 * g + i) * kS + col] = xb[i];
+      s.DYT[(4 * g + i) * kS + col] = dyb[i];
     }
     __syncthreads();
     // weight gradients of this wavefront's tiles: t < 8 dW1 (row tile t), t < 72 dW2
@@ -220,27 +319,27 @@ __global__ void __launch_bounds__(kBlock) k_mlp_train(const float* P, const floa
       const int t = wave + 4 * k;
       const short *A, *Bm;
       if (t < 8) {
-        A = s.D1T + (16 * t + r) * 64;
-        Bm = s.XT + r * 64;
+        A = s.D1T + (16 * t + r) * kS;
+        Bm = s.XT + r * kS;
       } else if (t < 72) {
-        A = s.D2T + (16 * ((t - 8) >> 3) + r) * 64;
-        Bm = s.H1T + (16 * ((t - 8) & 7) + r) * 64;
+        A = s.D2T + (16 * ((t - 8) >> 3) + r) * kS;
+        Bm = s.H1T + (16 * ((t - 8) & 7) + r) * kS;
       } else {
-        A = s.DYT + r * 64;
-        Bm = s.H2T + (16 * (t - 72) + r) * 64;
+        A = s.DYT + r * kS;
+        Bm = s.H2T + (16 * (t - 72) + r) * kS;
       }
 #pragma unroll
-      for (int kc = 0; kc < 4; ++kc) acc[k] = mfma(ld4(A + 16 * kc + 4 * g), ld4(Bm + 16 * kc + 4 * g), acc[k]);
+      for (int kc = 0; kc < 2; ++kc) acc[k] = mfma32(ld8(A + 32 * kc + 8 * g), ld8(Bm + 32 * kc + 8 * g), acc[k]);
     }
     // bias gradients: sums over the block's samples
     {
-      const short* Dr = tid < 128 ? s.D1T + tid * 64 : s.D2T + (tid - 128) * 64;
+      const short* Dr = tid < 128 ? s.D1T + tid * kS : s.D2T + (tid - 128) * kS;
       float a = 0.0f;
       for (int q = 0; q < 64; ++q) a += bf2f(Dr[q]);
       db += a;
       if (tid < 16) {
         float b = 0.0f;
-        for (int q = 0; q < 64; ++q) b += bf2f(s.DYT[tid * 64 + q]);
+        for (int q = 0; q < 64; ++q) b += bf2f(s.DYT[tid * kS + q]);
         db3 += b;
       }
     }
@@ -269,16 +368,36 @@ __global__ void __launch_bounds__(kBlock) k_mlp_train(const float* P, const floa
   if (tid == 0) out[kMlpParams] = (s.red[0] + s.red[1]) + (s.red[2] + s.red[3]);
 }
 
-// Sum of the block partials in block order (gradient and loss), then optionally one
-// Adam step on the float32 master weights: m, v moments; c1 = 1 / (1 - b1^t),
-// c2 = 1 / (1 - b2^t).
-__global__ void k_mlp_adam(float* P, float* Mo, float* Vo, const float* partial, int nblk, float lr, float b1,
-                           float b2, float eps, float c1, float c2, float inv3n, int update, float* grad_out,
-                           float* loss_out) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p > kMlpParams) return;
-  float gsum = 0.0f;
-  for (int b = 0; b < nblk; ++b) gsum += partial[(int64_t)b * (kMlpParams + 1) + p];
+// Sum of the block partials (gradient and loss), then optionally one Adam step on the
+// float32 master weights: m, v moments; c1 = 1 / (1 - b1^t), c2 = 1 / (1 - b2^t).  A
+// block takes 64 consecutive entries, one per lane; each of its four wavefronts sums one
+// quarter of the partials (a contiguous range, in block order) and the four sums are
+// added in wavefront order, a fixed order for a given batch size.
+__global__ void __launch_bounds__(kBlock) k_mlp_adam(float* P, float* Mo, float* Vo, const float* partial, int nblk,
+                                                     float lr, float b1, float b2, float eps, float c1, float c2,
+                                                     float inv3n, int update, float* grad_out, float* loss_out) {
+  __shared__ float part[kBlock / 64][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int p = blockIdx.x * 64 + lane;
+  const int quarter = (nblk + 3) / 4, r0 = min(nblk, wave * quarter), r1 = min(nblk, r0 + quarter);
+  float a = 0.0f;
+  if (p <= kMlpParams) {
+    const float* src = partial + p;
+    constexpr int64_t kRow = kMlpParams + 1;
+    int b = r0;
+    for (; b + 8 <= r1; b += 8) {
+      float v[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = src[(int64_t)(b + i) * kRow];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) a += v[i];
+    }
+    for (; b < r1; ++b) a += src[(int64_t)b * kRow];
+  }
+  part[wave][lane] = a;
+  __syncthreads();
+  if (wave != 0 || p > kMlpParams) return;
+  const float gsum = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
   if (p == kMlpParams) {
     loss_out[0] = gsum * inv3n;
     return;
@@ -346,11 +465,11 @@ __global__ void __launch_bounds__(kBlock) k_mlp_warm(Dev d) {
   load_forward_weights(s, d.mlp_P);
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, CM = d.CMAX;
-  f32x4 z1[8], z2[8];
+  f32x4 g1[8], g2[8];
   bf16x4 h1b[8], h2b[8];
   for (int base = (blockIdx.x * 4 + wave) * 16; base < c; base += gridDim.x * 64) {
     const int j = base + (lane & 15);
-    const f32x4 y = forward_tile(s, load_x(d.c_feat, j, c), z1, h1b, z2, h2b);
+    const f32x4 y = forward_tile(s, load_x(d.c_feat, j, c), g1, h1b, g2, h2b);
     if (lane < 16 && j < c) {
       const int sc = d.c_scene[j], cs = d.cs_off[sc], cnt = d.cs_off[sc + 1] - cs;
       const float kjj = d.K[d.k_off[sc] + (int64_t)(j - cs) * kstride(cnt) + (j - cs)];
@@ -401,7 +520,8 @@ void launch_mlp_train(const float* P, const float* X, const float* T, int n, flo
 void launch_mlp_adam(float* P, float* M, float* V, const float* partial, int n, float lr, float b1, float b2,
                      float eps, float c1, float c2, int update, float* grad_out, float* loss_out, hipStream_t st) {
   const int nb = mlp_train_blocks(n);
-  hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 1 + kBlock - 1) / kBlock), dim3(kBlock), 0, st, P, M, V,
+  static_assert(kBlock == 256, "four wavefronts per block");
+  hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 1 + 63) / 64), dim3(kBlock), 0, st, P, M, V,
                      partial, nb, lr, b1, b2, eps, c1, c2, 1.0f / (3.0f * (float)n), update, grad_out, loss_out);
 }
 

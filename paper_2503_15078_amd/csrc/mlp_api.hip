@@ -33,8 +33,11 @@ void release(lg_mlp* m) {
   delete m;
 }
 
+// the kernels read features (and parameters) as float4
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
 int check_batch(lg_mlp* m, const float* x, const float* t, int32_t n, bool need_t) {
-  if (!m || !x || (need_t && !t) || n <= 0 || (need_t && n > lg::kMlpMaxBatch)) {
+  if (!m || !x || (need_t && !t) || n <= 0 || (need_t && n > lg::kMlpMaxBatch) || !aligned16(x)) {
     lg::set_error("bad arguments");
     return SIM_E_ARG;
   }
@@ -188,9 +191,10 @@ int mlp_gradient(mlp_t m, const float* d_x, const float* d_t, int32_t n, void* h
 
 int mlp_gradient_noalloc(const float* d_params, const float* d_x, const float* d_t, int32_t n, float* d_out,
                          void* hip_stream) {
-  if (!d_params || !d_x || !d_t || !d_out || n <= 0 || n > SIM_MLP_NOALLOC_MAX_BATCH) {
+  if (!d_params || !d_x || !d_t || !d_out || n <= 0 || n > SIM_MLP_NOALLOC_MAX_BATCH || !aligned16(d_params) ||
+      !aligned16(d_x)) {
     lg::set_error("mlp_gradient_noalloc: bad arguments (batch must hold 1.." +
-                  std::to_string(SIM_MLP_NOALLOC_MAX_BATCH) + " samples)");
+                  std::to_string(SIM_MLP_NOALLOC_MAX_BATCH) + " samples; params and features 16-byte aligned)");
     return SIM_E_ARG;
   }
   float* part = nullptr;

@@ -175,6 +175,21 @@ def test_non_finite_prediction_falls_back_to_previous_impulse():
     np.testing.assert_array_equal(runs[0][2]["lam"], runs[1][2]["lam"])
 
 
+def test_misaligned_features_are_refused():
+    """Features are read as float4: a batch that starts one float off is SIM_E_ARG,
+    checked on the host before any launch."""
+    net = lgsim.Mlp(_params(3))
+    x, t = _batch(64, 4)
+    buf = torch.zeros(64 * 16 + 1, dtype=torch.float32, device="cuda:0")
+    X = buf[1:].view(64, 16)
+    X.copy_(_dev(x))
+    for call in (lambda: net.forward(X), lambda: net.train_step(X, _dev(t), 1e-3), lambda: net.gradient(X, _dev(t))):
+        with pytest.raises(lgsim.SimError) as e:
+            call()
+        assert e.value.code == -1
+    net.close()
+
+
 def test_mlp_mode_without_model_is_an_error():
     sim = lgsim.Sim(scenes.cube_drop(0), warm=lgsim.SIM_WARM_MLP)
     with pytest.raises(lgsim.SimError) as e:

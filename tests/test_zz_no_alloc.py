@@ -68,5 +68,14 @@ def test_noalloc_gradient_rejects_batches_beyond_its_scratch():
         with pytest.raises(lgsim.SimError) as e:
             lgsim.mlp_gradient_noalloc(P, X, T, out)
         assert e.value.code == -1  # SIM_E_ARG
+    # parameters and features are read as float4: a pointer off by one float is refused
+    x, t = _batch(64, 6)
+    X, T = _dev(x), _dev(t)
+    Pu = torch.zeros(lgsim.MLP_N_PARAMS + 1, dtype=torch.float32, device="cuda:0")[1:]
+    Xu = torch.zeros(64 * 16 + 1, dtype=torch.float32, device="cuda:0")[1:].view(64, 16)
+    for p_, x_ in ((Pu, X), (P, Xu)):
+        with pytest.raises(lgsim.SimError) as e:
+            lgsim.mlp_gradient_noalloc(p_, x_, T, out)
+        assert e.value.code == -1
     torch.cuda.synchronize()
     assert torch.count_nonzero(out).item() == 0  # nothing was launched
