@@ -41,10 +41,22 @@ COUNTER_PASS_LAUNCHES = 20
 # moves 128 bytes (a plain 256 MiB copy makes 2,097,320 requests) while FETCH_SIZE counts 64,
 # and WRITE_SIZE of the copy equals its bytes (profiles/hbm_counters.md)
 TRAFFIC = {
+    "k_cr<0>, 16 blocks, teaser": 4.7e6,
     "k_cr<0>, 32 blocks, teaser": 9.2e6,
+    "k_cr<0>, 48 blocks, teaser": 10.6e6,
     "k_cr<0>, 64 blocks, teaser": 11.0e6,
+    "k_cr<0>, 96 blocks, teaser": 11.1e6,
+    "k_cr<0>, 128 blocks, teaser": 10.9e6,
+    "k_cr<0>, 192 blocks, teaser": 12.2e6,
+    "k_cr<0>, 256 blocks, teaser": 13.6e6,
+    "k_cr<1>, 16 blocks, teaser": 5.5e6,
     "k_cr<1>, 32 blocks, teaser": 9.9e6,
+    "k_cr<1>, 48 blocks, teaser": 11.1e6,
     "k_cr<1>, 64 blocks, teaser": 11.4e6,
+    "k_cr<1>, 96 blocks, teaser": 11.2e6,
+    "k_cr<1>, 128 blocks, teaser": 10.7e6,
+    "k_cr<1>, 192 blocks, teaser": 11.4e6,
+    "k_cr<1>, 256 blocks, teaser": 12.2e6,
     "k_spmv_S (+k_spmv_S_finish), batch": 2.2152e9,
     "k_spmv_St, batch": 2.2281e9,
     "k_element (local step), batch": 269.5e6,
@@ -136,8 +148,9 @@ def counter_pass(sim):
         seq.append(("St", cg))
     sim.time_kernel(2, COUNTER_PASS_LAUNCHES)
     seq.append(("local_step",))
-    grids = sorted({sim.tuning()["cr_blocks"], 32, 64})
-    for variant in (0, 1):  # both CR forms at the handle's grid and at 32 and 64 blocks
+    # both CR forms at every grid the autotuner may choose (those the contact capacity allows)
+    grids = sorted({sim.tuning()["cr_blocks"], 16, 32, 48, 64, 96, 128, 192, 256})
+    for variant in (0, 1):
         sim.set_solver(CR_STEPS, 0.0, variant)
         for blocks in grids:
             try:
@@ -366,6 +379,8 @@ def main():
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--tol-frames", type=int, default=3)
+    ap.add_argument("--frame-dist", type=int, default=300,
+                    help="frames of the per-frame median / p90 pass (after 20 warm-up frames; 0 skips it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--launch", default=None,
@@ -453,6 +468,18 @@ def main():
     t1 = time.perf_counter()
     ms_frame = 1e3 * (t1 - t0) / args.steps
     ms_iter = ms_frame / ITERS
+    # per-frame distribution: 20 more warm-up frames, then 300 frames each followed by a
+    # device synchronisation (so each time includes one host round trip, which the
+    # back-to-back figure above does not)
+    per_frame = []
+    if args.frame_dist > 0:
+        log(f"per-frame times: {args.frame_dist} frames, each synchronised")
+        for i in range(20 + args.frame_dist):
+            a = time.perf_counter()
+            frame()
+            torch.cuda.synchronize()
+            if i >= 20:
+                per_frame.append(1e3 * (time.perf_counter() - a))
     sim.restore_state()
     contacts = sim.step(1, iters=ITERS, stats=True)[0]["contacts"]
 
@@ -567,6 +594,10 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_frame, 4),
+        "per_frame_ms": {"median": round(float(np.median(per_frame)), 4),
+                         "p90": round(float(np.percentile(per_frame, 90)), 4), "frames": len(per_frame),
+                         "warmup": 20, "timing": "wall clock around each frame and a device synchronisation"}
+        if per_frame else None,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
