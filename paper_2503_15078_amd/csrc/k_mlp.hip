@@ -70,6 +70,16 @@ constexpr int kW = 136, kS = 72;
 // group g reads positions 8 g .. 8 g + 7, which hold columns 4 g .. 4 g + 3 (the first
 // output tile's rows for that group) and 16 + 4 g .. 16 + 4 g + 3 (the second tile's).
 __host__ __device__ constexpr int kperm(int c) { return (c & ~31) + 8 * ((c & 15) >> 2) + 4 * ((c & 31) >> 4) + (c & 3); }
+constexpr bool kperm_valid() {  // a permutation of 0..127 that keeps runs of four whole
+  bool seen[128] = {};
+  for (int c = 0; c < 128; ++c) {
+    const int p = kperm(c);
+    if (p < 0 || p >= 128 || seen[p] || ((c & 3) != 0 && p != kperm(c - 1) + 1)) return false;
+    seen[p] = true;
+  }
+  return true;
+}
+static_assert(kperm_valid(), "kperm");
 
 constexpr int kOW1 = 0, kOB1 = 2048, kOW2 = 2176, kOB2 = 18560, kOW3 = 18688, kOB3 = 20736;
 static_assert(kOB3 + 16 == kMlpParams, "parameter layout");
